@@ -1,0 +1,225 @@
+/*
+ * tn.h - C ABI of libtn: contraction of a partitioned tensor network on one
+ * MI355X (gfx950) GPU.
+ *
+ * The problem is stated as in Sections 2.1-2.4 and 4 of "Optimizing tensor
+ * network partitioning using Simulated Annealing":
+ *   - a tensor network G = (V, E) of dense complex tensors with labelled legs;
+ *     a label on two slots is a bound edge (the two dimensions must agree), a
+ *     label on one slot is an open edge (Section 2.1);
+ *   - every bound edge is contracted, pairwise, into one tensor (Section 2.2);
+ *   - the order is a full binary contraction tree whose leaves are in
+ *     bijection with the tensors (Section 2.3);
+ *   - a partitioning K of V that the tree accepts: for every partition a tree
+ *     vertex whose leaves are exactly that partition (Section 2.4);
+ *   - the partitions are contracted in turn (on one GPU), then the part of the
+ *     tree above the partition roots, the reduction path (Section 4, phases 2
+ *     and 4).
+ * Every pairwise contraction runs as leg permutations and a complex GEMM
+ * (TTGT, Section 5.1), or, where one operand is tiny, as a single streaming
+ * pass that applies the small tensor in place.
+ *
+ * Conventions
+ *   - No C++ types or exceptions cross this interface.  Every function returns
+ *     a tn_status; a negative value is an error and tn_last_error() returns a
+ *     thread-local message describing it.  Nothing aborts on bad input.
+ *   - Tensors are dense, row-major in the order of their legs (the last leg
+ *     varies fastest); complex values are interleaved (re, im).
+ *   - Arrays passed in are borrowed for the duration of the call only;
+ *     tn_plan_load and tn_serve_submit copy whatever they keep.
+ *   - Device memory: the library never allocates device memory on its own.
+ *     All device data (leaves, descriptors, intermediates, caches) live in
+ *     the arena handed to tn_ctx_create, which stays owned by the caller and
+ *     must outlive the context.
+ *   - Precision: data on the GPU are complex64; the GEMMs run either in FP32
+ *     on the FP32 matrix cores or as a three-term split-BF16 product with FP32
+ *     accumulation.  Every intermediate carries an FP64 power-of-two scale
+ *     (log2) so that amplitudes cannot underflow, and the final contraction of
+ *     a closed network accumulates in FP64.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tn_status;
+
+enum {
+  TN_OK = 0,
+  TN_PENDING = 1,              /* serve: result not ready yet */
+  TN_E_INVALID_ARG = -1,       /* bad pointer, size, dtype or flag */
+  TN_E_INVALID_PLAN = -2,      /* the network / partition / tree violates Section 2 */
+  TN_E_NOMEM = -3,             /* the arena cannot hold what the call needs */
+  TN_E_DEVICE = -4,            /* a HIP runtime call failed */
+  TN_E_AGAIN = -5,             /* serve queue full; retry later */
+  TN_E_CANCELLED = -6,         /* serve request cancelled (context destroyed) */
+  TN_E_UNKNOWN_TICKET = -7     /* serve ticket never issued or already consumed */
+};
+
+typedef enum { TN_C64 = 0, TN_C128 = 1 } tn_dtype;
+
+/* flags of tn_plan_load (precision and GEMM form) and of tn_contract* */
+enum {
+  TN_PREC_FP32 = 0,        /* FP32 complex GEMM on the FP32 matrix cores */
+  TN_PREC_BF16X3 = 1,      /* x = h + l split into two BF16 terms; a*b ~ hh + hl + lh */
+  TN_FORM_4M = 0,          /* four real products per complex product */
+  TN_FORM_3M = 1 << 4,     /* three real products (Gauss) */
+  TN_FLAG_KEEP_SCALE = 1 << 8 /* return mantissa and log2 scale separately */
+};
+
+typedef struct tn_ctx tn_ctx;   /* arena, stream, caches, scheduler */
+typedef struct tn_plan tn_plan; /* immutable after load; shareable across threads */
+
+/*
+ * The network, its partitioning and its contraction tree (Sections 2.1-2.4).
+ *   num_tensors   |V| >= 1.
+ *   rank          d_v for every tensor (0 allowed: a scalar), length |V|.
+ *   legs          concatenated edge labels, length sum(d_v).  A bound label
+ *                 occurs on exactly two slots of two different tensors, an
+ *                 open label on one slot.  Self-loops and labels on three or
+ *                 more slots are rejected.
+ *   leg_dims      n_{v,a} for every slot (>= 1), same length as legs; both
+ *                 slots of a bound label must agree.
+ *   data          |V| host pointers, tensor v row-major in its leg order,
+ *                 prod(n_{v,.}) elements of data_dtype.
+ *   partition_of  partition index of every tensor, values 0..num_partitions-1,
+ *                 each value used (cover, disjoint, non-empty).
+ *   tree          SSA pairs: internal vertex |V|+j contracts tree[2j] and
+ *                 tree[2j+1]; |V|-1 pairs; every vertex but the last is used
+ *                 exactly once; the last pair is the root.  The tree must
+ *                 accept the partitioning.
+ *   output_legs   order of the open labels in the result (each exactly once);
+ *                 NULL with num_output_legs == 0 takes them in order of first
+ *                 appearance.  A closed network has none and yields a scalar.
+ */
+typedef struct {
+  int32_t num_tensors;
+  const int32_t *rank;
+  const int64_t *legs;
+  const int64_t *leg_dims;
+  const void *const *data;
+  tn_dtype data_dtype;
+  const int32_t *partition_of;
+  int32_t num_partitions;
+  const int32_t *tree;
+  const int64_t *output_legs;
+  int32_t num_output_legs;
+} tn_plan_desc;
+
+/*
+ * Exact cost integers of the loaded plan (Section 3), as (hi, lo) 64-bit
+ * halves of 128-bit values:
+ *   con_serial  eq. con_serial: sum over internal vertices of 2^vc;
+ *   con_par     eq. con_par: heaviest leaf-to-root path, leaf excluded;
+ *   con_dist    eq. con_dist with con = con_serial and comm = 0;
+ *   mem_elems   eq. mem, in elements.
+ * live_peak_bytes is the peak of this library's own execution order (every
+ * live intermediate plus TTGT scratch, 256-byte aligned), which eq. mem
+ * bounds from below.
+ */
+typedef struct {
+  uint64_t con_serial[2], con_par[2], con_dist[2], mem_elems[2];
+  uint64_t live_peak_bytes, largest_intermediate_elems;
+  int32_t num_internal_nodes, num_gemm_nodes, num_tiny_nodes;
+  int32_t num_stream_nodes, num_permutations;
+} tn_plan_costs;
+
+/* A leaf override: tensor `tensor` takes `data` (same size) for one query. */
+typedef struct {
+  int32_t tensor;
+  const void *data;
+  tn_dtype dtype;
+} tn_leaf;
+
+typedef struct {
+  tn_plan *plan;
+  int32_t num_overrides;
+  const tn_leaf *overrides;
+} tn_query;
+
+/*
+ * Create a context on the current HIP device.
+ *   arena_dev_ptr  device memory of arena_bytes bytes (256-byte aligned),
+ *                  borrowed until tn_ctx_destroy.
+ *   hip_stream     the hipStream_t every launch of this context goes to
+ *                  (NULL = the null stream), borrowed.
+ *   flags          0.
+ * Errors: TN_E_INVALID_ARG for a NULL or misaligned arena; TN_E_DEVICE if
+ * pinned staging memory cannot be allocated.
+ */
+tn_status tn_ctx_create(void *arena_dev_ptr, size_t arena_bytes, void *hip_stream, uint32_t flags,
+                        tn_ctx **out);
+
+/* Stop the serve scheduler (pending requests end TN_E_CANCELLED), wait for
+ * the device, release host resources.  Plans of this context must be freed
+ * first; returns TN_E_INVALID_ARG otherwise. */
+tn_status tn_ctx_destroy(tn_ctx *ctx);
+
+/* Message for the last negative status returned on this thread. */
+const char *tn_last_error(void);
+
+/*
+ * Validate the network, partitioning and tree (TN_E_INVALID_PLAN names the
+ * violated condition), derive legs(v) and 2^vc of every vertex, fix the TTGT
+ * schedule (leg order of every intermediate, GEMM shapes, which permutations
+ * are needed), compute the cost integers and the arena layout, and copy the
+ * leaves to the device as complex64.
+ *   ctx    may be NULL: the plan is then host-only (validation, schedule and
+ *          costs; no device upload) and can only be inspected.
+ *   flags  TN_PREC_* | TN_FORM_*.
+ * The plan stays valid until tn_plan_free and is read-only.
+ */
+tn_status tn_plan_load(tn_ctx *ctx, const tn_plan_desc *desc, uint32_t flags, tn_plan **out);
+tn_status tn_plan_costs_get(const tn_plan *plan, tn_plan_costs *out);
+tn_status tn_plan_free(tn_plan *plan);
+
+/*
+ * Contract the plan's network once (the plain path: one launch sequence per
+ * tree vertex, nothing cached).  Leaves listed in `overrides` are replaced
+ * for this call only.  Synchronous: returns when `out` (host memory, the
+ * product of the output dimensions elements of out_dtype, in output-leg order)
+ * holds the result.  With TN_FLAG_KEEP_SCALE in `flags` the mantissa is
+ * written and *log2_scale receives the FP64 exponent (value = out *
+ * 2^log2_scale); otherwise the scale is folded in and log2_scale, if not
+ * NULL, receives 0.
+ * Errors: TN_E_INVALID_ARG (host-only plan, bad override), TN_E_NOMEM (the
+ * arena cannot hold the workspace), TN_E_DEVICE.
+ */
+tn_status tn_contract(tn_plan *plan, int32_t num_overrides, const tn_leaf *overrides, void *out,
+                      tn_dtype out_dtype, double *log2_scale, uint32_t flags);
+
+/*
+ * Contract several queries.  Queries on the same plan run together: every
+ * tree vertex whose leaves include no overridden leaf is computed once and
+ * shared, and each remaining vertex is one launch over all queries of the
+ * plan.  Results as for tn_contract; per_query[i] receives each query's
+ * status (may be NULL).  Returns the first error, or TN_OK.
+ */
+tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *queries,
+                            void *const *outs, tn_dtype out_dtype, double *log2_scales,
+                            tn_status *per_query, uint32_t flags);
+
+/*
+ * Serving.  tn_serve_submit copies the query and returns a ticket at once
+ * (TN_E_AGAIN when the queue is full).  A library thread admits queued
+ * requests while their workspace fits the free arena, groups admitted
+ * requests on the same plan into one batched launch sequence and completes
+ * them with events, so requests that arrive while others run join the next
+ * round (continuous batching).  tn_serve_poll returns TN_PENDING until the
+ * result is ready, then writes it like tn_contract, sets *latency_s to
+ * submit-to-ready seconds and consumes the ticket.
+ */
+tn_status tn_serve_submit(tn_ctx *ctx, const tn_query *query, uint64_t *ticket);
+tn_status tn_serve_poll(tn_ctx *ctx, uint64_t ticket, void *out, tn_dtype out_dtype,
+                        double *log2_scale, double *latency_s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_H */

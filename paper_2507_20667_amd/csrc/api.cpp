@@ -1,0 +1,218 @@
+// C entry points of libtn (declared in include/tn.h).
+#include <cstring>
+#include <new>
+
+#include "tn_internal.h"
+
+using namespace tn;
+
+extern "C" {
+
+const char *tn_last_error(void) { return tn::last_error(); }
+
+tn_status tn_ctx_create(void *arena_dev_ptr, size_t arena_bytes, void *hip_stream, uint32_t flags,
+                        tn_ctx **out) {
+  if (!out || !arena_dev_ptr || arena_bytes < 4096 || ((uintptr_t)arena_dev_ptr & 255) || flags) {
+    set_error("tn_ctx_create: need a 256-byte aligned arena of at least 4 KiB, flags = 0");
+    return TN_E_INVALID_ARG;
+  }
+  tn_ctx *c = new (std::nothrow) tn_ctx;
+  if (!c) {
+    set_error("out of host memory");
+    return TN_E_NOMEM;
+  }
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    set_error("hipGetDevice failed");
+    return TN_E_DEVICE;
+  }
+  c->arena.init((uint8_t *)arena_dev_ptr, arena_bytes);
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return TN_OK;
+}
+
+tn_status tn_ctx_destroy(tn_ctx *ctx) {
+  if (!ctx) {
+    set_error("tn_ctx_destroy: NULL context");
+    return TN_E_INVALID_ARG;
+  }
+  serve_shutdown(ctx);
+  if (ctx->live_plans.load() > 0) {
+    set_error("tn_ctx_destroy: %d plan(s) of this context are still loaded", ctx->live_plans.load());
+    return TN_E_INVALID_ARG;
+  }
+  hipStreamSynchronize(ctx->stream);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  delete ctx;
+  return TN_OK;
+}
+
+tn_status tn_plan_load(tn_ctx *ctx, const tn_plan_desc *desc, uint32_t flags, tn_plan **out) {
+  if (!out) {
+    set_error("tn_plan_load: out is NULL");
+    return TN_E_INVALID_ARG;
+  }
+  *out = nullptr;
+  const uint32_t known = TN_PREC_BF16X3 | TN_FORM_3M;
+  if (flags & ~known) {
+    set_error("tn_plan_load: unknown flag bits 0x%x", flags & ~known);
+    return TN_E_INVALID_ARG;
+  }
+  tn_plan *p = new (std::nothrow) tn_plan;
+  if (!p) {
+    set_error("out of host memory");
+    return TN_E_NOMEM;
+  }
+  p->flags = flags;
+  tn_status st = build_plan(p, desc);
+  if (st != TN_OK) {
+    delete p;
+    return st;
+  }
+  if (ctx) {
+    std::lock_guard<std::mutex> g(ctx->exec_mu);
+    p->ctx = ctx;
+    p->dev_leaf_bytes = std::max<size_t>(p->leaf_host.size() * sizeof(float2), 256);
+    p->dev_desc_bytes = std::max<size_t>(p->desc_blob.size(), 256);
+    p->dev_leaf = ctx->arena.alloc(p->dev_leaf_bytes);
+    p->dev_desc = ctx->arena.alloc(p->dev_desc_bytes);
+    if (p->dev_leaf < 0 || p->dev_desc < 0) {
+      ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes);
+      ctx->arena.release(p->dev_desc, p->dev_desc_bytes);
+      delete p;
+      set_error("tn_plan_load: arena cannot hold the leaves and descriptors");
+      return TN_E_NOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(ctx->arena.base() + p->dev_leaf, p->leaf_host.data(),
+                                  p->leaf_host.size() * sizeof(float2), hipMemcpyHostToDevice,
+                                  ctx->stream);
+    if (e == hipSuccess && !p->desc_blob.empty())
+      e = hipMemcpyAsync(ctx->arena.base() + p->dev_desc, p->desc_blob.data(), p->desc_blob.size(),
+                         hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes);
+      ctx->arena.release(p->dev_desc, p->dev_desc_bytes);
+      delete p;
+      set_error("tn_plan_load: upload failed: %s", hipGetErrorString(e));
+      return TN_E_DEVICE;
+    }
+    ctx->live_plans++;
+  }
+  *out = p;
+  return TN_OK;
+}
+
+static void put128(uint64_t *dst, u128 v) {
+  dst[0] = (uint64_t)(v >> 64);
+  dst[1] = (uint64_t)v;
+}
+
+tn_status tn_plan_costs_get(const tn_plan *p, tn_plan_costs *out) {
+  if (!p || !out) {
+    set_error("tn_plan_costs_get: NULL argument");
+    return TN_E_INVALID_ARG;
+  }
+  memset(out, 0, sizeof(*out));
+  put128(out->con_serial, p->con_serial);
+  put128(out->con_par, p->con_par);
+  put128(out->con_dist, p->con_dist);
+  put128(out->mem_elems, p->mem);
+  out->live_peak_bytes = (uint64_t)p->plain.peak_intermediate;
+  out->largest_intermediate_elems = (uint64_t)p->largest;
+  out->num_internal_nodes = p->nv - 1;
+  out->num_gemm_nodes = p->num_gemm;
+  out->num_tiny_nodes = p->num_tiny;
+  out->num_stream_nodes = p->num_stream;
+  out->num_permutations = p->num_perm;
+  return TN_OK;
+}
+
+tn_status tn_plan_free(tn_plan *p) {
+  if (!p) {
+    set_error("tn_plan_free: NULL plan");
+    return TN_E_INVALID_ARG;
+  }
+  if (p->ctx) {
+    tn_ctx *ctx = p->ctx;
+    std::lock_guard<std::mutex> g(ctx->exec_mu);
+    hipStreamSynchronize(ctx->stream);
+    ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes);
+    ctx->arena.release(p->dev_desc, p->dev_desc_bytes);
+    ctx->live_plans--;
+  }
+  delete p;
+  return TN_OK;
+}
+
+tn_status tn_contract(tn_plan *p, int32_t num_overrides, const tn_leaf *overrides, void *out,
+                      tn_dtype out_dtype, double *log2_scale, uint32_t flags) {
+  if (!p || !p->ctx) {
+    set_error("tn_contract: plan is NULL or host-only (loaded without a context)");
+    return TN_E_INVALID_ARG;
+  }
+  if (num_overrides < 0 || (num_overrides > 0 && !overrides) || (flags & ~TN_FLAG_KEEP_SCALE)) {
+    set_error("tn_contract: bad overrides or flags");
+    return TN_E_INVALID_ARG;
+  }
+  QueryIO q;
+  q.ovr = overrides;
+  q.novr = num_overrides;
+  q.out = out;
+  q.log2s = log2_scale;
+  std::lock_guard<std::mutex> g(p->ctx->exec_mu);
+  return run_group(p->ctx, p, {q}, out_dtype, flags, false, p->ctx->stream);
+}
+
+tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *queries,
+                            void *const *outs, tn_dtype out_dtype, double *log2_scales,
+                            tn_status *per_query, uint32_t flags) {
+  if (!ctx || num_queries < 0 || (num_queries > 0 && (!queries || !outs)) ||
+      (flags & ~TN_FLAG_KEEP_SCALE)) {
+    set_error("tn_contract_batch: bad arguments");
+    return TN_E_INVALID_ARG;
+  }
+  // group queries by plan, keeping first-appearance order
+  std::vector<tn_plan *> plans;
+  std::vector<std::vector<int>> members;
+  for (int i = 0; i < num_queries; ++i) {
+    tn_plan *p = queries[i].plan;
+    if (!p || p->ctx != ctx || queries[i].num_overrides < 0 ||
+        (queries[i].num_overrides > 0 && !queries[i].overrides)) {
+      set_error("tn_contract_batch: query %d has no plan of this context or bad overrides", i);
+      if (per_query) per_query[i] = TN_E_INVALID_ARG;
+      return TN_E_INVALID_ARG;
+    }
+    size_t k = 0;
+    while (k < plans.size() && plans[k] != p) ++k;
+    if (k == plans.size()) {
+      plans.push_back(p);
+      members.emplace_back();
+    }
+    members[k].push_back(i);
+  }
+  tn_status first = TN_OK;
+  std::lock_guard<std::mutex> g(ctx->exec_mu);
+  for (size_t k = 0; k < plans.size(); ++k) {
+    std::vector<QueryIO> qs;
+    for (int i : members[k]) {
+      QueryIO q;
+      q.ovr = queries[i].overrides;
+      q.novr = queries[i].num_overrides;
+      q.out = outs[i];
+      q.log2s = log2_scales ? &log2_scales[i] : nullptr;
+      q.status = per_query ? &per_query[i] : nullptr;
+      qs.push_back(q);
+    }
+    tn_status st = run_group(ctx, plans[k], qs, out_dtype, flags, true, ctx->stream);
+    if (st != TN_OK) {
+      if (per_query)
+        for (int i : members[k]) per_query[i] = st;
+      if (first == TN_OK) first = st;
+    }
+  }
+  return first;
+}
+
+}  // extern "C"

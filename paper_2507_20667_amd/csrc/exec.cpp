@@ -1,0 +1,350 @@
+// Execution of a plan for a group of queries: partitions in turn, then the
+// reduction path (Section 4, phases 2 and 4, one GPU), one launch sequence per
+// tree vertex.  Vertices that no overridden leaf reaches are computed once and
+// shared when `share` is set; every other vertex runs once for all queries of
+// the group (grid dimension y = query).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "tn_internal.h"
+
+namespace tn {
+
+size_t result_elems(const tn_plan *p) {
+  return p->closed ? 1 : (size_t)p->result_layout.size();
+}
+
+static size_t rnd(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static tn_status ensure_pinned(tn_ctx *ctx, size_t bytes) {
+  if (ctx->pinned_bytes >= bytes) return TN_OK;
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  ctx->pinned = nullptr;
+  ctx->pinned_bytes = 0;
+  size_t nb = std::max(bytes, (size_t)1 << 20);
+  if (hipHostMalloc(&ctx->pinned, nb, hipHostMallocDefault) != hipSuccess) {
+    ctx->pinned = nullptr;
+    set_error("hipHostMalloc of %zu bytes of pinned staging failed", nb);
+    return TN_E_DEVICE;
+  }
+  ctx->pinned_bytes = nb;
+  return TN_OK;
+}
+
+static void to_c64(const tn_leaf &l, int64_t n, float2 *dst) {
+  if (l.dtype == TN_C128) {
+    const double *s = (const double *)l.data;
+    for (int64_t i = 0; i < n; ++i) dst[i] = make_float2((float)s[2 * i], (float)s[2 * i + 1]);
+  } else {
+    memcpy(dst, l.data, sizeof(float2) * n);
+  }
+}
+
+static void write_out(void *out, tn_dtype dt, size_t i, double re, double im) {
+  if (dt == TN_C128) {
+    ((double *)out)[2 * i] = re;
+    ((double *)out)[2 * i + 1] = im;
+  } else {
+    ((float *)out)[2 * i] = (float)re;
+    ((float *)out)[2 * i + 1] = (float)im;
+  }
+}
+
+#define TN_HIP(call, what)                                                                \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      set_error("%s: %s", what, hipGetErrorString(e_));                                   \
+      rc = TN_E_DEVICE;                                                                   \
+      goto done;                                                                          \
+    }                                                                                     \
+  } while (0)
+
+tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_dtype out_dtype,
+                    uint32_t flags, bool share, hipStream_t st) {
+  const int nv = p->nv, nn = 2 * nv - 1;
+  if (qs.empty()) return TN_OK;
+  if (out_dtype != TN_C64 && out_dtype != TN_C128) {
+    set_error("out_dtype must be TN_C64 or TN_C128");
+    return TN_E_INVALID_ARG;
+  }
+  // overridden leaves of the group
+  std::vector<int> ovr;
+  for (const QueryIO &q : qs) {
+    if (!q.out) {
+      set_error("output pointer is NULL");
+      return TN_E_INVALID_ARG;
+    }
+    for (int i = 0; i < q.novr; ++i) {
+      const tn_leaf &l = q.ovr[i];
+      if (l.tensor < 0 || l.tensor >= nv || !l.data || (l.dtype != TN_C64 && l.dtype != TN_C128)) {
+        set_error("override %d: tensor id out of range, NULL data or bad dtype", i);
+        return TN_E_INVALID_ARG;
+      }
+      ovr.push_back(l.tensor);
+    }
+  }
+  std::sort(ovr.begin(), ovr.end());
+  ovr.erase(std::unique(ovr.begin(), ovr.end()), ovr.end());
+  std::shared_ptr<ExecLayout> Lp = cached_layout(p, ovr, share);
+  const ExecLayout &L = *Lp;
+
+  // per-query override block: leaves in `ovr` order
+  std::vector<int64_t> ovr_off(nv, -1);
+  size_t ovr_bytes = 0;
+  for (int t : ovr) {
+    ovr_off[t] = (int64_t)ovr_bytes;
+    ovr_bytes += rnd(p->leaf[t].size() * 8);
+  }
+  const size_t perq = rnd(L.perq_bytes);
+  const size_t relems = result_elems(p);
+  const size_t final_bytes = p->fperm.needed ? rnd(relems * 8) : 0;
+  const size_t slot_bytes = (size_t)nn * sizeof(Slot);
+  int max_blocks = 1;
+  for (const Node &n : p->nodes)
+    if (n.kind == NK_DOT) max_blocks = std::max(max_blocks, n.dot_blocks);
+  const size_t shared_fixed = rnd(L.shared_bytes) + rnd(slot_bytes);
+  const size_t per_query = perq + slot_bytes + ovr_bytes + sizeof(Result) + final_bytes +
+                           (size_t)max_blocks * 16;
+  // queries per chunk that fit the arena
+  size_t avail = ctx->arena.largest_free();
+  if (avail < shared_fixed + per_query + 4096) {
+    set_error("arena too small: need %zu bytes for one query, largest free block %zu",
+              shared_fixed + per_query + 4096, avail);
+    return TN_E_NOMEM;
+  }
+  size_t chunk = (avail - shared_fixed - 4096) / (per_query + 1024);
+  chunk = std::min<size_t>(chunk, 65535);
+  chunk = std::max<size_t>(chunk, 1);
+  tn_status rc = TN_OK;
+  for (size_t q0 = 0; q0 < qs.size() && rc == TN_OK; q0 += chunk) {
+    const int Q = (int)std::min(chunk, qs.size() - q0);
+    // carve the workspace
+    size_t o = 0;
+    auto carve = [&](size_t b) {
+      size_t r = o;
+      o += rnd(b);
+      return r;
+    };
+    const size_t r_shared = carve(L.shared_bytes);
+    const size_t r_perq = carve(perq * Q);
+    const size_t r_slots = carve(slot_bytes * (Q + 1));
+    const size_t r_ovr = carve(ovr_bytes * Q);
+    const size_t r_res = carve(sizeof(Result) * Q);
+    const size_t r_final = carve(final_bytes * Q);
+    const size_t r_part = carve((size_t)max_blocks * 16 * Q);
+    const size_t total = o;
+    int64_t ws = ctx->arena.alloc(total);
+    if (ws < 0) {
+      set_error("arena exhausted (%zu bytes requested)", total);
+      return TN_E_NOMEM;
+    }
+    uint8_t *base = ctx->arena.base() + ws;
+    uint8_t *shared_base = base + r_shared, *perq_base = base + r_perq;
+    Slot *slots = (Slot *)(base + r_slots);
+    Slot *slots_sh = slots, *slots_q = slots + nn;
+    uint8_t *ovr_base = base + r_ovr;
+    Result *res = (Result *)(base + r_res);
+    float2 *fin = (float2 *)(base + r_final);
+    double2 *partials = (double2 *)(base + r_part);
+    const float2 *leaf_base = (const float2 *)(ctx->arena.base() + p->dev_leaf);
+    const uint8_t *desc_base = ctx->arena.base() + p->dev_desc;
+    const int64_t perq_el = (int64_t)(perq / 8), perq_sl = (int64_t)nn;
+    const int64_t ovr_el = (int64_t)(ovr_bytes / 8);
+
+    auto operand = [&](int t) -> Operand {
+      Operand o2;
+      if (t < nv) {
+        if (ovr_off[t] >= 0) {
+          o2.p = (const float2 *)(ovr_base + ovr_off[t]);
+          o2.bs = ovr_el;
+          o2.slot = slots_q + t;
+          o2.sbs = perq_sl;
+        } else {
+          o2.p = leaf_base + p->leaf_off[t];
+          o2.bs = 0;
+          o2.slot = slots_sh + t;
+          o2.sbs = 0;
+        }
+      } else if (L.shared[t]) {
+        o2.p = (const float2 *)(shared_base + L.off[t]);
+        o2.bs = 0;
+        o2.slot = slots_sh + t;
+        o2.sbs = 0;
+      } else {
+        o2.p = (const float2 *)(perq_base + L.off[t]);
+        o2.bs = perq_el;
+        o2.slot = slots_q + t;
+        o2.sbs = perq_sl;
+      }
+      return o2;
+    };
+    auto outop = [&](int t) -> OutOperand {
+      Operand i = operand(t);
+      OutOperand o2;
+      o2.p = const_cast<float2 *>(i.p);
+      o2.bs = i.bs;
+      o2.slot = const_cast<Slot *>(i.slot);
+      o2.sbs = i.sbs;
+      return o2;
+    };
+
+    {
+      // stage overrides (complex64) for every query of the chunk
+      if (ovr_bytes) {
+        rc = ensure_pinned(ctx, ovr_bytes * Q);
+        if (rc) goto done;
+        uint8_t *h = (uint8_t *)ctx->pinned;
+        for (int qi = 0; qi < Q; ++qi) {
+          const QueryIO &q = qs[q0 + qi];
+          for (int t : ovr) {
+            float2 *dst = (float2 *)(h + (size_t)qi * ovr_bytes + ovr_off[t]);
+            const int64_t n = p->leaf[t].size();
+            const tn_leaf *src = nullptr;
+            for (int i = 0; i < q.novr; ++i)
+              if (q.ovr[i].tensor == t) src = &q.ovr[i];
+            if (src)
+              to_c64(*src, n, dst);
+            else
+              memcpy(dst, p->leaf_host.data() + p->leaf_off[t], sizeof(float2) * n);
+          }
+        }
+        TN_HIP(hipMemcpyAsync(ovr_base, h, ovr_bytes * Q, hipMemcpyHostToDevice, st),
+               "override upload");
+      }
+      TN_HIP(launch_init_slots(st, slots, (int64_t)nn * (Q + 1)), "slot init");
+      for (int j : p->order) {
+        const Node &n = p->nodes[j];
+        const bool sh = L.shared[n.id] != 0;
+        const int nb = sh ? 1 : Q;
+        if (n.kind == NK_STREAM) {
+          TN_HIP(launch_stream(st, (const StreamDesc *)(desc_base + n.sdesc_off), n.nfib, n.ns,
+                               operand(n.x), operand(n.y), outop(n.id), nb),
+                 "stream contraction");
+        } else if (n.kind == NK_GEMM) {
+          Operand A = operand(n.ga), B = operand(n.gb);
+          uint8_t *pbase = sh ? shared_base : perq_base;
+          const int64_t pst = sh ? 0 : perq_el;
+          if (n.pa.needed) {
+            float2 *dst = (float2 *)(pbase + L.scr_a[j]);
+            TN_HIP(launch_permute(st, (const PermDesc *)(desc_base + n.pa.desc_off), n.pa.h, A.p,
+                                  A.bs, dst, pst, nb),
+                   "permute A");
+            A.p = dst;
+            A.bs = pst;
+          }
+          if (n.pb.needed) {
+            float2 *dst = (float2 *)(pbase + L.scr_b[j]);
+            TN_HIP(launch_permute(st, (const PermDesc *)(desc_base + n.pb.desc_off), n.pb.h, B.p,
+                                  B.bs, dst, pst, nb),
+                   "permute B");
+            B.p = dst;
+            B.bs = pst;
+          }
+          OutOperand C = outop(n.id);
+          GemmArgs g;
+          memset(&g, 0, sizeof(g));
+          g.A = A.p;
+          g.B = B.p;
+          g.C = C.p;
+          g.sa = A.slot;
+          g.sb = B.slot;
+          g.sc = C.slot;
+          g.lda = n.lda;
+          g.ldb = n.ldb;
+          g.ldc = n.ldc;
+          g.abs = A.bs;
+          g.bbs = B.bs;
+          g.cbs = C.bs;
+          g.sabs = A.sbs;
+          g.sbbs = B.sbs;
+          g.scbs = C.sbs;
+          g.M = n.M;
+          g.N = n.N;
+          g.K = n.K;
+          g.opA = n.opA;
+          g.opB = n.opB;
+          const int prec = (p->flags & TN_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
+          const int form = (p->flags & TN_FORM_3M) ? kForm3M : kForm4M;
+          TN_HIP(launch_gemm(st, g, prec, form, n.variant, nb), "complex GEMM");
+        } else {
+          const bool is_root = n.id == p->root;
+          TN_HIP(launch_dot(st, (const DotDesc *)(desc_base + n.ddesc_off), n.nelem, operand(n.c1),
+                            operand(n.c2), outop(n.id), is_root ? res : nullptr, 1, partials,
+                            n.dot_blocks, nb),
+                 "dot");
+        }
+      }
+      // result into output-leg order
+      const Operand R = operand(p->root);
+      if (p->fperm.needed)
+        TN_HIP(launch_permute(st, (const PermDesc *)(desc_base + p->fperm.desc_off), p->fperm.h,
+                              R.p, R.bs, fin, (int64_t)(final_bytes / 8),
+                              L.shared[p->root] ? 1 : Q),
+               "output permutation");
+      // read back
+      const bool root_shared = L.shared[p->root] != 0;
+      const bool dot_root = nv > 1 && p->nodes[p->root - nv].kind == NK_DOT;
+      size_t rb_vals = (size_t)Q * relems * 8, rb_slots = (size_t)Q * sizeof(Slot),
+             rb_res = (size_t)Q * sizeof(Result);
+      rc = ensure_pinned(ctx, rb_vals + rb_slots + rb_res);
+      if (rc) goto done;
+      uint8_t *h = (uint8_t *)ctx->pinned;
+      float2 *hv = (float2 *)h;
+      Slot *hs = (Slot *)(h + rb_vals);
+      Result *hr = (Result *)(h + rb_vals + rb_slots);
+      if (dot_root) {
+        TN_HIP(hipMemcpyAsync(hr, res, rb_res, hipMemcpyDeviceToHost, st), "result copy");
+      } else {
+        const int rq = root_shared ? 1 : Q;
+        if (p->fperm.needed) {
+          TN_HIP(hipMemcpyAsync(hv, fin, (size_t)rq * relems * 8, hipMemcpyDeviceToHost, st),
+                 "result copy");
+        } else {
+          const size_t pitch = R.bs ? (size_t)R.bs * 8 : relems * 8;
+          TN_HIP(hipMemcpy2DAsync(hv, relems * 8, R.p, pitch, relems * 8, rq,
+                                  hipMemcpyDeviceToHost, st),
+                 "result copy");
+        }
+        TN_HIP(hipMemcpy2DAsync(hs, sizeof(Slot), R.slot, (R.sbs ? R.sbs : 1) * sizeof(Slot),
+                                sizeof(Slot), rq, hipMemcpyDeviceToHost, st),
+               "scale copy");
+      }
+      TN_HIP(hipStreamSynchronize(st), "stream synchronize");
+      for (int qi = 0; qi < Q; ++qi) {
+        const QueryIO &q = qs[q0 + qi];
+        const bool keep = (flags & TN_FLAG_KEEP_SCALE) != 0;
+        if (dot_root) {
+          const Result &r = hr[root_shared ? 0 : qi];
+          if (keep) {
+            write_out(q.out, out_dtype, 0, r.re, r.im);
+            if (q.log2s) *q.log2s = r.log2s;
+          } else {
+            write_out(q.out, out_dtype, 0, std::ldexp(r.re, (int)r.log2s),
+                      std::ldexp(r.im, (int)r.log2s));
+            if (q.log2s) *q.log2s = 0.0;
+          }
+        } else {
+          const int src = root_shared ? 0 : qi;
+          const Slot &s = hs[src];
+          const float2 *v = hv + (size_t)src * relems;
+          for (size_t i = 0; i < relems; ++i) {
+            if (keep)
+              write_out(q.out, out_dtype, i, v[i].x, v[i].y);
+            else
+              write_out(q.out, out_dtype, i, std::ldexp((double)v[i].x, (int)s.log2s),
+                        std::ldexp((double)v[i].y, (int)s.log2s));
+          }
+          if (q.log2s) *q.log2s = keep ? s.log2s : 0.0;
+        }
+        if (q.status) *q.status = TN_OK;
+      }
+    }
+  done:
+    ctx->arena.release(ws, total);
+  }
+  return rc;
+}
+
+}  // namespace tn

@@ -1,0 +1,597 @@
+// gfx950 kernels for the pairwise contractions of a tensor network.
+//
+//   k_stream       small-operand contraction in one pass over the large operand
+//   k_perm_*       leg permutation (the T steps of TTGT, Section 5.1)
+//   k_cgemm_*      complex GEMM on the matrix cores (the G step of TTGT),
+//                  4M and 3M forms, FP32 and three-term split BF16
+//   k_dot_*        full inner product with FP64 accumulation (the closed
+//                  network's last contraction)
+//
+// Every kernel reads the scale records of its operands, multiplies by the
+// power of two that brings their maxima to [1, 2), writes the scale of its
+// output and contributes to the output's running max (Slot).
+#include "tn_device.h"
+
+namespace tn {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int slot_exp(uint32_t bits) {
+  if (bits == 0u) return 0;
+  const int e = (int)((bits >> 23) & 0xffu);
+  if (e == 0xff) return 0;
+  if (e == 0) return -126;
+  return e - 127;
+}
+
+__device__ __forceinline__ void wave_atomic_max(uint32_t *p, float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(p, __float_as_uint(v));
+}
+
+__device__ __forceinline__ float absmax2(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
+
+// --------------------------------------------------------------- slot init
+__global__ void k_init_slots(Slot *s, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    s[i].log2s = 0.0;
+    s[i].maxbits = 0u;
+    s[i].pad = 0u;
+  }
+}
+
+hipError_t launch_init_slots(hipStream_t st, Slot *slots, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_init_slots, dim3((unsigned)blocks), dim3(256), 0, st, slots, n);
+  return hipGetLastError();
+}
+
+// Segment decode helpers: the map is staged in LDS once per block.
+struct SegLds {
+  int64_t ext[kMaxSeg], s0[kMaxSeg], s1[kMaxSeg];
+  int32_t lg[kMaxSeg];
+};
+
+__device__ __forceinline__ void seg_stage(SegLds &L, const SegMap &m, int tid) {
+  if (tid < m.nseg) {
+    L.ext[tid] = m.ext[tid];
+    L.s0[tid] = m.s0[tid];
+    L.s1[tid] = m.s1[tid];
+    L.lg[tid] = m.lg[tid];
+  }
+}
+
+__device__ __forceinline__ void seg_decode(const SegLds &L, int nseg, bool pow2, int64_t idx,
+                                           int64_t &o0, int64_t &o1) {
+  o0 = 0;
+  o1 = 0;
+  if (pow2) {
+    for (int i = 0; i < nseg; ++i) {
+      const int64_t v = idx & (L.ext[i] - 1);
+      idx >>= L.lg[i];
+      o0 += v * L.s0[i];
+      o1 += v * L.s1[i];
+    }
+  } else {
+    for (int i = 0; i < nseg; ++i) {
+      const int64_t v = idx % L.ext[i];
+      idx /= L.ext[i];
+      o0 += v * L.s0[i];
+      o1 += v * L.s1[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------ stream kernel
+// One thread per fiber of X: gather the ns shared-index values, multiply by
+// the ns x nfy matrix of Y held in LDS, scatter nfy outputs.  Consecutive
+// threads take consecutive fibers, so reads and writes follow X's and C's
+// innermost free legs.
+template <int NSMAX>
+__global__ __launch_bounds__(256) void k_stream(const StreamDesc *__restrict__ d, Operand X,
+                                                Operand Y, OutOperand C) {
+  __shared__ float2 ys[kStreamMax];
+  __shared__ int64_t xs[kStreamMax], cy[kStreamMax];
+  __shared__ SegLds L;
+  const int tid = threadIdx.x;
+  const int q = blockIdx.y;
+  const float2 *xp = X.p + q * X.bs;
+  const float2 *yp = Y.p + q * Y.bs;
+  float2 *cp = C.p + q * C.bs;
+  const Slot *xsl = X.slot + q * X.sbs;
+  const Slot *ysl = Y.slot + q * Y.sbs;
+  Slot *csl = C.slot + q * C.sbs;
+  const int ns = d->ns, nfy = d->nfy, nseg = d->fib.nseg;
+  const bool p2 = d->fib.pow2 != 0;
+  const int64_t nfib = d->nfib;
+  const int ex = slot_exp(xsl->maxbits), ey = slot_exp(ysl->maxbits);
+  const float fx = ldexpf(1.0f, -ex), fy = ldexpf(1.0f, -ey);
+  if (tid < ns * nfy) {
+    const float2 v = yp[d->ymap[tid]];
+    ys[tid] = make_float2(v.x * fy, v.y * fy);
+  }
+  if (tid < ns) xs[tid] = d->xs[tid];
+  if (tid < nfy) cy[tid] = d->cy[tid];
+  seg_stage(L, d->fib, tid);
+  __syncthreads();
+  if (blockIdx.x == 0 && tid == 0) csl->log2s = xsl->log2s + ysl->log2s + (double)(ex + ey);
+  float mx = 0.0f;
+  for (int64_t f = (int64_t)blockIdx.x * 256 + tid; f < nfib; f += (int64_t)gridDim.x * 256) {
+    int64_t xo, co;
+    seg_decode(L, nseg, p2, f, xo, co);
+    float2 xv[NSMAX];
+#pragma unroll
+    for (int s = 0; s < NSMAX; ++s)
+      if (s < ns) xv[s] = xp[xo + xs[s]];
+    for (int j = 0; j < nfy; ++j) {
+      float re = 0.0f, im = 0.0f;
+#pragma unroll
+      for (int s = 0; s < NSMAX; ++s) {
+        if (s < ns) {
+          const float2 y = ys[s * nfy + j];
+          re = fmaf(xv[s].x, y.x, re);
+          re = fmaf(-xv[s].y, y.y, re);
+          im = fmaf(xv[s].x, y.y, im);
+          im = fmaf(xv[s].y, y.x, im);
+        }
+      }
+      const float2 r = make_float2(re * fx, im * fx);
+      cp[co + cy[j]] = r;
+      mx = fmaxf(mx, absmax2(r));
+    }
+  }
+  wave_atomic_max(&csl->maxbits, mx);
+}
+
+static int grid_for(int64_t work, int64_t per_block, int64_t cap) {
+  int64_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+hipError_t launch_stream(hipStream_t st, const StreamDesc *d_desc, int64_t nfib, int ns, Operand X,
+                         Operand Y, OutOperand C, int nbatch) {
+  const dim3 grid(grid_for(nfib, 256, 16384), nbatch);
+#define TN_STREAM_CASE(NS)                                                            \
+  if (ns <= NS) {                                                                     \
+    hipLaunchKernelGGL(k_stream<NS>, grid, dim3(256), 0, st, d_desc, X, Y, C);       \
+    return hipGetLastError();                                                         \
+  }
+  TN_STREAM_CASE(1)
+  TN_STREAM_CASE(2)
+  TN_STREAM_CASE(4)
+  TN_STREAM_CASE(8)
+  TN_STREAM_CASE(16)
+  TN_STREAM_CASE(32)
+  TN_STREAM_CASE(64)
+#undef TN_STREAM_CASE
+  return hipErrorInvalidValue;
+}
+
+// -------------------------------------------------------------- permutation
+// Generic: one thread per output element; writes are contiguous, reads follow
+// the map.  Used for small tensors, non-power-of-two legs and permutations
+// that keep the innermost legs in place (then reads are contiguous too).
+__global__ __launch_bounds__(256) void k_perm_generic(const PermDesc *__restrict__ d,
+                                                      const float2 *in, int64_t ibs, float2 *out,
+                                                      int64_t obs) {
+  __shared__ SegLds L;
+  const int tid = threadIdx.x;
+  const int q = blockIdx.y;
+  in += q * ibs;
+  out += q * obs;
+  seg_stage(L, d->map, tid);
+  __syncthreads();
+  const int nseg = d->map.nseg;
+  const bool p2 = d->map.pow2 != 0;
+  const int64_t n = d->nelem;
+  for (int64_t o = (int64_t)blockIdx.x * 256 + tid; o < n; o += (int64_t)gridDim.x * 256) {
+    int64_t io, oo;
+    seg_decode(L, nseg, p2, o, io, oo);
+    out[oo] = in[io];
+  }
+}
+
+// Tiled bit permutation.  With every extent a power of two the permutation
+// moves index bits: output bit j takes input bit inbit[j].  A tile spans the
+// lowest input bits and the input bits that feed the lowest output bits
+// (nu <= 10 bits, <= 1024 complex values = 8 KiB of LDS); the remaining
+// "outer" bits select the tile.  Loads run along the input's low bits and
+// stores along the output's low bits, so both sides move whole 256-byte runs.
+struct BitTile {
+  int32_t nu;          // tile bits
+  int32_t nouter;      // outer bits
+  int32_t u_in[12];    // tile bit k -> input bit
+  int32_t u_out[12];   // tile bit k -> output bit
+  int32_t g_to_k[12];  // output-ordered tile bit -> tile bit
+  int32_t o_in[48];    // outer bit -> input bit
+  int32_t o_out[48];   // outer bit -> output bit
+};
+
+__global__ __launch_bounds__(256) void k_perm_tiled(BitTile t, const float2 *in, int64_t ibs,
+                                                    float2 *out, int64_t obs) {
+  __shared__ float2 tile[1024 + 32];
+  const int tid = threadIdx.x;
+  const int q = blockIdx.y;
+  in += q * ibs;
+  out += q * obs;
+  const int nt = 1 << t.nu;
+  // per-thread offsets of the tile elements this thread loads and stores
+  int64_t lin[4], lout[4];
+  int le[4], ge[4];
+  int cnt = 0;
+  for (int e = tid; e < nt; e += 256, ++cnt) {
+    int64_t a = 0;
+    for (int k = 0; k < t.nu; ++k)
+      if ((e >> k) & 1) a += (int64_t)1 << t.u_in[k];
+    lin[cnt] = a;
+    le[cnt] = e + (e >> 5);
+    // output-ordered index g = e: g bit i corresponds to tile bit g_to_k[i]
+    int src = 0;
+    int64_t b = 0;
+    for (int i = 0; i < t.nu; ++i)
+      if ((e >> i) & 1) {
+        const int k = t.g_to_k[i];
+        src |= 1 << k;
+        b += (int64_t)1 << t.u_out[k];
+      }
+    lout[cnt] = b;
+    ge[cnt] = src + (src >> 5);
+  }
+  const int64_t ntiles = (int64_t)1 << t.nouter;
+  for (int64_t w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    int64_t bin = 0, bout = 0;
+    for (int k = 0; k < t.nouter; ++k)
+      if ((w >> k) & 1) {
+        bin += (int64_t)1 << t.o_in[k];
+        bout += (int64_t)1 << t.o_out[k];
+      }
+    for (int c = 0; c < cnt; ++c) tile[le[c]] = in[bin + lin[c]];
+    __syncthreads();
+    for (int c = 0; c < cnt; ++c) out[bout + lout[c]] = tile[ge[c]];
+    __syncthreads();
+  }
+}
+
+static bool build_bit_tile(const PermDesc &h, BitTile &t) {
+  const int r = h.bits;
+  if (r <= 0 || r > 47) return false;
+  int outpos[48];
+  for (int j = 0; j < r; ++j) outpos[h.inbit[j]] = j;
+  // innermost output bits already innermost in the input: nothing to tile
+  int same = 0;
+  while (same < r && h.inbit[same] == same) ++same;
+  if (same >= 5 || same == r) return false;
+  bool inu[48] = {false};
+  int nu = 0;
+  int u_in[12];
+  const int b = r < 5 ? r : 5;
+  for (int i = 0; i < b; ++i) {
+    inu[i] = true;
+    u_in[nu++] = i;
+  }
+  for (int j = 0; j < b; ++j) {
+    const int i = h.inbit[j];
+    if (!inu[i]) {
+      inu[i] = true;
+      u_in[nu++] = i;
+    }
+  }
+  for (int i = 0; i < r && nu < 10; ++i)
+    if (!inu[i]) {
+      inu[i] = true;
+      u_in[nu++] = i;
+    }
+  t.nu = nu;
+  for (int k = 0; k < nu; ++k) {
+    t.u_in[k] = u_in[k];
+    t.u_out[k] = outpos[u_in[k]];
+  }
+  // output-ordered tile bits: sort tile bits by output position
+  int order[12];
+  for (int k = 0; k < nu; ++k) order[k] = k;
+  for (int a = 0; a < nu; ++a)
+    for (int c = a + 1; c < nu; ++c)
+      if (t.u_out[order[c]] < t.u_out[order[a]]) {
+        const int tmp = order[a];
+        order[a] = order[c];
+        order[c] = tmp;
+      }
+  for (int i = 0; i < nu; ++i) t.g_to_k[i] = order[i];
+  int no = 0;
+  for (int i = 0; i < r; ++i)
+    if (!inu[i]) {
+      t.o_in[no] = i;
+      t.o_out[no] = outpos[i];
+      ++no;
+    }
+  t.nouter = no;
+  return true;
+}
+
+hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc &h, const float2 *in,
+                          int64_t ibs, float2 *out, int64_t obs, int nbatch) {
+  BitTile t;
+  if (h.nelem >= 4096 && build_bit_tile(h, t)) {
+    const int64_t ntiles = (int64_t)1 << t.nouter;
+    const dim3 grid(grid_for(ntiles, 1, 8192), nbatch);
+    hipLaunchKernelGGL(k_perm_tiled, grid, dim3(256), 0, st, t, in, ibs, out, obs);
+    return hipGetLastError();
+  }
+  const dim3 grid(grid_for(h.nelem, 256, 16384), nbatch);
+  hipLaunchKernelGGL(k_perm_generic, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- GEMM FP32
+// Block = 4 waves in a 2 x 2 grid; each wave owns (32*WM) x (32*WN) outputs
+// as WM x WN tiles of v_mfma_f32_32x32x2_f32.  For that instruction lane l
+// supplies A[l%32][l/32] and B[l/32][l%32] of a 32x2 / 2x32 step and holds
+// C[8*(v/4) + 4*(l/32) + v%4][l%32] in accumulator v.  A and B tiles are
+// staged in LDS as [k][m] / [k][n] interleaved complex, scaled on the way in.
+template <int WM, int WN, int FORM>
+__global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
+  constexpr int BM = 64 * WM, BN = 64 * WN, BK = 16, PAD = 2;
+  constexpr int NACC = FORM == kForm3M ? 3 : 2;
+  __shared__ float2 As[BK][BM + PAD];
+  __shared__ float2 Bs[BK][BN + PAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int q = blockIdx.y;
+  const float2 *A = g.A + q * g.abs;
+  const float2 *B = g.B + q * g.bbs;
+  float2 *C = g.C + q * g.cbs;
+  const Slot *sa = g.sa + q * g.sabs;
+  const Slot *sb = g.sb + q * g.sbbs;
+  Slot *sc = g.sc + q * g.scbs;
+  const int64_t tile = blockIdx.x;
+  const int64_t m0 = (tile / g.tiles_n) * BM, n0 = (tile % g.tiles_n) * BN;
+  const int ea = slot_exp(sa->maxbits), eb = slot_exp(sb->maxbits);
+  const float fa = ldexpf(1.0f, -ea), fb = ldexpf(1.0f, -eb);
+  if (tile == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
+
+  v16f acc[WM][WN][NACC];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b)
+#pragma unroll
+      for (int c = 0; c < NACC; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[a][b][c][v] = 0.0f;
+
+  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+    for (int i = 0; i < BM * BK / 256; ++i) {
+      const int e = tid + 256 * i;
+      int m, k;
+      if (g.opA == 0) {
+        m = e / BK;
+        k = e % BK;
+      } else {
+        k = e / BM;
+        m = e % BM;
+      }
+      const int64_t gm = m0 + m, gk = k0 + k;
+      float2 v = make_float2(0.0f, 0.0f);
+      if (gm < g.M && gk < g.K) v = g.opA == 0 ? A[gm * g.lda + gk] : A[gk * g.lda + gm];
+      As[k][m] = make_float2(v.x * fa, v.y * fa);
+    }
+#pragma unroll
+    for (int i = 0; i < BN * BK / 256; ++i) {
+      const int e = tid + 256 * i;
+      int n, k;
+      if (g.opB == 0) {
+        k = e / BN;
+        n = e % BN;
+      } else {
+        n = e / BK;
+        k = e % BK;
+      }
+      const int64_t gn = n0 + n, gk = k0 + k;
+      float2 v = make_float2(0.0f, 0.0f);
+      if (gn < g.N && gk < g.K) v = g.opB == 0 ? B[gk * g.ldb + gn] : B[gn * g.ldb + gk];
+      Bs[k][n] = make_float2(v.x * fb, v.y * fb);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      const int kr = kk + (lane >> 5);
+      float2 a[WM], b[WN];
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb) a[mb] = As[kr][wm * 32 * WM + mb * 32 + (lane & 31)];
+#pragma unroll
+      for (int nb = 0; nb < WN; ++nb) b[nb] = Bs[kr][wn * 32 * WN + nb * 32 + (lane & 31)];
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb) {
+          if (FORM == kForm4M) {
+            acc[mb][nb][0] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(a[mb].x, b[nb].x, acc[mb][nb][0], 0, 0, 0);
+            acc[mb][nb][0] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(-a[mb].y, b[nb].y, acc[mb][nb][0], 0, 0, 0);
+            acc[mb][nb][1] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(a[mb].x, b[nb].y, acc[mb][nb][1], 0, 0, 0);
+            acc[mb][nb][1] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(a[mb].y, b[nb].x, acc[mb][nb][1], 0, 0, 0);
+          } else {
+            acc[mb][nb][0] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(a[mb].x, b[nb].x, acc[mb][nb][0], 0, 0, 0);
+            acc[mb][nb][1] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(a[mb].y, b[nb].y, acc[mb][nb][1], 0, 0, 0);
+            acc[mb][nb][NACC - 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                a[mb].x + a[mb].y, b[nb].x + b[nb].y, acc[mb][nb][NACC - 1], 0, 0, 0);
+          }
+        }
+    }
+    __syncthreads();
+  }
+
+  float mx = 0.0f;
+#pragma unroll
+  for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < WN; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * 32 * WM + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int col = wn * 32 * WN + nb * 32 + (lane & 31);
+        const int64_t gm = m0 + row, gn = n0 + col;
+        float re, im;
+        if (FORM == kForm4M) {
+          re = acc[mb][nb][0][v];
+          im = acc[mb][nb][1][v];
+        } else {
+          const float t1 = acc[mb][nb][0][v], t2 = acc[mb][nb][1][v], t3 = acc[mb][nb][NACC - 1][v];
+          re = t1 - t2;
+          im = t3 - t1 - t2;
+        }
+        if (gm < g.M && gn < g.N) {
+          C[gm * g.ldc + gn] = make_float2(re, im);
+          mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+        }
+      }
+  wave_atomic_max(&sc->maxbits, mx);
+}
+
+struct GemmVariant {
+  int tm, tn;
+};
+static const GemmVariant kVariants[] = {{128, 128}, {64, 64}};
+
+int gemm_num_variants() { return 2; }
+int gemm_variant_tile_m(int v) { return kVariants[v].tm; }
+int gemm_variant_tile_n(int v) { return kVariants[v].tn; }
+
+hipError_t launch_gemm(hipStream_t st, const GemmArgs &g0, int prec, int form, int variant,
+                       int nbatch) {
+  if (prec != kPrecFP32) return hipErrorInvalidValue;
+  GemmArgs g = g0;
+  const int tm = kVariants[variant].tm, tn = kVariants[variant].tn;
+  g.tiles_m = (int)((g.M + tm - 1) / tm);
+  g.tiles_n = (int)((g.N + tn - 1) / tn);
+  const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
+  if (tiles <= 0 || tiles > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)tiles, nbatch);
+  if (variant == 0) {
+    if (form == kForm4M)
+      hipLaunchKernelGGL((k_cgemm_f32<2, 2, kForm4M>), grid, dim3(256), 0, st, g);
+    else
+      hipLaunchKernelGGL((k_cgemm_f32<2, 2, kForm3M>), grid, dim3(256), 0, st, g);
+  } else {
+    if (form == kForm4M)
+      hipLaunchKernelGGL((k_cgemm_f32<1, 1, kForm4M>), grid, dim3(256), 0, st, g);
+    else
+      hipLaunchKernelGGL((k_cgemm_f32<1, 1, kForm3M>), grid, dim3(256), 0, st, g);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- dot
+// Partial sums per block in FP64, then one block per query adds the partials
+// in a fixed order (deterministic), normalises the FP64 value to a mantissa in
+// [0.5, 1) and writes both the FP64 result and a complex64 copy.
+__global__ __launch_bounds__(256) void k_dot_partial(const DotDesc *__restrict__ d, Operand A,
+                                                     Operand B, double2 *partials, int nblocks) {
+  __shared__ SegLds L;
+  __shared__ double red_re[256], red_im[256];
+  const int tid = threadIdx.x;
+  const int q = blockIdx.y;
+  const float2 *ap = A.p + q * A.bs;
+  const float2 *bp = B.p + q * B.bs;
+  seg_stage(L, d->map, tid);
+  __syncthreads();
+  const int nseg = d->map.nseg;
+  const bool p2 = d->map.pow2 != 0;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < d->nelem; i += (int64_t)nblocks * 256) {
+    int64_t ao, bo;
+    seg_decode(L, nseg, p2, i, ao, bo);
+    const float2 a = ap[ao], b = bp[bo];
+    re += (double)a.x * (double)b.x - (double)a.y * (double)b.y;
+    im += (double)a.x * (double)b.y + (double)a.y * (double)b.x;
+  }
+  red_re[tid] = re;
+  red_im[tid] = im;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red_re[tid] += red_re[tid + s];
+      red_im[tid] += red_im[tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) partials[(int64_t)q * nblocks + blockIdx.x] = make_double2(red_re[0], red_im[0]);
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(const double2 *partials, int nblocks, Operand A,
+                                                   Operand B, OutOperand C, Result *res,
+                                                   int64_t rbs) {
+  __shared__ double red_re[256], red_im[256];
+  const int tid = threadIdx.x;
+  const int q = blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int i = tid; i < nblocks; i += 256) {
+    const double2 p = partials[(int64_t)q * nblocks + i];
+    re += p.x;
+    im += p.y;
+  }
+  red_re[tid] = re;
+  red_im[tid] = im;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red_re[tid] += red_re[tid + s];
+      red_im[tid] += red_im[tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const Slot *sa = A.slot + q * A.sbs;
+    const Slot *sb = B.slot + q * B.sbs;
+    double log2s = sa->log2s + sb->log2s;
+    double vr = red_re[0], vi = red_im[0];
+    const double m = fmax(fabs(vr), fabs(vi));
+    if (m > 0.0 && isfinite(m)) {
+      int e;
+      frexp(m, &e);
+      vr = ldexp(vr, -e);
+      vi = ldexp(vi, -e);
+      log2s += (double)e;
+    }
+    if (res) {
+      Result *r = res + q * rbs;
+      r->re = vr;
+      r->im = vi;
+      r->log2s = log2s;
+      r->pad = 0.0;
+    }
+    const float2 c = make_float2((float)vr, (float)vi);
+    C.p[q * C.bs] = c;
+    Slot *sc = C.slot + q * C.sbs;
+    sc->log2s = log2s;
+    sc->maxbits = __float_as_uint(fmaxf(fabsf(c.x), fabsf(c.y)));
+  }
+}
+
+int dot_blocks_for(int64_t nelem) { return grid_for(nelem, 256 * 8, 512); }
+
+hipError_t launch_dot(hipStream_t st, const DotDesc *d_desc, int64_t nelem, Operand A, Operand B,
+                      OutOperand C, Result *res, int64_t rbs, double2 *partials, int nblocks,
+                      int nbatch) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(nblocks, nbatch), dim3(256), 0, st, d_desc, A, B, partials,
+                     nblocks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dot_final, dim3(nbatch), dim3(256), 0, st, partials, nblocks, A, B, C, res,
+                     rbs);
+  return hipGetLastError();
+}
+
+}  // namespace tn

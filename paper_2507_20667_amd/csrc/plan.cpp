@@ -1,0 +1,827 @@
+// Plan loading: validation of the network, partitioning and tree (Sections
+// 2.1-2.4), derived legs and vertex congestion, the cost integers of
+// Section 3, the TTGT schedule of every contraction and the arena layout.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <set>
+#include <unordered_map>
+
+#include "tn_internal.h"
+
+namespace tn {
+
+static thread_local char g_err[512];
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+const char *last_error() { return g_err; }
+
+static const int64_t kMaxElems = (int64_t)1 << 40;
+
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+static int ilog2(int64_t x) {
+  int r = 0;
+  while ((int64_t)1 << r < x) ++r;
+  return r;
+}
+
+// ------------------------------------------------------------ index maps
+
+// Segments of an index space given as a list of legs (outermost first), each
+// leg with its extent and its strides into two tensors.  Adjacent legs fuse
+// when both strides continue the inner leg's run.
+struct LegMap {
+  int64_t ext, s0, s1;
+};
+
+static bool fill_segmap(const std::vector<LegMap> &legs_outer_first, SegMap &m) {
+  std::vector<LegMap> segs;  // innermost first
+  for (int i = (int)legs_outer_first.size() - 1; i >= 0; --i) {
+    const LegMap &l = legs_outer_first[i];
+    if (l.ext == 1) continue;
+    if (!segs.empty()) {
+      LegMap &in = segs.back();
+      if (l.s0 == in.s0 * in.ext && l.s1 == in.s1 * in.ext) {
+        in.ext *= l.ext;
+        continue;
+      }
+    }
+    segs.push_back(l);
+  }
+  if ((int)segs.size() > kMaxSeg) return false;
+  memset(&m, 0, sizeof(m));
+  m.nseg = (int)segs.size();
+  m.pow2 = 1;
+  for (int i = 0; i < m.nseg; ++i) {
+    m.ext[i] = segs[i].ext;
+    m.s0[i] = segs[i].s0;
+    m.s1[i] = segs[i].s1;
+    if (!is_pow2(segs[i].ext)) m.pow2 = 0;
+    m.lg[i] = ilog2(segs[i].ext);
+  }
+  return true;
+}
+
+// Permutation src -> dst (same leg set, dst order).
+static bool make_perm(const Layout &src, const Layout &dst, PermDesc &h) {
+  memset(&h, 0, sizeof(h));
+  h.nelem = src.size();
+  std::vector<int64_t> ss = src.strides(), ds = dst.strides();
+  std::vector<LegMap> legs;
+  for (int i = 0; i < dst.rank(); ++i) {
+    int j = src.find(dst.lab[i]);
+    legs.push_back({dst.dim[i], ss[j], ds[i]});
+  }
+  if (!fill_segmap(legs, h.map)) return false;
+  // bit form when every extent is a power of two
+  bool p2 = true;
+  int bits = 0;
+  for (int64_t d : src.dim) {
+    if (!is_pow2(d)) p2 = false;
+    bits += ilog2(d);
+  }
+  if (p2 && bits > 0 && bits <= 47) {
+    // bit offset of each leg's least significant bit
+    h.bits = bits;
+    for (int i = 0; i < dst.rank(); ++i) {
+      int j = src.find(dst.lab[i]);
+      int k = ilog2(dst.dim[i]);
+      int pd = ilog2(ds[i]), ps = ilog2(ss[j]);
+      for (int t = 0; t < k; ++t) h.inbit[pd + t] = ps + t;
+    }
+  }
+  return true;
+}
+
+static bool same_order(const Layout &a, const Layout &b) { return a.lab == b.lab; }
+
+// ------------------------------------------------------------- blob helpers
+template <typename T>
+static size_t blob_put(std::vector<uint8_t> &blob, const T &v) {
+  size_t off = (blob.size() + 255) & ~(size_t)255;
+  blob.resize(off + sizeof(T));
+  memcpy(blob.data() + off, &v, sizeof(T));
+  return off;
+}
+
+// --------------------------------------------------------------- schedule
+
+static tn_status schedule_stream(tn_plan *p, Node &n, const Layout &X, const Layout &Y, int xid,
+                                 int yid) {
+  n.kind = NK_STREAM;
+  n.x = xid;
+  n.y = yid;
+  std::vector<int64_t> S, FY;
+  for (int i = 0; i < Y.rank(); ++i) {
+    if (X.find(Y.lab[i]) >= 0)
+      S.push_back(Y.lab[i]);
+    else
+      FY.push_back(Y.lab[i]);
+  }
+  // C = X's legs with the shared legs removed and Y's free legs (Y order)
+  // inserted where X's first shared leg was.
+  Layout C;
+  bool inserted = false;
+  for (int i = 0; i < X.rank(); ++i) {
+    bool shared = std::find(S.begin(), S.end(), X.lab[i]) != S.end();
+    if (shared) {
+      if (!inserted) {
+        for (int64_t l : FY) {
+          C.lab.push_back(l);
+          C.dim.push_back(Y.dim[Y.find(l)]);
+        }
+        inserted = true;
+      }
+      continue;
+    }
+    C.lab.push_back(X.lab[i]);
+    C.dim.push_back(X.dim[i]);
+  }
+  if (!inserted)
+    for (int64_t l : FY) {
+      C.lab.push_back(l);
+      C.dim.push_back(Y.dim[Y.find(l)]);
+    }
+  n.out = C;
+  std::vector<int64_t> xs = X.strides(), ys = Y.strides(), cs = C.strides();
+  StreamDesc d;
+  memset(&d, 0, sizeof(d));
+  std::vector<LegMap> fib;
+  int64_t nfib = 1;
+  for (int i = 0; i < X.rank(); ++i) {
+    if (std::find(S.begin(), S.end(), X.lab[i]) != S.end()) continue;
+    fib.push_back({X.dim[i], xs[i], cs[C.find(X.lab[i])]});
+    nfib *= X.dim[i];
+  }
+  if (!fill_segmap(fib, d.fib)) {
+    set_error("tensor with too many index segments");
+    return TN_E_INVALID_PLAN;
+  }
+  // enumerate S (Y order) and FY (Y order) row-major
+  int64_t ns = 1, nfy = 1;
+  for (int64_t l : S) ns *= Y.dim[Y.find(l)];
+  for (int64_t l : FY) nfy *= Y.dim[Y.find(l)];
+  d.nfib = nfib;
+  d.ns = (int)ns;
+  d.nfy = (int)nfy;
+  for (int64_t s = 0; s < ns; ++s) {
+    int64_t rem = s, xo = 0, yo = 0;
+    for (int i = (int)S.size() - 1; i >= 0; --i) {
+      int yi = Y.find(S[i]);
+      int64_t v = rem % Y.dim[yi];
+      rem /= Y.dim[yi];
+      xo += v * xs[X.find(S[i])];
+      yo += v * ys[yi];
+    }
+    d.xs[s] = xo;
+    for (int64_t j = 0; j < nfy; ++j) {
+      int64_t r2 = j, yo2 = 0;
+      for (int i = (int)FY.size() - 1; i >= 0; --i) {
+        int yi = Y.find(FY[i]);
+        int64_t v = r2 % Y.dim[yi];
+        r2 /= Y.dim[yi];
+        yo2 += v * ys[yi];
+      }
+      d.ymap[s * nfy + j] = (int32_t)(yo + yo2);
+    }
+  }
+  for (int64_t j = 0; j < nfy; ++j) {
+    int64_t rem = j, co = 0;
+    for (int i = (int)FY.size() - 1; i >= 0; --i) {
+      int yi = Y.find(FY[i]);
+      int64_t v = rem % Y.dim[yi];
+      rem /= Y.dim[yi];
+      co += v * cs[C.find(FY[i])];
+    }
+    d.cy[j] = co;
+  }
+  n.nfib = nfib;
+  n.ns = (int)ns;
+  n.nfy = (int)nfy;
+  n.sdesc_off = blob_put(p->desc_blob, d);
+  return TN_OK;
+}
+
+// S block at the end / start of a layout (any internal order).
+static bool block_at_end(const Layout &L, const std::set<int64_t> &S) {
+  int r = L.rank(), s = (int)S.size();
+  for (int i = r - s; i < r; ++i)
+    if (!S.count(L.lab[i])) return false;
+  return true;
+}
+static bool block_at_start(const Layout &L, const std::set<int64_t> &S) {
+  int s = (int)S.size();
+  for (int i = 0; i < s; ++i)
+    if (!S.count(L.lab[i])) return false;
+  return true;
+}
+
+static std::vector<int64_t> select(const Layout &L, const std::set<int64_t> &S, bool in) {
+  std::vector<int64_t> out;
+  for (int64_t l : L.lab)
+    if ((S.count(l) > 0) == in) out.push_back(l);
+  return out;
+}
+
+static Layout make_layout(const std::vector<int64_t> &labs, const Layout &a, const Layout &b) {
+  Layout L;
+  for (int64_t l : labs) {
+    int i = a.find(l);
+    L.lab.push_back(l);
+    L.dim.push_back(i >= 0 ? a.dim[i] : b.dim[b.find(l)]);
+  }
+  return L;
+}
+
+static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layout &B) {
+  n.kind = NK_GEMM;
+  n.ga = n.c1;
+  n.gb = n.c2;
+  std::set<int64_t> S;
+  for (int64_t l : A.lab)
+    if (B.find(l) >= 0) S.insert(l);
+  std::vector<int64_t> FA = select(A, S, false), FB = select(B, S, false);
+  std::vector<int64_t> sA = select(A, S, true), sB = select(B, S, true);
+  // how each operand can enter the GEMM without a permutation
+  int aMode = block_at_end(A, S) ? 0 : (block_at_start(A, S) ? 1 : -1);   // 0: N, 1: T
+  int bMode = block_at_start(B, S) ? 0 : (block_at_end(B, S) ? 1 : -1);   // 0: N, 1: T
+  std::vector<int64_t> sorder;
+  bool permA = aMode < 0, permB = bMode < 0;
+  if (!permA && !permB) {
+    if (sA != sB) {
+      if (A.size() <= B.size()) {
+        permA = true;
+        sorder = sB;
+      } else {
+        permB = true;
+        sorder = sA;
+      }
+    } else {
+      sorder = sA;
+    }
+  } else if (!permA) {
+    sorder = sA;
+  } else if (!permB) {
+    sorder = sB;
+  } else {
+    sorder = sA;
+  }
+  n.M = n.N = n.K = 1;
+  for (int64_t l : FA) n.M *= A.dim[A.find(l)];
+  for (int64_t l : FB) n.N *= B.dim[B.find(l)];
+  for (int64_t l : sorder) n.K *= A.dim[A.find(l)];
+  if (permA) {
+    std::vector<int64_t> lab = FA;
+    lab.insert(lab.end(), sorder.begin(), sorder.end());
+    n.pa.needed = true;
+    n.pa.dst = make_layout(lab, A, B);
+    if (!make_perm(A, n.pa.dst, n.pa.h)) {
+      set_error("tensor with too many index segments");
+      return TN_E_INVALID_PLAN;
+    }
+    n.pa.desc_off = blob_put(p->desc_blob, n.pa.h);
+    n.opA = 0;
+  } else {
+    n.opA = aMode;
+  }
+  if (permB) {
+    std::vector<int64_t> lab = sorder;
+    lab.insert(lab.end(), FB.begin(), FB.end());
+    n.pb.needed = true;
+    n.pb.dst = make_layout(lab, A, B);
+    if (!make_perm(B, n.pb.dst, n.pb.h)) {
+      set_error("tensor with too many index segments");
+      return TN_E_INVALID_PLAN;
+    }
+    n.pb.desc_off = blob_put(p->desc_blob, n.pb.h);
+    n.opB = 0;
+  } else {
+    n.opB = bMode;
+  }
+  n.lda = n.opA == 0 ? n.K : n.M;
+  n.ldb = n.opB == 0 ? n.N : n.K;
+  n.ldc = n.N;
+  std::vector<int64_t> out = FA;
+  out.insert(out.end(), FB.begin(), FB.end());
+  n.out = make_layout(out, A, B);
+  n.variant = (n.M >= 128 && n.N >= 128) ? 0 : 1;
+  p->num_perm += (int)permA + (int)permB;
+  return TN_OK;
+}
+
+static tn_status schedule_dot(tn_plan *p, Node &n, const Layout &A, const Layout &B) {
+  n.kind = NK_DOT;
+  n.out = Layout();
+  DotDesc d;
+  memset(&d, 0, sizeof(d));
+  d.nelem = A.size();
+  std::vector<int64_t> as = A.strides(), bs = B.strides();
+  std::vector<LegMap> legs;
+  for (int i = 0; i < A.rank(); ++i) legs.push_back({A.dim[i], as[i], bs[B.find(A.lab[i])]});
+  if (!fill_segmap(legs, d.map)) {
+    set_error("tensor with too many index segments");
+    return TN_E_INVALID_PLAN;
+  }
+  n.nelem = d.nelem;
+  n.dot_blocks = dot_blocks_for(d.nelem);
+  n.ddesc_off = blob_put(p->desc_blob, d);
+  return TN_OK;
+}
+
+// Largest offsets a segment map can produce (sum of (extent - 1) * stride).
+static void seg_reach(const SegMap &m, int64_t &r0, int64_t &r1, int64_t &count) {
+  r0 = r1 = 0;
+  count = 1;
+  for (int i = 0; i < m.nseg; ++i) {
+    r0 += (m.ext[i] - 1) * m.s0[i];
+    r1 += (m.ext[i] - 1) * m.s1[i];
+    count *= m.ext[i];
+  }
+}
+
+// Every kernel of a node must stay inside its operands: checked here on the
+// host so that a scheduling mistake is a load error, never a device fault.
+static bool node_in_bounds(const tn_plan *p, const Node &n, const std::vector<Layout> &lay) {
+  const uint8_t *blob = p->desc_blob.data();
+  int64_t r0, r1, cnt;
+  if (n.kind == NK_STREAM) {
+    const StreamDesc &d = *(const StreamDesc *)(blob + n.sdesc_off);
+    seg_reach(d.fib, r0, r1, cnt);
+    if (cnt != d.nfib || d.ns < 1 || d.nfy < 1 || d.ns * d.nfy > kStreamMax) return false;
+    int64_t mx = 0, mc = 0;
+    for (int s = 0; s < d.ns; ++s) mx = std::max(mx, d.xs[s]);
+    for (int j = 0; j < d.nfy; ++j) mc = std::max(mc, d.cy[j]);
+    for (int i = 0; i < d.ns * d.nfy; ++i)
+      if (d.ymap[i] < 0 || d.ymap[i] >= lay[n.y].size()) return false;
+    return r0 + mx < lay[n.x].size() && r1 + mc < std::max<int64_t>(n.out.size(), 1);
+  }
+  auto perm_ok = [&](const PermStep &ps, const Layout &src) {
+    if (!ps.needed) return true;
+    seg_reach(ps.h.map, r0, r1, cnt);
+    if (ps.h.bits > 0 && ((int64_t)1 << ps.h.bits) != ps.h.nelem) return false;
+    return cnt == ps.h.nelem && ps.h.nelem == src.size() && r0 < src.size() && r1 < ps.h.nelem;
+  };
+  if (n.kind == NK_GEMM) {
+    if (!perm_ok(n.pa, lay[n.ga]) || !perm_ok(n.pb, lay[n.gb])) return false;
+    const int64_t sa = lay[n.ga].size(), sb = lay[n.gb].size();
+    const int64_t ea = n.opA == 0 ? (n.M - 1) * n.lda + n.K - 1 : (n.K - 1) * n.lda + n.M - 1;
+    const int64_t eb = n.opB == 0 ? (n.K - 1) * n.ldb + n.N - 1 : (n.N - 1) * n.ldb + n.K - 1;
+    const int64_t ec = (n.M - 1) * n.ldc + n.N - 1;
+    return n.M * n.K == sa && n.K * n.N == sb && ea < sa && eb < sb && ec < n.out.size();
+  }
+  const DotDesc &d = *(const DotDesc *)(blob + n.ddesc_off);
+  seg_reach(d.map, r0, r1, cnt);
+  return cnt == d.nelem && d.nelem == lay[n.c1].size() && lay[n.c1].size() == lay[n.c2].size() &&
+         r0 < lay[n.c1].size() && r1 < lay[n.c2].size();
+}
+
+static u128 mul_check(u128 a, u128 b, bool &ovf) {
+  if (a != 0 && b > (~(u128)0) / a) ovf = true;
+  return a * b;
+}
+
+tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
+  if (!d || d->num_tensors < 1 || !d->rank || !d->data || !d->partition_of) {
+    set_error("tn_plan_desc: num_tensors >= 1 and rank/data/partition_of pointers are required");
+    return TN_E_INVALID_ARG;
+  }
+  if (d->data_dtype != TN_C64 && d->data_dtype != TN_C128) {
+    set_error("tn_plan_desc: data_dtype must be TN_C64 or TN_C128");
+    return TN_E_INVALID_ARG;
+  }
+  const int nv = d->num_tensors;
+  p->nv = nv;
+  int64_t total = 0;
+  for (int v = 0; v < nv; ++v) {
+    if (d->rank[v] < 0 || d->rank[v] > 64) {
+      set_error("tensor %d: rank %d out of range [0, 64]", v, d->rank[v]);
+      return TN_E_INVALID_PLAN;
+    }
+    total += d->rank[v];
+  }
+  if (total > 0 && (!d->legs || !d->leg_dims)) {
+    set_error("tn_plan_desc: legs and leg_dims are required");
+    return TN_E_INVALID_ARG;
+  }
+  // edges: a label on two slots of two tensors with equal dims, or on one slot
+  struct LabInfo {
+    int count = 0;
+    int t0 = -1, t1 = -1;
+    int64_t dim = 0;
+    int64_t first = 0;
+  };
+  std::unordered_map<int64_t, LabInfo> labs;
+  std::vector<int64_t> first_order;
+  p->leaf.resize(nv);
+  int64_t pos = 0;
+  for (int v = 0; v < nv; ++v) {
+    Layout &L = p->leaf[v];
+    for (int a = 0; a < d->rank[v]; ++a, ++pos) {
+      int64_t lab = d->legs[pos], dim = d->leg_dims[pos];
+      if (dim < 1) {
+        set_error("tensor %d leg %d: dimension %lld < 1", v, a, (long long)dim);
+        return TN_E_INVALID_PLAN;
+      }
+      LabInfo &li = labs[lab];
+      if (li.count == 0) {
+        li.t0 = v;
+        li.dim = dim;
+        first_order.push_back(lab);
+      } else if (li.count == 1) {
+        if (li.t0 == v) {
+          set_error("label %lld appears twice on tensor %d (self-loop)", (long long)lab, v);
+          return TN_E_INVALID_PLAN;
+        }
+        if (li.dim != dim) {
+          set_error("label %lld: dimensions %lld and %lld differ (n_{u,a} must equal n_{v,b})",
+                    (long long)lab, (long long)li.dim, (long long)dim);
+          return TN_E_INVALID_PLAN;
+        }
+        li.t1 = v;
+      } else {
+        set_error("label %lld appears on more than two slots (hyperedge)", (long long)lab);
+        return TN_E_INVALID_PLAN;
+      }
+      li.count++;
+      L.lab.push_back(lab);
+      L.dim.push_back(dim);
+    }
+    if (L.size() > kMaxElems) {
+      set_error("tensor %d has more than 2^40 elements", v);
+      return TN_E_INVALID_PLAN;
+    }
+    if (!d->data[v]) {
+      set_error("tensor %d: data pointer is NULL", v);
+      return TN_E_INVALID_ARG;
+    }
+  }
+  // open legs and their output order
+  std::vector<int64_t> open;
+  for (int64_t l : first_order)
+    if (labs[l].count == 1) open.push_back(l);
+  if (d->num_output_legs > 0) {
+    if (!d->output_legs || d->num_output_legs != (int)open.size()) {
+      set_error("output_legs must list each of the %d open labels exactly once", (int)open.size());
+      return TN_E_INVALID_PLAN;
+    }
+    std::set<int64_t> seen;
+    for (int i = 0; i < d->num_output_legs; ++i) {
+      int64_t l = d->output_legs[i];
+      auto it = labs.find(l);
+      if (it == labs.end() || it->second.count != 1 || !seen.insert(l).second) {
+        set_error("output_legs[%d] = %lld is not an open label (or repeats)", i, (long long)l);
+        return TN_E_INVALID_PLAN;
+      }
+    }
+    p->out_labels.assign(d->output_legs, d->output_legs + d->num_output_legs);
+  } else {
+    p->out_labels = open;
+  }
+  p->closed = p->out_labels.empty();
+
+  // partitioning: cover, disjoint (one index per tensor), non-empty
+  if (d->num_partitions < 1 || d->num_partitions > nv) {
+    set_error("num_partitions %d out of range [1, %d]", d->num_partitions, nv);
+    return TN_E_INVALID_PLAN;
+  }
+  p->K = d->num_partitions;
+  p->partition_of.assign(d->partition_of, d->partition_of + nv);
+  std::vector<int> count(p->K, 0);
+  for (int v = 0; v < nv; ++v) {
+    int k = p->partition_of[v];
+    if (k < 0 || k >= p->K) {
+      set_error("partition_of[%d] = %d out of range", v, k);
+      return TN_E_INVALID_PLAN;
+    }
+    count[k]++;
+  }
+  for (int k = 0; k < p->K; ++k)
+    if (!count[k]) {
+      set_error("partition %d is empty (partitions must be non-empty)", k);
+      return TN_E_INVALID_PLAN;
+    }
+
+  // tree: full binary, leaves in bijection with V, every vertex used once
+  const int nn = 2 * nv - 1;
+  if (nv > 1 && !d->tree) {
+    set_error("tree is required for more than one tensor");
+    return TN_E_INVALID_ARG;
+  }
+  p->tree.assign(d->tree ? d->tree : (const int32_t *)nullptr,
+                 d->tree ? d->tree + 2 * (nv - 1) : (const int32_t *)nullptr);
+  std::vector<int> parent(nn, -1);
+  for (int j = 0; j < nv - 1; ++j) {
+    int a = p->tree[2 * j], b = p->tree[2 * j + 1], v = nv + j;
+    if (a < 0 || b < 0 || a >= v || b >= v || a == b) {
+      set_error("tree pair %d = (%d, %d): children must be distinct earlier vertices", j, a, b);
+      return TN_E_INVALID_PLAN;
+    }
+    if (parent[a] >= 0 || parent[b] >= 0) {
+      set_error("tree pair %d: vertex %d already has a parent", j, parent[a] >= 0 ? a : b);
+      return TN_E_INVALID_PLAN;
+    }
+    parent[a] = parent[b] = v;
+  }
+  p->root = nn - 1;
+  // acceptance: partition of all leaves under each vertex
+  std::vector<int> pk(nn), nleaf(nn);
+  for (int v = 0; v < nv; ++v) {
+    pk[v] = p->partition_of[v];
+    nleaf[v] = 1;
+  }
+  for (int j = 0; j < nv - 1; ++j) {
+    int a = p->tree[2 * j], b = p->tree[2 * j + 1], v = nv + j;
+    pk[v] = (pk[a] >= 0 && pk[a] == pk[b]) ? pk[a] : -1;
+    nleaf[v] = nleaf[a] + nleaf[b];
+  }
+  std::vector<int> proot(p->K, -1);
+  for (int v = 0; v < nn; ++v)
+    if (pk[v] >= 0 && nleaf[v] == count[pk[v]]) proot[pk[v]] = v;
+  for (int k = 0; k < p->K; ++k)
+    if (proot[k] < 0) {
+      set_error("the tree does not accept the partitioning: no subtree has exactly the leaves "
+                "of partition %d",
+                k);
+      return TN_E_INVALID_PLAN;
+    }
+
+  // legs, 2^vc, schedule
+  std::vector<Layout> lay(nn);
+  for (int v = 0; v < nv; ++v) lay[v] = p->leaf[v];
+  std::vector<u128> w(nn, 0), sz(nn, 0);
+  bool ovf = false;
+  for (int v = 0; v < nv; ++v) {
+    u128 s = 1;
+    for (int64_t dd : lay[v].dim) s = mul_check(s, (u128)dd, ovf);
+    sz[v] = s;
+  }
+  p->nodes.resize(nv - 1);
+  u128 con_serial = 0, mem = 0;
+  int64_t largest = 0;
+  for (int j = 0; j < nv - 1; ++j) {
+    Node &n = p->nodes[j];
+    n.id = nv + j;
+    n.c1 = p->tree[2 * j];
+    n.c2 = p->tree[2 * j + 1];
+    n.part = pk[n.id];
+    const Layout &A = lay[n.c1], &B = lay[n.c2];
+    // E(v) = union of the children's legs; legs(v) = symmetric difference
+    u128 wv = 1, sv = 1;
+    for (int i = 0; i < A.rank(); ++i) wv = mul_check(wv, (u128)A.dim[i], ovf);
+    bool any_free_b = false, any_free_a = false;
+    for (int i = 0; i < B.rank(); ++i) {
+      if (A.find(B.lab[i]) < 0) {
+        wv = mul_check(wv, (u128)B.dim[i], ovf);
+        sv = mul_check(sv, (u128)B.dim[i], ovf);
+        any_free_b = true;
+      }
+    }
+    for (int i = 0; i < A.rank(); ++i)
+      if (B.find(A.lab[i]) < 0) {
+        sv = mul_check(sv, (u128)A.dim[i], ovf);
+        any_free_a = true;
+      }
+    if (ovf) {
+      set_error("cost integers overflow 128 bits");
+      return TN_E_INVALID_PLAN;
+    }
+    if (sv > (u128)kMaxElems) {
+      set_error("intermediate %d would have more than 2^40 elements", n.id);
+      return TN_E_INVALID_PLAN;
+    }
+    n.weight = wv;
+    w[n.id] = wv;
+    sz[n.id] = sv;
+    con_serial += wv;
+    u128 m = sv + sz[n.c1] + sz[n.c2];
+    if (m > mem) mem = m;
+    if ((int64_t)sv > largest) largest = (int64_t)sv;
+    n.tiny = sv <= 4096 && sz[n.c1] <= 4096 && sz[n.c2] <= 4096;
+    tn_status st;
+    if (!any_free_a && !any_free_b) {
+      st = schedule_dot(p, n, A, B);
+    } else if (std::min(A.size(), B.size()) <= kStreamMax) {
+      bool a_big = A.size() >= B.size();
+      st = a_big ? schedule_stream(p, n, A, B, n.c1, n.c2) : schedule_stream(p, n, B, A, n.c2, n.c1);
+      p->num_stream++;
+    } else {
+      st = schedule_gemm(p, n, A, B);
+      p->num_gemm++;
+    }
+    if (st) return st;
+    if (n.tiny) p->num_tiny++;
+    lay[n.id] = n.out;
+    if (!node_in_bounds(p, n, lay)) {
+      set_error("internal schedule error at vertex %d: an index map leaves its operand", n.id);
+      return TN_E_INVALID_PLAN;
+    }
+  }
+  p->con_serial = con_serial;
+  p->mem = mem;
+  p->largest = largest;
+  // critical path
+  std::vector<u128> best(nn, 0);
+  for (int j = 0; j < nv - 1; ++j) {
+    int a = p->tree[2 * j], b = p->tree[2 * j + 1], v = nv + j;
+    best[v] = w[v] + std::max(best[a], best[b]);
+  }
+  p->con_par = nv > 1 ? best[nn - 1] : 0;
+  // con_dist with con = con_serial, comm = 0
+  u128 cd = 0;
+  for (int k = 0; k < p->K; ++k) {
+    u128 c = 0;
+    for (int v = nv; v < nn; ++v)
+      if (pk[v] == k) c += w[v];
+    for (int u = parent[proot[k]]; u >= 0; u = parent[u]) c += w[u];
+    cd = std::max(cd, c);
+  }
+  p->con_dist = cd;
+  // execution order: partitions in turn, then the reduction path
+  for (int k = 0; k < p->K; ++k)
+    for (int j = 0; j < nv - 1; ++j)
+      if (pk[nv + j] == k) p->order.push_back(j);
+  for (int j = 0; j < nv - 1; ++j)
+    if (pk[nv + j] < 0) p->order.push_back(j);
+
+  // result layout and the final permutation into output-leg order
+  const Layout &R = lay[p->root];
+  p->result_layout = make_layout(p->out_labels, R, R);
+  if (!p->closed && !same_order(R, p->result_layout)) {
+    p->fperm.needed = true;
+    p->fperm.dst = p->result_layout;
+    if (!make_perm(R, p->fperm.dst, p->fperm.h)) {
+      set_error("tensor with too many index segments");
+      return TN_E_INVALID_PLAN;
+    }
+    p->fperm.desc_off = blob_put(p->desc_blob, p->fperm.h);
+    int64_t r0, r1, cnt;
+    seg_reach(p->fperm.h.map, r0, r1, cnt);
+    if (cnt != R.size() || r0 >= R.size() || r1 >= R.size() ||
+        (p->fperm.h.bits > 0 && ((int64_t)1 << p->fperm.h.bits) != R.size())) {
+      set_error("internal schedule error in the output permutation");
+      return TN_E_INVALID_PLAN;
+    }
+  }
+
+  // leaves as complex64 (rounded once from complex128 input)
+  p->leaf_off.resize(nv);
+  int64_t off = 0;
+  for (int v = 0; v < nv; ++v) {
+    p->leaf_off[v] = off;
+    off += (p->leaf[v].size() + 31) & ~(int64_t)31;  // 256-byte aligned leaves
+  }
+  p->leaf_host.assign(off, make_float2(0.f, 0.f));
+  for (int v = 0; v < nv; ++v) {
+    int64_t n = p->leaf[v].size();
+    float2 *dst = p->leaf_host.data() + p->leaf_off[v];
+    if (d->data_dtype == TN_C128) {
+      const double *s = (const double *)d->data[v];
+      for (int64_t i = 0; i < n; ++i) dst[i] = make_float2((float)s[2 * i], (float)s[2 * i + 1]);
+    } else {
+      memcpy(dst, d->data[v], sizeof(float2) * n);
+    }
+  }
+  p->plain = make_exec_layout(p, {}, false);
+  return TN_OK;
+}
+
+// ---------------------------------------------------------- memory layout
+
+// Best-fit allocation over a growing range; records the high-water mark.
+class Packer {
+ public:
+  int64_t alloc(int64_t bytes) {
+    bytes = (bytes + 255) & ~(int64_t)255;
+    auto best = free_.end();
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes && (best == free_.end() || it->second < best->second)) best = it;
+    int64_t off;
+    if (best != free_.end()) {
+      off = best->first;
+      int64_t rem = best->second - bytes;
+      free_.erase(best);
+      if (rem) free_[off + bytes] = rem;
+    } else {
+      // extend, merging a free block that ends at the top
+      off = top_;
+      if (!free_.empty()) {
+        auto last = std::prev(free_.end());
+        if (last->first + last->second == top_) {
+          off = last->first;
+          free_.erase(last);
+        }
+      }
+      top_ = off + bytes;
+    }
+    peak_ = std::max(peak_, top_);
+    return off;
+  }
+  void release(int64_t off, int64_t bytes) {
+    bytes = (bytes + 255) & ~(int64_t)255;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int64_t peak() const { return peak_; }
+
+ private:
+  std::map<int64_t, int64_t> free_;
+  int64_t top_ = 0, peak_ = 0;
+};
+
+ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden, bool share) {
+  const int nv = p->nv, nn = 2 * nv - 1;
+  ExecLayout L;
+  L.off.assign(nn, -1);
+  L.shared.assign(nn, 1);
+  L.scr_a.assign(nv > 1 ? nv - 1 : 0, -1);
+  L.scr_b = L.scr_a;
+  L.partial = L.scr_a;
+  L.ovr_off.assign(nv, -1);
+  std::vector<uint8_t> ovr(nv, 0);
+  for (int t : overridden) ovr[t] = 1;
+  for (int v = 0; v < nv; ++v) L.shared[v] = ovr[v] ? 0 : 1;
+  for (const Node &n : p->nodes) L.shared[n.id] = L.shared[n.c1] && L.shared[n.c2];
+  if (!share)  // plain execution: every intermediate belongs to the query
+    for (int v = nv; v < nn; ++v) L.shared[v] = 0;
+  Packer pk[2];  // 0: per-query, 1: shared
+  for (int j : p->order) {
+    const Node &n = p->nodes[j];
+    const int part = L.shared[n.id] ? 1 : 0;
+    Packer &P = pk[part];
+    int64_t out_bytes = std::max<int64_t>(n.out.size(), 1) * 8;
+    L.off[n.id] = P.alloc(out_bytes);
+    std::vector<std::pair<int64_t, int64_t>> tmp;
+    if (n.kind == NK_GEMM) {
+      if (n.pa.needed) {
+        L.scr_a[j] = P.alloc(n.pa.h.nelem * 8);
+        tmp.push_back({L.scr_a[j], n.pa.h.nelem * 8});
+      }
+      if (n.pb.needed) {
+        L.scr_b[j] = P.alloc(n.pb.h.nelem * 8);
+        tmp.push_back({L.scr_b[j], n.pb.h.nelem * 8});
+      }
+    } else if (n.kind == NK_DOT) {
+      L.partial[j] = P.alloc((int64_t)n.dot_blocks * 16);
+      tmp.push_back({L.partial[j], (int64_t)n.dot_blocks * 16});
+    }
+    for (auto &t : tmp) P.release(t.first, t.second);
+    // children die here unless they live in the other part (shared results
+    // feeding per-query nodes stay for the whole execution)
+    for (int c : {n.c1, n.c2}) {
+      if (c < nv) continue;
+      if (L.shared[c] == L.shared[n.id]) {
+        const Node &cn = p->nodes[c - nv];
+        P.release(L.off[c], std::max<int64_t>(cn.out.size(), 1) * 8);
+      }
+    }
+  }
+  // the root (and shared roots) stay allocated: never released above
+  int64_t q = pk[0].peak(), s = pk[1].peak();
+  L.peak_intermediate = q;
+  auto carve = [](int64_t &top, int64_t bytes) {
+    int64_t off = top;
+    top += (bytes + 255) & ~(int64_t)255;
+    return off;
+  };
+  L.slots_perq = carve(q, (int64_t)nn * (int64_t)sizeof(Slot));
+  L.result_off = carve(q, sizeof(Result));
+  if (p->fperm.needed) L.final_off = carve(q, p->result_layout.size() * 8);
+  for (int v = 0; v < nv; ++v)
+    if (ovr[v]) L.ovr_off[v] = carve(q, p->leaf[v].size() * 8);
+  L.slots_shared = carve(s, (int64_t)nn * (int64_t)sizeof(Slot));
+  L.perq_bytes = q;
+  L.shared_bytes = s;
+  return L;
+}
+
+std::shared_ptr<ExecLayout> cached_layout(tn_plan *p, const std::vector<int> &overridden,
+                                          bool share) {
+  std::lock_guard<std::mutex> g(p->cache_mu);
+  std::vector<int> key = overridden;
+  key.push_back(share ? -1 : -2);
+  auto it = p->layouts.find(key);
+  if (it != p->layouts.end()) return it->second;
+  auto L = std::make_shared<ExecLayout>(make_exec_layout(p, overridden, share));
+  p->layouts[key] = L;
+  return L;
+}
+
+}  // namespace tn

@@ -1,0 +1,127 @@
+// Descriptor layouts shared by the host scheduler and the gfx950 kernels, and
+// the kernel launchers.  Plain structs only; every pointer is a device
+// address.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tn {
+
+// Scale record of one tensor: stored values times 2^log2s are the true values;
+// maxbits is the IEEE bit pattern of max(|re|, |im|) over the stored values
+// (non-negative floats order like their bit patterns, so atomicMax on the bits
+// gives the maximum).  A consumer multiplies the stored values by 2^-e, with
+// e = floor(log2(max)), and adds e to its own log2s.
+struct Slot {
+  double log2s;
+  uint32_t maxbits;
+  uint32_t pad;
+};
+
+constexpr int kMaxSeg = 40;     // fused index segments per map (>= legs of dim > 1 of any tensor below 2^40 elements)
+constexpr int kStreamMax = 64;  // largest tensor applied by the streaming kernel
+
+// An index space split into segments, innermost first.  Segment i has extent
+// ext[i] and contributes idx * s0[i] to a first offset and idx * s1[i] to a
+// second one.  pow2 = every extent is a power of two (lg = log2 extent).
+struct SegMap {
+  int32_t nseg;
+  int32_t pow2;
+  int64_t ext[kMaxSeg];
+  int64_t s0[kMaxSeg];
+  int64_t s1[kMaxSeg];
+  int32_t lg[kMaxSeg];
+};
+
+// Small-operand contraction C = X (.) Y, |Y| <= kStreamMax.  Fibers are the
+// values of X's free index; fiber f sits at X offset / C offset given by
+// `fib`.  For shared-index value s and Y-free value j:
+//   C[co + cy[j]] = sum_s X[xo + xs[s]] * Y[ymap[s * nfy + j]].
+struct StreamDesc {
+  int64_t nfib;
+  int32_t ns, nfy;
+  SegMap fib;
+  int64_t xs[kStreamMax];
+  int64_t cy[kStreamMax];
+  int32_t ymap[kStreamMax];
+};
+
+// out[o] = in[map(o)]: `map` runs over the output index (innermost first),
+// s0 = input stride, s1 = output stride.
+struct PermDesc {
+  int64_t nelem;
+  SegMap map;
+  // bit form, valid when bits > 0: element counts are 2^bits and output bit j
+  // is input bit inbit[j].
+  int32_t bits;
+  int32_t inbit[48];
+};
+
+// Full inner product of two tensors with the same legs: i runs over A's
+// row-major index; map gives (A offset, B offset).
+struct DotDesc {
+  int64_t nelem;
+  SegMap map;
+};
+
+// Complex GEMM C[M x N] = op(A) op(B) on interleaved complex64 data.
+// opA = 0: A is M x K row-major (lda >= K); 1: A is stored K x M (lda >= M).
+// opB = 0: B is K x N row-major (ldb >= N); 1: B is stored N x K (ldb >= K).
+// Batched over gridDim.y with element strides *bs (0 = shared operand).
+struct GemmArgs {
+  const float2 *A;
+  const float2 *B;
+  float2 *C;
+  const Slot *sa;
+  const Slot *sb;
+  Slot *sc;
+  int64_t lda, ldb, ldc;
+  int64_t abs, bbs, cbs;
+  int64_t sabs, sbbs, scbs;
+  int64_t M, N, K;
+  int32_t opA, opB;
+  int32_t tiles_m, tiles_n;
+};
+
+// One operand of a batched launch: base pointer plus per-query stride.
+struct Operand {
+  const float2 *p;
+  int64_t bs;
+  const Slot *slot;
+  int64_t sbs;
+};
+struct OutOperand {
+  float2 *p;
+  int64_t bs;
+  Slot *slot;
+  int64_t sbs;
+};
+
+// Result of a closed network: FP64 mantissa and FP64 log2 scale.
+struct Result {
+  double re, im, log2s, pad;
+};
+
+enum GemmForm { kForm4M = 0, kForm3M = 1 };
+enum GemmPrec { kPrecFP32 = 0, kPrecBF16x3 = 1 };
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_init_slots(hipStream_t st, Slot *slots, int64_t n);
+hipError_t launch_stream(hipStream_t st, const StreamDesc *d_desc, int64_t nfib, int ns,
+                         Operand X, Operand Y, OutOperand C, int nbatch);
+hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc &h_desc,
+                          const float2 *in, int64_t ibs, float2 *out, int64_t obs, int nbatch);
+hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int prec, int form, int variant,
+                       int nbatch);
+hipError_t launch_dot(hipStream_t st, const DotDesc *d_desc, int64_t nelem, Operand A, Operand B,
+                      OutOperand C, Result *res, int64_t rbs, double2 *partials, int nblocks,
+                      int nbatch);
+
+// Tile shape variants of the GEMM (index into a table in the kernel file).
+int gemm_num_variants();
+int gemm_variant_tile_m(int v);
+int gemm_variant_tile_n(int v);
+int dot_blocks_for(int64_t nelem);
+
+}  // namespace tn

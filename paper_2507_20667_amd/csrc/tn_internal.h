@@ -1,0 +1,243 @@
+// Host-side structures of libtn: plans, schedule, execution layouts, the arena
+// allocator and the context.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tn.h"
+#include "tn_device.h"
+
+namespace tn {
+
+typedef unsigned __int128 u128;
+
+void set_error(const char *fmt, ...);
+
+// Row-major layout of one tensor: its legs (labels) and their dimensions.
+struct Layout {
+  std::vector<int64_t> lab;
+  std::vector<int64_t> dim;
+  int64_t size() const {
+    int64_t s = 1;
+    for (int64_t d : dim) s *= d;
+    return s;
+  }
+  int rank() const { return (int)lab.size(); }
+  int find(int64_t l) const {
+    for (size_t i = 0; i < lab.size(); ++i)
+      if (lab[i] == l) return (int)i;
+    return -1;
+  }
+  std::vector<int64_t> strides() const {
+    std::vector<int64_t> s(lab.size());
+    int64_t acc = 1;
+    for (int i = (int)lab.size() - 1; i >= 0; --i) {
+      s[i] = acc;
+      acc *= dim[i];
+    }
+    return s;
+  }
+};
+
+enum NodeKind { NK_STREAM = 0, NK_GEMM = 1, NK_DOT = 2 };
+
+struct PermStep {
+  bool needed = false;
+  Layout dst;
+  size_t desc_off = 0;  // byte offset of the PermDesc in the descriptor blob
+  PermDesc h;           // host copy (grid sizing, bit tiling)
+};
+
+// One internal vertex of the contraction tree and how it runs.
+struct Node {
+  int id = 0;        // SSA id of the result tensor (nv + j)
+  int c1 = 0, c2 = 0;
+  int part = -1;     // partition whose subtree holds it; -1 on the reduction path
+  NodeKind kind = NK_STREAM;
+  Layout out;
+  u128 weight = 0;   // 2^vc
+  bool tiny = false;
+  // NK_STREAM
+  int x = 0, y = 0;
+  size_t sdesc_off = 0;
+  int64_t nfib = 0;
+  int ns = 0, nfy = 0;
+  // NK_GEMM: A = c1 side, B = c2 side
+  int ga = 0, gb = 0;
+  PermStep pa, pb;
+  int opA = 0, opB = 0;
+  int64_t M = 0, N = 0, K = 0, lda = 0, ldb = 0, ldc = 0;
+  int variant = 0;
+  // NK_DOT
+  size_t ddesc_off = 0;
+  int64_t nelem = 0;
+  int dot_blocks = 1;
+};
+
+// Where every tensor of one execution lives.  Intermediates and scratch are
+// either in the shared part (computed once for all queries of a batch) or in
+// the per-query part (one copy per query, `perq_stride` bytes apart).
+struct ExecLayout {
+  std::vector<int64_t> off;       // per tensor id: byte offset in its part (-1: leaf region)
+  std::vector<uint8_t> shared;    // per tensor id
+  std::vector<int64_t> scr_a, scr_b, partial;  // per node index j
+  std::vector<int64_t> ovr_off;   // per leaf: offset of its per-query override copy, or -1
+  int64_t shared_bytes = 0;
+  int64_t perq_bytes = 0;
+  int64_t slots_shared = 0, slots_perq = 0;  // slot arrays (one Slot per tensor id)
+  int64_t result_off = 0;         // per query: Result
+  int64_t final_off = -1;         // per query: result in output-leg order
+  int64_t peak_intermediate = 0;  // live peak (per-query part, intermediates + scratch)
+};
+
+struct tn_plan_impl;
+
+// Device arena: first-fit over a borrowed device range, 256-byte granules.
+class Arena {
+ public:
+  void init(uint8_t *base, size_t bytes) {
+    base_ = base;
+    bytes_ = bytes;
+    free_.clear();
+    if (bytes) free_[0] = bytes;
+  }
+  // returns offset or -1
+  int64_t alloc(size_t bytes) {
+    std::lock_guard<std::mutex> g(mu_);
+    bytes = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        int64_t off = it->first;
+        size_t rem = it->second - bytes;
+        free_.erase(it);
+        if (rem) free_[off + (int64_t)bytes] = rem;
+        used_ += bytes;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off, size_t bytes) {
+    if (off < 0) return;
+    std::lock_guard<std::mutex> g(mu_);
+    bytes = round(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace((int64_t)off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + (int64_t)it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + (int64_t)pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t largest_free() {
+    std::lock_guard<std::mutex> g(mu_);
+    size_t m = 0;
+    for (auto &kv : free_) m = kv.second > m ? kv.second : m;
+    return m;
+  }
+  size_t used() {
+    std::lock_guard<std::mutex> g(mu_);
+    return used_;
+  }
+  uint8_t *base() const { return base_; }
+  size_t bytes() const { return bytes_; }
+  static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
+
+ private:
+  std::mutex mu_;
+  uint8_t *base_ = nullptr;
+  size_t bytes_ = 0;
+  size_t used_ = 0;
+  std::map<int64_t, size_t> free_;
+};
+
+struct ServeState;  // serve.cpp
+
+}  // namespace tn
+
+struct tn_ctx {
+  tn::Arena arena;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::mutex exec_mu;              // tn_contract* are serialized per context
+  std::atomic<int> live_plans{0};
+  // pinned host staging for overrides and results
+  void *pinned = nullptr;
+  size_t pinned_bytes = 0;
+  tn::ServeState *serve = nullptr;
+  std::mutex serve_init_mu;
+};
+
+struct tn_plan {
+  tn_ctx *ctx = nullptr;
+  uint32_t flags = 0;
+  int nv = 0;
+  int K = 0;
+  std::vector<tn::Layout> leaf;
+  std::vector<int32_t> partition_of;
+  std::vector<int32_t> tree;
+  std::vector<tn::Node> nodes;   // SSA order: nodes[j] makes tensor nv + j
+  std::vector<int> order;        // execution order (indices into nodes)
+  std::vector<int64_t> out_labels;
+  bool closed = true;
+  int root = 0;                  // SSA id of the root tensor
+  tn::PermStep fperm;            // root layout -> output-leg order
+  tn::Layout result_layout;
+  // leaves as complex64 on the host (for per-query copies) and on the device
+  std::vector<float2> leaf_host;
+  std::vector<int64_t> leaf_off;  // element offset of each leaf in leaf_host / the leaf region
+  std::vector<uint8_t> desc_blob;
+  int64_t dev_leaf = -1, dev_desc = -1;  // arena offsets
+  size_t dev_leaf_bytes = 0, dev_desc_bytes = 0;
+  tn::u128 con_serial = 0, con_par = 0, con_dist = 0, mem = 0;
+  int64_t largest = 0;
+  int num_gemm = 0, num_tiny = 0, num_stream = 0, num_perm = 0;
+  tn::ExecLayout plain;          // nothing shared, one query
+  std::mutex cache_mu;
+  std::map<std::vector<int>, std::shared_ptr<tn::ExecLayout>> layouts;  // by override set
+};
+
+namespace tn {
+
+// plan.cpp
+tn_status build_plan(tn_plan *p, const tn_plan_desc *d);
+ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden, bool share);
+std::shared_ptr<ExecLayout> cached_layout(tn_plan *p, const std::vector<int> &overridden,
+                                          bool share);
+const char *last_error();
+
+// exec.cpp
+struct QueryIO {
+  const tn_leaf *ovr = nullptr;
+  int32_t novr = 0;
+  void *out = nullptr;
+  double *log2s = nullptr;
+  tn_status *status = nullptr;
+};
+tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_dtype out_dtype,
+                    uint32_t flags, bool share, hipStream_t st);
+size_t result_elems(const tn_plan *p);
+
+// serve.cpp
+void serve_shutdown(tn_ctx *ctx);
+
+}  // namespace tn

@@ -1,0 +1,287 @@
+"""ctypes binding of libtn (include/tn.h).
+
+Argument marshalling only: every step of a contraction runs in libtn's HIP
+kernels.  The functions carry the C names; `Context` adds the one convenience
+of taking its arena from a torch device tensor and its stream from torch.
+
+If libtn.so is missing this module raises on first use: there is no other
+code path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtn.so")
+
+TN_OK, TN_PENDING = 0, 1
+TN_E_INVALID_ARG, TN_E_INVALID_PLAN, TN_E_NOMEM, TN_E_DEVICE = -1, -2, -3, -4
+TN_E_AGAIN, TN_E_CANCELLED, TN_E_UNKNOWN_TICKET = -5, -6, -7
+TN_C64, TN_C128 = 0, 1
+TN_PREC_FP32, TN_PREC_BF16X3 = 0, 1
+TN_FORM_4M, TN_FORM_3M = 0, 1 << 4
+TN_FLAG_KEEP_SCALE = 1 << 8
+
+STATUS_NAMES = {0: "TN_OK", 1: "TN_PENDING", -1: "TN_E_INVALID_ARG", -2: "TN_E_INVALID_PLAN",
+                -3: "TN_E_NOMEM", -4: "TN_E_DEVICE", -5: "TN_E_AGAIN", -6: "TN_E_CANCELLED",
+                -7: "TN_E_UNKNOWN_TICKET"}
+
+EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_last_error", "tn_plan_load",
+            "tn_plan_costs_get", "tn_plan_free", "tn_contract", "tn_contract_batch",
+            "tn_serve_submit", "tn_serve_poll"]
+
+
+class TnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class tn_plan_desc(ctypes.Structure):
+    _fields_ = [("num_tensors", ctypes.c_int32),
+                ("rank", ctypes.c_void_p),
+                ("legs", ctypes.c_void_p),
+                ("leg_dims", ctypes.c_void_p),
+                ("data", ctypes.c_void_p),
+                ("data_dtype", ctypes.c_int),
+                ("partition_of", ctypes.c_void_p),
+                ("num_partitions", ctypes.c_int32),
+                ("tree", ctypes.c_void_p),
+                ("output_legs", ctypes.c_void_p),
+                ("num_output_legs", ctypes.c_int32)]
+
+
+class tn_plan_costs(ctypes.Structure):
+    _fields_ = [("con_serial", ctypes.c_uint64 * 2), ("con_par", ctypes.c_uint64 * 2),
+                ("con_dist", ctypes.c_uint64 * 2), ("mem_elems", ctypes.c_uint64 * 2),
+                ("live_peak_bytes", ctypes.c_uint64),
+                ("largest_intermediate_elems", ctypes.c_uint64),
+                ("num_internal_nodes", ctypes.c_int32), ("num_gemm_nodes", ctypes.c_int32),
+                ("num_tiny_nodes", ctypes.c_int32), ("num_stream_nodes", ctypes.c_int32),
+                ("num_permutations", ctypes.c_int32)]
+
+
+class tn_leaf(ctypes.Structure):
+    _fields_ = [("tensor", ctypes.c_int32), ("data", ctypes.c_void_p), ("dtype", ctypes.c_int)]
+
+
+class tn_query(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("num_overrides", ctypes.c_int32),
+                ("overrides", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2507_20667_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I32, U32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+        sig = {
+            "tn_ctx_create": [P, SZ, P, U32, P],
+            "tn_ctx_destroy": [P],
+            "tn_plan_load": [P, P, U32, P],
+            "tn_plan_costs_get": [P, P],
+            "tn_plan_free": [P],
+            "tn_contract": [P, I32, P, P, ctypes.c_int, P, U32],
+            "tn_contract_batch": [P, I32, P, P, ctypes.c_int, P, P, U32],
+            "tn_serve_submit": [P, P, P],
+            "tn_serve_poll": [P, ctypes.c_uint64, P, ctypes.c_int, P, P],
+        }
+        for name, args in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int32
+        lib.tn_last_error.argtypes = []
+        lib.tn_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def tn_last_error() -> str:
+    return load().tn_last_error().decode(errors="replace")
+
+
+def _check(st):
+    if st < 0:
+        raise TnError(st, tn_last_error())
+    return st
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ------------------------------------------------------------------ context
+
+def tn_ctx_create(arena_ptr: int, arena_bytes: int, stream_ptr: int = 0, flags: int = 0):
+    out = ctypes.c_void_p()
+    _check(load().tn_ctx_create(ctypes.c_void_p(arena_ptr), arena_bytes,
+                                ctypes.c_void_p(stream_ptr), flags, ctypes.byref(out)))
+    return out.value
+
+
+def tn_ctx_destroy(ctx):
+    _check(load().tn_ctx_destroy(ctypes.c_void_p(ctx)))
+
+
+# -------------------------------------------------------------------- plans
+
+def tn_plan_load(ctx, legs, dims, tensors, partition_of, num_partitions, tree,
+                 output_legs=None, flags: int = 0, data_dtype: int = TN_C128):
+    """legs: list of label lists; dims: label -> dimension; tensors: arrays in
+    leg order; tree: SSA pairs.  ctx None loads a host-only plan."""
+    nv = len(legs)
+    rank = np.array([len(l) for l in legs], dtype=np.int32)
+    lab = np.array([x for l in legs for x in l] or [0], dtype=np.int64)
+    ld = np.array([dims[x] for l in legs for x in l] or [1], dtype=np.int64)
+    npdt = np.complex128 if data_dtype == TN_C128 else np.complex64
+    arrs = [np.ascontiguousarray(t, dtype=npdt) for t in tensors]
+    ptrs = (ctypes.c_void_p * max(1, nv))(*[a.ctypes.data for a in arrs])
+    po = np.ascontiguousarray(partition_of, dtype=np.int32)
+    tr = np.array([x for pr in tree for x in pr] or [0], dtype=np.int32)
+    ol = np.array(list(output_legs or []) or [0], dtype=np.int64)
+    d = tn_plan_desc(nv, _p(rank).value, _p(lab).value, _p(ld).value,
+                     ctypes.cast(ptrs, ctypes.c_void_p).value, data_dtype, _p(po).value,
+                     num_partitions, _p(tr).value,
+                     _p(ol).value if output_legs else None, len(output_legs or []))
+    out = ctypes.c_void_p()
+    _check(load().tn_plan_load(ctypes.c_void_p(ctx) if ctx else None, ctypes.byref(d), flags,
+                               ctypes.byref(out)))
+    return out.value
+
+
+def _u128(a):
+    return (int(a[0]) << 64) | int(a[1])
+
+
+def tn_plan_costs_get(plan) -> dict:
+    c = tn_plan_costs()
+    _check(load().tn_plan_costs_get(ctypes.c_void_p(plan), ctypes.byref(c)))
+    return dict(con_serial=_u128(c.con_serial), con_par=_u128(c.con_par),
+                con_dist=_u128(c.con_dist), mem=_u128(c.mem_elems),
+                live_peak_bytes=int(c.live_peak_bytes),
+                largest_intermediate=int(c.largest_intermediate_elems),
+                num_internal_nodes=c.num_internal_nodes, num_gemm_nodes=c.num_gemm_nodes,
+                num_tiny_nodes=c.num_tiny_nodes, num_stream_nodes=c.num_stream_nodes,
+                num_permutations=c.num_permutations)
+
+
+def tn_plan_free(plan):
+    _check(load().tn_plan_free(ctypes.c_void_p(plan)))
+
+
+# -------------------------------------------------------------- contraction
+
+def _leaves(overrides):
+    keep = []
+    arr = (tn_leaf * max(1, len(overrides)))()
+    for i, (t, data) in enumerate(sorted(overrides.items())):
+        a = np.ascontiguousarray(data, dtype=np.complex128)
+        keep.append(a)
+        arr[i] = tn_leaf(int(t), a.ctypes.data, TN_C128)
+    return arr, keep
+
+
+def tn_contract(plan, overrides=None, result_shape=(), out_dtype=TN_C128, flags=0):
+    """Returns (result array, log2 scale)."""
+    overrides = overrides or {}
+    arr, keep = _leaves(overrides)
+    out = np.zeros(result_shape, dtype=np.complex128 if out_dtype == TN_C128 else np.complex64)
+    out = np.ascontiguousarray(out)
+    l2 = ctypes.c_double(0.0)
+    _check(load().tn_contract(ctypes.c_void_p(plan), len(overrides), ctypes.cast(arr, ctypes.c_void_p),
+                              _p(out), out_dtype, ctypes.byref(l2), flags))
+    return out, l2.value
+
+
+def tn_contract_batch(ctx, queries, result_shapes, out_dtype=TN_C128, flags=0):
+    """queries: list of (plan, overrides dict).  Returns (results, log2 scales,
+    per-query statuses)."""
+    n = len(queries)
+    qarr = (tn_query * max(1, n))()
+    keep = []
+    outs = []
+    for i, (plan, ovr) in enumerate(queries):
+        arr, k = _leaves(ovr or {})
+        keep.append((arr, k))
+        qarr[i] = tn_query(plan, len(ovr or {}), ctypes.cast(arr, ctypes.c_void_p).value)
+        outs.append(np.zeros(result_shapes[i], dtype=np.complex128 if out_dtype == TN_C128
+                             else np.complex64))
+    optrs = (ctypes.c_void_p * max(1, n))(*[o.ctypes.data for o in outs])
+    l2 = np.zeros(max(1, n), dtype=np.float64)
+    st = np.zeros(max(1, n), dtype=np.int32)
+    _check(load().tn_contract_batch(ctypes.c_void_p(ctx), n, ctypes.cast(qarr, ctypes.c_void_p),
+                                    ctypes.cast(optrs, ctypes.c_void_p), out_dtype, _p(l2), _p(st),
+                                    flags))
+    return outs, l2[:n], st[:n]
+
+
+def tn_serve_submit(ctx, plan, overrides=None) -> int:
+    overrides = overrides or {}
+    arr, keep = _leaves(overrides)
+    q = tn_query(plan, len(overrides), ctypes.cast(arr, ctypes.c_void_p).value)
+    t = ctypes.c_uint64()
+    _check(load().tn_serve_submit(ctypes.c_void_p(ctx), ctypes.byref(q), ctypes.byref(t)))
+    return t.value
+
+
+def tn_serve_poll(ctx, ticket, result_shape=(), out_dtype=TN_C128):
+    """Returns (status, result or None, log2 scale, latency seconds)."""
+    out = np.zeros(result_shape, dtype=np.complex128 if out_dtype == TN_C128 else np.complex64)
+    l2 = ctypes.c_double(0.0)
+    lat = ctypes.c_double(0.0)
+    st = load().tn_serve_poll(ctypes.c_void_p(ctx), ctypes.c_uint64(ticket), _p(out), out_dtype,
+                              ctypes.byref(l2), ctypes.byref(lat))
+    if st < 0:
+        raise TnError(st, tn_last_error())
+    return st, (out if st == TN_OK else None), l2.value, lat.value
+
+
+# --------------------------------------------------------- torch plumbing
+
+class Context:
+    """A libtn context whose arena is a torch uint8 device tensor and whose
+    stream is torch's current stream on `device`."""
+
+    def __init__(self, arena_bytes: int, device: str = "cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libtn needs a GPU; torch.cuda.is_available() is False")
+        load()
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.handle = tn_ctx_create(self.arena.data_ptr(), arena_bytes, self.stream.cuda_stream)
+        self.plans = []
+
+    def load_network(self, net, partition_of, num_partitions, tree, flags=0):
+        p = tn_plan_load(self.handle, net.legs, net.dims, net.tensors, partition_of,
+                         num_partitions, tree, net.output_legs or None, flags)
+        self.plans.append(p)
+        return p
+
+    def free_plan(self, p):
+        tn_plan_free(p)
+        self.plans.remove(p)
+
+    def close(self):
+        for p in list(self.plans):
+            tn_plan_free(p)
+        self.plans = []
+        if self.handle:
+            tn_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
