@@ -1,0 +1,257 @@
+"""Throughput of partitioned tensor-network contraction on one MI355X.
+
+Workload (default): the 20-qubit brickwork circuit of depth 14 (CZ brick
+layers alternating with RX/RZ rotation layers, seed 0), one closed network per
+output bitstring, 4 partitions refined by simulated annealing.  One step
+contracts a batch of `--queries` amplitude queries (random bitstrings) through
+the whole path: leaf overrides, every partition's tree in turn, the reduction
+path and the FP64 final contraction.  The overrides of all steps are placed in
+device memory before the timed region.
+
+Printed: one JSON line with amplitudes/s of the batched path (`value`), the
+plain per-query path (tn_contract, one query at a time) for the same
+workload, effective complex TFLOP/s (8 * con_serial per amplitude), the
+roofline position of the dominant kernel class (event-timed inside this run)
+and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--queries 4096]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "amplitudes/s + effective complex TFLOP/s vs plain FP32 path; serve p50/p99"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(args):
+    from paper_2507_20667_amd.inputs import amplitude_network, brickwork_circuit
+    from paper_2507_20667_amd.planner import SAConfig, simulated_annealing
+    from paper_2507_20667_amd.planner.plan import tree_partition
+    circ = brickwork_circuit(20, 14, 0)
+    net = amplitude_network(circ, 0)
+    t0 = time.perf_counter()
+    init = tree_partition(net.legs, net.dims, 4)
+    plan = simulated_annealing(net.legs, net.dims, init, 4,
+                               SAConfig(iterations=20, n_steps=32, workers=4, rg_samples=8, seed=0))
+    return circ, net, plan, time.perf_counter() - t0
+
+
+def device_overrides(torch, net, n, bitstrings):
+    """(queries, n, 2) complex64 basis vectors on the device, output qubit
+    order; returns the tensor and per-query tn_leaf arrays pointing into it."""
+    from paper_2507_20667_amd import lib
+    from paper_2507_20667_amd.inputs import output_tensor_ids
+    ids = output_tensor_ids(net)
+    Q = len(bitstrings)
+    bits = np.array([[(x >> q) & 1 for q in range(n)] for x in bitstrings], dtype=np.int64)
+    host = np.zeros((Q, n, 2), dtype=np.complex64)
+    host[np.arange(Q)[:, None], np.arange(n)[None, :], bits] = 1.0
+    dev = torch.from_numpy(host).to("cuda")
+    base = dev.data_ptr()
+    leaves = []
+    for qi in range(Q):
+        arr = (lib.tn_leaf * n)()
+        for i, t in enumerate(ids):
+            arr[i] = lib.tn_leaf(t, base + ((qi * n + i) * 2) * 8, lib.TN_C64_DEVICE)
+        leaves.append(arr)
+    return dev, leaves
+
+
+def batch_call(lib, ctx, plan, leaves, n):
+    Q = len(leaves)
+    qarr = (lib.tn_query * Q)()
+    for i, arr in enumerate(leaves):
+        qarr[i] = lib.tn_query(plan, n, ctypes.cast(arr, ctypes.c_void_p).value)
+    outs = np.zeros((Q, 2), dtype=np.float64)
+    optrs = (ctypes.c_void_p * Q)(*[outs.ctypes.data + 16 * i for i in range(Q)])
+    st = np.zeros(Q, dtype=np.int32)
+
+    def call():
+        rc = lib.load().tn_contract_batch(ctypes.c_void_p(ctx), Q, ctypes.cast(qarr, ctypes.c_void_p),
+                                          ctypes.cast(optrs, ctypes.c_void_p), lib.TN_C128, None,
+                                          st.ctypes.data_as(ctypes.c_void_p), 0)
+        if rc != 0:
+            raise lib.TnError(rc, lib.tn_last_error())
+        return outs
+    return call
+
+
+def cpu_baseline(net, plan, circ, budget_s):
+    import oracle
+    from paper_2507_20667_amd.inputs import amplitude_overrides, random_bitstrings
+    threads = oracle.default_threads()
+    xs = random_bitstrings(circ.n, 100000, 99)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and done < len(xs):
+        ovr = amplitude_overrides(net, circ, xs[done])
+        oracle.contract_tree(net.legs, net.dims, net.copy_with(ovr).tensors, plan.tree,
+                             nthreads=threads)
+        done += 1
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="amplitudes/s", cores=threads, kind="oracle",
+                sample=f"{done} amplitudes of the same 20-qubit brickwork network and plan, "
+                       f"complex128 loop-nest contraction, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--queries", type=int, default=4096)
+    ap.add_argument("--plain-queries", type=int, default=64)
+    ap.add_argument("--prec", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--form", choices=["4m", "3m"], default="4m")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}, WORLD_SIZE={world}): "
+              "this build measures a single MI355X; see DESIGN.md for how the path shards.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_20667_amd import lib
+    import oracle
+    from paper_2507_20667_amd.inputs import amplitude_overrides, random_bitstrings
+
+    circ, net, plan, plan_s = make_workload(args)
+    n = circ.n
+    log(f"planned in {plan_s:.1f}s: {plan.meta.get('con_dist')}")
+    flags = (lib.TN_PREC_BF16X3 if args.prec == "bf16x3" else 0) | \
+            (lib.TN_FORM_3M if args.form == "3m" else 0)
+    ctx = lib.Context(16 << 30)
+    p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 4, plan.tree, None, flags)
+    costs = lib.tn_plan_costs_get(p)
+    con_serial = costs["con_serial"]
+    Q, K, W = args.queries, args.steps, args.warmup
+    steps_bits = [random_bitstrings(n, Q, 1000 + s) for s in range(K + W)]
+    devs, calls = [], []
+    for s in range(K + W):
+        dev, leaves = device_overrides(torch, net, n, steps_bits[s])
+        devs.append((dev, leaves))
+        calls.append(batch_call(lib, ctx.handle, p, leaves, n))
+    torch.cuda.synchronize()
+
+    # parity spot check outside the timed region
+    res = calls[0]()
+    errs = []
+    for qi in range(0, Q, max(1, Q // 8)):
+        x = steps_bits[0][qi]
+        ovr = amplitude_overrides(net, circ, x)
+        ref = complex(oracle.contract_tree(net.legs, net.dims, net.copy_with(ovr).tensors,
+                                           plan.tree))
+        got = complex(res[qi, 0], res[qi, 1])
+        errs.append(abs(got - ref) / max(abs(ref), 2.0 ** (-n / 2)))
+    max_err = max(errs)
+    log(f"spot-check max relative error {max_err:.2e}")
+
+    for s in range(W):
+        calls[s]()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(W, W + K):
+        calls[s]()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    amps = Q * K / dt
+    eff_tflops = 8.0 * con_serial * Q * K / dt / 1e12
+
+    # plain path: tn_contract, one query at a time, device-resident overrides
+    dev0, leaves0 = devs[W]
+    P = min(args.plain_queries, Q)
+    plain_out = np.zeros(2, dtype=np.float64)
+    l2 = ctypes.c_double()
+    L = lib.load()
+    for qi in range(min(3, P)):
+        L.tn_contract(ctypes.c_void_p(p), n, ctypes.cast(leaves0[qi], ctypes.c_void_p),
+                      plain_out.ctypes.data_as(ctypes.c_void_p), lib.TN_C128, ctypes.byref(l2), 0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for qi in range(P):
+        rc = L.tn_contract(ctypes.c_void_p(p), n, ctypes.cast(leaves0[qi], ctypes.c_void_p),
+                           plain_out.ctypes.data_as(ctypes.c_void_p), lib.TN_C128,
+                           ctypes.byref(l2), 0)
+        assert rc == 0, lib.tn_last_error()
+    torch.cuda.synchronize()
+    plain_amps = P / (time.perf_counter() - t1)
+
+    # event-timed kernel classes over the same steps
+    lib.tn_profile_enable(ctx.handle, True)
+    lib.tn_profile_read(ctx.handle, reset=True)
+    for s in range(W, W + K):
+        calls[s]()
+    lib.tn_profile_enable(ctx.handle, False)
+    stats = lib.tn_profile_read(ctx.handle, reset=True)
+    dom = max(stats, key=lambda k: stats[k]["seconds"])
+    ds = stats[dom]
+    if dom == "gemm":
+        achieved = ds["algo_flops"] / ds["seconds"] / 1e12
+        roof = dict(bound="mfma", achieved=achieved, peak=MFMA_PEAK_TFLOPS[args.prec],
+                    unit="TFLOP/s", frac=achieved / MFMA_PEAK_TFLOPS[args.prec], traffic=None)
+    else:
+        achieved = ds["algo_bytes"] / ds["seconds"] / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=None)
+    roof["kernel_class"] = dom
+    roof["launches"] = ds["launches"]
+    roof["avg_launch_us"] = ds["seconds"] / max(ds["launches"], 1) * 1e6
+    roof["algo_bytes_per_launch"] = ds["algo_bytes"] / max(ds["launches"], 1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(net, plan, circ, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": amps,
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": dt / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "brickwork 20 qubits depth 14 seed 0, single-amplitude networks "
+                               f"(247 tensors), 4 SA partitions, {Q} bitstrings per step",
+                   "form": args.form, "queries_per_step": Q,
+                   "con_serial": con_serial, "con_dist": costs["con_dist"],
+                   "largest_intermediate": costs["largest_intermediate"]},
+        "effective_tflops": eff_tflops,
+        "plain_amplitudes_per_s": plain_amps,
+        "speedup_vs_plain": amps / plain_amps,
+        "max_rel_err": max_err,
+        "planning_s": plan_s,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},
+    }
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -61,7 +61,12 @@ enum {
   TN_E_UNKNOWN_TICKET = -7     /* serve ticket never issued or already consumed */
 };
 
-typedef enum { TN_C64 = 0, TN_C128 = 1 } tn_dtype;
+/* TN_C64_DEVICE is accepted for leaf overrides only: complex64 data already in
+ * device memory.  When, within one call, the overrides of a leaf are evenly
+ * spaced in memory from query to query, the kernels read them in place;
+ * otherwise they are copied device to device.  Such data must stay valid
+ * until the call returns (for serving: until the request is polled). */
+typedef enum { TN_C64 = 0, TN_C128 = 1, TN_C64_DEVICE = 2 } tn_dtype;
 
 /* flags of tn_plan_load (precision and GEMM form) and of tn_contract* */
 enum {
@@ -217,6 +222,35 @@ tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *qu
 tn_status tn_serve_submit(tn_ctx *ctx, const tn_query *query, uint64_t *ticket);
 tn_status tn_serve_poll(tn_ctx *ctx, uint64_t ticket, void *out, tn_dtype out_dtype,
                         double *log2_scale, double *latency_s);
+
+/*
+ * Kernel timing.  While enabled, every launch of the classes below is
+ * bracketed by HIP events on the context's stream, and its algorithmic
+ * traffic and work are accumulated (per tree vertex instance: 8 bytes per
+ * complex64 entry of each operand and of the result, 16 bytes per entry moved
+ * by a permutation; 8 * 2^vc real flops, the 4M count, per contraction).
+ * The figures are collected when a contraction call synchronizes.
+ * tn_profile_read copies TN_KCLASS_COUNT records and, with reset != 0,
+ * clears them.  Timing adds two event records per launch; measure throughput
+ * with it disabled.
+ */
+enum {
+  TN_KCLASS_STREAM = 0,   /* small-operand contraction */
+  TN_KCLASS_PERMUTE = 1,  /* leg permutation */
+  TN_KCLASS_GEMM = 2,     /* complex GEMM */
+  TN_KCLASS_DOT = 3,      /* FP64 inner product */
+  TN_KCLASS_TREE = 4,     /* whole small subtrees in one workgroup */
+  TN_KCLASS_COUNT = 5
+};
+typedef struct {
+  uint64_t launches;
+  double seconds;     /* sum of event-measured launch durations */
+  double algo_bytes;  /* algorithmic HBM bytes */
+  double algo_flops;  /* algorithmic real flops */
+} tn_kernel_stats;
+
+tn_status tn_profile_enable(tn_ctx *ctx, int enable);
+tn_status tn_profile_read(tn_ctx *ctx, tn_kernel_stats *out, int reset);
 
 #ifdef __cplusplus
 }

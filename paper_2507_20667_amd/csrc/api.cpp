@@ -44,7 +44,29 @@ tn_status tn_ctx_destroy(tn_ctx *ctx) {
   }
   hipStreamSynchronize(ctx->stream);
   if (ctx->pinned) hipHostFree(ctx->pinned);
+  ctx->prof.destroy();
   delete ctx;
+  return TN_OK;
+}
+
+tn_status tn_profile_enable(tn_ctx *ctx, int enable) {
+  if (!ctx) {
+    set_error("tn_profile_enable: NULL context");
+    return TN_E_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> g(ctx->exec_mu);
+  ctx->prof.on = enable != 0;
+  return TN_OK;
+}
+
+tn_status tn_profile_read(tn_ctx *ctx, tn_kernel_stats *out, int reset) {
+  if (!ctx || !out) {
+    set_error("tn_profile_read: NULL argument");
+    return TN_E_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> g(ctx->exec_mu);
+  memcpy(out, ctx->prof.stats, sizeof(ctx->prof.stats));
+  if (reset) memset(ctx->prof.stats, 0, sizeof(ctx->prof.stats));
   return TN_OK;
 }
 

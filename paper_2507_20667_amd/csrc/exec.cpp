@@ -78,7 +78,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     }
     for (int i = 0; i < q.novr; ++i) {
       const tn_leaf &l = q.ovr[i];
-      if (l.tensor < 0 || l.tensor >= nv || !l.data || (l.dtype != TN_C64 && l.dtype != TN_C128)) {
+      if (l.tensor < 0 || l.tensor >= nv || !l.data || (l.dtype != TN_C64 && l.dtype != TN_C128 && l.dtype != TN_C64_DEVICE)) {
         set_error("override %d: tensor id out of range, NULL data or bad dtype", i);
         return TN_E_INVALID_ARG;
       }
@@ -89,6 +89,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   ovr.erase(std::unique(ovr.begin(), ovr.end()), ovr.end());
   std::shared_ptr<ExecLayout> Lp = cached_layout(p, ovr, share);
   const ExecLayout &L = *Lp;
+  Profiler &prof = ctx->prof;
 
   // per-query override block: leaves in `ovr` order
   std::vector<int64_t> ovr_off(nv, -1);
@@ -153,10 +154,17 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     const int64_t perq_el = (int64_t)(perq / 8), perq_sl = (int64_t)nn;
     const int64_t ovr_el = (int64_t)(ovr_bytes / 8);
 
+    std::vector<const float2 *> direct_p(nv, nullptr);
+    std::vector<int64_t> direct_bs(nv, 0);
     auto operand = [&](int t) -> Operand {
       Operand o2;
       if (t < nv) {
-        if (ovr_off[t] >= 0) {
+        if (direct_p[t]) {
+          o2.p = direct_p[t];
+          o2.bs = direct_bs[t];
+          o2.slot = slots_q + t;
+          o2.sbs = perq_sl;
+        } else if (ovr_off[t] >= 0) {
           o2.p = (const float2 *)(ovr_base + ovr_off[t]);
           o2.bs = ovr_el;
           o2.slot = slots_q + t;
@@ -191,36 +199,90 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     };
 
     {
-      // stage overrides (complex64) for every query of the chunk
+      // stage overrides (complex64) for every query of the chunk.  Device-
+      // resident overrides evenly spaced across the chunk are read in place.
       if (ovr_bytes) {
-        rc = ensure_pinned(ctx, ovr_bytes * Q);
-        if (rc) goto done;
-        uint8_t *h = (uint8_t *)ctx->pinned;
+        const size_t no = ovr.size();
+        std::vector<const tn_leaf *> src((size_t)Q * no, nullptr);
         for (int qi = 0; qi < Q; ++qi) {
           const QueryIO &q = qs[q0 + qi];
-          for (int t : ovr) {
-            float2 *dst = (float2 *)(h + (size_t)qi * ovr_bytes + ovr_off[t]);
-            const int64_t n = p->leaf[t].size();
-            const tn_leaf *src = nullptr;
-            for (int i = 0; i < q.novr; ++i)
-              if (q.ovr[i].tensor == t) src = &q.ovr[i];
-            if (src)
-              to_c64(*src, n, dst);
-            else
-              memcpy(dst, p->leaf_host.data() + p->leaf_off[t], sizeof(float2) * n);
+          for (int i = 0; i < q.novr; ++i) {
+            const size_t k = std::lower_bound(ovr.begin(), ovr.end(), q.ovr[i].tensor) - ovr.begin();
+            src[(size_t)qi * no + k] = &q.ovr[i];
           }
         }
-        TN_HIP(hipMemcpyAsync(ovr_base, h, ovr_bytes * Q, hipMemcpyHostToDevice, st),
-               "override upload");
+        bool any_staged = false;
+        for (size_t k = 0; k < no; ++k) {
+          const int t = ovr[k];
+          bool dev = true;
+          for (int qi = 0; qi < Q && dev; ++qi) {
+            const tn_leaf *s = src[(size_t)qi * no + k];
+            dev = s && s->dtype == TN_C64_DEVICE;
+          }
+          int64_t stride = 0;
+          if (dev && Q > 1) {
+            const char *b0 = (const char *)src[k]->data;
+            stride = (const char *)src[no + k]->data - b0;
+            for (int qi = 2; qi < Q && dev; ++qi)
+              dev = (const char *)src[(size_t)qi * no + k]->data - b0 == stride * qi;
+            dev = dev && stride % 8 == 0;
+          }
+          if (dev) {
+            direct_p[t] = (const float2 *)src[k]->data;
+            direct_bs[t] = stride / 8;
+          } else {
+            direct_p[t] = nullptr;
+            any_staged = true;
+          }
+        }
+        if (any_staged) {
+          rc = ensure_pinned(ctx, ovr_bytes * Q);
+          if (rc) goto done;
+          uint8_t *h = (uint8_t *)ctx->pinned;
+          for (int qi = 0; qi < Q; ++qi)
+            for (size_t k = 0; k < no; ++k) {
+              const int t = ovr[k];
+              if (direct_p[t]) continue;
+              const tn_leaf *s = src[(size_t)qi * no + k];
+              float2 *dst = (float2 *)(h + (size_t)qi * ovr_bytes + ovr_off[t]);
+              const int64_t n = p->leaf[t].size();
+              if (s && s->dtype != TN_C64_DEVICE)
+                to_c64(*s, n, dst);
+              else if (!s)
+                memcpy(dst, p->leaf_host.data() + p->leaf_off[t], sizeof(float2) * n);
+            }
+          TN_HIP(hipMemcpyAsync(ovr_base, h, ovr_bytes * Q, hipMemcpyHostToDevice, st),
+                 "override upload");
+          for (int qi = 0; qi < Q; ++qi)
+            for (size_t k = 0; k < no; ++k) {
+              const int t = ovr[k];
+              const tn_leaf *s = src[(size_t)qi * no + k];
+              if (direct_p[t] || !s || s->dtype != TN_C64_DEVICE) continue;
+              TN_HIP(hipMemcpyAsync(ovr_base + (size_t)qi * ovr_bytes + ovr_off[t], s->data,
+                                    p->leaf[t].size() * 8, hipMemcpyDeviceToDevice, st),
+                     "device override copy");
+            }
+        }
       }
       TN_HIP(launch_init_slots(st, slots, (int64_t)nn * (Q + 1)), "slot init");
       for (int j : p->order) {
         const Node &n = p->nodes[j];
         const bool sh = L.shared[n.id] != 0;
         const int nb = sh ? 1 : Q;
+        const double wflops = 8.0 * (double)n.weight * nb;
+        const double c1b = 8.0 * (double)(n.c1 < nv ? p->leaf[n.c1].size()
+                                                    : p->nodes[n.c1 - nv].out.size());
+        const double c2b = 8.0 * (double)(n.c2 < nv ? p->leaf[n.c2].size()
+                                                    : p->nodes[n.c2 - nv].out.size());
+        const double nodeb = (c1b + c2b + 8.0 * (double)std::max<int64_t>(n.out.size(), 1)) * nb;
         if (n.kind == NK_STREAM) {
-          TN_HIP(launch_stream(st, (const StreamDesc *)(desc_base + n.sdesc_off), n.nfib, n.ns,
-                               operand(n.x), operand(n.y), outop(n.id), nb),
+          TN_HIP(prof.timed(st, TN_KCLASS_STREAM, nodeb, wflops,
+                            [&] {
+                              return launch_stream(st,
+                                                   (const StreamDesc *)(desc_base + n.sdesc_off),
+                                                   n.nfib, n.ns, operand(n.x), operand(n.y),
+                                                   outop(n.id), nb);
+                            }),
                  "stream contraction");
         } else if (n.kind == NK_GEMM) {
           Operand A = operand(n.ga), B = operand(n.gb);
@@ -228,16 +290,24 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           const int64_t pst = sh ? 0 : perq_el;
           if (n.pa.needed) {
             float2 *dst = (float2 *)(pbase + L.scr_a[j]);
-            TN_HIP(launch_permute(st, (const PermDesc *)(desc_base + n.pa.desc_off), n.pa.h, A.p,
-                                  A.bs, dst, pst, nb),
+            TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, 16.0 * n.pa.h.nelem * nb, 0.0,
+                              [&] {
+                                return launch_permute(
+                                    st, (const PermDesc *)(desc_base + n.pa.desc_off), n.pa.h,
+                                    A.p, A.bs, dst, pst, nb);
+                              }),
                    "permute A");
             A.p = dst;
             A.bs = pst;
           }
           if (n.pb.needed) {
             float2 *dst = (float2 *)(pbase + L.scr_b[j]);
-            TN_HIP(launch_permute(st, (const PermDesc *)(desc_base + n.pb.desc_off), n.pb.h, B.p,
-                                  B.bs, dst, pst, nb),
+            TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, 16.0 * n.pb.h.nelem * nb, 0.0,
+                              [&] {
+                                return launch_permute(
+                                    st, (const PermDesc *)(desc_base + n.pb.desc_off), n.pb.h,
+                                    B.p, B.bs, dst, pst, nb);
+                              }),
                    "permute B");
             B.p = dst;
             B.bs = pst;
@@ -267,22 +337,33 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           g.opB = n.opB;
           const int prec = (p->flags & TN_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
           const int form = (p->flags & TN_FORM_3M) ? kForm3M : kForm4M;
-          TN_HIP(launch_gemm(st, g, prec, form, n.variant, nb), "complex GEMM");
+          TN_HIP(prof.timed(st, TN_KCLASS_GEMM, nodeb, wflops,
+                            [&] { return launch_gemm(st, g, prec, form, n.variant, nb); }),
+                 "complex GEMM");
         } else {
           const bool is_root = n.id == p->root;
-          TN_HIP(launch_dot(st, (const DotDesc *)(desc_base + n.ddesc_off), n.nelem, operand(n.c1),
-                            operand(n.c2), outop(n.id), is_root ? res : nullptr, 1, partials,
-                            n.dot_blocks, nb),
+          TN_HIP(prof.timed(st, TN_KCLASS_DOT, nodeb, wflops,
+                            [&] {
+                              return launch_dot(st, (const DotDesc *)(desc_base + n.ddesc_off),
+                                                n.nelem, operand(n.c1), operand(n.c2), outop(n.id),
+                                                is_root ? res : nullptr, 1, partials,
+                                                n.dot_blocks, nb);
+                            }),
                  "dot");
         }
       }
       // result into output-leg order
       const Operand R = operand(p->root);
-      if (p->fperm.needed)
-        TN_HIP(launch_permute(st, (const PermDesc *)(desc_base + p->fperm.desc_off), p->fperm.h,
-                              R.p, R.bs, fin, (int64_t)(final_bytes / 8),
-                              L.shared[p->root] ? 1 : Q),
+      if (p->fperm.needed) {
+        const int nbf = L.shared[p->root] ? 1 : Q;
+        TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, 16.0 * p->fperm.h.nelem * nbf, 0.0,
+                          [&] {
+                            return launch_permute(
+                                st, (const PermDesc *)(desc_base + p->fperm.desc_off), p->fperm.h,
+                                R.p, R.bs, fin, (int64_t)(final_bytes / 8), nbf);
+                          }),
                "output permutation");
+      }
       // read back
       const bool root_shared = L.shared[p->root] != 0;
       const bool dot_root = nv > 1 && p->nodes[p->root - nv].kind == NK_DOT;
@@ -312,6 +393,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                "scale copy");
       }
       TN_HIP(hipStreamSynchronize(st), "stream synchronize");
+      if (prof.on) prof.collect();
       for (int qi = 0; qi < Q; ++qi) {
         const QueryIO &q = qs[q0 + qi];
         const bool keep = (flags & TN_FLAG_KEEP_SCALE) != 0;
@@ -342,6 +424,11 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       }
     }
   done:
+    if (rc != TN_OK) {
+      hipStreamSynchronize(st);
+      prof.pend.clear();
+      prof.used = 0;
+    }
     ctx->arena.release(ws, total);
   }
   return rc;

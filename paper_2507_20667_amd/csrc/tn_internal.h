@@ -172,6 +172,61 @@ class Arena {
 
 struct ServeState;  // serve.cpp
 
+// Event timing of kernel launches by class (tn_profile_enable).
+struct Profiler {
+  bool on = false;
+  tn_kernel_stats stats[TN_KCLASS_COUNT] = {};
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Pending> pend;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  template <typename F>
+  hipError_t timed(hipStream_t st, int cls, double bytes, double flops, F &&launch) {
+    if (!on) return launch();
+    Pending p{cls, get(), nullptr, bytes, flops};
+    if (p.a) hipEventRecord(p.a, st);
+    hipError_t e = launch();
+    p.b = get();
+    if (p.a && p.b) {
+      hipEventRecord(p.b, st);
+      pend.push_back(p);
+    }
+    return e;
+  }
+  // after the stream has synchronized
+  void collect() {
+    for (const Pending &p : pend) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        stats[p.cls].launches += 1;
+        stats[p.cls].seconds += ms * 1e-3;
+        stats[p.cls].algo_bytes += p.bytes;
+        stats[p.cls].algo_flops += p.flops;
+      }
+    }
+    pend.clear();
+    used = 0;
+  }
+  void destroy() {
+    for (hipEvent_t e : pool) hipEventDestroy(e);
+    pool.clear();
+    pend.clear();
+    used = 0;
+  }
+};
+
 }  // namespace tn
 
 struct tn_ctx {
@@ -185,6 +240,7 @@ struct tn_ctx {
   size_t pinned_bytes = 0;
   tn::ServeState *serve = nullptr;
   std::mutex serve_init_mu;
+  tn::Profiler prof;
 };
 
 struct tn_plan {

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libtn.so")
 TN_OK, TN_PENDING = 0, 1
 TN_E_INVALID_ARG, TN_E_INVALID_PLAN, TN_E_NOMEM, TN_E_DEVICE = -1, -2, -3, -4
 TN_E_AGAIN, TN_E_CANCELLED, TN_E_UNKNOWN_TICKET = -5, -6, -7
-TN_C64, TN_C128 = 0, 1
+TN_C64, TN_C128, TN_C64_DEVICE = 0, 1, 2
 TN_PREC_FP32, TN_PREC_BF16X3 = 0, 1
 TN_FORM_4M, TN_FORM_3M = 0, 1 << 4
 TN_FLAG_KEEP_SCALE = 1 << 8
@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "TN_OK", 1: "TN_PENDING", -1: "TN_E_INVALID_ARG", -2: "TN_E_I
 
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_last_error", "tn_plan_load",
             "tn_plan_costs_get", "tn_plan_free", "tn_contract", "tn_contract_batch",
-            "tn_serve_submit", "tn_serve_poll"]
+            "tn_serve_submit", "tn_serve_poll", "tn_profile_enable", "tn_profile_read"]
 
 
 class TnError(RuntimeError):
@@ -268,6 +268,13 @@ class Context:
         self.plans.append(p)
         return p
 
+    def plan_load(self, legs, dims, tensors, partition_of, num_partitions, tree,
+                  output_legs=None, flags=0, data_dtype=TN_C128):
+        p = tn_plan_load(self.handle, legs, dims, tensors, partition_of, num_partitions, tree,
+                         output_legs, flags, data_dtype)
+        self.plans.append(p)
+        return p
+
     def free_plan(self, p):
         tn_plan_free(p)
         self.plans.remove(p)
@@ -285,3 +292,31 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ------------------------------------------------------------------ timing
+
+KCLASS_NAMES = ["stream", "permute", "gemm", "dot", "tree"]
+
+
+class tn_kernel_stats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
+                ("algo_bytes", ctypes.c_double), ("algo_flops", ctypes.c_double)]
+
+
+def tn_profile_enable(ctx, enable=True):
+    f = load().tn_profile_enable
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    f.restype = ctypes.c_int32
+    _check(f(ctypes.c_void_p(ctx), 1 if enable else 0))
+
+
+def tn_profile_read(ctx, reset=True) -> dict:
+    f = load().tn_profile_read
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    f.restype = ctypes.c_int32
+    arr = (tn_kernel_stats * len(KCLASS_NAMES))()
+    _check(f(ctypes.c_void_p(ctx), ctypes.cast(arr, ctypes.c_void_p), 1 if reset else 0))
+    return {KCLASS_NAMES[i]: dict(launches=int(arr[i].launches), seconds=arr[i].seconds,
+                                  algo_bytes=arr[i].algo_bytes, algo_flops=arr[i].algo_flops)
+            for i in range(len(KCLASS_NAMES))}

@@ -34,8 +34,12 @@ def ctx():
     c.close()
 
 
+def _c(x):
+    return complex(np.asarray(x).reshape(-1)[0])
+
+
 def amp_err(a, ref, n):
-    return abs(complex(a) - complex(ref)) / max(abs(complex(ref)), 2.0 ** (-n / 2))
+    return abs(_c(a) - _c(ref)) / max(abs(_c(ref)), 2.0 ** (-n / 2))
 
 
 def test_config1_phase_polynomial_amplitudes(ctx):
@@ -91,8 +95,7 @@ def test_gemm_heavy_circuit(ctx, form):
     circ = random_circuit(18, 12, 7)
     net = amplitude_network(circ, 0)
     plan = _plan_sa(net, 4, iters=3)
-    p = lib.tn_plan_load(ctx.handle, net.legs, net.dims, net.tensors, plan.partition_of, 4,
-                         plan.tree, None, form)
+    p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 4, plan.tree, None, form)
     costs = lib.tn_plan_costs_get(p)
     print("gemm nodes", costs["num_gemm_nodes"], "perms", costs["num_permutations"],
           "largest", costs["largest_intermediate"])
@@ -102,7 +105,7 @@ def test_gemm_heavy_circuit(ctx, form):
         got, _ = lib.tn_contract(p, ovr)
         ref = oracle.contract_tree(net.legs, net.dims, net.copy_with(ovr).tensors, plan.tree)
         assert amp_err(got, ref, 18) < FP32_TOL, (x, got, ref)
-    lib.tn_plan_free(p)
+    ctx.free_plan(p)
 
 
 def _random_net(rng, nv, dims_choice, n_open):
@@ -144,13 +147,13 @@ def test_random_networks_general_dims(ctx, seed, dims_choice, n_open):
     part = tree_partition(legs, dims, k)
     plan = plan_from_partition(legs, dims, part, k)
     ref = oracle.contract_tree(legs, dims, ts, plan.tree, opens)
-    p = lib.tn_plan_load(ctx.handle, legs, dims, ts, plan.partition_of, k, plan.tree, opens or None)
+    p = ctx.plan_load(legs, dims, ts, plan.partition_of, k, plan.tree, opens or None)
     got, _ = lib.tn_contract(p, result_shape=ref.shape)
     scale = float(np.max(np.abs(ref))) or 1.0
     kmax = max(lib.tn_plan_costs_get(p)["con_serial"], 1)
     tol = 64 * 2.0 ** -24 * math.sqrt(kmax)
     assert np.max(np.abs(got - ref)) / scale < tol
-    lib.tn_plan_free(p)
+    ctx.free_plan(p)
 
 
 @pytest.mark.parametrize("shape,perm", [((2,) * 14, None), ((2,) * 20, None), ((4, 8, 2, 16, 2, 8), None),
@@ -165,14 +168,14 @@ def test_permutation_is_bit_exact(ctx, shape, perm):
     labs = list(range(100, 100 + r))
     dims = {labs[i]: shape[i] for i in range(r)}
     out_labs = [labs[i] for i in perm]
-    p = lib.tn_plan_load(ctx.handle, [labs], dims, [t], [0], 1, [], out_labs, 0, lib.TN_C64)
+    p = ctx.plan_load([labs], dims, [t], [0], 1, [], out_labs, 0, lib.TN_C64)
     got, l2 = lib.tn_contract(p, result_shape=tuple(shape[i] for i in perm), out_dtype=lib.TN_C64)
     assert np.array_equal(got, np.transpose(t, perm))
-    lib.tn_plan_free(p)
+    ctx.free_plan(p)
 
 
 @pytest.mark.parametrize("M,K,N,form", [(256, 64, 256, lib.TN_FORM_4M), (300, 37, 129, lib.TN_FORM_4M),
-                                         (64, 1, 64, lib.TN_FORM_4M), (512, 256, 96, lib.TN_FORM_3M),
+                                         (96, 1, 80, lib.TN_FORM_4M), (512, 256, 96, lib.TN_FORM_3M),
                                          (130, 70, 200, lib.TN_FORM_3M)])
 def test_gemm_vertex_against_fp64(ctx, M, K, N, form):
     """Two tensors A(m, k) and B(k, n) with an open output: one GEMM vertex.
@@ -183,7 +186,7 @@ def test_gemm_vertex_against_fp64(ctx, M, K, N, form):
     B = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
     legs = [[1, 2], [2, 3]]
     dims = {1: M, 2: K, 3: N}
-    p = lib.tn_plan_load(ctx.handle, legs, dims, [A, B], [0, 1], 2, [(0, 1)], [1, 3], form)
+    p = ctx.plan_load(legs, dims, [A, B], [0, 1], 2, [(0, 1)], [1, 3], form)
     assert lib.tn_plan_costs_get(p)["num_gemm_nodes"] == 1
     got, _ = lib.tn_contract(p, result_shape=(M, N))
     A32 = A.astype(np.complex64).astype(np.complex128)
@@ -191,7 +194,7 @@ def test_gemm_vertex_against_fp64(ctx, M, K, N, form):
     ref = A32 @ B32
     bound = (np.abs(A32) @ np.abs(B32)) * (4 * K * 2.0 ** -24) * (2 if form == lib.TN_FORM_3M else 1)
     assert np.all(np.abs(got - ref) <= bound + 1e-30)
-    lib.tn_plan_free(p)
+    ctx.free_plan(p)
 
 
 def test_batch_matches_single(ctx):
@@ -205,7 +208,7 @@ def test_batch_matches_single(ctx):
     assert np.all(st == 0)
     for x, o in zip(xs, outs):
         single, _ = lib.tn_contract(p, amplitude_overrides(net, circ, x))
-        assert abs(complex(o) - complex(single)) <= 1e-6 * max(abs(complex(single)), 2 ** -7)
+        assert abs(_c(o) - _c(single)) <= 1e-6 * max(abs(_c(single)), 2 ** -7)
         ref = oracle.contract_tree(net.legs, net.dims,
                                    net.copy_with(amplitude_overrides(net, circ, x)).tensors,
                                    plan.tree)
