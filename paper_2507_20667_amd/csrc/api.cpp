@@ -162,6 +162,8 @@ tn_status tn_plan_free(tn_plan *p) {
     hipStreamSynchronize(ctx->stream);
     ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes);
     ctx->arena.release(p->dev_desc, p->dev_desc_bytes);
+    for (auto &kv : p->layouts)
+      if (kv.second->tree_dev >= 0) ctx->arena.release(kv.second->tree_dev, kv.second->tree_dev_bytes);
     ctx->live_plans--;
   }
   delete p;

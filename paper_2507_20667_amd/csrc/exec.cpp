@@ -5,6 +5,9 @@
 // the group (grid dimension y = query).
 #include <algorithm>
 #include <cmath>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "tn_internal.h"
@@ -70,7 +73,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     return TN_E_INVALID_ARG;
   }
   // overridden leaves of the group
-  std::vector<int> ovr;
+  std::vector<char> is_ovr(nv, 0);
   for (const QueryIO &q : qs) {
     if (!q.out) {
       set_error("output pointer is NULL");
@@ -78,26 +81,69 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     }
     for (int i = 0; i < q.novr; ++i) {
       const tn_leaf &l = q.ovr[i];
-      if (l.tensor < 0 || l.tensor >= nv || !l.data || (l.dtype != TN_C64 && l.dtype != TN_C128 && l.dtype != TN_C64_DEVICE)) {
+      if (l.tensor < 0 || l.tensor >= nv || !l.data ||
+          (l.dtype != TN_C64 && l.dtype != TN_C128 && l.dtype != TN_C64_DEVICE)) {
         set_error("override %d: tensor id out of range, NULL data or bad dtype", i);
         return TN_E_INVALID_ARG;
       }
-      ovr.push_back(l.tensor);
+      is_ovr[l.tensor] = 1;
     }
   }
-  std::sort(ovr.begin(), ovr.end());
-  ovr.erase(std::unique(ovr.begin(), ovr.end()), ovr.end());
+  std::vector<int> ovr, kidx(nv, -1);
+  for (int t = 0; t < nv; ++t)
+    if (is_ovr[t]) {
+      kidx[t] = (int)ovr.size();
+      ovr.push_back(t);
+    }
+  const bool dbg = getenv("TN_DEBUG") != nullptr;
+  const auto t_enter = std::chrono::steady_clock::now();
+  auto ms_since = [](std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  };
   std::shared_ptr<ExecLayout> Lp = cached_layout(p, ovr, share);
   const ExecLayout &L = *Lp;
   Profiler &prof = ctx->prof;
 
-  // per-query override block: leaves in `ovr` order
-  std::vector<int64_t> ovr_off(nv, -1);
-  size_t ovr_bytes = 0;
-  for (int t : ovr) {
-    ovr_off[t] = (int64_t)ovr_bytes;
-    ovr_bytes += rnd(p->leaf[t].size() * 8);
+  // per-query override block: leaves in increasing id order
+  const std::vector<int64_t> &ovr_off = L.ovr_off;
+  const size_t ovr_bytes = (size_t)L.ovr_bytes;
+  const bool trees = L.n_tree_shared + L.n_tree_perq > 0;
+  if (trees && L.tree_dev < 0) {
+    // first use of this layout: upload its subtree programs
+    ExecLayout &Lm = const_cast<ExecLayout &>(L);
+    Lm.tree_dev_bytes = std::max<size_t>(L.tree_blob.size(), 256);
+    Lm.tree_dev = ctx->arena.alloc(Lm.tree_dev_bytes);
+    if (Lm.tree_dev < 0) {
+      set_error("arena cannot hold the subtree programs (%zu bytes)", Lm.tree_dev_bytes);
+      return TN_E_NOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(ctx->arena.base() + Lm.tree_dev, L.tree_blob.data(),
+                                  L.tree_blob.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      ctx->arena.release(Lm.tree_dev, Lm.tree_dev_bytes);
+      Lm.tree_dev = -1;
+      set_error("subtree program upload: %s", hipGetErrorString(e));
+      return TN_E_DEVICE;
+    }
   }
+  // algorithmic traffic and work of the subtree kernel (for the profiler)
+  double tree_bytes_sh = 0, tree_flops_sh = 0, tree_bytes_q = 0, tree_flops_q = 0;
+  if (trees)
+    for (const Node &n : p->nodes) {
+      if (!p->in_tree[n.id]) continue;
+      auto sz = [&](int t) {
+        return (double)(t < nv ? p->leaf[t].size() : std::max<int64_t>(p->nodes[t - nv].out.size(), 1));
+      };
+      const double b = 8.0 * (sz(n.c1) + sz(n.c2) + sz(n.id)), f = 8.0 * (double)n.weight;
+      if (L.shared[n.id]) {
+        tree_bytes_sh += b;
+        tree_flops_sh += f;
+      } else {
+        tree_bytes_q += b;
+        tree_flops_q += f;
+      }
+    }
   const size_t perq = rnd(L.perq_bytes);
   const size_t relems = result_elems(p);
   const size_t final_bytes = p->fperm.needed ? rnd(relems * 8) : 0;
@@ -207,7 +253,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         for (int qi = 0; qi < Q; ++qi) {
           const QueryIO &q = qs[q0 + qi];
           for (int i = 0; i < q.novr; ++i) {
-            const size_t k = std::lower_bound(ovr.begin(), ovr.end(), q.ovr[i].tensor) - ovr.begin();
+            const size_t k = (size_t)kidx[q.ovr[i].tensor];
             src[(size_t)qi * no + k] = &q.ovr[i];
           }
         }
@@ -264,9 +310,56 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
             }
         }
       }
-      TN_HIP(launch_init_slots(st, slots, (int64_t)nn * (Q + 1)), "slot init");
+      // scale records start at zero; not needed when the subtree kernel runs
+      // every vertex (it keeps its scales in LDS and writes its results' records)
+      if (!(trees && L.all_in_tree))
+        TN_HIP(launch_init_slots(st, slots, (int64_t)nn * (Q + 1)), "slot init");
+      if (trees) {
+        const uint8_t *tb = ctx->arena.base() + L.tree_dev;
+        TreeLaunch tl;
+        memset(&tl, 0, sizeof(tl));
+        tl.hdr = (const TreeHdr *)tb;
+        tl.chunks = (const TreeChunk *)(tb + L.tree_chunk_off);
+        tl.steps = (const TreeStep *)(tb + L.tree_step_off);
+        tl.loads = (const TreeLeafLoad *)(tb + L.tree_load_off);
+        tl.image = (const float2 *)(tb + L.tree_img_off);
+        // overridden leaves in id order: read in place or from the staging block
+        for (size_t k = 0; k < ovr.size() && k < (size_t)kTreeMaxOvr; ++k) {
+          const int t = ovr[k];
+          if (direct_p[t]) {
+            tl.ovr[k].p = direct_p[t];
+            tl.ovr[k].stride = direct_bs[t];
+          } else {
+            tl.ovr[k].p = (const float2 *)(ovr_base + ovr_off[t]);
+            tl.ovr[k].stride = ovr_el;
+          }
+        }
+        tl.shared_base = shared_base;
+        tl.perq_base = perq_base;
+        tl.perq_stride = (int64_t)perq;
+        tl.slots_sh = slots_sh;
+        tl.slots_q = slots_q;
+        tl.slot_stride = perq_sl;
+        tl.res = res;
+        if (L.n_tree_shared) {
+          tl.nq = 1;
+          tl.qw = 1;
+          TN_HIP(prof.timed(st, TN_KCLASS_TREE, tree_bytes_sh, tree_flops_sh,
+                            [&] { return launch_tree(st, tl, L.n_tree_shared, L.lds_shared); }),
+                 "subtree kernel (shared)");
+        }
+        if (L.n_tree_perq) {
+          tl.hdr = (const TreeHdr *)tb + L.n_tree_shared;
+          tl.nq = Q;
+          tl.qw = L.tree_qw;
+          TN_HIP(prof.timed(st, TN_KCLASS_TREE, tree_bytes_q * Q, tree_flops_q * Q,
+                            [&] { return launch_tree(st, tl, L.n_tree_perq, L.lds_perq); }),
+                 "subtree kernel");
+        }
+      }
       for (int j : p->order) {
         const Node &n = p->nodes[j];
+        if (trees && p->in_tree[n.id]) continue;
         const bool sh = L.shared[n.id] != 0;
         const int nb = sh ? 1 : Q;
         const double wflops = 8.0 * (double)n.weight * nb;
@@ -392,7 +485,11 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                                 sizeof(Slot), rq, hipMemcpyDeviceToHost, st),
                "scale copy");
       }
+      const double t_launched = dbg ? ms_since(t_enter) : 0.0;
       TN_HIP(hipStreamSynchronize(st), "stream synchronize");
+      if (dbg)
+        fprintf(stderr, "[tn] run_group %d queries: host prep+launch %.3f ms, device done at %.3f ms\n",
+                Q, t_launched, ms_since(t_enter));
       if (prof.on) prof.collect();
       for (int qi = 0; qi < Q; ++qi) {
         const QueryIO &q = qs[q0 + qi];

@@ -382,6 +382,8 @@ static bool node_in_bounds(const tn_plan *p, const Node &n, const std::vector<La
          r0 < lay[n.c1].size() && r1 < lay[n.c2].size();
 }
 
+static void select_trees(tn_plan *p, const std::vector<Layout> &lay);
+
 static u128 mul_check(u128 a, u128 b, bool &ovf) {
   if (a != 0 && b > (~(u128)0) / a) ovf = true;
   return a * b;
@@ -688,7 +690,8 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
       memcpy(dst, d->data[v], sizeof(float2) * n);
     }
   }
-  p->plain = make_exec_layout(p, {}, false);
+  select_trees(p, lay);
+  p->plain = make_exec_layout(p, {}, false, false);
   return TN_OK;
 }
 
@@ -697,8 +700,9 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
 // Best-fit allocation over a growing range; records the high-water mark.
 class Packer {
  public:
+  explicit Packer(int64_t granule = 256) : g_(granule) {}
   int64_t alloc(int64_t bytes) {
-    bytes = (bytes + 255) & ~(int64_t)255;
+    bytes = (bytes + g_ - 1) / g_ * g_;
     auto best = free_.end();
     for (auto it = free_.begin(); it != free_.end(); ++it)
       if (it->second >= bytes && (best == free_.end() || it->second < best->second)) best = it;
@@ -724,7 +728,7 @@ class Packer {
     return off;
   }
   void release(int64_t off, int64_t bytes) {
-    bytes = (bytes + 255) & ~(int64_t)255;
+    bytes = (bytes + g_ - 1) / g_ * g_;
     auto it = free_.emplace(off, bytes).first;
     auto nx = std::next(it);
     if (nx != free_.end() && it->first + it->second == nx->first) {
@@ -742,11 +746,373 @@ class Packer {
   int64_t peak() const { return peak_; }
 
  private:
+  int64_t g_;
   std::map<int64_t, int64_t> free_;
   int64_t top_ = 0, peak_ = 0;
 };
 
-ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden, bool share) {
+// ------------------------------------------------------ subtree programs
+
+static size_t tree_lds_bytes(int qw, int nscale, int shared_elems, int perq_elems) {
+  auto r2 = [](int64_t x) { return (x + 1) & ~(int64_t)1; };
+  size_t b = (size_t)2 * kTreeChunk * kTreeStepWords * 4;  // two chunk buffers
+  b += 256 * 16;                                  // FP64 reduction buffer
+  b += 8 * (size_t)r2((int64_t)qw * nscale);       // scale records
+  b += 8 * (size_t)r2(shared_elems);
+  b += 8 * (size_t)qw * (size_t)r2(perq_elems);
+  return b;
+}
+
+static bool tree_fill(const std::vector<LegMap> &legs, int32_t *ext, int32_t *s0, int32_t *s1,
+                      int32_t *lg, int32_t &nseg, bool &pow2) {
+  SegMap m;
+  if (!fill_segmap(legs, m) || m.nseg > kTreeSeg) return false;
+  nseg = m.nseg;
+  for (int i = 0; i < m.nseg; ++i) {
+    ext[i] = (int32_t)m.ext[i];
+    s0[i] = (int32_t)m.s0[i];
+    s1[i] = (int32_t)m.s1[i];
+    lg[i] = m.lg[i];
+  }
+  if (!m.pow2) pow2 = false;
+  return true;
+}
+
+// Step of vertex n: result index over n.out's legs, shared index over the
+// shared legs (A's order); a closed root is a full inner product.
+static bool tree_step(const tn_plan *p, const Node &n, const std::vector<Layout> &lay, bool final_dot,
+                      TreeStep &st) {
+  memset(&st, 0, sizeof(st));
+  const Layout &A = lay[n.c1], &B = lay[n.c2];
+  std::vector<int64_t> as = A.strides(), bs = B.strides();
+  bool p2 = true;
+  std::vector<LegMap> cl, sl;
+  int64_t nc = 1, ns = 1;
+  if (!final_dot) {
+    for (int i = 0; i < n.out.rank(); ++i) {
+      int ia = A.find(n.out.lab[i]), ib = B.find(n.out.lab[i]);
+      cl.push_back({n.out.dim[i], ia >= 0 ? as[ia] : 0, ib >= 0 ? bs[ib] : 0});
+      nc *= n.out.dim[i];
+    }
+  }
+  for (int i = 0; i < A.rank(); ++i) {
+    int ib = B.find(A.lab[i]);
+    if (ib < 0) continue;
+    sl.push_back({A.dim[i], as[i], bs[ib]});
+    ns *= A.dim[i];
+  }
+  if (!tree_fill(cl, st.cext, st.ca, st.cb, st.clg, st.ncs, p2)) return false;
+  if (!tree_fill(sl, st.sext, st.sa, st.sb, st.slg, st.nss, p2)) return false;
+  st.nc = (int32_t)nc;
+  st.ns = (int32_t)ns;
+  st.kind = final_dot ? 1 : 0;
+  st.pow2 = p2 ? 1 : 0;
+  (void)p;
+  return true;
+}
+
+// Level order of a subtree's vertices (level = 1 + the larger level of the
+// children, leaves at 0), cut into chunks of at most kTreeChunk vertices of one
+// level, and the LDS packing of their results in that order: a chunk's results
+// are allocated before the operands it consumes are released.
+struct LevelPlan {
+  std::vector<std::vector<int>> chunks;
+  std::map<int, int64_t> at;  // result offset (float2) of every vertex
+  int64_t peak = 0;
+};
+
+static LevelPlan level_plan(const tn_plan *p, const std::vector<int> &nodes) {
+  const int nv = p->nv;
+  std::map<int, int> lvl;
+  for (int u : nodes) {  // nodes are in SSA order, children first
+    const Node &n = p->nodes[u - nv];
+    int l = 0;
+    for (int c : {n.c1, n.c2})
+      if (c >= nv) l = std::max(l, lvl[c]);
+    lvl[u] = l + 1;
+  }
+  std::vector<int> ord(nodes);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return lvl[a] < lvl[b]; });
+  LevelPlan lp;
+  for (size_t i = 0; i < ord.size();) {
+    std::vector<int> ch;
+    const int l = lvl[ord[i]];
+    while (i < ord.size() && lvl[ord[i]] == l && (int)ch.size() < kTreeChunk) ch.push_back(ord[i++]);
+    lp.chunks.push_back(ch);
+  }
+  Packer P(2);
+  for (const auto &ch : lp.chunks) {
+    for (int u : ch) lp.at[u] = P.alloc(std::max<int64_t>(p->nodes[u - nv].out.size(), 1));
+    for (int u : ch)
+      for (int c : {p->nodes[u - nv].c1, p->nodes[u - nv].c2})
+        if (c >= nv) P.release(lp.at[c], std::max<int64_t>(p->nodes[c - nv].out.size(), 1));
+  }
+  lp.peak = P.peak();
+  return lp;
+}
+
+// Subtrees of small vertices: a vertex qualifies when it, both operands and
+// its result stay within kTreeMaxElems and both children are leaves or
+// qualifying vertices; a subtree is kept when its worst-case LDS use (one
+// query, every leaf copied) fits, otherwise its qualifying children are tried.
+static void select_trees(tn_plan *p, const std::vector<Layout> &lay) {
+  const int nv = p->nv, nn = 2 * nv - 1;
+  p->in_tree.assign(nn, 0);
+  p->tree_roots.clear();
+  if (!p->use_tree || nv < 2) return;
+  std::vector<char> ok(nn, 0);
+  std::vector<int> parent(nn, -1);
+  std::vector<TreeStep> tmp(1);
+  for (int j = 0; j < nv - 1; ++j) {
+    const Node &n = p->nodes[j];
+    parent[n.c1] = parent[n.c2] = n.id;
+    bool small = lay[n.c1].size() <= kTreeMaxElems && lay[n.c2].size() <= kTreeMaxElems &&
+                 n.out.size() <= kTreeMaxElems;
+    bool kids = (n.c1 < nv || ok[n.c1]) && (n.c2 < nv || ok[n.c2]);
+    bool final_dot = n.kind == NK_DOT && n.id == p->root;
+    bool dot_inside = n.kind == NK_DOT && !final_dot;
+    ok[n.id] = small && kids && !dot_inside && tree_step(p, n, lay, final_dot, tmp[0]);
+  }
+  // worst-case LDS of the subtree at v
+  auto lds_need = [&](int v) {
+    std::vector<int> nodes, stack{v};
+    int64_t leaf_elems = 0;
+    while (!stack.empty()) {
+      int u = stack.back();
+      stack.pop_back();
+      if (u < nv) {
+        leaf_elems += (lay[u].size() + 1) & ~(int64_t)1;
+        continue;
+      }
+      nodes.push_back(u);
+      stack.push_back(p->nodes[u - nv].c1);
+      stack.push_back(p->nodes[u - nv].c2);
+    }
+    std::sort(nodes.begin(), nodes.end());
+    const LevelPlan lp = level_plan(p, nodes);
+    return tree_lds_bytes(1, (int)nodes.size(), (int)leaf_elems, (int)lp.peak + 2);
+  };
+  std::vector<int> cand;
+  for (int v = nv; v < nn; ++v)
+    if (ok[v] && (parent[v] < 0 || !ok[parent[v]])) cand.push_back(v);
+  std::vector<int> roots;
+  while (!cand.empty()) {
+    int v = cand.back();
+    cand.pop_back();
+    if (lds_need(v) <= tree_lds_limit() * 3 / 4) {
+      roots.push_back(v);
+      continue;
+    }
+    for (int c : {p->nodes[v - nv].c1, p->nodes[v - nv].c2})
+      if (c >= nv && ok[c]) cand.push_back(c);
+  }
+  std::sort(roots.begin(), roots.end());
+  for (int r : roots) {
+    std::vector<int> stack{r};
+    while (!stack.empty()) {
+      int u = stack.back();
+      stack.pop_back();
+      if (u < nv) continue;
+      p->in_tree[u] = 1;
+      stack.push_back(p->nodes[u - nv].c1);
+      stack.push_back(p->nodes[u - nv].c2);
+    }
+  }
+  // a subtree is worth a launch of its own only above one vertex
+  for (int r : roots) {
+    const Node &n = p->nodes[r - nv];
+    if (n.c1 < nv && n.c2 < nv && r != p->root) {
+      p->in_tree[r] = 0;
+      continue;
+    }
+    p->tree_roots.push_back(r);
+  }
+}
+
+static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vector<uint8_t> &ovr,
+                                const std::vector<Layout> &lay) {
+  const int nv = p->nv;
+  std::vector<TreeHdr> hdrs;
+  std::vector<TreeChunk> chunks;
+  std::vector<TreeStep> steps;
+  std::vector<TreeLeafLoad> loads;
+  std::vector<float2> image;
+  std::vector<int> ovr_list;  // overridden leaves in id order: index = TreeLaunch::ovr slot
+  for (int t = 0; t < nv; ++t)
+    if (ovr[t]) ovr_list.push_back(t);
+  if ((int)ovr_list.size() > kTreeMaxOvr) {
+    L.tree_error = true;  // more overridden leaves than the launch carries
+    return;
+  }
+  std::vector<int> order;  // shared subtrees first
+  for (int r : p->tree_roots)
+    if (L.shared[r]) order.push_back(r);
+  L.n_tree_shared = (int)order.size();
+  for (int r : p->tree_roots)
+    if (!L.shared[r]) order.push_back(r);
+  L.n_tree_perq = (int)order.size() - L.n_tree_shared;
+  int max_scale_q = 0, max_sh_q = 0, max_pq_q = 0;
+  size_t lds_sh = 0;
+  for (int r : order) {
+    TreeHdr h;
+    memset(&h, 0, sizeof(h));
+    std::vector<int> nodes, leaves, stack{r};
+    while (!stack.empty()) {
+      int u = stack.back();
+      stack.pop_back();
+      if (u < nv) {
+        leaves.push_back(u);
+        continue;
+      }
+      nodes.push_back(u);
+      stack.push_back(p->nodes[u - nv].c1);
+      stack.push_back(p->nodes[u - nv].c2);
+    }
+    std::sort(nodes.begin(), nodes.end());
+    std::sort(leaves.begin(), leaves.end());
+    std::map<int, int32_t> loc;
+    std::map<int, int> scale;
+    // shared leaves: contiguous image; overridden leaves: front of the query region
+    h.image_off = (int64_t)image.size();
+    h.load0 = (int32_t)loads.size();
+    int32_t sh = 0, pq = 0;
+    for (int t : leaves) {
+      const int64_t n = p->leaf[t].size();
+      if (!ovr[t]) {
+        loc[t] = sh;
+        for (int64_t i = 0; i < n; ++i) image.push_back(p->leaf_host[p->leaf_off[t] + i]);
+        if (n & 1) image.push_back(make_float2(0.f, 0.f));
+        sh += (int32_t)((n + 1) & ~(int64_t)1);
+      } else {
+        loc[t] = kPerQuery | pq;
+        TreeLeafLoad ld;
+        ld.lds = kPerQuery | pq;
+        ld.n = (int32_t)n;
+        ld.src = (int32_t)(std::lower_bound(ovr_list.begin(), ovr_list.end(), t) - ovr_list.begin());
+        ld.pad = 0;
+        loads.push_back(ld);
+        pq += (int32_t)((n + 1) & ~(int64_t)1);
+      }
+    }
+    h.nloads = (int32_t)loads.size() - h.load0;
+    h.shared_elems = sh;
+    const int64_t base = pq;
+    const LevelPlan lp = level_plan(p, nodes);
+    for (int u : nodes) scale[u] = (int)scale.size();
+    h.chunk0 = (int32_t)chunks.size();
+    for (const auto &ch : lp.chunks) {
+      TreeChunk tc;
+      tc.step0 = (int32_t)steps.size();
+      tc.nsteps = (int32_t)ch.size();
+      for (int u : ch) loc[u] = kPerQuery | (int32_t)(base + lp.at.at(u));
+      for (int u : ch) {
+        const Node &n = p->nodes[u - nv];
+        TreeStep st;
+        const bool final_dot = n.kind == NK_DOT && u == p->root;
+        tree_step(p, n, lay, final_dot, st);
+        st.a = loc[n.c1];
+        st.b = loc[n.c2];
+        st.c = loc[u];
+        st.asl = n.c1 >= nv ? scale[n.c1] : -1;
+        st.bsl = n.c2 >= nv ? scale[n.c2] : -1;
+        st.csl = scale[u];
+        steps.push_back(st);
+        if (final_dot) h.final_dot = 1;
+      }
+      chunks.push_back(tc);
+    }
+    h.nchunks = (int32_t)chunks.size() - h.chunk0;
+    h.perq_elems = (int32_t)(base + lp.peak);
+    h.nscale = (int32_t)scale.size();
+    h.root_loc = loc[r];
+    h.root_scale = scale[r];
+    h.root_elems = (int32_t)std::max<int64_t>(p->nodes[r - nv].out.size(), 1);
+    h.root_in_perq = L.shared[r] ? 0 : 1;
+    h.root_off = L.off[r];
+    h.root_slot = r;
+    hdrs.push_back(h);
+    if (L.shared[r]) {
+      lds_sh = std::max(lds_sh, tree_lds_bytes(1, h.nscale, h.shared_elems, h.perq_elems));
+    } else {
+      max_scale_q = std::max(max_scale_q, h.nscale);
+      max_sh_q = std::max(max_sh_q, h.shared_elems);
+      max_pq_q = std::max(max_pq_q, h.perq_elems);
+      if (h.nloads) L.tree_reads_ovr = true;
+    }
+  }
+  // every LDS access of every step must stay inside its region, checked here
+  // so that a scheduling mistake disables the subtree kernel instead of
+  // faulting it
+  bool ok = true;
+  for (const TreeHdr &h : hdrs) {
+    auto reach = [](const int32_t *ext, const int32_t *s, int n) {
+      int64_t r = 0;
+      for (int i = 0; i < n; ++i) r += (int64_t)(ext[i] - 1) * s[i];
+      return r;
+    };
+    auto inside = [&](int32_t loc, int64_t r) {
+      if (loc & kPerQuery) return (loc & ~kPerQuery) + r < h.perq_elems;
+      return loc + r < h.shared_elems;
+    };
+    for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c) {
+      ok = ok && chunks[c].nsteps >= 1 && chunks[c].nsteps <= kTreeChunk;
+      for (int k = chunks[c].step0; k < chunks[c].step0 + chunks[c].nsteps; ++k) {
+        const TreeStep &st = steps[k];
+        const int64_t ra = reach(st.cext, st.ca, st.ncs) + reach(st.sext, st.sa, st.nss);
+        const int64_t rb = reach(st.cext, st.cb, st.ncs) + reach(st.sext, st.sb, st.nss);
+        ok = ok && inside(st.a, ra) && inside(st.b, rb) && (st.c & kPerQuery) &&
+             (st.c & ~kPerQuery) + st.nc <= h.perq_elems && st.csl >= 0 && st.csl < h.nscale &&
+             st.asl < h.nscale && st.bsl < h.nscale && st.nc >= 1 && st.ns >= 1;
+        // a closed-root inner product runs alone in the last chunk
+        if (st.kind == 1) ok = ok && chunks[c].nsteps == 1 && c == h.chunk0 + h.nchunks - 1;
+      }
+    }
+    for (int i = h.load0; i < h.load0 + h.nloads; ++i)
+      ok = ok && (loads[i].lds & kPerQuery) && (loads[i].lds & ~kPerQuery) + loads[i].n <= h.perq_elems &&
+           loads[i].src >= 0 && loads[i].src < (int)ovr_list.size() &&
+           p->leaf[ovr_list[loads[i].src]].size() == loads[i].n;
+    ok = ok && h.image_off + h.shared_elems <= (int64_t)image.size() + 1;
+    if (!h.final_dot) {
+      const int64_t part = h.root_in_perq ? L.perq_bytes : L.shared_bytes;
+      ok = ok && (h.root_loc & kPerQuery) && (h.root_loc & ~kPerQuery) + h.root_elems <= h.perq_elems &&
+           h.root_off >= 0 && h.root_off + 8 * (int64_t)h.root_elems <= part;
+    }
+  }
+  if (!ok) {
+    L.tree_error = true;
+    return;
+  }
+  L.lds_shared = lds_sh;
+  // as many queries per workgroup as leave room for two workgroups per CU
+  L.tree_qw = 1;
+  for (int qw : {16, 12, 8, 6, 5, 4, 3, 2}) {
+    if (tree_lds_bytes(qw, max_scale_q, max_sh_q, max_pq_q) <= tree_lds_limit() / 2) {
+      L.tree_qw = qw;
+      break;
+    }
+  }
+  L.lds_perq = tree_lds_bytes(L.tree_qw, max_scale_q, max_sh_q, max_pq_q);
+  if (getenv("TN_DEBUG"))
+    for (const TreeHdr &h : hdrs)
+      fprintf(stderr, "[tn]   subtree root %d: %d chunks, %d shared leaf entries, %d per-query entries, "
+              "%d scale records, %d loads\n", h.root_slot, h.nchunks, h.shared_elems, h.perq_elems,
+              h.nscale, h.nloads);
+  // blob
+  auto put = [&](const void *src, size_t bytes) {
+    size_t off = (L.tree_blob.size() + 255) & ~(size_t)255;
+    L.tree_blob.resize(off + bytes);
+    if (bytes) memcpy(L.tree_blob.data() + off, src, bytes);
+    return off;
+  };
+  put(hdrs.data(), hdrs.size() * sizeof(TreeHdr));
+  L.tree_chunk_off = put(chunks.data(), chunks.size() * sizeof(TreeChunk));
+  L.tree_step_off = put(steps.data(), steps.size() * sizeof(TreeStep));
+  L.tree_load_off = put(loads.data(), loads.size() * sizeof(TreeLeafLoad));
+  L.tree_img_off = put(image.data(), image.size() * sizeof(float2));
+}
+
+ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden, bool share,
+                            bool allow_trees) {
   const int nv = p->nv, nn = 2 * nv - 1;
   ExecLayout L;
   L.off.assign(nn, -1);
@@ -757,13 +1123,30 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
   L.ovr_off.assign(nv, -1);
   std::vector<uint8_t> ovr(nv, 0);
   for (int t : overridden) ovr[t] = 1;
+  // per-query override block: overridden leaves in increasing id order
+  int64_t ob = 0;
+  for (int t = 0; t < nv; ++t)
+    if (ovr[t]) {
+      L.ovr_off[t] = ob;
+      ob += (p->leaf[t].size() * 8 + 255) & ~(int64_t)255;
+    }
+  L.ovr_bytes = ob;
   for (int v = 0; v < nv; ++v) L.shared[v] = ovr[v] ? 0 : 1;
   for (const Node &n : p->nodes) L.shared[n.id] = L.shared[n.c1] && L.shared[n.c2];
   if (!share)  // plain execution: every intermediate belongs to the query
     for (int v = nv; v < nn; ++v) L.shared[v] = 0;
+  const bool trees = allow_trees && share && !p->tree_roots.empty();
+  auto is_root = [&](int v) {
+    return std::find(p->tree_roots.begin(), p->tree_roots.end(), v) != p->tree_roots.end();
+  };
   Packer pk[2];  // 0: per-query, 1: shared
+  // subtree results are written before any other vertex runs
+  if (trees)
+    for (int r : p->tree_roots)
+      L.off[r] = pk[L.shared[r] ? 1 : 0].alloc(std::max<int64_t>(p->nodes[r - nv].out.size(), 1) * 8);
   for (int j : p->order) {
     const Node &n = p->nodes[j];
+    if (trees && p->in_tree[n.id]) continue;
     const int part = L.shared[n.id] ? 1 : 0;
     Packer &P = pk[part];
     int64_t out_bytes = std::max<int64_t>(n.out.size(), 1) * 8;
@@ -784,31 +1167,27 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
     }
     for (auto &t : tmp) P.release(t.first, t.second);
     // children die here unless they live in the other part (shared results
-    // feeding per-query nodes stay for the whole execution)
+    // feeding per-query vertices stay for the whole execution)
     for (int c : {n.c1, n.c2}) {
-      if (c < nv) continue;
+      if (c < nv || L.off[c] < 0) continue;
       if (L.shared[c] == L.shared[n.id]) {
         const Node &cn = p->nodes[c - nv];
         P.release(L.off[c], std::max<int64_t>(cn.out.size(), 1) * 8);
       }
     }
   }
-  // the root (and shared roots) stay allocated: never released above
-  int64_t q = pk[0].peak(), s = pk[1].peak();
-  L.peak_intermediate = q;
-  auto carve = [](int64_t &top, int64_t bytes) {
-    int64_t off = top;
-    top += (bytes + 255) & ~(int64_t)255;
-    return off;
-  };
-  L.slots_perq = carve(q, (int64_t)nn * (int64_t)sizeof(Slot));
-  L.result_off = carve(q, sizeof(Result));
-  if (p->fperm.needed) L.final_off = carve(q, p->result_layout.size() * 8);
-  for (int v = 0; v < nv; ++v)
-    if (ovr[v]) L.ovr_off[v] = carve(q, p->leaf[v].size() * 8);
-  L.slots_shared = carve(s, (int64_t)nn * (int64_t)sizeof(Slot));
-  L.perq_bytes = q;
-  L.shared_bytes = s;
+  (void)is_root;
+  L.peak_intermediate = pk[0].peak();
+  L.perq_bytes = pk[0].peak();
+  L.shared_bytes = pk[1].peak();
+  if (trees) {
+    L.all_in_tree = true;
+    for (const Node &n : p->nodes) L.all_in_tree = L.all_in_tree && p->in_tree[n.id];
+    std::vector<Layout> lay(nn);
+    for (int v = 0; v < nv; ++v) lay[v] = p->leaf[v];
+    for (const Node &n : p->nodes) lay[n.id] = n.out;
+    build_tree_programs(p, L, ovr, lay);
+  }
   return L;
 }
 
@@ -819,7 +1198,17 @@ std::shared_ptr<ExecLayout> cached_layout(tn_plan *p, const std::vector<int> &ov
   key.push_back(share ? -1 : -2);
   auto it = p->layouts.find(key);
   if (it != p->layouts.end()) return it->second;
-  auto L = std::make_shared<ExecLayout>(make_exec_layout(p, overridden, share));
+  auto L = std::make_shared<ExecLayout>(make_exec_layout(p, overridden, share, true));
+  if (L->tree_error)  // fall back to one launch per vertex
+    L = std::make_shared<ExecLayout>(make_exec_layout(p, overridden, share, false));
+  if (getenv("TN_DEBUG"))
+    fprintf(stderr,
+            "[tn] layout: %zu overridden leaves, share %d, subtrees %d shared + %d per query, "
+            "%d queries/workgroup, LDS %zu / %zu bytes, per-query part %lld bytes, shared part "
+            "%lld bytes, tree error %d\n",
+            overridden.size(), (int)share, L->n_tree_shared, L->n_tree_perq, L->tree_qw,
+            L->lds_shared, L->lds_perq, (long long)L->perq_bytes, (long long)L->shared_bytes,
+            (int)L->tree_error);
   p->layouts[key] = L;
   return L;
 }

@@ -103,6 +103,83 @@ struct Result {
   double re, im, log2s, pad;
 };
 
+// ----------------------------------------------------------- subtree kernel
+// A subtree whose vertices are all small runs in one workgroup for a group of
+// queries, every operand in LDS.  LDS holds a shared region (leaves no query
+// overrides) and one region per query (its overridden leaves and the live
+// intermediates).  Locations are float2 offsets; kPerQuery marks the
+// per-query region.
+constexpr int kTreeSeg = 6;
+constexpr int32_t kPerQuery = 1 << 30;
+constexpr int kTreeMaxElems = 4096;
+constexpr int kTreeChunk = 16;     // steps of one level run between two barriers
+constexpr int kTreeMaxOvr = 64;    // overridden leaves read in place per launch
+
+struct TreeStep {
+  int32_t a, b, c;        // LDS locations of the operands and the result
+  int32_t asl, bsl, csl;  // scale index of each (-1: a leaf, scale 1)
+  int32_t nc, ns;         // result entries, shared-index entries
+  int32_t ncs, nss;       // segment counts of the two maps
+  int32_t kind;           // 0: contraction, 1: final FP64 inner product
+  int32_t pow2;           // every extent a power of two
+  // result index -> (A offset, B offset), innermost first
+  int32_t cext[kTreeSeg], ca[kTreeSeg], cb[kTreeSeg], clg[kTreeSeg];
+  // shared index -> (A offset, B offset)
+  int32_t sext[kTreeSeg], sa[kTreeSeg], sb[kTreeSeg], slg[kTreeSeg];
+};
+constexpr int kTreeStepWords = (int)(sizeof(TreeStep) / 4);
+
+struct TreeLeafLoad {
+  int32_t lds;      // LDS location (kPerQuery set: per-query region)
+  int32_t n;        // entries
+  int32_t src;      // which overridden leaf (index into TreeLaunch::ovr)
+  int32_t pad;
+};
+
+// A chunk: up to kTreeChunk steps of one level (mutually independent).
+struct TreeChunk {
+  int32_t step0, nsteps;
+};
+
+struct TreeHdr {
+  int32_t chunk0, nchunks;
+  int32_t load0, nloads;             // per-query leaf loads (overridden leaves)
+  int32_t shared_elems, perq_elems;  // LDS sizes (float2)
+  int32_t nscale;                    // scale records per query
+  int32_t root_loc;                  // LDS location of the subtree result
+  int32_t root_scale;
+  int32_t final_dot;                 // the subtree root is the network's closed root
+  int32_t root_elems;
+  int32_t root_in_perq;              // result goes to the per-query part
+  int64_t root_off;                  // byte offset of the result in its part
+  int64_t image_off;                 // shared leaves: offset in the leaf image
+  int32_t root_slot;                 // tensor id (slot index) of the result
+  int32_t pad;
+};
+
+struct OvrSrc {
+  const float2 *p;      // query 0's copy of an overridden leaf
+  int64_t stride;       // float2 from one query to the next
+};
+
+struct TreeLaunch {
+  const TreeHdr *hdr;
+  const TreeChunk *chunks;
+  const TreeStep *steps;
+  const TreeLeafLoad *loads;
+  const float2 *image;  // shared leaves of every subtree, each in its LDS order
+  OvrSrc ovr[kTreeMaxOvr];
+  uint8_t *shared_base;
+  uint8_t *perq_base;
+  int64_t perq_stride;  // bytes per query
+  Slot *slots_sh;
+  Slot *slots_q;
+  int64_t slot_stride;  // Slot records per query
+  Result *res;
+  int32_t nq;           // queries in this launch
+  int32_t qw;           // queries per workgroup
+};
+
 enum GemmForm { kForm4M = 0, kForm3M = 1 };
 enum GemmPrec { kPrecFP32 = 0, kPrecBF16x3 = 1 };
 
@@ -117,6 +194,9 @@ hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int prec, int form, in
 hipError_t launch_dot(hipStream_t st, const DotDesc *d_desc, int64_t nelem, Operand A, Operand B,
                       OutOperand C, Result *res, int64_t rbs, double2 *partials, int nblocks,
                       int nbatch);
+
+hipError_t launch_tree(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes);
+size_t tree_lds_limit();
 
 // Tile shape variants of the GEMM (index into a table in the kernel file).
 int gemm_num_variants();

@@ -96,10 +96,19 @@ struct ExecLayout {
   std::vector<int64_t> ovr_off;   // per leaf: offset of its per-query override copy, or -1
   int64_t shared_bytes = 0;
   int64_t perq_bytes = 0;
-  int64_t slots_shared = 0, slots_perq = 0;  // slot arrays (one Slot per tensor id)
-  int64_t result_off = 0;         // per query: Result
-  int64_t final_off = -1;         // per query: result in output-leg order
+  int64_t ovr_bytes = 0;          // bytes of one query's override block
   int64_t peak_intermediate = 0;  // live peak (per-query part, intermediates + scratch)
+  // subtree programs: [TreeHdr...][TreeStep...][TreeLeafLoad...][image float2...]
+  std::vector<uint8_t> tree_blob;
+  size_t tree_chunk_off = 0, tree_step_off = 0, tree_load_off = 0, tree_img_off = 0;
+  int n_tree_shared = 0, n_tree_perq = 0;  // headers: shared subtrees first
+  size_t lds_shared = 0, lds_perq = 0;     // dynamic LDS of the two launches
+  int tree_qw = 1;                         // queries per workgroup (per-query launch)
+  bool tree_reads_ovr = false;             // per-query subtrees load overridden leaves
+  bool tree_error = false;                 // programs failed the bounds check
+  bool all_in_tree = false;                // every vertex runs in the subtree kernel
+  int64_t tree_dev = -1;                   // arena offset of the uploaded blob
+  size_t tree_dev_bytes = 0;
 };
 
 struct tn_plan_impl;
@@ -267,6 +276,10 @@ struct tn_plan {
   tn::u128 con_serial = 0, con_par = 0, con_dist = 0, mem = 0;
   int64_t largest = 0;
   int num_gemm = 0, num_tiny = 0, num_stream = 0, num_perm = 0;
+  // subtrees of small vertices run by the subtree kernel
+  std::vector<char> in_tree;     // per tensor id: internal vertex inside such a subtree
+  std::vector<int> tree_roots;   // their root tensor ids, SSA order
+  bool use_tree = true;
   tn::ExecLayout plain;          // nothing shared, one query
   std::mutex cache_mu;
   std::map<std::vector<int>, std::shared_ptr<tn::ExecLayout>> layouts;  // by override set
@@ -276,7 +289,8 @@ namespace tn {
 
 // plan.cpp
 tn_status build_plan(tn_plan *p, const tn_plan_desc *d);
-ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden, bool share);
+ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden, bool share,
+                            bool allow_trees);
 std::shared_ptr<ExecLayout> cached_layout(tn_plan *p, const std::vector<int> &overridden,
                                           bool share);
 const char *last_error();
