@@ -93,6 +93,98 @@ def batch_call(lib, ctx, plan, leaves, n):
     return call
 
 
+def serve_bench(lib, ctx, seconds, rate, flags, seed=0):
+    """Poisson arrivals of amplitude and <Z_i Z_j> requests over a pool of
+    seeded random circuits (12-22 qubits, depth 8-16, the 30-qubit family's
+    generator with n/4 CX pairs per layer): p50/p99 of submit-to-ready latency,
+    offered and achieved rates; then the same requests all at once
+    (saturation throughput)."""
+    import threading
+    from paper_2507_20667_amd.inputs import (amplitude_network, amplitude_overrides,
+                                             random_circuit, zz_network)
+    from paper_2507_20667_amd.planner import SAConfig, simulated_annealing
+    from paper_2507_20667_amd.planner.plan import tree_partition
+    rng = np.random.default_rng(seed)
+    pool = []
+    t0 = time.perf_counter()
+    for c in range(8):
+        n = int(rng.integers(12, 23))
+        d = int(rng.integers(8, 17))
+        circ = random_circuit(n, d, 100 + c)
+        nets = [("amp", amplitude_network(circ, 0), None)]
+        for _ in range(2):
+            i, j = sorted(int(v) for v in rng.choice(n, 2, replace=False))
+            nets.append(("zz", zz_network(circ, i, j), (i, j)))
+        for kind, net, ij in nets:
+            k = 2 if net.num_tensors < 200 else 4
+            pl = simulated_annealing(net.legs, net.dims, tree_partition(net.legs, net.dims, k), k,
+                                     SAConfig(iterations=3, n_steps=8, workers=2, rg_samples=4))
+            p = ctx.plan_load(net.legs, net.dims, net.tensors, pl.partition_of, k, pl.tree, None,
+                              flags)
+            pool.append((kind, circ, net, p))
+    plan_s = time.perf_counter() - t0
+    amp_plans = [x for x in pool if x[0] == "amp"]
+    zz_plans = [x for x in pool if x[0] == "zz"]
+    nreq = max(1, int(seconds * rate))
+    reqs = []
+    for _ in range(nreq):
+        if rng.random() < 0.5:
+            kind, circ, net, p = amp_plans[int(rng.integers(0, len(amp_plans)))]
+            x = int(rng.integers(0, 1 << circ.n))
+            reqs.append((p, amplitude_overrides(net, circ, x)))
+        else:
+            kind, circ, net, p = zz_plans[int(rng.integers(0, len(zz_plans)))]
+            reqs.append((p, {}))
+    gaps = rng.exponential(1.0 / rate, size=nreq)
+
+    def run(paced):
+        tickets = [None] * nreq
+
+        def submitter():
+            t_next = time.perf_counter()
+            for i, (p, ovr) in enumerate(reqs):
+                if paced:
+                    t_next += gaps[i]
+                    while time.perf_counter() < t_next:
+                        time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
+                tickets[i] = lib.tn_serve_submit(ctx.handle, p, ovr)
+
+        th = threading.Thread(target=submitter)
+        start = time.perf_counter()
+        th.start()
+        lat = []
+        done = 0
+        while done < nreq:
+            progressed = False
+            for i in range(nreq):
+                t = tickets[i]
+                if t is None or t < 0:
+                    continue
+                st, out, _, l = lib.tn_serve_poll(ctx.handle, t)
+                if st == lib.TN_PENDING:
+                    continue
+                tickets[i] = -1
+                lat.append(l)
+                done += 1
+                progressed = True
+            if not progressed:
+                time.sleep(2e-4)
+        th.join()
+        wall = time.perf_counter() - start
+        return np.array(lat), wall
+
+    lat, wall = run(True)
+    lat_s, wall_s = run(False)
+    return dict(requests=nreq, offered_per_s=rate, achieved_per_s=nreq / wall,
+                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                saturated_per_s=nreq / wall_s,
+                saturated_p50_ms=float(np.percentile(lat_s, 50) * 1e3),
+                saturated_p99_ms=float(np.percentile(lat_s, 99) * 1e3),
+                pool="8 random circuits 12-22 qubits depth 8-16 (n/4 CX per layer, 70% nearest-"
+                     "neighbour), amplitude + 2 <ZZ> networks each, 50/50 mix",
+                planning_s=plan_s)
+
+
 def cpu_baseline(net, plan, circ, budget_s):
     import oracle
     from paper_2507_20667_amd.inputs import amplitude_overrides, random_bitstrings
@@ -122,6 +214,8 @@ def main():
     ap.add_argument("--form", choices=["4m", "3m"], default="4m")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -218,6 +312,10 @@ def main():
     roof["avg_launch_us"] = ds["seconds"] / max(ds["launches"], 1) * 1e6
     roof["algo_bytes_per_launch"] = ds["algo_bytes"] / max(ds["launches"], 1)
 
+    serve = None
+    if args.serve_seconds > 0:
+        serve = serve_bench(lib, ctx, args.serve_seconds, args.serve_rate, flags)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(net, plan, circ, args.cpu_seconds)
@@ -247,6 +345,7 @@ def main():
         "planning_s": plan_s,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serve": serve,
         "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},
     }
     ctx.close()

@@ -214,10 +214,18 @@ tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *qu
  * (TN_E_AGAIN when the queue is full).  A library thread admits queued
  * requests while their workspace fits the free arena, groups admitted
  * requests on the same plan into one batched launch sequence and completes
- * them with events, so requests that arrive while others run join the next
- * round (continuous batching).  tn_serve_poll returns TN_PENDING until the
- * result is ready, then writes it like tn_contract, sets *latency_s to
- * submit-to-ready seconds and consumes the ticket.
+ * them, so requests that arrive while others run join the next batch
+ * (continuous batching); batches of different worker threads (each with its
+ * own stream; TN_SERVE_WORKERS, default 2) overlap on the device.  Admission
+ * reserves a batch's whole workspace in the arena first; a request that cannot
+ * fit even alone on an idle device ends with TN_E_NOMEM.  Host override data
+ * is copied at submit; TN_C64_DEVICE data must stay valid until polled.
+ * tn_serve_poll returns TN_PENDING until the result is ready; then it writes
+ * the result (as tn_contract does: the mantissa with *log2_scale = the FP64
+ * exponent when log2_scale is not NULL, the scaled value otherwise), sets
+ * *latency_s (may be NULL) to the submit-to-ready time in seconds and
+ * consumes the ticket.  A plan cannot be freed while requests on it are
+ * pending.  Both calls are thread-safe.
  */
 tn_status tn_serve_submit(tn_ctx *ctx, const tn_query *query, uint64_t *ticket);
 tn_status tn_serve_poll(tn_ctx *ctx, uint64_t ticket, void *out, tn_dtype out_dtype,

@@ -6,6 +6,17 @@
 
 using namespace tn;
 
+// The calling thread's resources for tn_contract*: the context's stream,
+// staging and profiler (these calls are serialized by exec_mu).
+static ExecRes ctx_res(tn_ctx *ctx) {
+  ExecRes r;
+  r.st = ctx->stream;
+  r.pinned = &ctx->pinned;
+  r.pinned_bytes = &ctx->pinned_bytes;
+  r.prof = &ctx->prof;
+  return r;
+}
+
 extern "C" {
 
 const char *tn_last_error(void) { return tn::last_error(); }
@@ -156,6 +167,11 @@ tn_status tn_plan_free(tn_plan *p) {
     set_error("tn_plan_free: NULL plan");
     return TN_E_INVALID_ARG;
   }
+  if (p->ctx && serve_pending_on(p->ctx, p) > 0) {
+    set_error("tn_plan_free: %d serve request(s) on this plan are still pending",
+              serve_pending_on(p->ctx, p));
+    return TN_E_INVALID_ARG;
+  }
   if (p->ctx) {
     tn_ctx *ctx = p->ctx;
     std::lock_guard<std::mutex> g(ctx->exec_mu);
@@ -186,7 +202,8 @@ tn_status tn_contract(tn_plan *p, int32_t num_overrides, const tn_leaf *override
   q.out = out;
   q.log2s = log2_scale;
   std::lock_guard<std::mutex> g(p->ctx->exec_mu);
-  return run_group(p->ctx, p, {q}, out_dtype, flags, false, p->ctx->stream);
+  ExecRes r = ctx_res(p->ctx);
+  return run_group(p->ctx, p, {q}, out_dtype, flags, false, r);
 }
 
 tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *queries,
@@ -229,7 +246,8 @@ tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *qu
       q.status = per_query ? &per_query[i] : nullptr;
       qs.push_back(q);
     }
-    tn_status st = run_group(ctx, plans[k], qs, out_dtype, flags, true, ctx->stream);
+    ExecRes r = ctx_res(ctx);
+    tn_status st = run_group(ctx, plans[k], qs, out_dtype, flags, true, r);
     if (st != TN_OK) {
       if (per_query)
         for (int i : members[k]) per_query[i] = st;

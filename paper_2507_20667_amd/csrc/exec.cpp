@@ -20,19 +20,34 @@ size_t result_elems(const tn_plan *p) {
 
 static size_t rnd(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static tn_status ensure_pinned(tn_ctx *ctx, size_t bytes) {
-  if (ctx->pinned_bytes >= bytes) return TN_OK;
-  if (ctx->pinned) hipHostFree(ctx->pinned);
-  ctx->pinned = nullptr;
-  ctx->pinned_bytes = 0;
+static tn_status ensure_pinned(ExecRes &r, size_t bytes) {
+  if (*r.pinned_bytes >= bytes) return TN_OK;
+  // the previous staging may still feed a copy in flight on this stream
+  hipStreamSynchronize(r.st);
+  if (*r.pinned) hipHostFree(*r.pinned);
+  *r.pinned = nullptr;
+  *r.pinned_bytes = 0;
   size_t nb = std::max(bytes, (size_t)1 << 20);
-  if (hipHostMalloc(&ctx->pinned, nb, hipHostMallocDefault) != hipSuccess) {
-    ctx->pinned = nullptr;
+  if (hipHostMalloc(r.pinned, nb, hipHostMallocDefault) != hipSuccess) {
+    *r.pinned = nullptr;
     set_error("hipHostMalloc of %zu bytes of pinned staging failed", nb);
     return TN_E_DEVICE;
   }
-  ctx->pinned_bytes = nb;
+  *r.pinned_bytes = nb;
   return TN_OK;
+}
+
+// Device bytes of one execution chunk of Q queries (carved in run_group).
+size_t group_workspace_bytes(const tn_plan *p, const ExecLayout &L, int Q) {
+  const int nn = 2 * p->nv - 1;
+  const size_t relems = result_elems(p);
+  const size_t final_bytes = p->fperm.needed ? rnd(relems * 8) : 0;
+  int max_blocks = 1;
+  for (const Node &n : p->nodes)
+    if (n.kind == NK_DOT) max_blocks = std::max(max_blocks, n.dot_blocks);
+  return rnd(L.shared_bytes) + rnd(rnd(L.perq_bytes) * Q) + rnd((size_t)nn * sizeof(Slot) * (Q + 1)) +
+         rnd((size_t)L.ovr_bytes * Q) + rnd(sizeof(Result) * Q) + rnd(final_bytes * Q) +
+         rnd((size_t)max_blocks * 16 * Q);
 }
 
 static void to_c64(const tn_leaf &l, int64_t n, float2 *dst) {
@@ -65,7 +80,7 @@ static void write_out(void *out, tn_dtype dt, size_t i, double re, double im) {
   } while (0)
 
 tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_dtype out_dtype,
-                    uint32_t flags, bool share, hipStream_t st) {
+                    uint32_t flags, bool share, ExecRes &rs) {
   const int nv = p->nv, nn = 2 * nv - 1;
   if (qs.empty()) return TN_OK;
   if (out_dtype != TN_C64 && out_dtype != TN_C128) {
@@ -102,12 +117,15 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   };
   std::shared_ptr<ExecLayout> Lp = cached_layout(p, ovr, share);
   const ExecLayout &L = *Lp;
-  Profiler &prof = ctx->prof;
+  Profiler idle_prof;
+  Profiler &prof = rs.prof ? *rs.prof : idle_prof;
+  const hipStream_t st = rs.st;
 
   // per-query override block: leaves in increasing id order
   const std::vector<int64_t> &ovr_off = L.ovr_off;
   const size_t ovr_bytes = (size_t)L.ovr_bytes;
   const bool trees = L.n_tree_shared + L.n_tree_perq > 0;
+  std::unique_lock<std::mutex> upload_lock(p->cache_mu);
   if (trees && L.tree_dev < 0) {
     // first use of this layout: upload its subtree programs
     ExecLayout &Lm = const_cast<ExecLayout &>(L);
@@ -127,6 +145,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       return TN_E_DEVICE;
     }
   }
+  upload_lock.unlock();
   // algorithmic traffic and work of the subtree kernel (for the profiler)
   double tree_bytes_sh = 0, tree_flops_sh = 0, tree_bytes_q = 0, tree_flops_q = 0;
   if (trees)
@@ -154,16 +173,25 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   const size_t shared_fixed = rnd(L.shared_bytes) + rnd(slot_bytes);
   const size_t per_query = perq + slot_bytes + ovr_bytes + sizeof(Result) + final_bytes +
                            (size_t)max_blocks * 16;
-  // queries per chunk that fit the arena
-  size_t avail = ctx->arena.largest_free();
-  if (avail < shared_fixed + per_query + 4096) {
-    set_error("arena too small: need %zu bytes for one query, largest free block %zu",
-              shared_fixed + per_query + 4096, avail);
-    return TN_E_NOMEM;
+  // queries per chunk that fit the arena (or the caller's reserved workspace)
+  size_t chunk;
+  if (rs.ws >= 0) {
+    if (group_workspace_bytes(p, L, (int)qs.size()) > rs.ws_bytes) {
+      set_error("reserved workspace too small for %zu queries", qs.size());
+      return TN_E_NOMEM;
+    }
+    chunk = qs.size();
+  } else {
+    size_t avail = ctx->arena.largest_free();
+    if (avail < shared_fixed + per_query + 4096) {
+      set_error("arena too small: need %zu bytes for one query, largest free block %zu",
+                shared_fixed + per_query + 4096, avail);
+      return TN_E_NOMEM;
+    }
+    chunk = (avail - shared_fixed - 4096) / (per_query + 1024);
+    chunk = std::min<size_t>(chunk, 65535);
+    chunk = std::max<size_t>(chunk, 1);
   }
-  size_t chunk = (avail - shared_fixed - 4096) / (per_query + 1024);
-  chunk = std::min<size_t>(chunk, 65535);
-  chunk = std::max<size_t>(chunk, 1);
   tn_status rc = TN_OK;
   for (size_t q0 = 0; q0 < qs.size() && rc == TN_OK; q0 += chunk) {
     const int Q = (int)std::min(chunk, qs.size() - q0);
@@ -182,7 +210,8 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     const size_t r_final = carve(final_bytes * Q);
     const size_t r_part = carve((size_t)max_blocks * 16 * Q);
     const size_t total = o;
-    int64_t ws = ctx->arena.alloc(total);
+    const bool own_ws = rs.ws < 0;
+    int64_t ws = own_ws ? ctx->arena.alloc(total) : rs.ws;
     if (ws < 0) {
       set_error("arena exhausted (%zu bytes requested)", total);
       return TN_E_NOMEM;
@@ -282,9 +311,9 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           }
         }
         if (any_staged) {
-          rc = ensure_pinned(ctx, ovr_bytes * Q);
+          rc = ensure_pinned(rs, ovr_bytes * Q);
           if (rc) goto done;
-          uint8_t *h = (uint8_t *)ctx->pinned;
+          uint8_t *h = (uint8_t *)*rs.pinned;
           for (int qi = 0; qi < Q; ++qi)
             for (size_t k = 0; k < no; ++k) {
               const int t = ovr[k];
@@ -462,9 +491,11 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       const bool dot_root = nv > 1 && p->nodes[p->root - nv].kind == NK_DOT;
       size_t rb_vals = (size_t)Q * relems * 8, rb_slots = (size_t)Q * sizeof(Slot),
              rb_res = (size_t)Q * sizeof(Result);
-      rc = ensure_pinned(ctx, rb_vals + rb_slots + rb_res);
+      // (growing the staging synchronizes the stream first: the override copy
+      // above may still read it)
+      rc = ensure_pinned(rs, rb_vals + rb_slots + rb_res);
       if (rc) goto done;
-      uint8_t *h = (uint8_t *)ctx->pinned;
+      uint8_t *h = (uint8_t *)*rs.pinned;
       float2 *hv = (float2 *)h;
       Slot *hs = (Slot *)(h + rb_vals);
       Result *hr = (Result *)(h + rb_vals + rb_slots);
@@ -526,7 +557,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       prof.pend.clear();
       prof.used = 0;
     }
-    ctx->arena.release(ws, total);
+    if (own_ws) ctx->arena.release(ws, total);
   }
   return rc;
 }

@@ -471,6 +471,7 @@ int gemm_variant_tile_n(int v) { return kVariants[v].tn; }
 
 hipError_t launch_gemm(hipStream_t st, const GemmArgs &g0, int prec, int form, int variant,
                        int nbatch) {
+  if (prec == kPrecBF16x3) return launch_gemm_bf16x3(st, g0, form, nbatch);
   if (prec != kPrecFP32) return hipErrorInvalidValue;
   GemmArgs g = g0;
   const int tm = kVariants[variant].tm, tn = kVariants[variant].tn;

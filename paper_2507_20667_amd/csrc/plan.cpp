@@ -292,8 +292,10 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
     n.opA = aMode;
   }
   if (permB) {
-    std::vector<int64_t> lab = sorder;
-    lab.insert(lab.end(), FB.begin(), FB.end());
+    // a permuted B is written [FB, S] (N x K, k contiguous): both GEMM
+    // operands then stream rows of consecutive k into the tile loaders
+    std::vector<int64_t> lab = FB;
+    lab.insert(lab.end(), sorder.begin(), sorder.end());
     n.pb.needed = true;
     n.pb.dst = make_layout(lab, A, B);
     if (!make_perm(B, n.pb.dst, n.pb.h)) {
@@ -301,7 +303,7 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
       return TN_E_INVALID_PLAN;
     }
     n.pb.desc_off = blob_put(p->desc_blob, n.pb.h);
-    n.opB = 0;
+    n.opB = 1;
   } else {
     n.opB = bMode;
   }
@@ -692,6 +694,16 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
   }
   select_trees(p, lay);
   p->plain = make_exec_layout(p, {}, false, false);
+  if (getenv("TN_DEBUG")) {
+    for (const Node &n : p->nodes)
+      if (n.kind == NK_GEMM)
+        fprintf(stderr, "[tn] gemm vertex %d: M %lld N %lld K %lld op %d%d perm %d%d variant %d\n",
+                n.id, (long long)n.M, (long long)n.N, (long long)n.K, n.opA, n.opB,
+                (int)n.pa.needed, (int)n.pb.needed, n.variant);
+    fprintf(stderr, "[tn] plan: %d vertices, %d gemm, %d stream, %d in subtrees (%zu roots)\n",
+            nv - 1, p->num_gemm, p->num_stream,
+            (int)std::count(p->in_tree.begin(), p->in_tree.end(), (char)1), p->tree_roots.size());
+  }
   return TN_OK;
 }
 

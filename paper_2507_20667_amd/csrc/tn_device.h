@@ -191,6 +191,7 @@ hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc
                           const float2 *in, int64_t ibs, float2 *out, int64_t obs, int nbatch);
 hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int prec, int form, int variant,
                        int nbatch);
+hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g, int form, int nbatch);
 hipError_t launch_dot(hipStream_t st, const DotDesc *d_desc, int64_t nelem, Operand A, Operand B,
                       OutOperand C, Result *res, int64_t rbs, double2 *partials, int nblocks,
                       int nbatch);

@@ -303,11 +303,23 @@ struct QueryIO {
   double *log2s = nullptr;
   tn_status *status = nullptr;
 };
+// Resources of one executing thread: its stream, its pinned staging, an
+// optional profiler and optionally a workspace reserved beforehand.
+struct ExecRes {
+  hipStream_t st = nullptr;
+  void **pinned = nullptr;
+  size_t *pinned_bytes = nullptr;
+  Profiler *prof = nullptr;
+  int64_t ws = -1;
+  size_t ws_bytes = 0;
+};
 tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_dtype out_dtype,
-                    uint32_t flags, bool share, hipStream_t st);
+                    uint32_t flags, bool share, ExecRes &res);
+size_t group_workspace_bytes(const tn_plan *p, const ExecLayout &L, int Q);
 size_t result_elems(const tn_plan *p);
 
 // serve.cpp
 void serve_shutdown(tn_ctx *ctx);
+int serve_pending_on(tn_ctx *ctx, const tn_plan *plan);
 
 }  // namespace tn

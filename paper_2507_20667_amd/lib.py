@@ -232,13 +232,14 @@ def tn_serve_submit(ctx, plan, overrides=None) -> int:
     return t.value
 
 
-def tn_serve_poll(ctx, ticket, result_shape=(), out_dtype=TN_C128):
-    """Returns (status, result or None, log2 scale, latency seconds)."""
+def tn_serve_poll(ctx, ticket, result_shape=(), out_dtype=TN_C128, keep_scale=False):
+    """Returns (status, result or None, log2 scale, latency seconds).  With
+    keep_scale the result is the mantissa and the scale is returned apart."""
     out = np.zeros(result_shape, dtype=np.complex128 if out_dtype == TN_C128 else np.complex64)
     l2 = ctypes.c_double(0.0)
     lat = ctypes.c_double(0.0)
     st = load().tn_serve_poll(ctypes.c_void_p(ctx), ctypes.c_uint64(ticket), _p(out), out_dtype,
-                              ctypes.byref(l2), ctypes.byref(lat))
+                              ctypes.byref(l2) if keep_scale else None, ctypes.byref(lat))
     if st < 0:
         raise TnError(st, tn_last_error())
     return st, (out if st == TN_OK else None), l2.value, lat.value

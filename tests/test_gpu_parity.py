@@ -228,3 +228,49 @@ def test_keep_scale_and_open_legs(ctx):
     assert err < FP32_TOL
     assert abs(np.sum(np.abs(full) ** 2) - 1) < 1e-5
     ctx.free_plan(p)
+
+
+@pytest.mark.parametrize("M,K,N,form", [(256, 64, 256, lib.TN_FORM_4M), (300, 37, 129, lib.TN_FORM_4M),
+                                         (512, 256, 96, lib.TN_FORM_3M), (130, 70, 200, lib.TN_FORM_3M),
+                                         (1024, 512, 1024, lib.TN_FORM_4M)])
+def test_gemm_vertex_bf16x3_against_fp64(ctx, M, K, N, form):
+    """Three-term split BF16: each real product a*b is carried as
+    ha*hb + ha*lb + la*hb with h = bf16(a), l = bf16(a - h), so the dropped
+    terms are below 2^-15 |a||b|; FP32 accumulation adds K * 2^-24.  Bound per
+    entry: 4 (2^-15 + K 2^-24) (|A||B|) for 4M, twice that for 3M (whose
+    products carry (Ar + Ai)(Br + Bi))."""
+    rng = np.random.default_rng(M * 7 + K + N)
+    A = rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
+    legs = [[1, 2], [2, 3]]
+    dims = {1: M, 2: K, 3: N}
+    p = ctx.plan_load(legs, dims, [A, B], [0, 1], 2, [(0, 1)], [1, 3], lib.TN_PREC_BF16X3 | form)
+    got, _ = lib.tn_contract(p, result_shape=(M, N))
+    A32 = A.astype(np.complex64).astype(np.complex128)
+    B32 = B.astype(np.complex64).astype(np.complex128)
+    ref = A32 @ B32
+    gamma = 4 * (2.0 ** -15 + K * 2.0 ** -24) * (2 if form == lib.TN_FORM_3M else 1)
+    bound = (np.abs(A32) @ np.abs(B32)) * gamma
+    assert np.all(np.abs(got - ref) <= bound)
+    # and it is not FP32-exact: the split really ran (the error is far above FP32 rounding)
+    assert np.max(np.abs(got - ref) / bound) > 1e-4
+    ctx.free_plan(p)
+
+
+@pytest.mark.parametrize("form", [lib.TN_FORM_4M, lib.TN_FORM_3M])
+def test_gemm_heavy_circuit_bf16x3(ctx, form):
+    circ = random_circuit(18, 12, 7)
+    net = amplitude_network(circ, 0)
+    plan = _plan_sa(net, 4, iters=3)
+    p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 4, plan.tree, None,
+                      lib.TN_PREC_BF16X3 | form)
+    worst = 0.0
+    for x in [0] + random_bitstrings(18, 3, 2):
+        ovr = amplitude_overrides(net, circ, x)
+        got, _ = lib.tn_contract(p, ovr)
+        ref = oracle.contract_tree(net.legs, net.dims, net.copy_with(ovr).tensors, plan.tree)
+        e = amp_err(got, ref, 18)
+        worst = max(worst, e)
+        assert e < 1e-3, (x, got, ref)
+    print("bf16x3 circuit max err", worst)
+    ctx.free_plan(p)
