@@ -409,36 +409,43 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         } else if (n.kind == NK_GEMM) {
           Operand A = operand(n.ga), B = operand(n.gb);
           uint8_t *pbase = sh ? shared_base : perq_base;
-          const int64_t pst = sh ? 0 : perq_el;
+          // batch stride of the staged copies: float2 entries, or bf16 entries
+          // for split planes
+          const int64_t pst = sh ? 0 : (n.planes > 0 ? perq_el * 4 : perq_el);
+          const void *ga = A.p, *gb = B.p;
+          int64_t gabs = A.bs, gbbs = B.bs;
+          const double pbytes = n.planes > 0 ? 8.0 + 2.0 * n.planes : 16.0;
           if (n.pa.needed) {
-            float2 *dst = (float2 *)(pbase + L.scr_a[j]);
-            TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, 16.0 * n.pa.h.nelem * nb, 0.0,
+            void *dst = pbase + L.scr_a[j];
+            TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, pbytes * n.pa.h.nelem * nb, 0.0,
                               [&] {
                                 return launch_permute(
                                     st, (const PermDesc *)(desc_base + n.pa.desc_off), n.pa.h,
-                                    A.p, A.bs, dst, pst, nb);
+                                    A.p, A.bs, dst, pst, nb, n.planes, n.pa.h.nelem, A.slot,
+                                    A.sbs);
                               }),
                    "permute A");
-            A.p = dst;
-            A.bs = pst;
+            ga = dst;
+            gabs = pst;
           }
           if (n.pb.needed) {
-            float2 *dst = (float2 *)(pbase + L.scr_b[j]);
-            TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, 16.0 * n.pb.h.nelem * nb, 0.0,
+            void *dst = pbase + L.scr_b[j];
+            TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, pbytes * n.pb.h.nelem * nb, 0.0,
                               [&] {
                                 return launch_permute(
                                     st, (const PermDesc *)(desc_base + n.pb.desc_off), n.pb.h,
-                                    B.p, B.bs, dst, pst, nb);
+                                    B.p, B.bs, dst, pst, nb, n.planes, n.pb.h.nelem, B.slot,
+                                    B.sbs);
                               }),
                    "permute B");
-            B.p = dst;
-            B.bs = pst;
+            gb = dst;
+            gbbs = pst;
           }
           OutOperand C = outop(n.id);
           GemmArgs g;
           memset(&g, 0, sizeof(g));
-          g.A = A.p;
-          g.B = B.p;
+          g.A = ga;
+          g.B = gb;
           g.C = C.p;
           g.sa = A.slot;
           g.sb = B.slot;
@@ -446,8 +453,8 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           g.lda = n.lda;
           g.ldb = n.ldb;
           g.ldc = n.ldc;
-          g.abs = A.bs;
-          g.bbs = B.bs;
+          g.abs = gabs;
+          g.bbs = gbbs;
           g.cbs = C.bs;
           g.sabs = A.sbs;
           g.sbbs = B.sbs;
@@ -457,6 +464,9 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           g.K = n.K;
           g.opA = n.opA;
           g.opB = n.opB;
+          g.planes = n.planes;
+          g.pa = n.M * n.K;
+          g.pb = n.N * n.K;
           const int prec = (p->flags & TN_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
           const int form = (p->flags & TN_FORM_3M) ? kForm3M : kForm4M;
           TN_HIP(prof.timed(st, TN_KCLASS_GEMM, nodeb, wflops,

@@ -8,12 +8,20 @@
 // 12 BF16 products per complex one) or the 3M form (T1 = ArBr, T2 = AiBi,
 // T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2, Im = T3 - T1 - T2: 9 products).
 //
+// The operands arrive already split, as bf16 planes with k contiguous
+// (A: [M][K], B: [N][K]; planes re-hi, re-lo, im-hi, im-lo [, sum-hi,
+// sum-lo]), written by the permutation kernel that puts them in GEMM order,
+// so the split costs one pass over each operand instead of one per tile.
+// That kernel also divides each operand by 2^e of its scale record, so the
+// planes hold values below 2 in magnitude and the products cannot overflow.
+//
 // Block = 4 waves in a 2 x 2 grid; each wave owns 64 x 64 outputs as 2 x 2
 // tiles of v_mfma_f32_32x32x16_bf16 (lane l supplies eight consecutive k of
 // row l%32 of A and of column l%32 of B; A and B use the same k mapping, so
-// the sum over k is the same whatever order the hardware assigns).  Tiles
-// are split while staged into LDS as bf16 planes [row][k], rows padded to 48
-// bytes so that the 16-byte fragment reads of 16 lanes hit distinct banks.
+// the sum over k is the same whatever order the hardware assigns).  Each
+// stage moves 16-byte plane vectors into LDS rows padded to 48 bytes (16
+// lanes of a fragment read hit distinct banks); the next stage's global loads
+// are in flight while the current one multiplies.
 #include "tn_device.h"
 
 namespace tn {
@@ -30,25 +38,8 @@ __device__ __forceinline__ int slot_exp_b(uint32_t bits) {
   return e - 127;
 }
 
-// bf16 bits of x rounded to nearest even (finite inputs)
-__device__ __forceinline__ uint32_t bf16_rne(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-
-__device__ __forceinline__ void split(float x, uint16_t &h, uint16_t &l) {
-  const uint32_t hb = bf16_rne(x);
-  h = (uint16_t)hb;
-  l = (uint16_t)bf16_rne(x - __uint_as_float(hb << 16));
-}
-
 constexpr int BK16 = 16;   // complex k per stage (one MFMA k-step)
 constexpr int ROWH = 24;   // bf16 per LDS row (16 used, 8 of padding)
-
-template <int FORM>
-struct Planes {
-  static constexpr int N = FORM == kForm3M ? 6 : 4;  // rh rl ih il [sh sl]
-};
 
 __device__ __forceinline__ v8bf ld8(const uint16_t *p) { return *(const v8bf *)p; }
 
@@ -58,26 +49,45 @@ __device__ __forceinline__ v8bf neg8(v8bf v) {
   return *(v8bf *)&u;
 }
 
+// 8 consecutive k of one plane row: a 16-byte load when aligned and in range,
+// else entry by entry with zeros past the edge
+__device__ __forceinline__ v4u load8(const uint16_t *row, int64_t k, int64_t K, bool vec_ok) {
+  if (vec_ok && k + 8 <= K) return *(const v4u *)(row + k);
+  uint16_t e[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) e[i] = (k + i < K) ? row[k + i] : (uint16_t)0;
+  v4u w;
+  w.x = e[0] | ((uint32_t)e[1] << 16);
+  w.y = e[2] | ((uint32_t)e[3] << 16);
+  w.z = e[4] | ((uint32_t)e[5] << 16);
+  w.w = e[6] | ((uint32_t)e[7] << 16);
+  return w;
+}
+
 template <int FORM>
 __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
-  constexpr int BM = 128, BN = 128, NP = Planes<FORM>::N;
+  constexpr int BM = 128, BN = 128, NP = FORM == kForm3M ? 6 : 4;
   constexpr int NACC = FORM == kForm3M ? 3 : 2;
   __shared__ __align__(16) uint16_t As[NP][BM * ROWH];
   __shared__ __align__(16) uint16_t Bs[NP][BN * ROWH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int q = blockIdx.y;
-  const float2 *A = g.A + q * g.abs;
-  const float2 *B = g.B + q * g.bbs;
+  const uint16_t *A = (const uint16_t *)g.A + q * g.abs;
+  const uint16_t *B = (const uint16_t *)g.B + q * g.bbs;
   float2 *C = g.C + q * g.cbs;
   const Slot *sa = g.sa + q * g.sabs;
   const Slot *sb = g.sb + q * g.sbbs;
   Slot *sc = g.sc + q * g.scbs;
-  const int64_t tile = blockIdx.x;
-  const int64_t m0 = (tile / g.tiles_n) * BM, n0 = (tile % g.tiles_n) * BN;
+  // XCD-aware order: blocks land on the 8 XCDs round-robin; give each XCD a
+  // contiguous run of tiles, M-tiles fastest, so that the tiles sharing a B
+  // panel run together on one XCD's L2
+  const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
+  int64_t t = blockIdx.x;
+  if (ntiles % 8 == 0 && ntiles >= 64) t = (t % 8) * (ntiles / 8) + t / 8;
+  const int64_t m0 = (t % g.tiles_m) * BM, n0 = (t / g.tiles_m) * BN;
   const int ea = slot_exp_b(sa->maxbits), eb = slot_exp_b(sb->maxbits);
-  const float fa = ldexpf(1.0f, -ea), fb = ldexpf(1.0f, -eb);
-  if (tile == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
+  if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
 
   v16f_b acc[2][2][NACC];
 #pragma unroll
@@ -89,84 +99,36 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[a][b][c][v] = 0.0f;
 
-  // staging: each thread handles 8 complex values of A and 8 of B per stage
-  // as (row, 8 consecutive k) when the operand is k-contiguous, otherwise
-  // element by element
+  // staging: thread -> (row tid/2, k offset 0 or 8) of each plane
   const int srow = tid >> 1, sk = (tid & 1) * 8;
+  const bool vec_ok = (g.K % 8) == 0;
+  const int64_t gm = m0 + srow, gn = n0 + srow;
+  const bool rowA = gm < g.M, rowB = gn < g.N;
+  const uint16_t *arow = A + gm * g.lda;
+  const uint16_t *brow = B + gn * g.ldb;
+  v4u ra[NP], rb[NP];
+  const v4u zero = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int pl = 0; pl < NP; ++pl) {
+    ra[pl] = rowA ? load8(arow + pl * g.pa, sk, g.K, vec_ok) : zero;
+    rb[pl] = rowB ? load8(brow + pl * g.pb, sk, g.K, vec_ok) : zero;
+  }
+  const int fr = lane & 31, fk = (lane >> 5) * 8;
   for (int64_t k0 = 0; k0 < g.K; k0 += BK16) {
-    // ---- A tile
-    {
-      float2 v[8];
-      const int64_t gm = m0 + srow;
-      if (g.opA == 0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t gk = k0 + sk + e;
-          v[e] = (gm < g.M && gk < g.K) ? A[gm * g.lda + gk] : make_float2(0.f, 0.f);
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t gk = k0 + sk + e;
-          v[e] = (gm < g.M && gk < g.K) ? A[gk * g.lda + gm] : make_float2(0.f, 0.f);
-        }
-      }
-      uint16_t p[NP][8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float re = v[e].x * fa, im = v[e].y * fa;
-        split(re, p[0][e], p[1][e]);
-        split(im, p[2][e], p[3][e]);
-        if (FORM == kForm3M) split(re + im, p[NP - 2][e], p[NP - 1][e]);
-      }
-#pragma unroll
-      for (int pl = 0; pl < NP; ++pl) {
-        v4u w;
-        w.x = p[pl][0] | ((uint32_t)p[pl][1] << 16);
-        w.y = p[pl][2] | ((uint32_t)p[pl][3] << 16);
-        w.z = p[pl][4] | ((uint32_t)p[pl][5] << 16);
-        w.w = p[pl][6] | ((uint32_t)p[pl][7] << 16);
-        *(v4u *)&As[pl][srow * ROWH + sk] = w;
-      }
-    }
-    // ---- B tile, stored [n][k]
-    {
-      float2 v[8];
-      const int64_t gn = n0 + srow;
-      if (g.opB == 1) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t gk = k0 + sk + e;
-          v[e] = (gn < g.N && gk < g.K) ? B[gn * g.ldb + gk] : make_float2(0.f, 0.f);
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t gk = k0 + sk + e;
-          v[e] = (gn < g.N && gk < g.K) ? B[gk * g.ldb + gn] : make_float2(0.f, 0.f);
-        }
-      }
-      uint16_t p[NP][8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float re = v[e].x * fb, im = v[e].y * fb;
-        split(re, p[0][e], p[1][e]);
-        split(im, p[2][e], p[3][e]);
-        if (FORM == kForm3M) split(re + im, p[NP - 2][e], p[NP - 1][e]);
-      }
-#pragma unroll
-      for (int pl = 0; pl < NP; ++pl) {
-        v4u w;
-        w.x = p[pl][0] | ((uint32_t)p[pl][1] << 16);
-        w.y = p[pl][2] | ((uint32_t)p[pl][3] << 16);
-        w.z = p[pl][4] | ((uint32_t)p[pl][5] << 16);
-        w.w = p[pl][6] | ((uint32_t)p[pl][7] << 16);
-        *(v4u *)&Bs[pl][srow * ROWH + sk] = w;
-      }
+    for (int pl = 0; pl < NP; ++pl) {
+      *(v4u *)&As[pl][srow * ROWH + sk] = ra[pl];
+      *(v4u *)&Bs[pl][srow * ROWH + sk] = rb[pl];
     }
     __syncthreads();
-    // ---- MFMA: lane reads row l%32, k = 8*(l/32) .. +7 of each plane
-    const int fr = lane & 31, fk = (lane >> 5) * 8;
+    if (k0 + BK16 < g.K) {
+      const int64_t kn = k0 + BK16 + sk;
+#pragma unroll
+      for (int pl = 0; pl < NP; ++pl) {
+        ra[pl] = rowA ? load8(arow + pl * g.pa, kn, g.K, vec_ok) : zero;
+        rb[pl] = rowB ? load8(brow + pl * g.pb, kn, g.K, vec_ok) : zero;
+      }
+    }
     v8bf a[2][NP], b[2][NP];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
@@ -224,7 +186,7 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
       for (int v = 0; v < 16; ++v) {
         const int row = wm * 64 + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
         const int col = wn * 64 + nb * 32 + (lane & 31);
-        const int64_t gm = m0 + row, gn = n0 + col;
+        const int64_t cm = m0 + row, cn = n0 + col;
         float re, im;
         if (FORM == kForm4M) {
           re = acc[mb][nb][0][v];
@@ -234,8 +196,8 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
           re = t1 - t2;
           im = t3 - t1 - t2;
         }
-        if (gm < g.M && gn < g.N) {
-          C[gm * g.ldc + gn] = make_float2(re, im);
+        if (cm < g.M && cn < g.N) {
+          C[cm * g.ldc + cn] = make_float2(re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
       }
@@ -246,6 +208,7 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
 
 hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g0, int form, int nbatch) {
   GemmArgs g = g0;
+  if (g.opA != 0 || g.opB != 1 || g.planes != (form == kForm3M ? 6 : 4)) return hipErrorInvalidValue;
   g.tiles_m = (int)((g.M + 127) / 128);
   g.tiles_n = (int)((g.N + 127) / 128);
   const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;

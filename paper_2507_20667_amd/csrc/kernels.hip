@@ -174,17 +174,60 @@ hipError_t launch_stream(hipStream_t st, const StreamDesc *d_desc, int64_t nfib,
 }
 
 // -------------------------------------------------------------- permutation
+// The output is either complex64 (NP = 0) or, for the split-BF16 GEMM, NP
+// bf16 planes (re hi, re lo, im hi, im lo [, (re+im) hi, (re+im) lo]) each
+// with the output's element order, `pstride` entries apart: the split runs
+// once per element here instead of once per GEMM tile that reads it.
+template <int NP>
+__device__ __forceinline__ void perm_emit(void *out, int64_t pstride, int64_t idx, float2 v,
+                                          float fs) {
+  if (NP == 0) {
+    ((float2 *)out)[idx] = v;
+  } else {
+    uint16_t *o = (uint16_t *)out;
+    uint16_t h, l;
+    v.x *= fs;
+    v.y *= fs;
+    tn_split_bf16(v.x, h, l);
+    o[idx] = h;
+    o[pstride + idx] = l;
+    tn_split_bf16(v.y, h, l);
+    o[2 * pstride + idx] = h;
+    o[3 * pstride + idx] = l;
+    if (NP == 6) {
+      tn_split_bf16(v.x + v.y, h, l);
+      o[4 * pstride + idx] = h;
+      o[5 * pstride + idx] = l;
+    }
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void *perm_out_base(void *out, int64_t obs, int q) {
+  return NP == 0 ? (void *)((float2 *)out + q * obs) : (void *)((uint16_t *)out + q * obs);
+}
+
+// Split planes carry the operand divided by 2^e (e from its scale record), as
+// the GEMM that reads them expects; complex64 output is copied unscaled.
+template <int NP>
+__device__ __forceinline__ float perm_scale(const Slot *sl, int64_t sbs, int q) {
+  return NP == 0 ? 1.0f : ldexpf(1.0f, -slot_exp(sl[q * sbs].maxbits));
+}
+
 // Generic: one thread per output element; writes are contiguous, reads follow
 // the map.  Used for small tensors, non-power-of-two legs and permutations
 // that keep the innermost legs in place (then reads are contiguous too).
+template <int NP>
 __global__ __launch_bounds__(256) void k_perm_generic(const PermDesc *__restrict__ d,
-                                                      const float2 *in, int64_t ibs, float2 *out,
-                                                      int64_t obs) {
+                                                      const float2 *in, int64_t ibs, void *out,
+                                                      int64_t obs, int64_t pstride,
+                                                      const Slot *sl, int64_t sbs) {
   __shared__ SegLds L;
   const int tid = threadIdx.x;
   const int q = blockIdx.y;
   in += q * ibs;
-  out += q * obs;
+  void *ob = perm_out_base<NP>(out, obs, q);
+  const float fs = perm_scale<NP>(sl, sbs, q);
   seg_stage(L, d->map, tid);
   __syncthreads();
   const int nseg = d->map.nseg;
@@ -193,7 +236,7 @@ __global__ __launch_bounds__(256) void k_perm_generic(const PermDesc *__restrict
   for (int64_t o = (int64_t)blockIdx.x * 256 + tid; o < n; o += (int64_t)gridDim.x * 256) {
     int64_t io, oo;
     seg_decode(L, nseg, p2, o, io, oo);
-    out[oo] = in[io];
+    perm_emit<NP>(ob, pstride, oo, in[io], fs);
   }
 }
 
@@ -213,13 +256,16 @@ struct BitTile {
   int32_t o_out[48];   // outer bit -> output bit
 };
 
+template <int NP>
 __global__ __launch_bounds__(256) void k_perm_tiled(BitTile t, const float2 *in, int64_t ibs,
-                                                    float2 *out, int64_t obs) {
+                                                    void *out, int64_t obs, int64_t pstride,
+                                                    const Slot *sl, int64_t sbs) {
   __shared__ float2 tile[1024 + 32];
   const int tid = threadIdx.x;
   const int q = blockIdx.y;
   in += q * ibs;
-  out += q * obs;
+  void *ob = perm_out_base<NP>(out, obs, q);
+  const float fs = perm_scale<NP>(sl, sbs, q);
   const int nt = 1 << t.nu;
   // per-thread offsets of the tile elements this thread loads and stores
   int64_t lin[4], lout[4];
@@ -253,7 +299,7 @@ __global__ __launch_bounds__(256) void k_perm_tiled(BitTile t, const float2 *in,
       }
     for (int c = 0; c < cnt; ++c) tile[le[c]] = in[bin + lin[c]];
     __syncthreads();
-    for (int c = 0; c < cnt; ++c) out[bout + lout[c]] = tile[ge[c]];
+    for (int c = 0; c < cnt; ++c) perm_emit<NP>(ob, pstride, bout + lout[c], tile[ge[c]], fs);
     __syncthreads();
   }
 }
@@ -315,16 +361,29 @@ static bool build_bit_tile(const PermDesc &h, BitTile &t) {
 }
 
 hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc &h, const float2 *in,
-                          int64_t ibs, float2 *out, int64_t obs, int nbatch) {
+                          int64_t ibs, void *out, int64_t obs, int nbatch, int np,
+                          int64_t pstride, const Slot *sl, int64_t sbs) {
+  if (np != 0 && np != 4 && np != 6) return hipErrorInvalidValue;
+  if (np != 0 && (!sl || pstride < h.nelem)) return hipErrorInvalidValue;
   BitTile t;
   if (h.nelem >= 4096 && build_bit_tile(h, t)) {
     const int64_t ntiles = (int64_t)1 << t.nouter;
     const dim3 grid(grid_for(ntiles, 1, 8192), nbatch);
-    hipLaunchKernelGGL(k_perm_tiled, grid, dim3(256), 0, st, t, in, ibs, out, obs);
+    if (np == 0)
+      hipLaunchKernelGGL(k_perm_tiled<0>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs);
+    else if (np == 4)
+      hipLaunchKernelGGL(k_perm_tiled<4>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs);
+    else
+      hipLaunchKernelGGL(k_perm_tiled<6>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs);
     return hipGetLastError();
   }
   const dim3 grid(grid_for(h.nelem, 256, 16384), nbatch);
-  hipLaunchKernelGGL(k_perm_generic, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs);
+  if (np == 0)
+    hipLaunchKernelGGL(k_perm_generic<0>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs);
+  else if (np == 4)
+    hipLaunchKernelGGL(k_perm_generic<4>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs);
+  else
+    hipLaunchKernelGGL(k_perm_generic<6>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs);
   return hipGetLastError();
 }
 
@@ -343,8 +402,8 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int q = blockIdx.y;
-  const float2 *A = g.A + q * g.abs;
-  const float2 *B = g.B + q * g.bbs;
+  const float2 *A = (const float2 *)g.A + q * g.abs;
+  const float2 *B = (const float2 *)g.B + q * g.bbs;
   float2 *C = g.C + q * g.cbs;
   const Slot *sa = g.sa + q * g.sabs;
   const Slot *sb = g.sb + q * g.sbbs;

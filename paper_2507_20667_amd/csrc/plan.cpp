@@ -254,7 +254,14 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   int bMode = block_at_start(B, S) ? 0 : (block_at_end(B, S) ? 1 : -1);   // 0: N, 1: T
   std::vector<int64_t> sorder;
   bool permA = aMode < 0, permB = bMode < 0;
-  if (!permA && !permB) {
+  // the split-BF16 GEMM reads both operands as k-contiguous bf16 planes, which
+  // the permutation kernel writes (an identity map where the order is right)
+  n.planes = 0;
+  if (p->flags & TN_PREC_BF16X3) {
+    n.planes = (p->flags & TN_FORM_3M) ? 6 : 4;
+    sorder = !permA || permB ? sA : sB;
+    permA = permB = true;
+  } else if (!permA && !permB) {
     if (sA != sB) {
       if (A.size() <= B.size()) {
         permA = true;
@@ -1165,13 +1172,15 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
     L.off[n.id] = P.alloc(out_bytes);
     std::vector<std::pair<int64_t, int64_t>> tmp;
     if (n.kind == NK_GEMM) {
+      // complex64 (8 bytes an entry) or split planes (2 bytes a plane)
+      const int64_t eb = n.planes > 0 ? 2 * n.planes : 8;
       if (n.pa.needed) {
-        L.scr_a[j] = P.alloc(n.pa.h.nelem * 8);
-        tmp.push_back({L.scr_a[j], n.pa.h.nelem * 8});
+        L.scr_a[j] = P.alloc(n.pa.h.nelem * eb);
+        tmp.push_back({L.scr_a[j], n.pa.h.nelem * eb});
       }
       if (n.pb.needed) {
-        L.scr_b[j] = P.alloc(n.pb.h.nelem * 8);
-        tmp.push_back({L.scr_b[j], n.pb.h.nelem * 8});
+        L.scr_b[j] = P.alloc(n.pb.h.nelem * eb);
+        tmp.push_back({L.scr_b[j], n.pb.h.nelem * eb});
       }
     } else if (n.kind == NK_DOT) {
       L.partial[j] = P.alloc((int64_t)n.dot_blocks * 16);

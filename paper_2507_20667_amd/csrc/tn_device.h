@@ -69,9 +69,12 @@ struct DotDesc {
 // opA = 0: A is M x K row-major (lda >= K); 1: A is stored K x M (lda >= M).
 // opB = 0: B is K x N row-major (ldb >= N); 1: B is stored N x K (ldb >= K).
 // Batched over gridDim.y with element strides *bs (0 = shared operand).
+// planes > 0: A and B are instead `planes` bf16 planes each (the split form of
+// the three-term BF16 product), with opA = 0 and opB = 1; pa / pb are the plane
+// strides and lda / ldb / abs / bbs count bf16 entries.
 struct GemmArgs {
-  const float2 *A;
-  const float2 *B;
+  const void *A;
+  const void *B;
   float2 *C;
   const Slot *sa;
   const Slot *sb;
@@ -82,6 +85,8 @@ struct GemmArgs {
   int64_t M, N, K;
   int32_t opA, opB;
   int32_t tiles_m, tiles_n;
+  int32_t planes, pad;
+  int64_t pa, pb;
 };
 
 // One operand of a batched launch: base pointer plus per-query stride.
@@ -180,6 +185,18 @@ struct TreeLaunch {
   int32_t qw;           // queries per workgroup
 };
 
+// Split x = h + l with h = bf16(x) and l = bf16(x - h), both rounded to nearest
+// even (finite inputs): the two terms carry 16 significant bits of x.
+__device__ __forceinline__ uint32_t tn_bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ void tn_split_bf16(float x, uint16_t &h, uint16_t &l) {
+  const uint32_t hb = tn_bf16_rne(x);
+  h = (uint16_t)hb;
+  l = (uint16_t)tn_bf16_rne(x - __uint_as_float(hb << 16));
+}
+
 enum GemmForm { kForm4M = 0, kForm3M = 1 };
 enum GemmPrec { kPrecFP32 = 0, kPrecBF16x3 = 1 };
 
@@ -187,8 +204,13 @@ enum GemmPrec { kPrecFP32 = 0, kPrecBF16x3 = 1 };
 hipError_t launch_init_slots(hipStream_t st, Slot *slots, int64_t n);
 hipError_t launch_stream(hipStream_t st, const StreamDesc *d_desc, int64_t nfib, int ns,
                          Operand X, Operand Y, OutOperand C, int nbatch);
+// out: complex64 (np = 0) or np bf16 planes `pstride` entries apart, holding
+// the input divided by 2^e of its scale record `sl` (query stride sbs); obs in
+// units of the output's entries (float2, or uint16 for planes)
 hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc &h_desc,
-                          const float2 *in, int64_t ibs, float2 *out, int64_t obs, int nbatch);
+                          const float2 *in, int64_t ibs, void *out, int64_t obs, int nbatch,
+                          int np = 0, int64_t pstride = 0, const Slot *sl = nullptr,
+                          int64_t sbs = 0);
 hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int prec, int form, int variant,
                        int nbatch);
 hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g, int form, int nbatch);

@@ -78,6 +78,7 @@ struct Node {
   int ga = 0, gb = 0;
   PermStep pa, pb;
   int opA = 0, opB = 0;
+  int planes = 0;    // > 0: both operands staged as split-BF16 planes
   int64_t M = 0, N = 0, K = 0, lda = 0, ldb = 0, ldc = 0;
   int variant = 0;
   // NK_DOT
