@@ -111,6 +111,8 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       ovr.push_back(t);
     }
   const bool dbg = getenv("TN_DEBUG") != nullptr;
+  // TN_DEBUG=gemm: also time every GEMM launch on its own (synchronizing)
+  const bool dbg_gemm = dbg && strcmp(getenv("TN_DEBUG"), "gemm") == 0;
   const auto t_enter = std::chrono::steady_clock::now();
   auto ms_since = [](std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -467,11 +469,23 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           g.planes = n.planes;
           g.pa = n.M * n.K;
           g.pb = n.N * n.K;
+          g.ksplit = n.ksplit;
+          g.kchunk = n.kchunk;
+          if (n.ksplit > 1) {
+            g.part = (float2 *)(pbase + L.partial[j]);
+            g.partbs = sh ? 0 : perq_el;
+          }
           const int prec = (p->flags & TN_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
           const int form = (p->flags & TN_FORM_3M) ? kForm3M : kForm4M;
+          const auto tg = std::chrono::steady_clock::now();
           TN_HIP(prof.timed(st, TN_KCLASS_GEMM, nodeb, wflops,
                             [&] { return launch_gemm(st, g, prec, form, n.variant, nb); }),
                  "complex GEMM");
+          if (dbg_gemm) {
+            hipStreamSynchronize(st);
+            fprintf(stderr, "[tn] gemm M %lld N %lld K %lld batch %d: %.3f ms\n", (long long)n.M,
+                    (long long)n.N, (long long)n.K, nb, ms_since(tg));
+          }
         } else {
           const bool is_root = n.id == p->root;
           TN_HIP(prof.timed(st, TN_KCLASS_DOT, nodeb, wflops,

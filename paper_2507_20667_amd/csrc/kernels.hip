@@ -408,11 +408,16 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
   const Slot *sa = g.sa + q * g.sabs;
   const Slot *sb = g.sb + q * g.sbbs;
   Slot *sc = g.sc + q * g.scbs;
-  const int64_t tile = blockIdx.x;
+  // block -> (k chunk ks, tile)
+  const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
+  const int ks = (int)(blockIdx.x / ntiles);
+  const int64_t tile = blockIdx.x - (int64_t)ks * ntiles;
   const int64_t m0 = (tile / g.tiles_n) * BM, n0 = (tile % g.tiles_n) * BN;
+  const int64_t kbeg = (int64_t)ks * g.kchunk;
+  const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
   const int ea = slot_exp(sa->maxbits), eb = slot_exp(sb->maxbits);
   const float fa = ldexpf(1.0f, -ea), fb = ldexpf(1.0f, -eb);
-  if (tile == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
+  if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
 
   v16f acc[WM][WN][NACC];
 #pragma unroll
@@ -424,7 +429,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[a][b][c][v] = 0.0f;
 
-  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
     for (int i = 0; i < BM * BK / 256; ++i) {
       const int e = tid + 256 * i;
@@ -438,7 +443,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
       }
       const int64_t gm = m0 + m, gk = k0 + k;
       float2 v = make_float2(0.0f, 0.0f);
-      if (gm < g.M && gk < g.K) v = g.opA == 0 ? A[gm * g.lda + gk] : A[gk * g.lda + gm];
+      if (gm < g.M && gk < kend) v = g.opA == 0 ? A[gm * g.lda + gk] : A[gk * g.lda + gm];
       As[k][m] = make_float2(v.x * fa, v.y * fa);
     }
 #pragma unroll
@@ -454,7 +459,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
       }
       const int64_t gn = n0 + n, gk = k0 + k;
       float2 v = make_float2(0.0f, 0.0f);
-      if (gn < g.N && gk < g.K) v = g.opB == 0 ? B[gk * g.ldb + gn] : B[gn * g.ldb + gk];
+      if (gn < g.N && gk < kend) v = g.opB == 0 ? B[gk * g.ldb + gn] : B[gn * g.ldb + gk];
       Bs[k][n] = make_float2(v.x * fb, v.y * fb);
     }
     __syncthreads();
@@ -492,6 +497,10 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
     __syncthreads();
   }
 
+  // C (and the max for the scale record), or a split-k partial
+  const bool partial = g.ksplit > 1;
+  if (partial) C = g.part + q * g.partbs + (int64_t)ks * g.M * g.N;
+  const int64_t ldc = partial ? g.N : g.ldc;
   float mx = 0.0f;
 #pragma unroll
   for (int mb = 0; mb < WM; ++mb)
@@ -512,11 +521,50 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
           im = t3 - t1 - t2;
         }
         if (gm < g.M && gn < g.N) {
-          C[gm * g.ldc + gn] = make_float2(re, im);
+          C[gm * ldc + gn] = make_float2(re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
       }
-  wave_atomic_max(&sc->maxbits, mx);
+  if (!partial) wave_atomic_max(&sc->maxbits, mx);
+}
+
+// Split-k reduction: C[m][n] = sum over chunks s (in order) of the partials,
+// and the max for C's scale record.
+__global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
+  const int q = blockIdx.y;
+  const int64_t mn = g.M * g.N;
+  const float2 *P = g.part + q * g.partbs;
+  float2 *C = g.C + q * g.cbs;
+  float mx = 0.0f;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mn; e += (int64_t)gridDim.x * 256) {
+    float2 s = P[e];
+    for (int c = 1; c < g.ksplit; ++c) {
+      const float2 v = P[(int64_t)c * mn + e];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    C[(e / g.N) * g.ldc + e % g.N] = s;
+    mx = fmaxf(mx, fmaxf(fabsf(s.x), fabsf(s.y)));
+  }
+  wave_atomic_max(&(g.sc + q * g.scbs)->maxbits, mx);
+}
+
+hipError_t launch_splitk_reduce(hipStream_t st, const GemmArgs &g, int nbatch) {
+  const dim3 grid(grid_for(g.M * g.N, 256, 4096), nbatch);
+  hipLaunchKernelGGL(k_splitk_reduce, grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+// Split k when the output tiles alone cannot fill the chip: aim at about 512
+// blocks, each chunk at least 1024 deep and a multiple of 32.
+int gemm_ksplit(int64_t M, int64_t N, int64_t K, int tile_m, int tile_n, int64_t *kchunk) {
+  const int64_t tiles = ((M + tile_m - 1) / tile_m) * ((N + tile_n - 1) / tile_n);
+  int s = 1;
+  while (tiles * s * 2 <= 512 && K / (s * 2) >= 1024 && s < 64) s *= 2;
+  int64_t kc = (K + s - 1) / s;
+  kc = (kc + 31) / 32 * 32;
+  if (kchunk) *kchunk = kc;
+  return (int)((K + kc - 1) / kc);
 }
 
 struct GemmVariant {
@@ -536,7 +584,11 @@ hipError_t launch_gemm(hipStream_t st, const GemmArgs &g0, int prec, int form, i
   const int tm = kVariants[variant].tm, tn = kVariants[variant].tn;
   g.tiles_m = (int)((g.M + tm - 1) / tm);
   g.tiles_n = (int)((g.N + tn - 1) / tn);
-  const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
+  if (g.ksplit < 1) g.ksplit = 1;
+  if (g.ksplit == 1) g.kchunk = g.K;
+  if (g.kchunk < 1 || (int64_t)g.ksplit * g.kchunk < g.K || (g.ksplit > 1 && !g.part))
+    return hipErrorInvalidValue;
+  const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n * g.ksplit;
   if (tiles <= 0 || tiles > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)tiles, nbatch);
   if (variant == 0) {
@@ -550,7 +602,9 @@ hipError_t launch_gemm(hipStream_t st, const GemmArgs &g0, int prec, int form, i
     else
       hipLaunchKernelGGL((k_cgemm_f32<1, 1, kForm3M>), grid, dim3(256), 0, st, g);
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || g.ksplit == 1) return e;
+  return launch_splitk_reduce(st, g, nbatch);
 }
 
 // ------------------------------------------------------------------- dot

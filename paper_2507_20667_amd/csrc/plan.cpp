@@ -321,6 +321,10 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   out.insert(out.end(), FB.begin(), FB.end());
   n.out = make_layout(out, A, B);
   n.variant = (n.M >= 128 && n.N >= 128) ? 0 : 1;
+  {
+    const int tile = n.planes > 0 ? 128 : gemm_variant_tile_m(n.variant);
+    n.ksplit = gemm_ksplit(n.M, n.N, n.K, tile, tile, &n.kchunk);
+  }
   p->num_perm += (int)permA + (int)permB;
   return TN_OK;
 }
@@ -704,9 +708,9 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
   if (getenv("TN_DEBUG")) {
     for (const Node &n : p->nodes)
       if (n.kind == NK_GEMM)
-        fprintf(stderr, "[tn] gemm vertex %d: M %lld N %lld K %lld op %d%d perm %d%d variant %d\n",
+        fprintf(stderr, "[tn] gemm vertex %d: M %lld N %lld K %lld op %d%d perm %d%d variant %d ksplit %d\n",
                 n.id, (long long)n.M, (long long)n.N, (long long)n.K, n.opA, n.opB,
-                (int)n.pa.needed, (int)n.pb.needed, n.variant);
+                (int)n.pa.needed, (int)n.pb.needed, n.variant, n.ksplit);
     fprintf(stderr, "[tn] plan: %d vertices, %d gemm, %d stream, %d in subtrees (%zu roots)\n",
             nv - 1, p->num_gemm, p->num_stream,
             (int)std::count(p->in_tree.begin(), p->in_tree.end(), (char)1), p->tree_roots.size());
@@ -1181,6 +1185,11 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
       if (n.pb.needed) {
         L.scr_b[j] = P.alloc(n.pb.h.nelem * eb);
         tmp.push_back({L.scr_b[j], n.pb.h.nelem * eb});
+      }
+      if (n.ksplit > 1) {
+        const int64_t pb = (int64_t)n.ksplit * n.M * n.N * 8;
+        L.partial[j] = P.alloc(pb);
+        tmp.push_back({L.partial[j], pb});
       }
     } else if (n.kind == NK_DOT) {
       L.partial[j] = P.alloc((int64_t)n.dot_blocks * 16);

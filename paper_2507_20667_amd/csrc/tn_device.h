@@ -72,6 +72,9 @@ struct DotDesc {
 // planes > 0: A and B are instead `planes` bf16 planes each (the split form of
 // the three-term BF16 product), with opA = 0 and opB = 1; pa / pb are the plane
 // strides and lda / ldb / abs / bbs count bf16 entries.
+// ksplit > 1: the k range is cut into ksplit chunks of kchunk; chunk s of batch
+// q writes its M x N partial product (row-major) to part + q * partbs + s * M * N
+// and launch_gemm follows with a reduction into C (fixed order: deterministic).
 struct GemmArgs {
   const void *A;
   const void *B;
@@ -85,8 +88,10 @@ struct GemmArgs {
   int64_t M, N, K;
   int32_t opA, opB;
   int32_t tiles_m, tiles_n;
-  int32_t planes, pad;
+  int32_t planes, ksplit;
   int64_t pa, pb;
+  float2 *part;
+  int64_t partbs, kchunk;
 };
 
 // One operand of a batched launch: base pointer plus per-query stride.
@@ -214,6 +219,9 @@ hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc
 hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int prec, int form, int variant,
                        int nbatch);
 hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g, int form, int nbatch);
+hipError_t launch_splitk_reduce(hipStream_t st, const GemmArgs &g, int nbatch);
+// k chunks of a GEMM with tiles_m x tiles_n output tiles (1: no split)
+int gemm_ksplit(int64_t M, int64_t N, int64_t K, int tile_m, int tile_n, int64_t *kchunk);
 hipError_t launch_dot(hipStream_t st, const DotDesc *d_desc, int64_t nelem, Operand A, Operand B,
                       OutOperand C, Result *res, int64_t rbs, double2 *partials, int nblocks,
                       int nbatch);

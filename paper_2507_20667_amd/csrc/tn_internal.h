@@ -79,6 +79,8 @@ struct Node {
   PermStep pa, pb;
   int opA = 0, opB = 0;
   int planes = 0;    // > 0: both operands staged as split-BF16 planes
+  int ksplit = 1;    // k chunks (partials reduced after the GEMM)
+  int64_t kchunk = 0;
   int64_t M = 0, N = 0, K = 0, lda = 0, ldb = 0, ldc = 0;
   int variant = 0;
   // NK_DOT
@@ -93,7 +95,7 @@ struct Node {
 struct ExecLayout {
   std::vector<int64_t> off;       // per tensor id: byte offset in its part (-1: leaf region)
   std::vector<uint8_t> shared;    // per tensor id
-  std::vector<int64_t> scr_a, scr_b, partial;  // per node index j
+  std::vector<int64_t> scr_a, scr_b, partial;  // per node index j (partial: dot blocks or split-k)
   std::vector<int64_t> ovr_off;   // per leaf: offset of its per-query override copy, or -1
   int64_t shared_bytes = 0;
   int64_t perq_bytes = 0;

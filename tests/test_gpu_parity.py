@@ -176,7 +176,9 @@ def test_permutation_is_bit_exact(ctx, shape, perm):
 
 @pytest.mark.parametrize("M,K,N,form", [(256, 64, 256, lib.TN_FORM_4M), (300, 37, 129, lib.TN_FORM_4M),
                                          (96, 1, 80, lib.TN_FORM_4M), (512, 256, 96, lib.TN_FORM_3M),
-                                         (130, 70, 200, lib.TN_FORM_3M)])
+                                         (130, 70, 200, lib.TN_FORM_3M),
+                                         # few output tiles, deep k: split into k chunks
+                                         (64, 4100, 96, lib.TN_FORM_4M), (100, 8192, 70, lib.TN_FORM_3M)])
 def test_gemm_vertex_against_fp64(ctx, M, K, N, form):
     """Two tensors A(m, k) and B(k, n) with an open output: one GEMM vertex.
     Error bound |dC| <= gamma * |A||B| with gamma = 4 * K * 2^-24 (FP32 inputs
@@ -232,7 +234,10 @@ def test_keep_scale_and_open_legs(ctx):
 
 @pytest.mark.parametrize("M,K,N,form", [(256, 64, 256, lib.TN_FORM_4M), (300, 37, 129, lib.TN_FORM_4M),
                                          (512, 256, 96, lib.TN_FORM_3M), (130, 70, 200, lib.TN_FORM_3M),
-                                         (1024, 512, 1024, lib.TN_FORM_4M)])
+                                         (1024, 512, 1024, lib.TN_FORM_4M),
+                                         # split into k chunks (aligned, ragged and unaligned k)
+                                         (64, 4096, 96, lib.TN_FORM_4M), (200, 3000, 130, lib.TN_FORM_3M),
+                                         (64, 2050, 64, lib.TN_FORM_4M)])
 def test_gemm_vertex_bf16x3_against_fp64(ctx, M, K, N, form):
     """Three-term split BF16: each real product a*b is carried as
     ha*hb + ha*lb + la*hb with h = bf16(a), l = bf16(a - h), so the dropped
