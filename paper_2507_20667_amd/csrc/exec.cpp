@@ -14,6 +14,19 @@
 
 namespace tn {
 
+// k-tiled output order of a GEMM operand's split planes (rows = M or N)
+static KTile ktile_of(const Node &n, int64_t rows) {
+  KTile t{0, 0, -1, 0};
+  if (!n.ktile) return t;
+  t.rows = rows;
+  t.kdim = n.K;
+  t.on = 1;
+  if ((n.K & (n.K - 1)) == 0)
+    for (t.kshift = 0; ((int64_t)1 << t.kshift) < n.K; ++t.kshift) {
+    }
+  return t;
+}
+
 size_t result_elems(const tn_plan *p) {
   return p->closed ? 1 : (size_t)p->result_layout.size();
 }
@@ -424,7 +437,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                                 return launch_permute(
                                     st, (const PermDesc *)(desc_base + n.pa.desc_off), n.pa.h,
                                     A.p, A.bs, dst, pst, nb, n.planes, n.pa.h.nelem, A.slot,
-                                    A.sbs);
+                                    A.sbs, ktile_of(n, n.M));
                               }),
                    "permute A");
             ga = dst;
@@ -437,7 +450,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                                 return launch_permute(
                                     st, (const PermDesc *)(desc_base + n.pb.desc_off), n.pb.h,
                                     B.p, B.bs, dst, pst, nb, n.planes, n.pb.h.nelem, B.slot,
-                                    B.sbs);
+                                    B.sbs, ktile_of(n, n.N));
                               }),
                    "permute B");
             gb = dst;
@@ -470,6 +483,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           g.pa = n.M * n.K;
           g.pb = n.N * n.K;
           g.ksplit = n.ksplit;
+          g.ktile = n.ktile ? 1 : 0;
           g.kchunk = n.kchunk;
           if (n.ksplit > 1) {
             g.part = (float2 *)(pbase + L.partial[j]);

@@ -20,12 +20,15 @@
 // eight consecutive k of row l%32 of A and of column l%32 of B; A and B use
 // the same k mapping, so the sum over k is the same whatever order the
 // hardware assigns).  A stage covers 32 k: each plane row is 64 bytes of LDS,
-// its four 16-byte chunks stored in the order chunk ^ ((row / 2) % 4) so that
-// the eight rows a group of lanes reads fall on distinct banks.  Global loads
+// its four 16-byte chunks stored in the order chunk ^ swz(row), chosen so that
+// the rows read together by one 16-byte-per-lane LDS access (8 rows on 32
+// banks, 16 rows on 64 banks) fall on distinct banks.  Global loads
 // of the next stage are issued before the current stage's products; the 4M
 // form double-buffers LDS (one barrier a stage), the 3M form, with six planes,
 // has room for one buffer.  Consecutive products go to different accumulators
 // so that no MFMA waits on the previous one.
+#include <type_traits>
+
 #include "tn_device.h"
 
 namespace tn {
@@ -47,6 +50,13 @@ constexpr int BKS = 32;     // k per stage
 constexpr int ROWE = BKS;   // bf16 per LDS row (no padding: swizzled chunks)
 
 __device__ __forceinline__ v8bf as_bf(v4u u) { return *(v8bf *)&u; }
+
+// Chunk swizzle of LDS row r (rows are 64 bytes, 4 chunks): (b3 ^ b1, b2) of
+// r's bits.  Rows r..r+15 then cover every (r % 4, chunk slot) pair once, and
+// rows r..r+7 every (r % 2, chunk slot) pair once.
+__device__ __forceinline__ int swz(int r) {
+  return ((((r >> 3) ^ (r >> 1)) & 1) << 1) | ((r >> 2) & 1);
+}
 
 __device__ __forceinline__ v4u neg4(v4u u) { return u ^ 0x80008000u; }
 
@@ -79,7 +89,11 @@ __device__ constexpr int prod_3m(int i, int f) {
   return t[i][f];
 }
 
-template <int FORM>
+// EXACT: every k chunk is a whole number of stages (K % 32 == 0), so the main
+// loop has no bounds checks and forms one basic block the scheduler can
+// interleave.  Rows past M or N are clamped to the last row: they only feed
+// outputs that the epilogue discards.
+template <int FORM, bool EXACT>
 __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
   constexpr int NP = FORM == kForm3M ? 6 : 4;
   constexpr int NACC = FORM == kForm3M ? 3 : 2;
@@ -122,87 +136,147 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
   // staging: thread -> rows tid/4 and tid/4 + 64 of every plane, chunk tid%4
   const int srow = tid >> 2, sch = tid & 3;
   const bool vec_ok = (g.K % 8) == 0 && (kbeg % 8) == 0;
-  const uint16_t *arow[2], *brow[2];
-  bool rowA[2], rowB[2];
+  // loads address a block-uniform base (scalar registers) plus a 32-bit byte
+  // offset per thread and row (rows past M or N clamped to the last one)
+  const uint8_t *abase = (const uint8_t *)(A + m0 * g.lda);
+  const uint8_t *bbase = (const uint8_t *)(B + n0 * g.ldb);
+  uint32_t aoff[2], boff[2];
   int spos[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int r = srow + 64 * i;
-    rowA[i] = m0 + r < g.M;
-    rowB[i] = n0 + r < g.N;
-    arow[i] = A + (m0 + r) * g.lda;
-    brow[i] = B + (n0 + r) * g.ldb;
-    spos[i] = r * ROWE + ((sch ^ ((r >> 1) & 3)) * 8);
+    const int64_t ra_ = m0 + r < g.M ? r : g.M - 1 - m0;
+    const int64_t rb_ = n0 + r < g.N ? r : g.N - 1 - n0;
+    aoff[i] = (uint32_t)((ra_ * g.lda + sch * 8) * 2);
+    boff[i] = (uint32_t)((rb_ * g.ldb + sch * 8) * 2);
+    spos[i] = r * ROWE + ((sch ^ swz(r)) * 8);
   }
-  v4u ra[NP][2], rb[NP][2];
-  const v4u zero = {0u, 0u, 0u, 0u};
-  auto gload = [&](int64_t k0) {
-    const int64_t k = k0 + sch * 8;
+  // register staging: two sets, so that a stage's loads can be issued two
+  // stages before they are stored to LDS
+  v4u ra[2][NP][2], rb[2][NP][2];
+  auto gload = [&](int set, int64_t k0) {
 #pragma unroll
-    for (int pl = 0; pl < NP; ++pl)
+    for (int pl = 0; pl < NP; ++pl) {
+      const uint8_t *pa_ = abase + (pl * g.pa + k0) * 2;
+      const uint8_t *pb_ = bbase + (pl * g.pb + k0) * 2;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        ra[pl][i] = rowA[i] ? load8(arow[i] + pl * g.pa, k, kend, vec_ok) : zero;
-        rb[pl][i] = rowB[i] ? load8(brow[i] + pl * g.pb, k, kend, vec_ok) : zero;
+        if (EXACT) {
+          ra[set][pl][i] = *(const v4u *)(pa_ + aoff[i]);
+          rb[set][pl][i] = *(const v4u *)(pb_ + boff[i]);
+        } else {
+          const int64_t kk = k0 + sch * 8;
+          ra[set][pl][i] = load8((const uint16_t *)(pa_ + aoff[i]) - kk, kk, kend, vec_ok);
+          rb[set][pl][i] = load8((const uint16_t *)(pb_ + boff[i]) - kk, kk, kend, vec_ok);
+        }
       }
+    }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int set, int buf) {
     uint16_t *la = lds + buf * 2 * OPER, *lb = la + OPER;
 #pragma unroll
     for (int pl = 0; pl < NP; ++pl)
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        *(v4u *)&la[pl * PLANE + spos[i]] = ra[pl][i];
-        *(v4u *)&lb[pl * PLANE + spos[i]] = rb[pl][i];
+        *(v4u *)&la[pl * PLANE + spos[i]] = ra[set][pl][i];
+        *(v4u *)&lb[pl * PLANE + spos[i]] = rb[set][pl][i];
       }
   };
   // fragment rows: (wm|wn)*64 + mb*32 + lane%32; the swizzle term depends on
-  // lane%32 alone since the rest is a multiple of 8
-  const int fr = lane & 31, fsw = (fr >> 1) & 3, fhalf = lane >> 5;
+  // lane%32 alone since the rest is a multiple of 16
+  const int fr = lane & 31, fsw = swz(fr), fhalf = lane >> 5;
 
-  const int64_t nk = (kend - kbeg + BKS - 1) / BKS;
-  gload(kbeg);
-  lstore(0);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = NBUF == 2 ? (int)(kt & 1) : 0;
-    const bool more = kt + 1 < nk;
-    if (more) gload(kbeg + (kt + 1) * BKS);
-    const uint16_t *la = lds + cur * 2 * OPER, *lb = la + OPER;
+  auto frag_read = [&](int buf, int ss, v4u (&a)[2][NP], v4u (&b)[2][NP]) {
+    const uint16_t *la = lds + buf * 2 * OPER, *lb = la + OPER;
+    const int cpos = ((2 * ss + fhalf) ^ fsw) * 8;
 #pragma unroll
-    for (int ss = 0; ss < 2; ++ss) {
-      const int cpos = ((2 * ss + fhalf) ^ fsw) * 8;
-      v4u a[2][NP], b[2][NP];
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+      for (int pl = 0; pl < NP; ++pl)
+        a[mb][pl] = *(const v4u *)&la[pl * PLANE + (wm * 64 + mb * 32 + fr) * ROWE + cpos];
 #pragma unroll
-        for (int pl = 0; pl < NP; ++pl)
-          a[mb][pl] = *(const v4u *)&la[pl * PLANE + (wm * 64 + mb * 32 + fr) * ROWE + cpos];
+    for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
+      for (int pl = 0; pl < NP; ++pl)
+        b[nb][pl] = *(const v4u *)&lb[pl * PLANE + (wn * 64 + nb * 32 + fr) * ROWE + cpos];
+  };
+  // products p0 .. p1-1 of the table on one 16-deep k step
+  auto mma = [&](const v4u (&a)[2][NP], const v4u (&b)[2][NP], int p0, int p1) {
 #pragma unroll
-        for (int pl = 0; pl < NP; ++pl)
-          b[nb][pl] = *(const v4u *)&lb[pl * PLANE + (wn * 64 + nb * 32 + fr) * ROWE + cpos];
+    for (int pi = 0; pi < NPROD; ++pi) {
+      if (pi < p0 || pi >= p1) continue;
+      const int c = FORM == kForm3M ? prod_3m(pi, 0) : prod_4m(pi, 0);
+      const int ap = FORM == kForm3M ? prod_3m(pi, 1) : prod_4m(pi, 1);
+      const int bp = FORM == kForm3M ? prod_3m(pi, 2) : prod_4m(pi, 2);
+      const int ng = FORM == kForm3M ? prod_3m(pi, 3) : prod_4m(pi, 3);
 #pragma unroll
-      for (int pi = 0; pi < NPROD; ++pi) {
-        const int c = FORM == kForm3M ? prod_3m(pi, 0) : prod_4m(pi, 0);
-        const int ap = FORM == kForm3M ? prod_3m(pi, 1) : prod_4m(pi, 1);
-        const int bp = FORM == kForm3M ? prod_3m(pi, 2) : prod_4m(pi, 2);
-        const int ng = FORM == kForm3M ? prod_3m(pi, 3) : prod_4m(pi, 3);
+      for (int mb = 0; mb < 2; ++mb) {
+        const v8bf av = as_bf(ng ? neg4(a[mb][ap]) : a[mb][ap]);
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-          const v8bf av = as_bf(ng ? neg4(a[mb][ap]) : a[mb][ap]);
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
-            acc[mb][nb][c] =
-                __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf(b[nb][bp]), acc[mb][nb][c], 0, 0, 0);
-        }
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb][c] =
+              __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf(b[nb][bp]), acc[mb][nb][c], 0, 0, 0);
       }
     }
-    if (more) {
-      if (NBUF == 1) __syncthreads();
-      lstore(NBUF == 2 ? (int)((kt + 1) & 1) : 0);
+  };
+
+  const int64_t nk = (kend - kbeg + BKS - 1) / BKS;
+  // (fence between the two 16-deep steps: one fragment set live at a time)
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int ss = 0; ss < 2; ++ss) {
+      v4u a[2][NP], b[2][NP];
+      frag_read(buf, ss, a, b);
+      mma(a, b, 0, NPROD);
+      if (EXACT && NBUF == 2 && ss == 0) __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  if (EXACT && NBUF == 2) {
+    // Stage kt sits in LDS buffer kt % 2 while it is multiplied; stage kt + 1
+    // is in register set (kt + 1) % 2 (loaded or in flight) and goes to the
+    // other buffer at the end; stage kt + 2 is requested into set kt % 2 at
+    // the start.  Scheduling fences keep the requests at the top: left free,
+    // the compiler sinks them next to the stores that wait on them.
+    auto body = [&](auto sc, int64_t kt, bool load, bool store) {
+      constexpr int S = decltype(sc)::value;
+      if (load) gload(S, kbeg + (kt + 2) * BKS);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(S);
+      __builtin_amdgcn_sched_barrier(0);
+      if (store) lstore(S ^ 1, S ^ 1);
       __syncthreads();
+    };
+    const std::integral_constant<int, 0> s0;
+    const std::integral_constant<int, 1> s1;
+    gload(0, kbeg);
+    lstore(0, 0);
+    if (nk > 1) gload(1, kbeg + BKS);
+    __syncthreads();
+    int64_t kt = 0;
+    for (; kt + 3 < nk; kt += 2) {
+      body(s0, kt, true, true);
+      body(s1, kt + 1, true, true);
+    }
+    for (; kt < nk; ++kt) {
+      if (kt & 1)
+        body(s1, kt, kt + 2 < nk, kt + 1 < nk);
+      else
+        body(s0, kt, kt + 2 < nk, kt + 1 < nk);
+    }
+  } else {
+    gload(0, kbeg);
+    lstore(0, 0);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const int cur = NBUF == 2 ? (int)(kt & 1) : 0;
+      const bool more = kt + 1 < nk;
+      if (more) gload(0, kbeg + (kt + 1) * BKS);
+      compute(cur);
+      if (more) {
+        if (NBUF == 1) __syncthreads();
+        lstore(0, NBUF == 2 ? (int)((kt + 1) & 1) : 0);
+        __syncthreads();
+      }
     }
   }
 
@@ -241,6 +315,199 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
   }
 }
 
+// ------------------------------------------------- direct-to-LDS form (4M)
+// For k a multiple of 16 the permutation writes the planes k-tiled (16
+// consecutive k of consecutive rows contiguous), so one stage of a tile is a
+// contiguous 4 KB block of each plane, and the 4M product streams it straight
+// from global memory into LDS (global_load_lds_dwordx4: each lane's 16 bytes land
+// at the wave's LDS segment base + 16 * lane), with no staging registers and
+// no LDS stores.  Four 32 KB stages of 16 k form a ring, filled three stages
+// ahead; a wave waits for its own loads of a stage (vmcnt) and the barrier
+// that follows publishes everyone's.  Past the last stage the requests repeat
+// the last stage into the free slot, so the count of loads in flight, and the
+// wait, are the same in every iteration.  The four slots are distinct arrays
+// named statically (the loop is unrolled by four), which lets the compiler
+// see that a read of one slot does not depend on loads into another.
+//
+// LDS layout of a slot: [A planes 0-3][B planes 0-3], each 128 rows x 32
+// bytes; row r's 16-byte chunk c sits at position c ^ dswz(r), so the 16
+// rows read together fall on distinct banks.  While the fragments of stage
+// kt are read, the second half of stage kt-1's products runs.
+constexpr int DBK = 16;               // k per stage
+constexpr int DPLANE = BT * DBK;      // bf16 per plane tile (4 KB)
+constexpr int DSTAGE = 8 * DPLANE;    // A and B, four planes each (32 KB)
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
+
+__global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
+  __shared__ __align__(16) uint16_t ring0[DSTAGE], ring1[DSTAGE], ring2[DSTAGE], ring3[DSTAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int q = blockIdx.y;
+  const uint16_t *A = (const uint16_t *)g.A + q * g.abs;
+  const uint16_t *B = (const uint16_t *)g.B + q * g.bbs;
+  const Slot *sa = g.sa + q * g.sabs;
+  const Slot *sb = g.sb + q * g.sbbs;
+  Slot *sc = g.sc + q * g.scbs;
+  const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
+  const int ks = (int)(blockIdx.x / ntiles);
+  int64_t t = blockIdx.x - (int64_t)ks * ntiles;
+  if (ntiles % 8 == 0 && ntiles >= 64) t = (t % 8) * (ntiles / 8) + t / 8;
+  const int64_t m0 = (t % g.tiles_m) * BT, n0 = (t / g.tiles_m) * BT;
+  const int64_t kbeg = (int64_t)ks * g.kchunk;
+  const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
+  const int ea = slot_exp_b(sa->maxbits), eb = slot_exp_b(sb->maxbits);
+  if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
+
+  v16f_b acc[2][2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[a][b][c][v] = 0.0f;
+
+  // this lane's load: row 32 * wave + lane / 2 of every plane tile, logical
+  // chunk (lane % 2) ^ dswz(row) (rows past M or N clamped to the last one);
+  // in the k-tiled planes row r of k block kb starts at (kb * rows + r) * 16
+  const uint8_t *abase = (const uint8_t *)(A + m0 * DBK);
+  const uint8_t *bbase = (const uint8_t *)(B + n0 * DBK);
+  uint32_t aoff, boff;
+  {
+    const int r = 32 * wave + (lane >> 1);
+    const int c = (lane & 1) ^ dswz(r);
+    const int64_t ra_ = m0 + r < g.M ? r : g.M - 1 - m0;
+    const int64_t rb_ = n0 + r < g.N ? r : g.N - 1 - n0;
+    aoff = (uint32_t)((ra_ * DBK + c * 8) * 2);
+    boff = (uint32_t)((rb_ * DBK + c * 8) * 2);
+  }
+  const int64_t nk = (kend - kbeg) / DBK;
+#define TN_RING(S) ((S) == 0 ? ring0 : (S) == 1 ? ring1 : (S) == 2 ? ring2 : ring3)
+  auto issue = [&](auto slot, int64_t stg) {
+    constexpr int S = decltype(slot)::value;
+    uint16_t *rb = TN_RING(S) + wave * (DPLANE / 4);
+    const int64_t kb = kbeg / DBK + (stg < nk ? stg : nk - 1);
+    const uint8_t *ak = abase + kb * g.M * DBK * 2, *bk = bbase + kb * g.N * DBK * 2;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      __builtin_amdgcn_global_load_lds((const void *)(ak + pl * g.pa * 2 + aoff),
+                                       (lds_void *)(rb + pl * DPLANE), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(bk + pl * g.pb * 2 + boff),
+                                       (lds_void *)(rb + (4 + pl) * DPLANE), 16, 0, 0);
+    }
+  };
+  const int fr = lane & 31, fpos = ((lane >> 5) ^ dswz(fr)) * 8;
+  auto fread = [&](auto slot, v4u (&a)[2][4], v4u (&b)[2][4]) {
+    constexpr int S = decltype(slot)::value;
+    const uint16_t *rb = TN_RING(S);
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        a[mb][pl] = *(const v4u *)(rb + pl * DPLANE + (wm * 64 + mb * 32 + fr) * DBK + fpos);
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        b[nb][pl] = *(const v4u *)(rb + (4 + pl) * DPLANE + (wn * 64 + nb * 32 + fr) * DBK + fpos);
+  };
+#undef TN_RING
+  auto mma = [&](const v4u (&a)[2][4], const v4u (&b)[2][4], int p0, int p1) {
+#pragma unroll
+    for (int pi = 0; pi < 12; ++pi) {
+      if (pi < p0 || pi >= p1) continue;
+      const int c = prod_4m(pi, 0), ap = prod_4m(pi, 1), bp = prod_4m(pi, 2), ng = prod_4m(pi, 3);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const v8bf av = as_bf(ng ? neg4(a[mb][ap]) : a[mb][ap]);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb][c] =
+              __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf(b[nb][bp]), acc[mb][nb][c], 0, 0, 0);
+      }
+    }
+  };
+  v4u fa0[2][4], fb0[2][4], fa1[2][4], fb1[2][4];
+  // one stage: wait for it (two stages of loads may stay in flight; every
+  // fragment read done), barrier, request stage kt + 3 into the slot freed by
+  // stage kt - 1, read stage kt's fragments, then the second half of stage
+  // kt - 1's products and the first half of stage kt's
+  auto stage = [&](auto slot, int64_t kt, bool first) {
+    constexpr int S = decltype(slot)::value;
+    __builtin_amdgcn_s_waitcnt((1 << 14) | (7 << 4));  // vmcnt(16) expcnt(7) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    issue(std::integral_constant<int, (S + 3) % 4>(), kt + 3);
+    if (S % 2 == 0)
+      fread(slot, fa0, fb0);
+    else
+      fread(slot, fa1, fb1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (!first) {
+      if (S % 2 == 0)
+        mma(fa1, fb1, 6, 12);
+      else
+        mma(fa0, fb0, 6, 12);
+    }
+    if (S % 2 == 0)
+      mma(fa0, fb0, 0, 6);
+    else
+      mma(fa1, fb1, 0, 6);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  const std::integral_constant<int, 0> s0;
+  const std::integral_constant<int, 1> s1;
+  const std::integral_constant<int, 2> s2;
+  const std::integral_constant<int, 3> s3;
+  __builtin_amdgcn_s_waitcnt(0);  // nothing else in flight when the ring starts
+  issue(s0, 0);
+  issue(s1, 1);
+  issue(s2, 2);
+  stage(s0, 0, true);
+  int64_t kt = 1;
+  for (; kt + 4 <= nk; kt += 4) {
+    stage(s1, kt, false);
+    stage(s2, kt + 1, false);
+    stage(s3, kt + 2, false);
+    stage(s0, kt + 3, false);
+  }
+  if (kt < nk) stage(s1, kt, false);
+  if (kt + 1 < nk) stage(s2, kt + 1, false);
+  if (kt + 2 < nk) stage(s3, kt + 2, false);
+  if ((nk - 1) & 1)
+    mma(fa1, fb1, 6, 12);
+  else
+    mma(fa0, fb0, 6, 12);
+  __builtin_amdgcn_s_waitcnt(0);  // no load may still write LDS when the block ends
+
+  const bool partial = g.ksplit > 1;
+  float2 *C = partial ? g.part + q * g.partbs + (int64_t)ks * g.M * g.N : g.C + q * g.cbs;
+  const int64_t ldc = partial ? g.N : g.ldc;
+  float mx = 0.0f;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * 64 + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int col = wn * 64 + nb * 32 + (lane & 31);
+        const int64_t cm = m0 + row, cn = n0 + col;
+        const float re = acc[mb][nb][0][v], im = acc[mb][nb][1][v];
+        if (cm < g.M && cn < g.N) {
+          C[cm * ldc + cn] = make_float2(re, im);
+          mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+        }
+      }
+  if (!partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) atomicMax(&sc->maxbits, __float_as_uint(mx));
+  }
+}
+
 hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g0, int form, int nbatch) {
   GemmArgs g = g0;
   if (g.opA != 0 || g.opB != 1 || g.planes != (form == kForm3M ? 6 : 4)) return hipErrorInvalidValue;
@@ -253,10 +520,21 @@ hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g0, int form, int 
   const int64_t blocks = (int64_t)g.tiles_m * g.tiles_n * g.ksplit;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks, nbatch);
-  if (form == kForm4M)
-    hipLaunchKernelGGL(k_cgemm_bf16x3<kForm4M>, grid, dim3(256), 0, st, g);
-  else
-    hipLaunchKernelGGL(k_cgemm_bf16x3<kForm3M>, grid, dim3(256), 0, st, g);
+  const bool exact = g.K % BKS == 0 && g.kchunk % BKS == 0;
+  if (g.ktile) {
+    if (form != kForm4M || g.K % DBK != 0 || g.kchunk % DBK != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cgemm_bf16x3_dma, grid, dim3(256), 0, st, g);
+  } else if (form == kForm4M) {
+    if (exact)
+      hipLaunchKernelGGL((k_cgemm_bf16x3<kForm4M, true>), grid, dim3(256), 0, st, g);
+    else
+      hipLaunchKernelGGL((k_cgemm_bf16x3<kForm4M, false>), grid, dim3(256), 0, st, g);
+  } else {
+    if (exact)
+      hipLaunchKernelGGL((k_cgemm_bf16x3<kForm3M, true>), grid, dim3(256), 0, st, g);
+    else
+      hipLaunchKernelGGL((k_cgemm_bf16x3<kForm3M, false>), grid, dim3(256), 0, st, g);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.ksplit == 1) return e;
   return launch_splitk_reduce(st, g, nbatch);

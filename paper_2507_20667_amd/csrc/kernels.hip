@@ -207,6 +207,19 @@ __device__ __forceinline__ void *perm_out_base(void *out, int64_t obs, int q) {
   return NP == 0 ? (void *)((float2 *)out + q * obs) : (void *)((uint16_t *)out + q * obs);
 }
 
+__device__ __forceinline__ int64_t ktile_index(const KTile &t, int64_t o) {
+  if (!t.on) return o;
+  int64_t r, k;
+  if (t.kshift >= 0) {
+    r = o >> t.kshift;
+    k = o & (t.kdim - 1);
+  } else {
+    r = o / t.kdim;
+    k = o - r * t.kdim;
+  }
+  return ((k >> 4) * t.rows + r) * 16 + (k & 15);
+}
+
 // Split planes carry the operand divided by 2^e (e from its scale record), as
 // the GEMM that reads them expects; complex64 output is copied unscaled.
 template <int NP>
@@ -221,7 +234,7 @@ template <int NP>
 __global__ __launch_bounds__(256) void k_perm_generic(const PermDesc *__restrict__ d,
                                                       const float2 *in, int64_t ibs, void *out,
                                                       int64_t obs, int64_t pstride,
-                                                      const Slot *sl, int64_t sbs) {
+                                                      const Slot *sl, int64_t sbs, KTile kt) {
   __shared__ SegLds L;
   const int tid = threadIdx.x;
   const int q = blockIdx.y;
@@ -236,7 +249,7 @@ __global__ __launch_bounds__(256) void k_perm_generic(const PermDesc *__restrict
   for (int64_t o = (int64_t)blockIdx.x * 256 + tid; o < n; o += (int64_t)gridDim.x * 256) {
     int64_t io, oo;
     seg_decode(L, nseg, p2, o, io, oo);
-    perm_emit<NP>(ob, pstride, oo, in[io], fs);
+    perm_emit<NP>(ob, pstride, ktile_index(kt, oo), in[io], fs);
   }
 }
 
@@ -259,7 +272,7 @@ struct BitTile {
 template <int NP>
 __global__ __launch_bounds__(256) void k_perm_tiled(BitTile t, const float2 *in, int64_t ibs,
                                                     void *out, int64_t obs, int64_t pstride,
-                                                    const Slot *sl, int64_t sbs) {
+                                                    const Slot *sl, int64_t sbs, KTile kt) {
   __shared__ float2 tile[1024 + 32];
   const int tid = threadIdx.x;
   const int q = blockIdx.y;
@@ -299,7 +312,7 @@ __global__ __launch_bounds__(256) void k_perm_tiled(BitTile t, const float2 *in,
       }
     for (int c = 0; c < cnt; ++c) tile[le[c]] = in[bin + lin[c]];
     __syncthreads();
-    for (int c = 0; c < cnt; ++c) perm_emit<NP>(ob, pstride, bout + lout[c], tile[ge[c]], fs);
+    for (int c = 0; c < cnt; ++c) perm_emit<NP>(ob, pstride, ktile_index(kt, bout + lout[c]), tile[ge[c]], fs);
     __syncthreads();
   }
 }
@@ -362,28 +375,31 @@ static bool build_bit_tile(const PermDesc &h, BitTile &t) {
 
 hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc &h, const float2 *in,
                           int64_t ibs, void *out, int64_t obs, int nbatch, int np,
-                          int64_t pstride, const Slot *sl, int64_t sbs) {
+                          int64_t pstride, const Slot *sl, int64_t sbs, KTile kt) {
   if (np != 0 && np != 4 && np != 6) return hipErrorInvalidValue;
   if (np != 0 && (!sl || pstride < h.nelem)) return hipErrorInvalidValue;
+  if (kt.on && (np == 0 || kt.kdim % 16 != 0 || kt.rows * kt.kdim != h.nelem ||
+                (kt.kshift >= 0 && ((int64_t)1 << kt.kshift) != kt.kdim)))
+    return hipErrorInvalidValue;
   BitTile t;
   if (h.nelem >= 4096 && build_bit_tile(h, t)) {
     const int64_t ntiles = (int64_t)1 << t.nouter;
     const dim3 grid(grid_for(ntiles, 1, 8192), nbatch);
     if (np == 0)
-      hipLaunchKernelGGL(k_perm_tiled<0>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs);
+      hipLaunchKernelGGL(k_perm_tiled<0>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs, kt);
     else if (np == 4)
-      hipLaunchKernelGGL(k_perm_tiled<4>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs);
+      hipLaunchKernelGGL(k_perm_tiled<4>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs, kt);
     else
-      hipLaunchKernelGGL(k_perm_tiled<6>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs);
+      hipLaunchKernelGGL(k_perm_tiled<6>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs, kt);
     return hipGetLastError();
   }
   const dim3 grid(grid_for(h.nelem, 256, 16384), nbatch);
   if (np == 0)
-    hipLaunchKernelGGL(k_perm_generic<0>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs);
+    hipLaunchKernelGGL(k_perm_generic<0>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs, kt);
   else if (np == 4)
-    hipLaunchKernelGGL(k_perm_generic<4>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs);
+    hipLaunchKernelGGL(k_perm_generic<4>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs, kt);
   else
-    hipLaunchKernelGGL(k_perm_generic<6>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs);
+    hipLaunchKernelGGL(k_perm_generic<6>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs, kt);
   return hipGetLastError();
 }
 
@@ -411,8 +427,12 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
   // block -> (k chunk ks, tile)
   const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
   const int ks = (int)(blockIdx.x / ntiles);
-  const int64_t tile = blockIdx.x - (int64_t)ks * ntiles;
-  const int64_t m0 = (tile / g.tiles_n) * BM, n0 = (tile % g.tiles_n) * BN;
+  int64_t tile = blockIdx.x - (int64_t)ks * ntiles;
+  // XCD-aware order: blocks land on the 8 XCDs round-robin; each XCD takes a
+  // contiguous run of tiles, M-tiles fastest, so that the tiles sharing a B
+  // panel run together on one XCD's L2
+  if (ntiles % 8 == 0 && ntiles >= 64) tile = (tile % 8) * (ntiles / 8) + tile / 8;
+  const int64_t m0 = (tile % g.tiles_m) * BM, n0 = (tile / g.tiles_m) * BN;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
   const int ea = slot_exp(sa->maxbits), eb = slot_exp(sb->maxbits);

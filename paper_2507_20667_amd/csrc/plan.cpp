@@ -325,6 +325,7 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
     const int tile = n.planes > 0 ? 128 : gemm_variant_tile_m(n.variant);
     n.ksplit = gemm_ksplit(n.M, n.N, n.K, tile, tile, &n.kchunk);
   }
+  n.ktile = n.planes == 4 && n.K % 16 == 0 && (n.ksplit == 1 || n.kchunk % 16 == 0);
   p->num_perm += (int)permA + (int)permB;
   return TN_OK;
 }

@@ -92,6 +92,18 @@ struct GemmArgs {
   int64_t pa, pb;
   float2 *part;
   int64_t partbs, kchunk;
+  // ktile = 1: the planes are k-tiled (row r, k at ((k / 16) * rows + r) * 16
+  // + k % 16, rows = M for A and N for B), K a multiple of 16
+  int32_t ktile, pad2;
+};
+
+// Output order of a permutation into split planes: ktile.on = 1 writes the
+// row-major [rows][kdim] index o = r * kdim + k at ((k / 16) * rows + r) * 16
+// + k % 16, so that 16 consecutive k of consecutive rows are contiguous (one
+// GEMM stage of a tile is one block); kshift = log2(kdim), or -1.
+struct KTile {
+  int64_t rows, kdim;
+  int32_t kshift, on;
 };
 
 // One operand of a batched launch: base pointer plus per-query stride.
@@ -215,7 +227,7 @@ hipError_t launch_stream(hipStream_t st, const StreamDesc *d_desc, int64_t nfib,
 hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc &h_desc,
                           const float2 *in, int64_t ibs, void *out, int64_t obs, int nbatch,
                           int np = 0, int64_t pstride = 0, const Slot *sl = nullptr,
-                          int64_t sbs = 0);
+                          int64_t sbs = 0, KTile kt = KTile{0, 0, -1, 0});
 hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int prec, int form, int variant,
                        int nbatch);
 hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g, int form, int nbatch);

@@ -79,6 +79,7 @@ struct Node {
   PermStep pa, pb;
   int opA = 0, opB = 0;
   int planes = 0;    // > 0: both operands staged as split-BF16 planes
+  bool ktile = false;  // planes k-tiled for the direct-to-LDS 4M GEMM
   int ksplit = 1;    // k chunks (partials reduced after the GEMM)
   int64_t kchunk = 0;
   int64_t M = 0, N = 0, K = 0, lda = 0, ldb = 0, ldc = 0;
