@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtn.so")
 ARCH = os.environ.get("TN_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "tree.hip", "gemm_bf16.hip", "plan.cpp", "exec.cpp", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "tree.hip", "gemm_bf16.hip", "gemm_f32.hip", "plan.cpp", "exec.cpp", "api.cpp", "serve.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           f"--offload-arch={ARCH}",

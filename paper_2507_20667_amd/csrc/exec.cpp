@@ -424,12 +424,12 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         } else if (n.kind == NK_GEMM) {
           Operand A = operand(n.ga), B = operand(n.gb);
           uint8_t *pbase = sh ? shared_base : perq_base;
-          // batch stride of the staged copies: float2 entries, or bf16 entries
-          // for split planes
-          const int64_t pst = sh ? 0 : (n.planes > 0 ? perq_el * 4 : perq_el);
+          // batch stride of the staged copies, in their entries: float2, float
+          // (FP32 planes) or bf16 (split planes)
+          const int64_t pst = sh ? 0 : n.planes == 2 ? perq_el * 2 : n.planes > 0 ? perq_el * 4 : perq_el;
           const void *ga = A.p, *gb = B.p;
           int64_t gabs = A.bs, gbbs = B.bs;
-          const double pbytes = n.planes > 0 ? 8.0 + 2.0 * n.planes : 16.0;
+          const double pbytes = n.planes > 2 ? 8.0 + 2.0 * n.planes : 16.0;
           if (n.pa.needed) {
             void *dst = pbase + L.scr_a[j];
             TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, pbytes * n.pa.h.nelem * nb, 0.0,

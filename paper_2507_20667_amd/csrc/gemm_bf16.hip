@@ -332,8 +332,9 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
 // LDS layout of a slot: [A planes 0-3][B planes 0-3], each 128 rows x 32
 // bytes; row r's 16-byte chunk c sits at position c ^ dswz(r), so the 16
 // rows read together fall on distinct banks.  While the fragments of stage
-// kt are read, the second half of stage kt-1's products runs.
+// kt are read, the last two thirds of stage kt-1's products run.
 constexpr int DBK = 16;               // k per stage
+constexpr int DSPLIT = 4;             // products of a stage run before the next barrier
 constexpr int DPLANE = BT * DBK;      // bf16 per plane tile (4 KB)
 constexpr int DSTAGE = 8 * DPLANE;    // A and B, four planes each (32 KB)
 typedef __attribute__((address_space(3))) void lds_void;
@@ -433,8 +434,8 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
   v4u fa0[2][4], fb0[2][4], fa1[2][4], fb1[2][4];
   // one stage: wait for it (two stages of loads may stay in flight; every
   // fragment read done), barrier, request stage kt + 3 into the slot freed by
-  // stage kt - 1, read stage kt's fragments, then the second half of stage
-  // kt - 1's products and the first half of stage kt's
+  // stage kt - 1, read stage kt's fragments, then the remaining products of
+  // stage kt - 1 and the first DSPLIT of stage kt's
   auto stage = [&](auto slot, int64_t kt, bool first) {
     constexpr int S = decltype(slot)::value;
     __builtin_amdgcn_s_waitcnt((1 << 14) | (7 << 4));  // vmcnt(16) expcnt(7) lgkmcnt(0)
@@ -447,14 +448,14 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
     __builtin_amdgcn_sched_barrier(0);
     if (!first) {
       if (S % 2 == 0)
-        mma(fa1, fb1, 6, 12);
+        mma(fa1, fb1, DSPLIT, 12);
       else
-        mma(fa0, fb0, 6, 12);
+        mma(fa0, fb0, DSPLIT, 12);
     }
     if (S % 2 == 0)
-      mma(fa0, fb0, 0, 6);
+      mma(fa0, fb0, 0, DSPLIT);
     else
-      mma(fa1, fb1, 0, 6);
+      mma(fa1, fb1, 0, DSPLIT);
     __builtin_amdgcn_sched_barrier(0);
   };
   const std::integral_constant<int, 0> s0;
@@ -477,9 +478,9 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
   if (kt + 1 < nk) stage(s2, kt + 1, false);
   if (kt + 2 < nk) stage(s3, kt + 2, false);
   if ((nk - 1) & 1)
-    mma(fa1, fb1, 6, 12);
+    mma(fa1, fb1, DSPLIT, 12);
   else
-    mma(fa0, fb0, 6, 12);
+    mma(fa0, fb0, DSPLIT, 12);
   __builtin_amdgcn_s_waitcnt(0);  // no load may still write LDS when the block ends
 
   const bool partial = g.ksplit > 1;

@@ -1,0 +1,275 @@
+// FP32 complex GEMM on v_mfma_f32_32x32x2_f32 from k-tiled float planes.
+//
+// The permutation that puts a vertex's operands in GEMM order writes them as
+// two float planes (re, im), divided by 2^e of the operand's scale record and
+// k-tiled: row r, k sits at ((k / 16) * rows + r) * 16 + k % 16, so that one
+// 16-deep stage of a 128-row tile is a contiguous 8 KB block of each plane.
+// Stages stream straight from global memory into a four-slot LDS ring
+// (global_load_lds_dwordx4, three stages ahead, no staging registers); the
+// wait for a stage is a vmcnt on the wave's own loads followed by a barrier.
+// Past the last stage the requests repeat the last stage into the free slot,
+// so the number of loads in flight, and the wait, never change.  The slots are
+// distinct arrays named statically (the loop is unrolled by four), which lets
+// the compiler see that a read of one slot does not wait on loads into
+// another.
+//
+// Block = 4 waves in a 2 x 2 grid over a 128 x 128 output tile, each wave
+// 64 x 64 outputs as 2 x 2 MFMA tiles.  For that instruction lane l supplies
+// A[l%32][kk] and B[kk][l%32] with kk = l/32 of a 2-deep step and holds
+// C[8(v/4) + 4(l/32) + v%4][l%32] in accumulator v.  Within a stage, step s
+// gives lane half h the k value 8h + s (A and B alike, so the sum over k is
+// unchanged): a lane's eight k of a row are two 16-byte LDS reads.  Rows are
+// 64 bytes; row r's chunk c sits at position c ^ swz(r), so the rows one LDS
+// access touches fall on distinct banks.  A stage is 128 MFMAs per wave (4M),
+// so the fragments of stage kt are read while stage kt-1 multiplies.
+// 4M form only (Re = ArBr - AiBi, Im = ArBi + AiBr): the 3M form's third
+// accumulator set does not fit beside two fragment sets, and takes the
+// complex64 kernel.
+#include <type_traits>
+
+#include "tn_device.h"
+
+namespace tn {
+
+typedef float v16f_c __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void_f;
+
+constexpr int FT = 128;               // tile rows and columns
+constexpr int FBK = 16;               // k per stage
+constexpr int FPLANE = FT * FBK;      // floats per plane tile (8 KB)
+constexpr int FSTAGE = 4 * FPLANE;    // A re, A im, B re, B im (32 KB)
+
+__device__ __forceinline__ int slot_exp_f(uint32_t bits) {
+  if (bits == 0u) return 0;
+  const int e = (int)((bits >> 23) & 0xffu);
+  if (e == 0xff) return 0;
+  if (e == 0) return -126;
+  return e - 127;
+}
+
+// (b3 ^ b1, b2) of the row index: rows r..r+15 cover every (r % 4, chunk)
+// pair and rows r..r+7 every (r % 2, chunk) pair once
+__device__ __forceinline__ int fswz(int r) {
+  return ((((r >> 3) ^ (r >> 1)) & 1) << 1) | ((r >> 2) & 1);
+}
+
+__global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
+  constexpr int NACC = 2;
+  __shared__ __align__(16) float ring0[FSTAGE], ring1[FSTAGE], ring2[FSTAGE], ring3[FSTAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int q = blockIdx.y;
+  const float *A = (const float *)g.A + q * g.abs;
+  const float *B = (const float *)g.B + q * g.bbs;
+  const Slot *sa = g.sa + q * g.sabs;
+  const Slot *sb = g.sb + q * g.sbbs;
+  Slot *sc = g.sc + q * g.scbs;
+  // block -> (k chunk, tile); XCD-aware order: each XCD takes a contiguous
+  // run of tiles, M-tiles fastest, so tiles sharing a B panel share an L2
+  const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
+  const int ks = (int)(blockIdx.x / ntiles);
+  int64_t t = blockIdx.x - (int64_t)ks * ntiles;
+  if (ntiles % 8 == 0 && ntiles >= 64) t = (t % 8) * (ntiles / 8) + t / 8;
+  const int64_t m0 = (t % g.tiles_m) * FT, n0 = (t / g.tiles_m) * FT;
+  const int64_t kbeg = (int64_t)ks * g.kchunk;
+  const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
+  const int ea = slot_exp_f(sa->maxbits), eb = slot_exp_f(sb->maxbits);
+  if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
+
+  v16f_c acc[2][2][NACC];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < NACC; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[a][b][c][v] = 0.0f;
+
+  // this lane's loads: instruction j covers rows 32 * wave + 16 * j + lane / 4
+  // of a plane tile; position lane % 4 of the row holds logical chunk
+  // (lane % 4) ^ fswz(row) (rows past M or N clamped to the last one)
+  const uint8_t *abase = (const uint8_t *)(A + m0 * FBK);
+  const uint8_t *bbase = (const uint8_t *)(B + n0 * FBK);
+  uint32_t aoff[2], boff[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int r = 32 * wave + 16 * j + (lane >> 2);
+    const int c = (lane & 3) ^ fswz(r);
+    const int64_t ra_ = m0 + r < g.M ? r : g.M - 1 - m0;
+    const int64_t rb_ = n0 + r < g.N ? r : g.N - 1 - n0;
+    aoff[j] = (uint32_t)((ra_ * FBK + c * 4) * 4);
+    boff[j] = (uint32_t)((rb_ * FBK + c * 4) * 4);
+  }
+  const int64_t nk = (kend - kbeg) / FBK;
+#define TN_FRING(S) ((S) == 0 ? ring0 : (S) == 1 ? ring1 : (S) == 2 ? ring2 : ring3)
+  auto issue = [&](auto slot, int64_t stg) {
+    constexpr int S = decltype(slot)::value;
+    float *rb = TN_FRING(S) + wave * (FPLANE / 4);
+    const int64_t kb = kbeg / FBK + (stg < nk ? stg : nk - 1);
+    const uint8_t *ak = abase + kb * g.M * FBK * 4, *bk = bbase + kb * g.N * FBK * 4;
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        __builtin_amdgcn_global_load_lds((const void *)(ak + pl * g.pa * 4 + aoff[j]),
+                                         (lds_void_f *)(rb + pl * FPLANE + j * (FPLANE / 8)), 16, 0,
+                                         0);
+        __builtin_amdgcn_global_load_lds((const void *)(bk + pl * g.pb * 4 + boff[j]),
+                                         (lds_void_f *)(rb + (2 + pl) * FPLANE + j * (FPLANE / 8)),
+                                         16, 0, 0);
+      }
+  };
+  // fragments: lane half h reads k 8h .. 8h+7 of its row (logical chunks 2h
+  // and 2h + 1) from each plane
+  const int fr = lane & 31, fh = lane >> 5;
+  const int fp0 = ((2 * fh) ^ fswz(fr)) * 4, fp1 = ((2 * fh + 1) ^ fswz(fr)) * 4;
+  auto fread = [&](auto slot, v4f (&a)[2][2][2], v4f (&b)[2][2][2]) {
+    constexpr int S = decltype(slot)::value;
+    const float *rb = TN_FRING(S);
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl) {
+        const float *row = rb + pl * FPLANE + (wm * 64 + mb * 32 + fr) * FBK;
+        a[mb][pl][0] = *(const v4f *)(row + fp0);
+        a[mb][pl][1] = *(const v4f *)(row + fp1);
+      }
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl) {
+        const float *row = rb + (2 + pl) * FPLANE + (wn * 64 + nb * 32 + fr) * FBK;
+        b[nb][pl][0] = *(const v4f *)(row + fp0);
+        b[nb][pl][1] = *(const v4f *)(row + fp1);
+      }
+  };
+#undef TN_FRING
+  auto mma = [&](const v4f (&a)[2][2][2], const v4f (&b)[2][2][2]) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      float ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        ar[x] = a[x][0][s >> 2][s & 3];
+        ai[x] = a[x][1][s >> 2][s & 3];
+        br[x] = b[x][0][s >> 2][s & 3];
+        bi[x] = b[x][1][s >> 2][s & 3];
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[mb], br[nb], acc[mb][nb][0], 0, 0, 0);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[mb], bi[nb], acc[mb][nb][1], 0, 0, 0);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[mb], bi[nb], acc[mb][nb][0], 0, 0, 0);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[mb], br[nb], acc[mb][nb][1], 0, 0, 0);
+    }
+  };
+  v4f fa0[2][2][2], fb0[2][2][2], fa1[2][2][2], fb1[2][2][2];
+  // one stage: wait for it (two stages of loads may stay in flight, every
+  // fragment read done), barrier, request stage kt + 3 into the slot stage
+  // kt - 1 used, read stage kt's fragments, multiply stage kt - 1's
+  auto stage = [&](auto slot, int64_t kt, bool first) {
+    constexpr int S = decltype(slot)::value;
+    __builtin_amdgcn_s_waitcnt((1 << 14) | (7 << 4));  // vmcnt(16) expcnt(7) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    issue(std::integral_constant<int, (S + 3) % 4>(), kt + 3);
+    if (S % 2 == 0)
+      fread(slot, fa0, fb0);
+    else
+      fread(slot, fa1, fb1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (!first) {
+      if (S % 2 == 0)
+        mma(fa1, fb1);
+      else
+        mma(fa0, fb0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  const std::integral_constant<int, 0> s0;
+  const std::integral_constant<int, 1> s1;
+  const std::integral_constant<int, 2> s2;
+  const std::integral_constant<int, 3> s3;
+  __builtin_amdgcn_s_waitcnt(0);  // nothing else in flight when the ring starts
+  issue(s0, 0);
+  issue(s1, 1);
+  issue(s2, 2);
+  stage(s0, 0, true);
+  int64_t kt = 1;
+  for (; kt + 4 <= nk; kt += 4) {
+    stage(s1, kt, false);
+    stage(s2, kt + 1, false);
+    stage(s3, kt + 2, false);
+    stage(s0, kt + 3, false);
+  }
+  if (kt < nk) stage(s1, kt, false);
+  if (kt + 1 < nk) stage(s2, kt + 1, false);
+  if (kt + 2 < nk) stage(s3, kt + 2, false);
+  if ((nk - 1) & 1)
+    mma(fa1, fb1);
+  else
+    mma(fa0, fb0);
+  __builtin_amdgcn_s_waitcnt(0);  // no load may still write LDS when the block ends
+
+  const bool partial = g.ksplit > 1;
+  float2 *C = partial ? g.part + q * g.partbs + (int64_t)ks * g.M * g.N : g.C + q * g.cbs;
+  const int64_t ldc = partial ? g.N : g.ldc;
+  float mx = 0.0f;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * 64 + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int col = wn * 64 + nb * 32 + (lane & 31);
+        const int64_t cm = m0 + row, cn = n0 + col;
+        const float re = acc[mb][nb][0][v], im = acc[mb][nb][1][v];
+        if (cm < g.M && cn < g.N) {
+          C[cm * ldc + cn] = make_float2(re, im);
+          mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+        }
+      }
+  if (!partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) atomicMax(&sc->maxbits, __float_as_uint(mx));
+  }
+}
+
+hipError_t launch_gemm_f32_planes(hipStream_t st, const GemmArgs &g0, int form, int nbatch) {
+  GemmArgs g = g0;
+  if (g.opA != 0 || g.opB != 1 || g.planes != 2 || !g.ktile || g.K % FBK != 0 || form != kForm4M)
+    return hipErrorInvalidValue;
+  g.tiles_m = (int)((g.M + FT - 1) / FT);
+  g.tiles_n = (int)((g.N + FT - 1) / FT);
+  if (g.ksplit < 1) g.ksplit = 1;
+  if (g.ksplit == 1) g.kchunk = g.K;
+  if (g.kchunk < 1 || g.kchunk % FBK != 0 || (int64_t)g.ksplit * g.kchunk < g.K ||
+      (g.ksplit > 1 && !g.part))
+    return hipErrorInvalidValue;
+  const int64_t blocks = (int64_t)g.tiles_m * g.tiles_n * g.ksplit;
+  if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks, nbatch);
+  hipLaunchKernelGGL(k_cgemm_f32_planes, grid, dim3(256), 0, st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || g.ksplit == 1) return e;
+  return launch_splitk_reduce(st, g, nbatch);
+}
+
+}  // namespace tn

@@ -174,15 +174,20 @@ hipError_t launch_stream(hipStream_t st, const StreamDesc *d_desc, int64_t nfib,
 }
 
 // -------------------------------------------------------------- permutation
-// The output is either complex64 (NP = 0) or, for the split-BF16 GEMM, NP
-// bf16 planes (re hi, re lo, im hi, im lo [, (re+im) hi, (re+im) lo]) each
-// with the output's element order, `pstride` entries apart: the split runs
-// once per element here instead of once per GEMM tile that reads it.
+// The output is complex64 (NP = 0); or, for the FP32 GEMM, two float planes
+// (NP = 2: re, im); or, for the split-BF16 GEMM, NP bf16 planes (re hi, re
+// lo, im hi, im lo [, (re+im) hi, (re+im) lo]).  Planes have the output's
+// element order and lie `pstride` entries apart: the split runs once per
+// element here instead of once per GEMM tile that reads it.
 template <int NP>
 __device__ __forceinline__ void perm_emit(void *out, int64_t pstride, int64_t idx, float2 v,
                                           float fs) {
   if (NP == 0) {
     ((float2 *)out)[idx] = v;
+  } else if (NP == 2) {
+    float *o = (float *)out;
+    o[idx] = v.x * fs;
+    o[pstride + idx] = v.y * fs;
   } else {
     uint16_t *o = (uint16_t *)out;
     uint16_t h, l;
@@ -204,7 +209,8 @@ __device__ __forceinline__ void perm_emit(void *out, int64_t pstride, int64_t id
 
 template <int NP>
 __device__ __forceinline__ void *perm_out_base(void *out, int64_t obs, int q) {
-  return NP == 0 ? (void *)((float2 *)out + q * obs) : (void *)((uint16_t *)out + q * obs);
+  return NP == 0 ? (void *)((float2 *)out + q * obs)
+                 : NP == 2 ? (void *)((float *)out + q * obs) : (void *)((uint16_t *)out + q * obs);
 }
 
 __device__ __forceinline__ int64_t ktile_index(const KTile &t, int64_t o) {
@@ -376,7 +382,7 @@ static bool build_bit_tile(const PermDesc &h, BitTile &t) {
 hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc &h, const float2 *in,
                           int64_t ibs, void *out, int64_t obs, int nbatch, int np,
                           int64_t pstride, const Slot *sl, int64_t sbs, KTile kt) {
-  if (np != 0 && np != 4 && np != 6) return hipErrorInvalidValue;
+  if (np != 0 && np != 2 && np != 4 && np != 6) return hipErrorInvalidValue;
   if (np != 0 && (!sl || pstride < h.nelem)) return hipErrorInvalidValue;
   if (kt.on && (np == 0 || kt.kdim % 16 != 0 || kt.rows * kt.kdim != h.nelem ||
                 (kt.kshift >= 0 && ((int64_t)1 << kt.kshift) != kt.kdim)))
@@ -387,6 +393,8 @@ hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc
     const dim3 grid(grid_for(ntiles, 1, 8192), nbatch);
     if (np == 0)
       hipLaunchKernelGGL(k_perm_tiled<0>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs, kt);
+    else if (np == 2)
+      hipLaunchKernelGGL(k_perm_tiled<2>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs, kt);
     else if (np == 4)
       hipLaunchKernelGGL(k_perm_tiled<4>, grid, dim3(256), 0, st, t, in, ibs, out, obs, pstride, sl, sbs, kt);
     else
@@ -396,6 +404,8 @@ hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc
   const dim3 grid(grid_for(h.nelem, 256, 16384), nbatch);
   if (np == 0)
     hipLaunchKernelGGL(k_perm_generic<0>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs, kt);
+  else if (np == 2)
+    hipLaunchKernelGGL(k_perm_generic<2>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs, kt);
   else if (np == 4)
     hipLaunchKernelGGL(k_perm_generic<4>, grid, dim3(256), 0, st, d_desc, in, ibs, out, obs, pstride, sl, sbs, kt);
   else
@@ -600,6 +610,8 @@ hipError_t launch_gemm(hipStream_t st, const GemmArgs &g0, int prec, int form, i
                        int nbatch) {
   if (prec == kPrecBF16x3) return launch_gemm_bf16x3(st, g0, form, nbatch);
   if (prec != kPrecFP32) return hipErrorInvalidValue;
+  if (g0.planes == 2) return launch_gemm_f32_planes(st, g0, form, nbatch);
+  if (g0.planes != 0) return hipErrorInvalidValue;
   GemmArgs g = g0;
   const int tm = kVariants[variant].tm, tn = kVariants[variant].tn;
   g.tiles_m = (int)((g.M + tm - 1) / tm);

@@ -254,11 +254,17 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   int bMode = block_at_start(B, S) ? 0 : (block_at_end(B, S) ? 1 : -1);   // 0: N, 1: T
   std::vector<int64_t> sorder;
   bool permA = aMode < 0, permB = bMode < 0;
-  // the split-BF16 GEMM reads both operands as k-contiguous bf16 planes, which
-  // the permutation kernel writes (an identity map where the order is right)
+  // The split-BF16 GEMM, and the FP32 4M GEMM when k is a multiple of 16,
+  // read both operands as planes that the permutation kernel writes (an
+  // identity map where the order is right).
+  int64_t k_all = 1;
+  for (int64_t l : sA) k_all *= A.dim[A.find(l)];
   n.planes = 0;
-  if (p->flags & TN_PREC_BF16X3) {
+  if (p->flags & TN_PREC_BF16X3)
     n.planes = (p->flags & TN_FORM_3M) ? 6 : 4;
+  else if (!(p->flags & TN_FORM_3M) && k_all % 16 == 0)
+    n.planes = 2;
+  if (n.planes > 0) {
     sorder = !permA || permB ? sA : sB;
     permA = permB = true;
   } else if (!permA && !permB) {
@@ -325,7 +331,8 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
     const int tile = n.planes > 0 ? 128 : gemm_variant_tile_m(n.variant);
     n.ksplit = gemm_ksplit(n.M, n.N, n.K, tile, tile, &n.kchunk);
   }
-  n.ktile = n.planes == 4 && n.K % 16 == 0 && (n.ksplit == 1 || n.kchunk % 16 == 0);
+  n.ktile = (n.planes == 4 || n.planes == 2) && n.K % 16 == 0 &&
+            (n.ksplit == 1 || n.kchunk % 16 == 0);
   p->num_perm += (int)permA + (int)permB;
   return TN_OK;
 }
@@ -1177,8 +1184,9 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
     L.off[n.id] = P.alloc(out_bytes);
     std::vector<std::pair<int64_t, int64_t>> tmp;
     if (n.kind == NK_GEMM) {
-      // complex64 (8 bytes an entry) or split planes (2 bytes a plane)
-      const int64_t eb = n.planes > 0 ? 2 * n.planes : 8;
+      // complex64 or two float planes (8 bytes an entry), or split bf16 planes
+      // (2 bytes a plane)
+      const int64_t eb = n.planes > 2 ? 2 * n.planes : 8;
       if (n.pa.needed) {
         L.scr_a[j] = P.alloc(n.pa.h.nelem * eb);
         tmp.push_back({L.scr_a[j], n.pa.h.nelem * eb});

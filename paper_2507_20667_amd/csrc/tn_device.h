@@ -69,9 +69,10 @@ struct DotDesc {
 // opA = 0: A is M x K row-major (lda >= K); 1: A is stored K x M (lda >= M).
 // opB = 0: B is K x N row-major (ldb >= N); 1: B is stored N x K (ldb >= K).
 // Batched over gridDim.y with element strides *bs (0 = shared operand).
-// planes > 0: A and B are instead `planes` bf16 planes each (the split form of
-// the three-term BF16 product), with opA = 0 and opB = 1; pa / pb are the plane
-// strides and lda / ldb / abs / bbs count bf16 entries.
+// planes > 0: A and B are instead planes, with opA = 0 and opB = 1: 2 float
+// planes (re, im) for FP32, 4 or 6 bf16 planes (the split form of the
+// three-term BF16 product) for BF16x3; pa / pb are the plane strides and
+// lda / ldb / abs / bbs count plane entries.
 // ksplit > 1: the k range is cut into ksplit chunks of kchunk; chunk s of batch
 // q writes its M x N partial product (row-major) to part + q * partbs + s * M * N
 // and launch_gemm follows with a reduction into C (fixed order: deterministic).
@@ -231,6 +232,7 @@ hipError_t launch_permute(hipStream_t st, const PermDesc *d_desc, const PermDesc
 hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int prec, int form, int variant,
                        int nbatch);
 hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g, int form, int nbatch);
+hipError_t launch_gemm_f32_planes(hipStream_t st, const GemmArgs &g, int form, int nbatch);
 hipError_t launch_splitk_reduce(hipStream_t st, const GemmArgs &g, int nbatch);
 // k chunks of a GEMM with tiles_m x tiles_n output tiles (1: no split)
 int gemm_ksplit(int64_t M, int64_t N, int64_t K, int tile_m, int tile_n, int64_t *kchunk);

@@ -178,7 +178,9 @@ def test_permutation_is_bit_exact(ctx, shape, perm):
                                          (96, 1, 80, lib.TN_FORM_4M), (512, 256, 96, lib.TN_FORM_3M),
                                          (130, 70, 200, lib.TN_FORM_3M),
                                          # few output tiles, deep k: split into k chunks
-                                         (64, 4100, 96, lib.TN_FORM_4M), (100, 8192, 70, lib.TN_FORM_3M)])
+                                         (64, 4100, 96, lib.TN_FORM_4M), (100, 8192, 70, lib.TN_FORM_3M),
+                                         # k a multiple of 16: float planes, k-tiled, ragged M and N
+                                         (130, 48, 300, lib.TN_FORM_4M), (200, 4096, 72, lib.TN_FORM_4M)])
 def test_gemm_vertex_against_fp64(ctx, M, K, N, form):
     """Two tensors A(m, k) and B(k, n) with an open output: one GEMM vertex.
     Error bound |dC| <= gamma * |A||B| with gamma = 4 * K * 2^-24 (FP32 inputs
