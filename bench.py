@@ -12,7 +12,9 @@ Printed: one JSON line with amplitudes/s of the batched path (`value`), the
 plain per-query path (tn_contract, one query at a time) for the same
 workload, effective complex TFLOP/s (8 * con_serial per amplitude), the
 roofline position of the dominant kernel class (event-timed inside this run)
-and the CPU oracle timed on a bounded sample.
+the CPU oracle timed on a bounded sample, and (unless --no-largest) the GEMM
+phase of the 30-qubit configuration in FP32 and three-term split BF16 with its
+MFMA utilisation and its error against stored state-vector amplitudes.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--queries 4096]
 """
@@ -256,6 +258,71 @@ def cpu_baseline(net, plan, circ, budget_s):
                        f"complex128 loop-nest contraction, {dt:.1f} s")
 
 
+def gemm_phase_leg(lib, reps=3):
+    """The largest configuration: 30-qubit random circuit (depth 20, 7 CX pairs
+    per layer, 70 % nearest-neighbour), 8 SA partitions, largest intermediate
+    2^27 complex64.  Per precision: event-timed GEMM phase (effective complex
+    TFLOP/s and the fraction of the MFMA peak of the instruction it runs on),
+    plain per-amplitude time, and the error of the sampled amplitudes against
+    the oracle's state-vector values in tests/golden/config3_amplitudes.json."""
+    from paper_2507_20667_amd.inputs import amplitude_network, amplitude_overrides, random_circuit
+    from paper_2507_20667_amd.planner import SAConfig, simulated_annealing
+    from paper_2507_20667_amd.planner.plan import tree_partition
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "config3_amplitudes.json")))
+    c = gold["circuit"]
+    circ = random_circuit(c["n"], c["depth"], c["seed"], cx_per_layer=c["cx_per_layer"],
+                          p_nn=c["p_nn"])
+    net = amplitude_network(circ, 0)
+    t0 = time.perf_counter()
+    plan = simulated_annealing(net.legs, net.dims, tree_partition(net.legs, net.dims, 8), 8,
+                               SAConfig(iterations=8, seed=0))
+    plan_s = time.perf_counter() - t0
+    ctx = lib.Context(16 << 30)
+    out = {"workload": f"random circuit {c['n']} qubits depth {c['depth']} seed {c['seed']}, "
+                       f"{c['cx_per_layer']} CX pairs per layer (p_nn {c['p_nn']}), single-amplitude "
+                       "networks, 8 SA partitions", "planning_s": plan_s}
+    # bf16 MFMA operations per effective complex flop: 4M = 12 products of
+    # 2 flops per 8 effective flops, 3M = 9 products
+    for name, flags, peak, mul in [("fp32_4m", 0, MFMA_PEAK_TFLOPS["fp32"], 1.0),
+                                   ("bf16x3_4m", lib.TN_PREC_BF16X3, MFMA_PEAK_TFLOPS["bf16x3"], 3.0),
+                                   ("bf16x3_3m", lib.TN_PREC_BF16X3 | lib.TN_FORM_3M,
+                                    MFMA_PEAK_TFLOPS["bf16x3"], 2.25)]:
+        p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 8, plan.tree, None, flags)
+        costs = lib.tn_plan_costs_get(p)
+        worst = 0.0
+        for x in gold["bitstrings"]:
+            got, _ = lib.tn_contract(p, amplitude_overrides(net, circ, x))
+            ref = complex(*gold["amplitudes"][str(x)])
+            worst = max(worst, abs(complex(np.asarray(got).reshape(-1)[0]) - ref)
+                        / max(abs(ref), 2.0 ** (-c["n"] / 2)))
+        ovr = amplitude_overrides(net, circ, 0)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            lib.tn_contract(p, ovr)
+        amp_ms = (time.perf_counter() - t1) / reps * 1e3
+        lib.tn_profile_enable(ctx.handle, True)
+        lib.tn_profile_read(ctx.handle, reset=True)
+        for _ in range(reps):
+            lib.tn_contract(p, ovr)
+        lib.tn_profile_enable(ctx.handle, False)
+        st = lib.tn_profile_read(ctx.handle, reset=True)
+        g = st["gemm"]
+        eff = g["algo_flops"] / g["seconds"] / 1e12
+        out[name] = {"gemm_effective_tflops": eff, "mfma_peak_tflops": peak,
+                     "mfma_util": eff * mul / peak, "gemm_ms_per_amplitude": g["seconds"] / reps * 1e3,
+                     "gemm_launches_per_amplitude": g["launches"] // reps,
+                     "plain_ms_per_amplitude": amp_ms,
+                     "permute_ms_per_amplitude": st["permute"]["seconds"] / reps * 1e3,
+                     "con_serial": costs["con_serial"],
+                     "largest_intermediate": costs["largest_intermediate"],
+                     "max_rel_err_vs_statevector": worst, "amplitudes_checked": len(gold["bitstrings"])}
+        log(f"{name}: GEMM phase {eff:.1f} effective TFLOP/s ({out[name]['mfma_util']:.1%} of the "
+            f"MFMA peak), {amp_ms:.2f} ms per amplitude, max err {worst:.1e}")
+        ctx.free_plan(p)
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +339,8 @@ def main():
                          "that hardware byte counters can be scaled against it")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--no-largest", action="store_true",
+                    help="skip the 30-qubit GEMM-phase leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -365,6 +434,10 @@ def main():
     if args.serve_seconds > 0:
         serve = serve_bench(lib, ctx, args.serve_seconds, args.serve_rate, flags)
 
+    largest = None
+    if not args.no_largest:
+        largest = gemm_phase_leg(lib)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(net, plan, circ, args.cpu_seconds)
@@ -395,6 +468,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serve": serve,
+        "largest_config_gemm_phase": largest,
         "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},
     }
     ctx.close()

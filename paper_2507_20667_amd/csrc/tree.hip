@@ -119,6 +119,13 @@ __device__ __forceinline__ void tree_step_impl(const TreeStep *Sp, int lane, int
     sb[i] = Sp->sb[i];
     slg[i] = Sp->slg[i];
   }
+  // shared-index offsets, computed once per wave: hardware lane l holds those
+  // of s = l (ns <= 64), read back in the inner loop with readlane (s is the
+  // same in every lane there); every lane of the wave is active here
+  const int hl = threadIdx.x & 63;
+  const bool stab = ns <= 64;
+  int soa = 0, sob = 0;
+  if (stab && hl < ns) seg2r<P2>(sext, sa, sb, slg, nss, hl, soa, sob);
   int qprev = -1;
   float mx = 0.f, f = 1.f;
   const float2 *A = nullptr, *B = nullptr;
@@ -145,14 +152,25 @@ __device__ __forceinline__ void tree_step_impl(const TreeStep *Sp, int lane, int
     int ao, bo;
     seg2r<P2>(cext, ca, cb, clg, ncs, ci, ao, bo);
     float re = 0.f, im = 0.f;
-    for (int s = 0; s < ns; ++s) {
-      int oa, ob;
-      seg2r<P2>(sext, sa, sb, slg, nss, s, oa, ob);
-      const float2 x = A[ao + oa], y = B[bo + ob];
-      re = fmaf(x.x, y.x, re);
-      re = fmaf(-x.y, y.y, re);
-      im = fmaf(x.x, y.y, im);
-      im = fmaf(x.y, y.x, im);
+    if (stab) {
+      for (int s = 0; s < ns; ++s) {
+        const int oa = __builtin_amdgcn_readlane(soa, s), ob = __builtin_amdgcn_readlane(sob, s);
+        const float2 x = A[ao + oa], y = B[bo + ob];
+        re = fmaf(x.x, y.x, re);
+        re = fmaf(-x.y, y.y, re);
+        im = fmaf(x.x, y.y, im);
+        im = fmaf(x.y, y.x, im);
+      }
+    } else {
+      for (int s = 0; s < ns; ++s) {
+        int oa, ob;
+        seg2r<P2>(sext, sa, sb, slg, nss, s, oa, ob);
+        const float2 x = A[ao + oa], y = B[bo + ob];
+        re = fmaf(x.x, y.x, re);
+        re = fmaf(-x.y, y.y, re);
+        im = fmaf(x.x, y.y, im);
+        im = fmaf(x.y, y.x, im);
+      }
     }
     re *= f;
     im *= f;
