@@ -323,6 +323,97 @@ def gemm_phase_leg(lib, reps=3):
     return out
 
 
+def batch_mix_leg(lib, queries=512, reps=3):
+    """Uneven batch: 64 seeded circuits of the random family (n ~ U{12..26},
+    depth ~ U{8..20}, floor(n/4) CX pairs per layer; a seed is skipped when
+    the planned largest intermediate leaves [2^4, 2^24]), 4 SA partitions
+    each, `queries` amplitude queries whose circuit follows a truncated
+    Zipf(1.2) law over the 64 (bitstrings uniform).  Plain path (tn_contract
+    per query) against one tn_contract_batch call over all of them; the
+    executed flops of the batched call (shared parts once) come from the
+    event-timed kernel classes."""
+    import oracle
+    from paper_2507_20667_amd.inputs import amplitude_network, amplitude_overrides, circuit_mix, zipf_indices
+    from paper_2507_20667_amd.planner import SAConfig, simulated_annealing
+    from paper_2507_20667_amd.planner.cost import largest_intermediate
+    from paper_2507_20667_amd.planner.plan import tree_partition
+    t0 = time.perf_counter()
+    circs, seed = [], 0
+    while len(circs) < 64:
+        (s, circ), = circuit_mix(1, seed)
+        seed += 1
+        net = amplitude_network(circ, 0)
+        plan = simulated_annealing(net.legs, net.dims, tree_partition(net.legs, net.dims, 4), 4,
+                                   SAConfig(iterations=4, n_steps=16, workers=2, rg_samples=4, seed=s))
+        li = largest_intermediate(net.legs, net.dims, plan.tree)
+        if li > 1 << 24 or li < 1 << 4:
+            continue
+        circs.append((circ, net, plan))
+    plan_s = time.perf_counter() - t0
+    idx = zipf_indices(len(circs), queries, 1.2, 7)
+    rng = np.random.default_rng(8)
+    bits = [int(rng.integers(0, 1 << circs[i][0].n)) for i in idx]
+    ctx = lib.Context(32 << 30)
+    handles = [ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 4, plan.tree, None, 0)
+               for _, net, plan in circs]
+    cs = [lib.tn_plan_costs_get(h)["con_serial"] for h in handles]
+    qs = [(handles[i], amplitude_overrides(circs[i][1], circs[i][0], x)) for i, x in zip(idx, bits)]
+    shapes = [()] * queries
+    work = 8.0 * sum(cs[i] for i in idx)
+
+    def amp(o, l2):
+        return complex(o.reshape(-1)[0]) * 2.0 ** float(l2)
+
+    outs, l2s, st = lib.tn_contract_batch(ctx.handle, qs, shapes)  # warm-up: layouts, programs
+    assert all(int(x) == 0 for x in st), st
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        outs, l2s, st = lib.tn_contract_batch(ctx.handle, qs, shapes)
+    bt = (time.perf_counter() - t1) / reps
+    lib.tn_profile_enable(ctx.handle, True)
+    lib.tn_profile_read(ctx.handle, reset=True)
+    lib.tn_contract_batch(ctx.handle, qs, shapes)
+    lib.tn_profile_enable(ctx.handle, False)
+    prof = lib.tn_profile_read(ctx.handle, reset=True)
+    exec_flops = sum(v["algo_flops"] for v in prof.values())
+    kern_s = sum(v["seconds"] for v in prof.values())
+    plain = []
+    for q in qs[:8]:
+        lib.tn_contract(*q)
+    t2 = time.perf_counter()
+    for q in qs:
+        plain.append(lib.tn_contract(*q))
+    pt = time.perf_counter() - t2
+    diff = max(abs(amp(outs[k], l2s[k]) - amp(*plain[k])) / max(abs(amp(*plain[k])), 2.0 ** (-circs[i][0].n / 2))
+               for k, i in enumerate(idx))
+    # the oracle on the queries of the smallest circuits
+    errs = []
+    for k, i in enumerate(idx):
+        circ, net, plan = circs[i]
+        if circ.n > 16 or len(errs) >= 8:
+            continue
+        ref = complex(oracle.contract_tree(net.legs, net.dims, net.copy_with(qs[k][1]).tensors, plan.tree))
+        errs.append(abs(amp(outs[k], l2s[k]) - ref) / max(abs(ref), 2.0 ** (-circ.n / 2)))
+    ctx.close()
+    out = {"workload": f"{queries} amplitude queries over 64 random-family circuits (12-26 qubits, "
+                       "depth 8-20, floor(n/4) CX per layer), circuit ~ truncated Zipf(1.2), 4 SA "
+                       "partitions each",
+           "planning_s": plan_s, "queries": queries,
+           "distinct_circuits_queried": len(set(idx)),
+           "batched_amplitudes_per_s": queries / bt, "plain_amplitudes_per_s": queries / pt,
+           "speedup_vs_plain": pt / bt,
+           "effective_tflops_batched": work / bt / 1e12,
+           "effective_tflops_plain": work / pt / 1e12,
+           "executed_tflops_batched": exec_flops / bt / 1e12,
+           "kernel_seconds_batched": kern_s, "wall_seconds_batched": bt,
+           "max_rel_diff_batched_vs_plain": diff,
+           "max_rel_err_vs_oracle": max(errs) if errs else None, "oracle_checked": len(errs)}
+    log(f"batch mix: {out['batched_amplitudes_per_s']:.0f} amplitudes/s batched vs "
+        f"{out['plain_amplitudes_per_s']:.0f} plain (x{out['speedup_vs_plain']:.1f}), "
+        f"max diff {diff:.1e}, oracle err {out['max_rel_err_vs_oracle']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,6 +432,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the 30-qubit GEMM-phase leg")
+    ap.add_argument("--no-mix", action="store_true",
+                    help="skip the uneven 64-circuit batch leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -438,6 +531,10 @@ def main():
     if not args.no_largest:
         largest = gemm_phase_leg(lib)
 
+    mix = None
+    if not args.no_mix:
+        mix = batch_mix_leg(lib)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(net, plan, circ, args.cpu_seconds)
@@ -469,6 +566,7 @@ def main():
         "cpu_baseline": cpu,
         "serve": serve,
         "largest_config_gemm_phase": largest,
+        "uneven_batch": mix,
         "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},
     }
     ctx.close()

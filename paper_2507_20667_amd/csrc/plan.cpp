@@ -862,8 +862,13 @@ static LevelPlan level_plan(const tn_plan *p, const std::vector<int> &nodes) {
       if (c >= nv) l = std::max(l, lvl[c]);
     lvl[u] = l + 1;
   }
+  // within a level, largest contraction first: the kernel deals a chunk's
+  // steps to its waves round robin, so this evens out their shares
   std::vector<int> ord(nodes);
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return lvl[a] < lvl[b]; });
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (lvl[a] != lvl[b]) return lvl[a] < lvl[b];
+    return p->nodes[a - nv].weight > p->nodes[b - nv].weight;
+  });
   LevelPlan lp;
   for (size_t i = 0; i < ord.size();) {
     std::vector<int> ch;

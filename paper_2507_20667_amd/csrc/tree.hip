@@ -286,7 +286,8 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
       // one step (a spine contraction): the whole workgroup on it
       tree_step(S, tid, 256, nqw, pq, perq, shr, scl, h.nscale);
     } else {
-      // several independent steps of one level: one wave per step
+      // several independent steps of one level (largest first): one wave per
+      // step, round robin
       const int wave = tid >> 6, lane = tid & 63;
       for (int i = wave; i < cur; i += 4) tree_step(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale);
     }

@@ -187,3 +187,28 @@ def random_circuit(n: int, depth: int, seed: int, cx_per_layer: int | None = Non
 def random_bitstrings(n: int, count: int, seed: int) -> list:
     rng = np.random.default_rng(seed)
     return [int(x) for x in rng.integers(0, 1 << n, size=count, dtype=np.int64)]
+
+
+def circuit_mix(count: int, seed0: int = 0, n_range=(12, 26), d_range=(8, 20)) -> list:
+    """`count` circuits of the random family, circuit i drawn from seed
+    seed0 + i: n ~ U{n_range}, depth ~ U{d_range}, floor(n/4) CX pairs per
+    layer (70 % nearest-neighbour).  Returns (seed, circuit) pairs."""
+    out = []
+    for i in range(count):
+        seed = seed0 + i
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        d = int(rng.integers(d_range[0], d_range[1] + 1))
+        out.append((seed, random_circuit(n, d, seed, cx_per_layer=n // 4)))
+    return out
+
+
+def zipf_indices(count: int, num: int, s: float, seed: int) -> list:
+    """`num` indices in [0, count) from a Zipf(s) law truncated to `count`
+    values (draws above the range are redrawn): index 0 is the most likely."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < num:
+        v = rng.zipf(s, size=num)
+        out.extend(int(x) - 1 for x in v if x <= count)
+    return out[:num]
