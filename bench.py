@@ -8,7 +8,9 @@ the whole path: leaf overrides, every partition's tree in turn, the reduction
 path and the FP64 final contraction.  The overrides of all steps are placed in
 device memory before the timed region.
 
-Printed: one JSON line with amplitudes/s of the batched path (`value`), the
+Printed: one JSON line with amplitudes/s of the batched path (`value`:
+tn_contract_strided, the overridden output vectors read in place from one
+device buffer; tn_contract_batch with per-query descriptors beside it), the
 plain per-query path (tn_contract, one query at a time) for the same
 workload, effective complex TFLOP/s (8 * con_serial per amplitude), the
 roofline position of the dominant kernel class (event-timed inside this run)
@@ -75,6 +77,31 @@ def device_overrides(torch, net, n, bitstrings):
             arr[i] = lib.tn_leaf(t, base + ((qi * n + i) * 2) * 8, lib.TN_C64_DEVICE)
         leaves.append(arr)
     return dev, leaves
+
+
+def strided_call(lib, plan, dev, net, n):
+    """tn_contract_strided over the (queries, n, 2) device tensor: one leaf
+    descriptor per output qubit with a stride of one query's block."""
+    from paper_2507_20667_amd.inputs import output_tensor_ids
+    ids = output_tensor_ids(net)
+    Q = dev.shape[0]
+    base = dev.data_ptr()
+    arr = (lib.tn_leaf * n)()
+    strides = (ctypes.c_int64 * n)()
+    for i, t in enumerate(ids):
+        arr[i] = lib.tn_leaf(t, base + i * 16, lib.TN_C64_DEVICE)
+        strides[i] = n * 16
+    outs = np.zeros((Q, 2), dtype=np.float64)
+
+    def call():
+        rc = lib.load().tn_contract_strided(ctypes.c_void_p(plan), Q, n, ctypes.cast(arr, ctypes.c_void_p),
+                                            ctypes.cast(strides, ctypes.c_void_p),
+                                            outs.ctypes.data_as(ctypes.c_void_p), 1, lib.TN_C128, None, 0)
+        if rc != 0:
+            raise lib.TnError(rc, lib.tn_last_error())
+        return outs
+    call.keep = (arr, strides, dev)
+    return call
 
 
 def batch_call(lib, ctx, plan, leaves, n):
@@ -464,11 +491,12 @@ def main():
     con_serial = costs["con_serial"]
     Q, K, W = args.queries, args.steps, args.warmup
     steps_bits = [random_bitstrings(n, Q, 1000 + s) for s in range(K + W)]
-    devs, calls = [], []
+    devs, calls, bcalls = [], [], []
     for s in range(K + W):
         dev, leaves = device_overrides(torch, net, n, steps_bits[s])
         devs.append((dev, leaves))
-        calls.append(batch_call(lib, ctx.handle, p, leaves, n))
+        calls.append(strided_call(lib, p, dev, net, n))
+        bcalls.append(batch_call(lib, ctx.handle, p, leaves, n))
     torch.cuda.synchronize()
 
     # parity spot check outside the timed region
@@ -494,6 +522,15 @@ def main():
     dt = time.perf_counter() - t0
     amps = Q * K / dt
     eff_tflops = 8.0 * con_serial * Q * K / dt / 1e12
+    # the same steps through tn_contract_batch (one descriptor per query and leaf)
+    for s in range(W):
+        bcalls[s]()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for s in range(W, W + K):
+        bcalls[s]()
+    torch.cuda.synchronize()
+    batch_api_amps = Q * K / (time.perf_counter() - tb)
 
     # plain path: tn_contract, one query at a time, device-resident overrides
     dev0, leaves0 = devs[W]
@@ -558,6 +595,7 @@ def main():
                    "con_serial": con_serial, "con_dist": costs["con_dist"],
                    "largest_intermediate": costs["largest_intermediate"]},
         "effective_tflops": eff_tflops,
+        "batch_api_amplitudes_per_s": batch_api_amps,
         "plain_amplitudes_per_s": plain_amps,
         "speedup_vs_plain": amps / plain_amps,
         "max_rel_err": max_err,

@@ -210,6 +210,32 @@ tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *qu
                             tn_status *per_query, uint32_t flags);
 
 /*
+ * Contract num_queries queries of one plan whose overridden leaves are laid
+ * out with fixed strides, as tn_contract_batch does, without per-query
+ * descriptors: the host work is independent of the number of queries.
+ * This is the batched amplitude form of Section 4: every query keeps the
+ * network and the tree and replaces the same leaves (for amplitudes, the
+ * output basis vectors).
+ *   overrides[k]   leaf tensor id, dtype and query 0's copy of overridden
+ *                  leaf k (layout as in tn_leaf);
+ *   strides[k]     bytes from one query's copy to the next (0: all queries
+ *                  share query 0's copy).  TN_C64_DEVICE data with a stride
+ *                  that is a multiple of 8 is read in place by the kernels,
+ *                  other data is staged.  The caller keeps the data alive
+ *                  and unchanged until the call returns.
+ *   out            host memory; query q's result (the product of the output
+ *                  dimensions elements of out_dtype) starts out_stride
+ *                  elements after query q - 1's.
+ *   log2_scales    num_queries values (TN_FLAG_KEEP_SCALE) or NULL.
+ * Errors: TN_E_INVALID_ARG (bad ids, dtypes, strides, out_stride smaller
+ * than a result, host-only plan), TN_E_NOMEM, TN_E_DEVICE.  Synchronous.
+ */
+tn_status tn_contract_strided(tn_plan *plan, int32_t num_queries, int32_t num_overrides,
+                              const tn_leaf *overrides, const int64_t *strides, void *out,
+                              int64_t out_stride, tn_dtype out_dtype, double *log2_scales,
+                              uint32_t flags);
+
+/*
  * Serving.  tn_serve_submit copies the query and returns a ticket at once
  * (TN_E_AGAIN when the queue is full).  A library thread admits queued
  * requests while their workspace fits the free arena, groups admitted

@@ -206,6 +206,40 @@ tn_status tn_contract(tn_plan *p, int32_t num_overrides, const tn_leaf *override
   return run_group(p->ctx, p, {q}, out_dtype, flags, false, r);
 }
 
+tn_status tn_contract_strided(tn_plan *p, int32_t num_queries, int32_t num_overrides,
+                              const tn_leaf *overrides, const int64_t *strides, void *out,
+                              int64_t out_stride, tn_dtype out_dtype, double *log2_scales,
+                              uint32_t flags) {
+  if (!p || !p->ctx) {
+    set_error("tn_contract_strided: plan is NULL or host-only (loaded without a context)");
+    return TN_E_INVALID_ARG;
+  }
+  if (num_queries < 0 || num_overrides < 0 || (num_overrides > 0 && (!overrides || !strides)) ||
+      (num_queries > 0 && !out) || (flags & ~TN_FLAG_KEEP_SCALE) ||
+      (out_dtype != TN_C64 && out_dtype != TN_C128)) {
+    set_error("tn_contract_strided: bad arguments");
+    return TN_E_INVALID_ARG;
+  }
+  if (out_stride < (int64_t)result_elems(p)) {
+    set_error("tn_contract_strided: out_stride %lld is smaller than a result (%zu elements)",
+              (long long)out_stride, result_elems(p));
+    return TN_E_INVALID_ARG;
+  }
+  if (num_queries == 0) return TN_OK;
+  StridedOvr so;
+  so.leaves.assign(overrides, overrides + num_overrides);
+  so.strides.assign(strides, strides + num_overrides);
+  const size_t esz = out_dtype == TN_C128 ? 16 : 8;
+  std::vector<QueryIO> qs((size_t)num_queries);
+  for (int32_t i = 0; i < num_queries; ++i) {
+    qs[i].out = (char *)out + (size_t)i * (size_t)out_stride * esz;
+    qs[i].log2s = log2_scales ? &log2_scales[i] : nullptr;
+  }
+  std::lock_guard<std::mutex> g(p->ctx->exec_mu);
+  ExecRes r = ctx_res(p->ctx);
+  return run_group(p->ctx, p, qs, out_dtype, flags, true, r, &so);
+}
+
 tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *queries,
                             void *const *outs, tn_dtype out_dtype, double *log2_scales,
                             tn_status *per_query, uint32_t flags) {

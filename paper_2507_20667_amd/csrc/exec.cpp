@@ -93,7 +93,7 @@ static void write_out(void *out, tn_dtype dt, size_t i, double re, double im) {
   } while (0)
 
 tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_dtype out_dtype,
-                    uint32_t flags, bool share, ExecRes &rs) {
+                    uint32_t flags, bool share, ExecRes &rs, const StridedOvr *so) {
   const int nv = p->nv, nn = 2 * nv - 1;
   if (qs.empty()) return TN_OK;
   if (out_dtype != TN_C64 && out_dtype != TN_C128) {
@@ -102,11 +102,26 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   }
   // overridden leaves of the group
   std::vector<char> is_ovr(nv, 0);
+  std::vector<int> so_of(so ? nv : 0, -1);  // strided form: leaf -> its entry
+  if (so)
+    for (size_t i = 0; i < so->leaves.size(); ++i) {
+      const tn_leaf &l = so->leaves[i];
+      if (l.tensor < 0 || l.tensor >= nv || !l.data || is_ovr[l.tensor] ||
+          (l.dtype != TN_C64 && l.dtype != TN_C128 && l.dtype != TN_C64_DEVICE) ||
+          so->strides[i] < 0) {
+        set_error("override %zu: tensor id out of range or repeated, NULL data, bad dtype or "
+                  "negative stride", i);
+        return TN_E_INVALID_ARG;
+      }
+      is_ovr[l.tensor] = 1;
+      so_of[l.tensor] = (int)i;
+    }
   for (const QueryIO &q : qs) {
     if (!q.out) {
       set_error("output pointer is NULL");
       return TN_E_INVALID_ARG;
     }
+    if (so) continue;
     for (int i = 0; i < q.novr; ++i) {
       const tn_leaf &l = q.ovr[i];
       if (l.tensor < 0 || l.tensor >= nv || !l.data ||
@@ -132,6 +147,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   };
   std::shared_ptr<ExecLayout> Lp = cached_layout(p, ovr, share);
   const ExecLayout &L = *Lp;
+  const double t_layout = dbg ? ms_since(t_enter) : 0.0;
   Profiler idle_prof;
   Profiler &prof = rs.prof ? *rs.prof : idle_prof;
   const hipStream_t st = rs.st;
@@ -226,7 +242,9 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     const size_t r_part = carve((size_t)max_blocks * 16 * Q);
     const size_t total = o;
     const bool own_ws = rs.ws < 0;
+    const double t_carve = dbg ? ms_since(t_enter) : 0.0;
     int64_t ws = own_ws ? ctx->arena.alloc(total) : rs.ws;
+    const double t_alloc = dbg ? ms_since(t_enter) : 0.0;
     if (ws < 0) {
       set_error("arena exhausted (%zu bytes requested)", total);
       return TN_E_NOMEM;
@@ -291,7 +309,45 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     {
       // stage overrides (complex64) for every query of the chunk.  Device-
       // resident overrides evenly spaced across the chunk are read in place.
-      if (ovr_bytes) {
+      if (ovr_bytes && so) {
+        bool any_staged = false;
+        for (int t : ovr) {
+          const tn_leaf &l = so->leaves[so_of[t]];
+          const int64_t stride = so->strides[so_of[t]];
+          if (l.dtype == TN_C64_DEVICE && stride % 8 == 0) {
+            direct_p[t] = (const float2 *)((const char *)l.data + (int64_t)q0 * stride);
+            direct_bs[t] = stride / 8;
+          } else {
+            direct_p[t] = nullptr;
+            any_staged = true;
+          }
+        }
+        if (any_staged) {
+          rc = ensure_pinned(rs, ovr_bytes * Q);
+          if (rc) goto done;
+          uint8_t *h = (uint8_t *)*rs.pinned;
+          for (int qi = 0; qi < Q; ++qi)
+            for (int t : ovr) {
+              const tn_leaf &l = so->leaves[so_of[t]];
+              if (direct_p[t] || l.dtype == TN_C64_DEVICE) continue;
+              tn_leaf lq = l;
+              lq.data = (const char *)l.data + (int64_t)(q0 + qi) * so->strides[so_of[t]];
+              to_c64(lq, p->leaf[t].size(), (float2 *)(h + (size_t)qi * ovr_bytes + ovr_off[t]));
+            }
+          TN_HIP(hipMemcpyAsync(ovr_base, h, ovr_bytes * Q, hipMemcpyHostToDevice, st),
+                 "override upload");
+          // device data whose stride the kernels cannot step: one copy per query
+          for (int qi = 0; qi < Q; ++qi)
+            for (int t : ovr) {
+              const tn_leaf &l = so->leaves[so_of[t]];
+              if (direct_p[t] || l.dtype != TN_C64_DEVICE) continue;
+              TN_HIP(hipMemcpyAsync(ovr_base + (size_t)qi * ovr_bytes + ovr_off[t],
+                                    (const char *)l.data + (int64_t)(q0 + qi) * so->strides[so_of[t]],
+                                    p->leaf[t].size() * 8, hipMemcpyDeviceToDevice, st),
+                     "device override copy");
+            }
+        }
+      } else if (ovr_bytes) {
         const size_t no = ovr.size();
         std::vector<const tn_leaf *> src((size_t)Q * no, nullptr);
         for (int qi = 0; qi < Q; ++qi) {
@@ -358,6 +414,10 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       // every vertex (it keeps its scales in LDS and writes its results' records)
       if (!(trees && L.all_in_tree))
         TN_HIP(launch_init_slots(st, slots, (int64_t)nn * (Q + 1)), "slot init");
+      const double t_staged = dbg ? ms_since(t_enter) : 0.0;
+      if (dbg)
+        fprintf(stderr, "[tn] run_group host: layout %.3f, carve %.3f, alloc %.3f, staged %.3f ms\n",
+                t_layout, t_carve, t_alloc, t_staged);
       if (trees) {
         const uint8_t *tb = ctx->arena.base() + L.tree_dev;
         TreeLaunch tl;

@@ -809,6 +809,72 @@ static bool tree_fill(const std::vector<LegMap> &legs, int32_t *ext, int32_t *s0
   return true;
 }
 
+// Kind 2 step of vertex n: the small operand Y (<= 16 entries, ns and nfy in
+// {1, 2, 4}) applied along the fibers of the large one X.  `swap`: Y is the
+// first child (the caller then puts X's location in `a`).
+static bool tree_stream_step(const Node &n, const std::vector<Layout> &lay, TreeStep &st,
+                             bool &swap) {
+  const Layout &L1 = lay[n.c1], &L2 = lay[n.c2];
+  swap = L1.size() < L2.size();
+  const Layout &X = swap ? L2 : L1, &Y = swap ? L1 : L2;
+  if (Y.size() > 16 || n.out.rank() == 0) return false;
+  const std::vector<int64_t> xst = X.strides(), yst = Y.strides(), ost = n.out.strides();
+  std::vector<int> sh, yf;  // Y's legs: shared with X, free
+  for (int i = 0; i < Y.rank(); ++i) (X.find(Y.lab[i]) >= 0 ? sh : yf).push_back(i);
+  int64_t ns = 1, nfy = 1;
+  for (int i : sh) ns *= Y.dim[i];
+  for (int i : yf) nfy *= Y.dim[i];
+  auto small = [](int64_t v) { return v == 1 || v == 2 || v == 4; };
+  if (!small(ns) || !small(nfy)) return false;
+  int64_t ys[4], yj[4];
+  for (int64_t v = 0; v < ns; ++v) {  // shared index, last leg fastest
+    int64_t r = v, xo = 0, yo = 0;
+    for (int k = (int)sh.size() - 1; k >= 0; --k) {
+      const int i = sh[k];
+      const int64_t d = r % Y.dim[i];
+      r /= Y.dim[i];
+      yo += d * yst[i];
+      xo += d * xst[X.find(Y.lab[i])];
+    }
+    st.xs[v] = (int32_t)xo;
+    ys[v] = yo;
+  }
+  for (int64_t v = 0; v < nfy; ++v) {  // Y's free index
+    int64_t r = v, yo = 0, co = 0;
+    for (int k = (int)yf.size() - 1; k >= 0; --k) {
+      const int i = yf[k];
+      const int64_t d = r % Y.dim[i];
+      r /= Y.dim[i];
+      yo += d * yst[i];
+      const int io = n.out.find(Y.lab[i]);
+      if (io < 0) return false;
+      co += d * ost[io];
+    }
+    st.cy[v] = (int32_t)co;
+    yj[v] = yo;
+  }
+  for (int64_t a = 0; a < ns; ++a)
+    for (int64_t b = 0; b < nfy; ++b) st.ymap[a * nfy + b] = (int32_t)(ys[a] + yj[b]);
+  std::vector<LegMap> fl;  // X's free legs: fiber -> (X offset, C offset)
+  int64_t nfib = 1;
+  for (int i = 0; i < X.rank(); ++i) {
+    if (Y.find(X.lab[i]) >= 0) continue;
+    const int io = n.out.find(X.lab[i]);
+    if (io < 0) return false;
+    fl.push_back({X.dim[i], xst[i], ost[io]});
+    nfib *= X.dim[i];
+  }
+  bool p2 = true;
+  if (!tree_fill(fl, st.cext, st.ca, st.cb, st.clg, st.ncs, p2)) return false;
+  if (nfib * nfy != n.out.size()) return false;
+  st.nc = (int32_t)(nfib * nfy);
+  st.ns = (int32_t)ns;
+  st.nss = (int32_t)nfy;
+  st.kind = 2;
+  st.pow2 = p2 ? 1 : 0;
+  return true;
+}
+
 // Step of vertex n: result index over n.out's legs, shared index over the
 // shared legs (A's order); a closed root is a full inner product.
 static bool tree_step(const tn_plan *p, const Node &n, const std::vector<Layout> &lay, bool final_dot,
@@ -1045,12 +1111,18 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
         const Node &n = p->nodes[u - nv];
         TreeStep st;
         const bool final_dot = n.kind == NK_DOT && u == p->root;
-        tree_step(p, n, lay, final_dot, st);
-        st.a = loc[n.c1];
-        st.b = loc[n.c2];
+        bool swap = false;
+        memset(&st, 0, sizeof(st));
+        if (final_dot || !tree_stream_step(n, lay, st, swap)) {
+          swap = false;
+          tree_step(p, n, lay, final_dot, st);
+        }
+        const int ca_ = swap ? n.c2 : n.c1, cb_ = swap ? n.c1 : n.c2;
+        st.a = loc[ca_];
+        st.b = loc[cb_];
         st.c = loc[u];
-        st.asl = n.c1 >= nv ? scale[n.c1] : -1;
-        st.bsl = n.c2 >= nv ? scale[n.c2] : -1;
+        st.asl = ca_ >= nv ? scale[ca_] : -1;
+        st.bsl = cb_ >= nv ? scale[cb_] : -1;
         st.csl = scale[u];
         steps.push_back(st);
         if (final_dot) h.final_dot = 1;
@@ -1094,6 +1166,26 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       ok = ok && chunks[c].nsteps >= 1 && chunks[c].nsteps <= kTreeChunk;
       for (int k = chunks[c].step0; k < chunks[c].step0 + chunks[c].nsteps; ++k) {
         const TreeStep &st = steps[k];
+        if (st.kind == 2) {
+          // fibers: X reach + largest shared offset; C reach + largest cy < nc
+          const int ns = st.ns, nfy = st.nss;
+          ok = ok && (ns == 1 || ns == 2 || ns == 4) && (nfy == 1 || nfy == 2 || nfy == 4) &&
+               st.nc % nfy == 0;
+          if (!ok) break;
+          int64_t mx = 0, mc = 0, my = 0;
+          for (int v = 0; v < ns; ++v) mx = std::max<int64_t>(mx, st.xs[v]);
+          for (int v = 0; v < nfy; ++v) mc = std::max<int64_t>(mc, st.cy[v]);
+          for (int v = 0; v < ns * nfy; ++v) my = std::max<int64_t>(my, st.ymap[v]);
+          const bool neg = std::min({st.xs[0], st.cy[0], st.ymap[0]}) < 0;
+          int64_t fib = 1;
+          for (int i = 0; i < st.ncs; ++i) fib *= st.cext[i];
+          ok = ok && !neg && fib * nfy == st.nc && inside(st.a, reach(st.cext, st.ca, st.ncs) + mx) &&
+               inside(st.b, my) && (st.c & kPerQuery) &&
+               reach(st.cext, st.cb, st.ncs) + mc < st.nc &&
+               (st.c & ~kPerQuery) + st.nc <= h.perq_elems && st.csl >= 0 && st.csl < h.nscale &&
+               st.asl < h.nscale && st.bsl < h.nscale;
+          continue;
+        }
         const int64_t ra = reach(st.cext, st.ca, st.ncs) + reach(st.sext, st.sa, st.nss);
         const int64_t rb = reach(st.cext, st.cb, st.ncs) + reach(st.sext, st.sb, st.nss);
         ok = ok && inside(st.a, ra) && inside(st.b, rb) && (st.c & kPerQuery) &&
@@ -1127,12 +1219,24 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       break;
     }
   }
+  if (const char *e = getenv("TN_TREE_QW")) {  // tuning override
+    const int qw = atoi(e);
+    if (qw >= 1 && qw <= 16 && tree_lds_bytes(qw, max_scale_q, max_sh_q, max_pq_q) <= tree_lds_limit())
+      L.tree_qw = qw;
+  }
   L.lds_perq = tree_lds_bytes(L.tree_qw, max_scale_q, max_sh_q, max_pq_q);
   if (getenv("TN_DEBUG"))
-    for (const TreeHdr &h : hdrs)
-      fprintf(stderr, "[tn]   subtree root %d: %d chunks, %d shared leaf entries, %d per-query entries, "
-              "%d scale records, %d loads\n", h.root_slot, h.nchunks, h.shared_elems, h.perq_elems,
-              h.nscale, h.nloads);
+    for (const TreeHdr &h : hdrs) {
+      int gate = 0, nsteps = 0;
+      for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c)
+        for (int k = chunks[c].step0; k < chunks[c].step0 + chunks[c].nsteps; ++k) {
+          ++nsteps;
+          gate += steps[k].kind == 2;
+        }
+      fprintf(stderr, "[tn]   subtree root %d: %d chunks, %d steps (%d gate form), %d shared leaf "
+              "entries, %d per-query entries, %d scale records, %d loads\n", h.root_slot, h.nchunks,
+              nsteps, gate, h.shared_elems, h.perq_elems, h.nscale, h.nloads);
+    }
   // blob
   auto put = [&](const void *src, size_t bytes) {
     size_t off = (L.tree_blob.size() + 255) & ~(size_t)255;

@@ -138,17 +138,30 @@ constexpr int kTreeMaxElems = 4096;
 constexpr int kTreeChunk = 16;     // steps of one level run between two barriers
 constexpr int kTreeMaxOvr = 64;    // overridden leaves read in place per launch
 
+// kind 0, a contraction: C[i] = sum_s A[ca(i) + sa(s)] B[cb(i) + sb(s)].
+// kind 1, the closed root: the FP64 inner product sum_s A[sa(s)] B[sb(s)].
+// kind 2, a small operand (a gate) applied along the fibers of a large one:
+// A is the large operand X, B the small one Y (<= 16 entries); for every value
+// f of X's free index (the map: f -> (X offset ca, C offset cb), nc / nfy
+// values) and j < nfy: C[cb(f) + cy[j]] = sum_{s < ns} X[ca(f) + xs[s]] *
+// Y[ymap[s * nfy + j]], with ns, nfy in {1, 2, 4}.
 struct TreeStep {
   int32_t a, b, c;        // LDS locations of the operands and the result
   int32_t asl, bsl, csl;  // scale index of each (-1: a leaf, scale 1)
   int32_t nc, ns;         // result entries, shared-index entries
-  int32_t ncs, nss;       // segment counts of the two maps
-  int32_t kind;           // 0: contraction, 1: final FP64 inner product
+  int32_t ncs, nss;       // segment counts of the two maps (kind 2: nss = nfy)
+  int32_t kind;
   int32_t pow2;           // every extent a power of two
-  // result index -> (A offset, B offset), innermost first
+  // result index -> (A offset, B offset), innermost first (kind 2: fibers)
   int32_t cext[kTreeSeg], ca[kTreeSeg], cb[kTreeSeg], clg[kTreeSeg];
-  // shared index -> (A offset, B offset)
-  int32_t sext[kTreeSeg], sa[kTreeSeg], sb[kTreeSeg], slg[kTreeSeg];
+  union {
+    struct {  // kinds 0 and 1: shared index -> (A offset, B offset)
+      int32_t sext[kTreeSeg], sa[kTreeSeg], sb[kTreeSeg], slg[kTreeSeg];
+    };
+    struct {  // kind 2
+      int32_t xs[4], cy[4], ymap[16];
+    };
+  };
 };
 constexpr int kTreeStepWords = (int)(sizeof(TreeStep) / 4);
 

@@ -307,6 +307,12 @@ struct QueryIO {
   double *log2s = nullptr;
   tn_status *status = nullptr;
 };
+// Overrides of a group given once with per-query byte strides (query q's copy
+// of leaf k at leaves[k].data + q * strides[k]); QueryIO::ovr is then unused.
+struct StridedOvr {
+  std::vector<tn_leaf> leaves;
+  std::vector<int64_t> strides;
+};
 // Resources of one executing thread: its stream, its pinned staging, an
 // optional profiler and optionally a workspace reserved beforehand.
 struct ExecRes {
@@ -318,7 +324,7 @@ struct ExecRes {
   size_t ws_bytes = 0;
 };
 tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_dtype out_dtype,
-                    uint32_t flags, bool share, ExecRes &res);
+                    uint32_t flags, bool share, ExecRes &rs, const StridedOvr *so = nullptr);
 size_t group_workspace_bytes(const tn_plan *p, const ExecLayout &L, int Q);
 size_t result_elems(const tn_plan *p);
 

@@ -85,6 +85,11 @@ __device__ __forceinline__ void tree_step_impl(const TreeStep *Sp, int lane, int
                                                float2 *pq, int perq, const float2 *shr, int2 *scl,
                                                int nscale);
 
+template <bool P2, int NS, int NFY>
+__device__ __forceinline__ void tree_stream_impl(const TreeStep *Sp, int lane, int nthr, int nqw,
+                                                 float2 *pq, int perq, const float2 *shr,
+                                                 int2 *scl, int nscale);
+
 // One contraction for every query of the group, by `nthr` threads starting at
 // `lane`.  The step's maps live in registers; each thread keeps the running
 // max of its results per query and folds it into the scale record once per
@@ -92,10 +97,114 @@ __device__ __forceinline__ void tree_step_impl(const TreeStep *Sp, int lane, int
 __device__ __forceinline__ void tree_step(const TreeStep *Sp, int lane, int nthr, int nqw,
                                           float2 *pq, int perq, const float2 *shr, int2 *scl,
                                           int nscale) {
+  if (Sp->kind == 2) {
+    // a small operand along the fibers of a large one: ns, nfy in {1, 2, 4}
+    const int sel = (Sp->ns >> 1) * 3 + (Sp->nss >> 1) + (Sp->pow2 ? 0 : 9);
+#define TN_TS(P, A, B) tree_stream_impl<P, A, B>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale)
+    switch (sel) {
+      case 0: TN_TS(true, 1, 1); break;
+      case 1: TN_TS(true, 1, 2); break;
+      case 2: TN_TS(true, 1, 4); break;
+      case 3: TN_TS(true, 2, 1); break;
+      case 4: TN_TS(true, 2, 2); break;
+      case 5: TN_TS(true, 2, 4); break;
+      case 6: TN_TS(true, 4, 1); break;
+      case 7: TN_TS(true, 4, 2); break;
+      case 8: TN_TS(true, 4, 4); break;
+      case 9: TN_TS(false, 1, 1); break;
+      case 10: TN_TS(false, 1, 2); break;
+      case 11: TN_TS(false, 1, 4); break;
+      case 12: TN_TS(false, 2, 1); break;
+      case 13: TN_TS(false, 2, 2); break;
+      case 14: TN_TS(false, 2, 4); break;
+      case 15: TN_TS(false, 4, 1); break;
+      case 16: TN_TS(false, 4, 2); break;
+      default: TN_TS(false, 4, 4); break;
+    }
+#undef TN_TS
+    return;
+  }
   if (Sp->pow2)
     tree_step_impl<true>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale);
   else
     tree_step_impl<false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale);
+}
+
+// Kind 2: one thread per fiber of the large operand X (and query) reads the
+// fiber's ns entries once and writes nfy results; the small operand Y sits in
+// registers, reloaded when a thread moves to another query.
+template <bool P2, int NS, int NFY>
+__device__ __forceinline__ void tree_stream_impl(const TreeStep *Sp, int lane, int nthr, int nqw,
+                                                 float2 *pq, int perq, const float2 *shr,
+                                                 int2 *scl, int nscale) {
+  const int a = Sp->a, b = Sp->b, c = Sp->c;
+  const int asl = Sp->asl, bsl = Sp->bsl, csl = Sp->csl;
+  const int nfib = Sp->nc / NFY, ncs = Sp->ncs;
+  const int lgf = P2 ? __builtin_ctz((unsigned)nfib) : 0;
+  int32_t fext[kTreeSeg], fx[kTreeSeg], fc[kTreeSeg], flg[kTreeSeg];
+#pragma unroll
+  for (int i = 0; i < kTreeSeg; ++i) {
+    fext[i] = Sp->cext[i];
+    fx[i] = Sp->ca[i];
+    fc[i] = Sp->cb[i];
+    flg[i] = Sp->clg[i];
+  }
+  int xs[NS], cy[NFY], ym[NS * NFY];
+#pragma unroll
+  for (int v = 0; v < NS; ++v) xs[v] = Sp->xs[v];
+#pragma unroll
+  for (int v = 0; v < NFY; ++v) cy[v] = Sp->cy[v];
+#pragma unroll
+  for (int v = 0; v < NS * NFY; ++v) ym[v] = Sp->ymap[v];
+  int qprev = -1;
+  float mx = 0.f, f = 1.f;
+  const float2 *X = nullptr;
+  float2 *C = nullptr;
+  int2 *sc = nullptr;
+  float2 y[NS * NFY];
+  for (int w = lane; w < nqw * nfib; w += nthr) {
+    const int q = P2 ? (w >> lgf) : w / nfib;
+    const int fi = w - q * nfib;
+    if (q != qprev) {
+      if (qprev >= 0) atomicMax((unsigned int *)&sc[csl].y, __float_as_uint(mx));
+      qprev = q;
+      mx = 0.f;
+      float2 *base = pq + q * perq;
+      X = (a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a;
+      const float2 *Y = (b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b;
+      C = base + (c & ~kPerQuery);
+      sc = scl + q * nscale;
+      const int2 za = asl >= 0 ? sc[asl] : make_int2(0, 0);
+      const int2 zb = bsl >= 0 ? sc[bsl] : make_int2(0, 0);
+      const int ea = tree_exp((uint32_t)za.y), eb = tree_exp((uint32_t)zb.y);
+      f = ldexpf(1.0f, -(ea + eb));
+      if (fi == 0) sc[csl].x = za.x + zb.x + ea + eb;
+#pragma unroll
+      for (int v = 0; v < NS * NFY; ++v) y[v] = Y[ym[v]];
+    }
+    int xo, co;
+    seg2r<P2>(fext, fx, fc, flg, ncs, fi, xo, co);
+    float2 x[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) x[s] = X[xo + xs[s]];
+#pragma unroll
+    for (int j = 0; j < NFY; ++j) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const float2 yv = y[s * NFY + j];
+        re = fmaf(x[s].x, yv.x, re);
+        re = fmaf(-x[s].y, yv.y, re);
+        im = fmaf(x[s].x, yv.y, im);
+        im = fmaf(x[s].y, yv.x, im);
+      }
+      re *= f;
+      im *= f;
+      C[co + cy[j]] = make_float2(re, im);
+      mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+    }
+  }
+  if (qprev >= 0) atomicMax((unsigned int *)&sc[csl].y, __float_as_uint(mx));
 }
 
 template <bool P2>

@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "TN_OK", 1: "TN_PENDING", -1: "TN_E_INVALID_ARG", -2: "TN_E_I
                 -7: "TN_E_UNKNOWN_TICKET"}
 
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_last_error", "tn_plan_load",
-            "tn_plan_costs_get", "tn_plan_free", "tn_contract", "tn_contract_batch",
+            "tn_plan_costs_get", "tn_plan_free", "tn_contract", "tn_contract_batch", "tn_contract_strided",
             "tn_serve_submit", "tn_serve_poll", "tn_profile_enable", "tn_profile_read"]
 
 
@@ -91,6 +91,7 @@ def load():
             "tn_plan_free": [P],
             "tn_contract": [P, I32, P, P, ctypes.c_int, P, U32],
             "tn_contract_batch": [P, I32, P, P, ctypes.c_int, P, P, U32],
+            "tn_contract_strided": [P, I32, I32, P, P, P, ctypes.c_int64, ctypes.c_int, P, U32],
             "tn_serve_submit": [P, P, P],
             "tn_serve_poll": [P, ctypes.c_uint64, P, ctypes.c_int, P, P],
         }
@@ -221,6 +222,34 @@ def tn_contract_batch(ctx, queries, result_shapes, out_dtype=TN_C128, flags=0):
                                     ctypes.cast(optrs, ctypes.c_void_p), out_dtype, _p(l2), _p(st),
                                     flags))
     return outs, l2[:n], st[:n]
+
+
+def tn_contract_strided(plan, num_queries, overrides, result_shape=(), out_dtype=TN_C128, flags=0):
+    """overrides: list of (tensor id, data, stride bytes, dtype) where data is a
+    numpy array holding every query's copy (its base address is query 0's) or
+    a device address (int) with dtype TN_C64_DEVICE.  Returns (results of
+    shape (num_queries,) + result_shape, log2 scales)."""
+    n = len(overrides)
+    arr = (tn_leaf * max(1, n))()
+    strides = (ctypes.c_int64 * max(1, n))()
+    keep = []
+    for i, (t, data, stride, dt) in enumerate(overrides):
+        if isinstance(data, np.ndarray):
+            a = np.ascontiguousarray(data)
+            keep.append(a)
+            ptr = a.ctypes.data
+        else:
+            ptr = int(data)
+        arr[i] = tn_leaf(int(t), ptr, dt)
+        strides[i] = int(stride)
+    res = int(np.prod(result_shape)) if result_shape else 1
+    out = np.zeros((num_queries,) + tuple(result_shape),
+                   dtype=np.complex128 if out_dtype == TN_C128 else np.complex64)
+    l2 = np.zeros(max(1, num_queries), dtype=np.float64)
+    _check(load().tn_contract_strided(ctypes.c_void_p(plan), int(num_queries), n,
+                                      ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(strides, ctypes.c_void_p),
+                                      _p(out), ctypes.c_int64(res), out_dtype, _p(l2), flags))
+    return out, l2[:num_queries]
 
 
 def tn_serve_submit(ctx, plan, overrides=None) -> int:

@@ -3,6 +3,8 @@ runs whole small subtrees in one workgroup, shared subtrees computed once,
 partial and device-resident overrides.  Each result is compared with the
 oracle (amplitude error as in test_gpu_parity, bound 1e-5 for FP32) and with
 the same query run alone through tn_contract."""
+import math
+
 import numpy as np
 import pytest
 
@@ -150,4 +152,104 @@ def test_profile_counts_subtree_kernel(ctx):
     stats = lib.tn_profile_read(ctx.handle, reset=True)
     lib.tn_profile_enable(ctx.handle, False)
     assert stats["tree"]["launches"] >= 1 and stats["tree"]["seconds"] > 0
+    ctx.free_plan(p)
+
+
+def _gate_net(rng, dims_choice, n_state, n_gates):
+    """A rank-n_state tensor with gate-like tensors (one or two of its legs in,
+    as many out) applied one after the other, then closed by rank-1 boundary
+    tensors: small operands along the fibers of a large one, with legs of the
+    given dimensions."""
+    lab = 0
+    cur, dims = [], {}
+    for _ in range(n_state):
+        dims[lab] = int(rng.choice(dims_choice))
+        cur.append(lab)
+        lab += 1
+    legs = [list(cur)]
+    for _ in range(n_gates):
+        k = int(rng.integers(1, 3))
+        pos = [int(x) for x in rng.choice(n_state, k, replace=False)]
+        new = []
+        for p_ in pos:
+            dims[lab] = dims[cur[p_]]
+            new.append(lab)
+            lab += 1
+        legs.append([cur[p_] for p_ in pos] + new)
+        for p_, l in zip(pos, new):
+            cur[p_] = l
+    for l in cur:
+        legs.append([l])
+    ts = [rng.standard_normal(tuple(dims[x] for x in l)) + 1j * rng.standard_normal(tuple(dims[x] for x in l))
+          for l in legs]
+    return legs, dims, ts
+
+
+@pytest.mark.parametrize("seed,dims_choice", [(0, (2,)), (1, (2, 3)), (2, (3, 4)), (3, (1, 2, 5)), (4, (2, 4))])
+def test_batch_general_dims(ctx, seed, dims_choice):
+    """Subtrees over legs of any dimension (the gate-along-fibers form and the
+    general form, power-of-two and mixed-radix index maps), each of 24
+    queries overriding the first boundary tensor, against the oracle."""
+    from paper_2507_20667_amd.planner import plan_from_partition
+    rng = np.random.default_rng(seed)
+    legs, dims, ts = _gate_net(rng, dims_choice, 7, 12)
+    nv = len(legs)
+    plan = plan_from_partition(legs, dims, tree_partition(legs, dims, 2), 2)
+    p = ctx.plan_load(legs, dims, ts, plan.partition_of, 2, plan.tree)
+    first = nv - 7
+    queries, refs = [], []
+    for _ in range(24):
+        v = rng.standard_normal(ts[first].shape) + 1j * rng.standard_normal(ts[first].shape)
+        queries.append((p, {first: v}))
+        refs.append(complex(oracle.contract_tree(legs, dims, ts[:first] + [v] + ts[first + 1:], plan.tree)))
+    outs, l2, st = lib.tn_contract_batch(ctx.handle, queries, [()] * len(queries))
+    assert np.all(st == 0)
+    scale = max(abs(r) for r in refs) or 1.0
+    tol = 64 * 2.0 ** -24 * math.sqrt(max(lib.tn_plan_costs_get(p)["con_serial"], 1))
+    for o, r in zip(outs, refs):
+        assert abs(_c(o) - r) / scale < tol, (o, r)
+    ctx.free_plan(p)
+
+
+@pytest.mark.parametrize("where", ["host", "device", "device_unaligned"])
+def test_strided_matches_batch(ctx, where):
+    """tn_contract_strided (one descriptor and one stride per overridden leaf)
+    gives the same results as tn_contract_batch on the same queries, with the
+    overrides in host memory (staged), on the device read in place, and on the
+    device at a stride the kernels cannot step (copied per query); and agrees
+    with the oracle."""
+    import torch
+    circ = random_circuit(14, 8, 21)
+    net = amplitude_network(circ, 0)
+    plan = _plan(net, 4)
+    p = ctx.load_network(net, plan.partition_of, 4, plan.tree)
+    xs = random_bitstrings(circ.n, 40, 9)
+    ids = output_tensor_ids(net)
+    # one array per overridden leaf: (queries, 2) basis vectors, in query order
+    vec = {t: np.stack([amplitude_overrides(net, circ, x)[t] for x in xs]) for t in ids}
+    ref, _, st = lib.tn_contract_batch(ctx.handle, [(p, amplitude_overrides(net, circ, x)) for x in xs],
+                                       [()] * len(xs))
+    assert np.all(st == 0)
+    keep = []
+    ovr = []
+    for t in ids:
+        if where == "host":
+            ovr.append((t, vec[t].astype(np.complex128), 16 * vec[t].shape[1], lib.TN_C128))
+        else:
+            # floats per query: 4 (the two complex64 entries, a 16-byte stride) or 5
+            # (a 20-byte stride the kernels cannot step)
+            cols = 5 if where == "device_unaligned" else 4
+            d = torch.zeros((len(xs), cols), dtype=torch.float32, device="cuda")
+            v = torch.from_numpy(vec[t].astype(np.complex64).view(np.float32)).to("cuda")
+            d[:, :4] = v.reshape(len(xs), 4)
+            keep.append(d)
+            stride = d.shape[1] * 4
+            ovr.append((t, d.data_ptr(), stride, lib.TN_C64_DEVICE))
+    torch.cuda.synchronize()
+    got, l2 = lib.tn_contract_strided(p, len(xs), ovr)
+    for i, x in enumerate(xs):
+        assert abs(complex(got[i]) - _c(ref[i])) <= 1e-6 * max(abs(_c(ref[i])), 2.0 ** -7)
+    for i in (0, 17, 39):
+        r = _ref(net, plan, amplitude_overrides(net, circ, xs[i]))
+        assert err(got[i], r, circ.n) < TOL
     ctx.free_plan(p)
