@@ -404,13 +404,24 @@ def batch_mix_leg(lib, queries=512, reps=3):
     prof = lib.tn_profile_read(ctx.handle, reset=True)
     exec_flops = sum(v["algo_flops"] for v in prof.values())
     kern_s = sum(v["seconds"] for v in prof.values())
-    plain = []
+    plain, per_q = [], []
     for q in qs[:8]:
         lib.tn_contract(*q)
     t2 = time.perf_counter()
     for q in qs:
+        t3 = time.perf_counter()
         plain.append(lib.tn_contract(*q))
+        per_q.append(time.perf_counter() - t3)
     pt = time.perf_counter() - t2
+    # the paper's cost model against measured time: per circuit, mean plain
+    # time per amplitude against con_serial (Pearson r, linear and log-log)
+    by_c = {}
+    for k, i in enumerate(idx):
+        by_c.setdefault(i, []).append(per_q[k])
+    xs_ = np.array([float(cs[i]) for i in by_c])
+    ys_ = np.array([float(np.median(v)) for v in by_c.values()])
+    r_lin = float(np.corrcoef(xs_, ys_)[0, 1]) if len(by_c) > 2 else None
+    r_log = float(np.corrcoef(np.log(xs_), np.log(ys_))[0, 1]) if len(by_c) > 2 else None
     diff = max(abs(amp(outs[k], l2s[k]) - amp(*plain[k])) / max(abs(amp(*plain[k])), 2.0 ** (-circs[i][0].n / 2))
                for k, i in enumerate(idx))
     # the oracle on the queries of the smallest circuits
@@ -434,7 +445,11 @@ def batch_mix_leg(lib, queries=512, reps=3):
            "executed_tflops_batched": exec_flops / bt / 1e12,
            "kernel_seconds_batched": kern_s, "wall_seconds_batched": bt,
            "max_rel_diff_batched_vs_plain": diff,
-           "max_rel_err_vs_oracle": max(errs) if errs else None, "oracle_checked": len(errs)}
+           "max_rel_err_vs_oracle": max(errs) if errs else None, "oracle_checked": len(errs),
+           "cost_model_vs_time": {"circuits": len(by_c), "pearson_r_con_serial_vs_plain_time": r_lin,
+                                  "pearson_r_log": r_log,
+                                  "con_serial_range": [float(xs_.min()), float(xs_.max())],
+                                  "plain_seconds_range": [float(ys_.min()), float(ys_.max())]}}
     log(f"batch mix: {out['batched_amplitudes_per_s']:.0f} amplitudes/s batched vs "
         f"{out['plain_amplitudes_per_s']:.0f} plain (x{out['speedup_vs_plain']:.1f}), "
         f"max diff {diff:.1e}, oracle err {out['max_rel_err_vs_oracle']}")
@@ -559,6 +574,8 @@ def main():
     lib.tn_profile_enable(ctx.handle, False)
     stats = lib.tn_profile_read(ctx.handle, reset=True)
     roof = roofline(stats, args.prec)
+    # executed work (vertices actually run, shared parts once) per unprofiled step time
+    exec_tflops = sum(v["algo_flops"] for v in stats.values()) / K / (dt / K) / 1e12
 
     serve = None
     if args.serve_seconds > 0:
@@ -595,6 +612,7 @@ def main():
                    "con_serial": con_serial, "con_dist": costs["con_dist"],
                    "largest_intermediate": costs["largest_intermediate"]},
         "effective_tflops": eff_tflops,
+        "executed_tflops": exec_tflops,
         "batch_api_amplitudes_per_s": batch_api_amps,
         "plain_amplitudes_per_s": plain_amps,
         "speedup_vs_plain": amps / plain_amps,

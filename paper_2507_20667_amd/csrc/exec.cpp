@@ -178,20 +178,35 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   }
   upload_lock.unlock();
   // algorithmic traffic and work of the subtree kernel (for the profiler)
+  // (a vertex counts as its subtree runs: once when the subtree's root is
+  // shared, once per query otherwise, whatever the vertex itself depends on)
   double tree_bytes_sh = 0, tree_flops_sh = 0, tree_bytes_q = 0, tree_flops_q = 0;
+  std::vector<int> troots(p->tree_roots);
+  troots.insert(troots.end(), L.islands.begin(), L.islands.end());
   if (trees)
-    for (const Node &n : p->nodes) {
-      if (!p->in_tree[n.id]) continue;
-      auto sz = [&](int t) {
-        return (double)(t < nv ? p->leaf[t].size() : std::max<int64_t>(p->nodes[t - nv].out.size(), 1));
-      };
-      const double b = 8.0 * (sz(n.c1) + sz(n.c2) + sz(n.id)), f = 8.0 * (double)n.weight;
-      if (L.shared[n.id]) {
-        tree_bytes_sh += b;
-        tree_flops_sh += f;
-      } else {
-        tree_bytes_q += b;
-        tree_flops_q += f;
+    for (int r : troots) {
+      const bool shr = L.shared[r] != 0;
+      std::vector<int> stack{r};
+      while (!stack.empty()) {
+        const int u = stack.back();
+        stack.pop_back();
+        if (u < nv) continue;
+        // an island inside a per-query subtree runs (and counts) on its own
+        if (u != r && std::binary_search(L.islands.begin(), L.islands.end(), u)) continue;
+        const Node &n = p->nodes[u - nv];
+        stack.push_back(n.c1);
+        stack.push_back(n.c2);
+        auto sz = [&](int t) {
+          return (double)(t < nv ? p->leaf[t].size() : std::max<int64_t>(p->nodes[t - nv].out.size(), 1));
+        };
+        const double b = 8.0 * (sz(n.c1) + sz(n.c2) + sz(n.id)), f = 8.0 * (double)n.weight;
+        if (shr) {
+          tree_bytes_sh += b;
+          tree_flops_sh += f;
+        } else {
+          tree_bytes_q += b;
+          tree_flops_q += f;
+        }
       }
     }
   const size_t perq = rnd(L.perq_bytes);
@@ -426,6 +441,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         tl.chunks = (const TreeChunk *)(tb + L.tree_chunk_off);
         tl.steps = (const TreeStep *)(tb + L.tree_step_off);
         tl.loads = (const TreeLeafLoad *)(tb + L.tree_load_off);
+        tl.sloads = (const TreeSharedLoad *)(tb + L.tree_sload_off);
         tl.image = (const float2 *)(tb + L.tree_img_off);
         // overridden leaves in id order: read in place or from the staging block
         for (size_t k = 0; k < ovr.size() && k < (size_t)kTreeMaxOvr; ++k) {

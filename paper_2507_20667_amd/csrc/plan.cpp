@@ -925,7 +925,7 @@ static LevelPlan level_plan(const tn_plan *p, const std::vector<int> &nodes) {
     const Node &n = p->nodes[u - nv];
     int l = 0;
     for (int c : {n.c1, n.c2})
-      if (c >= nv) l = std::max(l, lvl[c]);
+      if (c >= nv && lvl.count(c)) l = std::max(l, lvl[c]);
     lvl[u] = l + 1;
   }
   // within a level, largest contraction first: the kernel deals a chunk's
@@ -947,7 +947,8 @@ static LevelPlan level_plan(const tn_plan *p, const std::vector<int> &nodes) {
     for (int u : ch) lp.at[u] = P.alloc(std::max<int64_t>(p->nodes[u - nv].out.size(), 1));
     for (int u : ch)
       for (int c : {p->nodes[u - nv].c1, p->nodes[u - nv].c2})
-        if (c >= nv) P.release(lp.at[c], std::max<int64_t>(p->nodes[c - nv].out.size(), 1));
+        if (c >= nv && lp.at.count(c))  // (inputs from outside the subtree live elsewhere)
+          P.release(lp.at[c], std::max<int64_t>(p->nodes[c - nv].out.size(), 1));
   }
   lp.peak = P.peak();
   return lp;
@@ -1046,9 +1047,13 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     L.tree_error = true;  // more overridden leaves than the launch carries
     return;
   }
-  std::vector<int> order;  // shared subtrees first
+  std::vector<TreeSharedLoad> sloads;
+  std::vector<char> is_island(2 * nv - 1, 0);
+  for (int u : L.islands) is_island[u] = 1;
+  std::vector<int> order;  // shared subtrees (and islands) first
   for (int r : p->tree_roots)
     if (L.shared[r]) order.push_back(r);
+  for (int u : L.islands) order.push_back(u);
   L.n_tree_shared = (int)order.size();
   for (int r : p->tree_roots)
     if (!L.shared[r]) order.push_back(r);
@@ -1058,12 +1063,16 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   for (int r : order) {
     TreeHdr h;
     memset(&h, 0, sizeof(h));
-    std::vector<int> nodes, leaves, stack{r};
+    std::vector<int> nodes, leaves, inputs, stack{r};  // inputs: islands read in
     while (!stack.empty()) {
       int u = stack.back();
       stack.pop_back();
       if (u < nv) {
         leaves.push_back(u);
+        continue;
+      }
+      if (u != r && is_island[u]) {
+        inputs.push_back(u);
         continue;
       }
       nodes.push_back(u);
@@ -1072,6 +1081,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     }
     std::sort(nodes.begin(), nodes.end());
     std::sort(leaves.begin(), leaves.end());
+    std::sort(inputs.begin(), inputs.end());
     std::map<int, int32_t> loc;
     std::map<int, int> scale;
     // shared leaves: contiguous image; overridden leaves: front of the query region
@@ -1097,6 +1107,22 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       }
     }
     h.nloads = (int32_t)loads.size() - h.load0;
+    // islands this subtree reads: after the shared leaves, scale records first
+    h.sload0 = (int32_t)sloads.size();
+    for (int u : inputs) {
+      const int64_t n = std::max<int64_t>(p->nodes[u - nv].out.size(), 1);
+      loc[u] = sh;
+      scale[u] = (int)scale.size();
+      TreeSharedLoad sl;
+      sl.lds = sh;
+      sl.n = (int32_t)n;
+      sl.scale = scale[u];
+      sl.slot = u;
+      sl.off = L.off[u];
+      sloads.push_back(sl);
+      sh += (int32_t)((n + 1) & ~(int64_t)1);
+    }
+    h.nsloads = (int32_t)sloads.size() - h.sload0;
     h.shared_elems = sh;
     const int64_t base = pq;
     const LevelPlan lp = level_plan(p, nodes);
@@ -1195,11 +1221,19 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
         if (st.kind == 1) ok = ok && chunks[c].nsteps == 1 && c == h.chunk0 + h.nchunks - 1;
       }
     }
+    for (int i = h.sload0; i < h.sload0 + h.nsloads; ++i)
+      ok = ok && sloads[i].lds >= 0 && sloads[i].lds + sloads[i].n <= h.shared_elems &&
+           sloads[i].scale >= 0 && sloads[i].scale < h.nscale && sloads[i].slot >= nv &&
+           sloads[i].slot < 2 * nv - 1 && sloads[i].off >= 0 &&
+           sloads[i].off + 8 * (int64_t)sloads[i].n <= L.shared_bytes &&
+           std::max<int64_t>(p->nodes[sloads[i].slot - nv].out.size(), 1) == sloads[i].n;
     for (int i = h.load0; i < h.load0 + h.nloads; ++i)
       ok = ok && (loads[i].lds & kPerQuery) && (loads[i].lds & ~kPerQuery) + loads[i].n <= h.perq_elems &&
            loads[i].src >= 0 && loads[i].src < (int)ovr_list.size() &&
            p->leaf[ovr_list[loads[i].src]].size() == loads[i].n;
-    ok = ok && h.image_off + h.shared_elems <= (int64_t)image.size() + 1;
+    // the image holds the shared leaves; the islands read in follow them in LDS
+    const int64_t nimg = h.nsloads ? sloads[h.sload0].lds : h.shared_elems;
+    ok = ok && h.image_off + nimg <= (int64_t)image.size() + 1;
     if (!h.final_dot) {
       const int64_t part = h.root_in_perq ? L.perq_bytes : L.shared_bytes;
       ok = ok && (h.root_loc & kPerQuery) && (h.root_loc & ~kPerQuery) + h.root_elems <= h.perq_elems &&
@@ -1248,6 +1282,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   L.tree_chunk_off = put(chunks.data(), chunks.size() * sizeof(TreeChunk));
   L.tree_step_off = put(steps.data(), steps.size() * sizeof(TreeStep));
   L.tree_load_off = put(loads.data(), loads.size() * sizeof(TreeLeafLoad));
+  L.tree_sload_off = put(sloads.data(), sloads.size() * sizeof(TreeSharedLoad));
   L.tree_img_off = put(image.data(), image.size() * sizeof(float2));
 }
 
@@ -1280,10 +1315,34 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
     return std::find(p->tree_roots.begin(), p->tree_roots.end(), v) != p->tree_roots.end();
   };
   Packer pk[2];  // 0: per-query, 1: shared
-  // subtree results are written before any other vertex runs
+  // Islands: the largest vertices that no override reaches inside a per-query
+  // subtree.  They run once, as shared subtrees of their own, and the
+  // per-query programs read their results instead of recomputing them for
+  // every query.
+  L.islands.clear();
   if (trees)
+    for (int r : p->tree_roots) {
+      if (L.shared[r]) continue;
+      std::vector<int> stack{r};
+      while (!stack.empty()) {
+        const int u = stack.back();
+        stack.pop_back();
+        for (int c : {p->nodes[u - nv].c1, p->nodes[u - nv].c2}) {
+          if (c < nv) continue;
+          if (L.shared[c])
+            L.islands.push_back(c);
+          else
+            stack.push_back(c);
+        }
+      }
+    }
+  std::sort(L.islands.begin(), L.islands.end());
+  // subtree results are written before any other vertex runs
+  if (trees) {
     for (int r : p->tree_roots)
       L.off[r] = pk[L.shared[r] ? 1 : 0].alloc(std::max<int64_t>(p->nodes[r - nv].out.size(), 1) * 8);
+    for (int u : L.islands) L.off[u] = pk[1].alloc(std::max<int64_t>(p->nodes[u - nv].out.size(), 1) * 8);
+  }
   for (int j : p->order) {
     const Node &n = p->nodes[j];
     if (trees && p->in_tree[n.id]) continue;

@@ -190,7 +190,20 @@ struct TreeHdr {
   int64_t root_off;                  // byte offset of the result in its part
   int64_t image_off;                 // shared leaves: offset in the leaf image
   int32_t root_slot;                 // tensor id (slot index) of the result
+  int32_t sload0;                    // shared intermediates read from device memory
+  int32_t nsloads;
   int32_t pad;
+};
+
+// A shared intermediate that a per-query subtree takes as an input: computed
+// once by the shared launch, read from the shared part into the LDS shared
+// region, its scale record into every query's scale table.
+struct TreeSharedLoad {
+  int32_t lds;    // float2 offset in the LDS shared region
+  int32_t n;      // entries
+  int32_t scale;  // index in the subtree's scale table
+  int32_t slot;   // tensor id (its record in the shared scale records)
+  int64_t off;    // byte offset in the shared part
 };
 
 struct OvrSrc {
@@ -203,6 +216,7 @@ struct TreeLaunch {
   const TreeChunk *chunks;
   const TreeStep *steps;
   const TreeLeafLoad *loads;
+  const TreeSharedLoad *sloads;
   const float2 *image;  // shared leaves of every subtree, each in its LDS order
   OvrSrc ovr[kTreeMaxOvr];
   uint8_t *shared_base;

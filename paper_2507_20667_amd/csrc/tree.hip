@@ -313,7 +313,22 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
   const int32_t *gw = (const int32_t *)t.steps;
 
   for (int i = tid; i < qw * h.nscale; i += 256) scl[i] = make_int2(0, 0);
-  for (int i = tid; i < h.shared_elems; i += 256) shr[i] = t.image[h.image_off + i];
+  // shared leaves from the image; shared intermediates (computed by the shared
+  // launch before this one) from the shared part, after them
+  const int nimg = h.nsloads ? t.sloads[h.sload0].lds : h.shared_elems;
+  for (int i = tid; i < nimg; i += 256) shr[i] = t.image[h.image_off + i];
+  if (h.nsloads) {
+    __syncthreads();  // the scale records are cleared
+    for (int k = 0; k < h.nsloads; ++k) {
+      const TreeSharedLoad S = t.sloads[h.sload0 + k];
+      const float2 *src = (const float2 *)(t.shared_base + S.off);
+      for (int i = tid; i < S.n; i += 256) shr[S.lds + i] = src[i];
+      if (tid < nqw) {
+        const Slot &z = t.slots_sh[S.slot];
+        scl[tid * h.nscale + S.scale] = make_int2((int)z.log2s, (int)z.maxbits);
+      }
+    }
+  }
   for (int w = tid; w < h.nloads * nqw; w += 256) {
     const int li = w / nqw, q = w - li * nqw;
     const TreeLeafLoad L = t.loads[h.load0 + li];
