@@ -397,6 +397,15 @@ def batch_mix_leg(lib, queries=512, reps=3):
     for _ in range(reps):
         outs, l2s, st = lib.tn_contract_batch(ctx.handle, qs, shapes)
     bt = (time.perf_counter() - t1) / reps
+    # the same batch with each plan group's launch sequence captured once as a
+    # HIP graph and replayed (the first call captures)
+    og, l2g, st = lib.tn_contract_batch(ctx.handle, qs, shapes, flags=lib.TN_FLAG_GRAPH)
+    assert all(int(x) == 0 for x in st), st
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        og, l2g, st = lib.tn_contract_batch(ctx.handle, qs, shapes, flags=lib.TN_FLAG_GRAPH)
+    btg = (time.perf_counter() - t1) / reps
+    gdiff = max(abs(amp(og[k], l2g[k]) - amp(outs[k], l2s[k])) for k in range(queries))
     lib.tn_profile_enable(ctx.handle, True)
     lib.tn_profile_read(ctx.handle, reset=True)
     lib.tn_contract_batch(ctx.handle, qs, shapes)
@@ -439,6 +448,7 @@ def batch_mix_leg(lib, queries=512, reps=3):
            "planning_s": plan_s, "queries": queries,
            "distinct_circuits_queried": len(set(idx)),
            "batched_amplitudes_per_s": queries / bt, "plain_amplitudes_per_s": queries / pt,
+           "batched_graph_amplitudes_per_s": queries / btg, "graph_max_abs_diff": gdiff,
            "speedup_vs_plain": pt / bt,
            "effective_tflops_batched": work / bt / 1e12,
            "effective_tflops_plain": work / pt / 1e12,
@@ -450,7 +460,8 @@ def batch_mix_leg(lib, queries=512, reps=3):
                                   "pearson_r_log": r_log,
                                   "con_serial_range": [float(xs_.min()), float(xs_.max())],
                                   "plain_seconds_range": [float(ys_.min()), float(ys_.max())]}}
-    log(f"batch mix: {out['batched_amplitudes_per_s']:.0f} amplitudes/s batched vs "
+    log(f"batch mix: {out['batched_amplitudes_per_s']:.0f} amplitudes/s batched "
+        f"({out['batched_graph_amplitudes_per_s']:.0f} with graphs) vs "
         f"{out['plain_amplitudes_per_s']:.0f} plain (x{out['speedup_vs_plain']:.1f}), "
         f"max diff {diff:.1e}, oracle err {out['max_rel_err_vs_oracle']}")
     return out

@@ -74,7 +74,10 @@ enum {
   TN_PREC_BF16X3 = 1,      /* x = h + l split into two BF16 terms; a*b ~ hh + hl + lh */
   TN_FORM_4M = 0,          /* four real products per complex product */
   TN_FORM_3M = 1 << 4,     /* three real products (Gauss) */
-  TN_FLAG_KEEP_SCALE = 1 << 8 /* return mantissa and log2 scale separately */
+  TN_FLAG_KEEP_SCALE = 1 << 8, /* return mantissa and log2 scale separately */
+  TN_FLAG_GRAPH = 1 << 9       /* batched calls: capture each plan group's launch
+                                  sequence as a HIP graph and replay it (see
+                                  tn_contract_batch) */
 };
 
 typedef struct tn_ctx tn_ctx;   /* arena, stream, caches, scheduler */
@@ -204,6 +207,14 @@ tn_status tn_contract(tn_plan *plan, int32_t num_overrides, const tn_leaf *overr
  * shared, and each remaining vertex is one launch over all queries of the
  * plan.  Results as for tn_contract; per_query[i] receives each query's
  * status (may be NULL).  Returns the first error, or TN_OK.
+ * TN_FLAG_GRAPH: the launch sequence of each plan's group is captured as a
+ * HIP graph on its first run and replayed on later calls with the same plan,
+ * overridden leaves, query count and output type (overrides are staged into
+ * the group's own workspace first; device overrides read in place are part of
+ * the match).  The plan then keeps that workspace and a pinned result buffer
+ * until it is freed or a call with another group replaces the graph.  Groups
+ * that do not fit the arena at once, and calls while profiling is on, run
+ * without a graph.
  */
 tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *queries,
                             void *const *outs, tn_dtype out_dtype, double *log2_scales,

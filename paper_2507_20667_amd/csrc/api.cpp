@@ -55,6 +55,11 @@ tn_status tn_ctx_destroy(tn_ctx *ctx) {
   }
   hipStreamSynchronize(ctx->stream);
   if (ctx->pinned) hipHostFree(ctx->pinned);
+  if (ctx->graph_st) {
+    hipStreamSynchronize(ctx->graph_st);
+    hipStreamDestroy(ctx->graph_st);
+  }
+  if (ctx->graph_ev) hipEventDestroy(ctx->graph_ev);
   ctx->prof.destroy();
   delete ctx;
   return TN_OK;
@@ -180,6 +185,7 @@ tn_status tn_plan_free(tn_plan *p) {
     ctx->arena.release(p->dev_desc, p->dev_desc_bytes);
     for (auto &kv : p->layouts)
       if (kv.second->tree_dev >= 0) ctx->arena.release(kv.second->tree_dev, kv.second->tree_dev_bytes);
+    if (p->graph) release_graph(ctx, *p->graph);
     ctx->live_plans--;
   }
   delete p;
@@ -215,7 +221,7 @@ tn_status tn_contract_strided(tn_plan *p, int32_t num_queries, int32_t num_overr
     return TN_E_INVALID_ARG;
   }
   if (num_queries < 0 || num_overrides < 0 || (num_overrides > 0 && (!overrides || !strides)) ||
-      (num_queries > 0 && !out) || (flags & ~TN_FLAG_KEEP_SCALE) ||
+      (num_queries > 0 && !out) || (flags & ~(TN_FLAG_KEEP_SCALE | TN_FLAG_GRAPH)) ||
       (out_dtype != TN_C64 && out_dtype != TN_C128)) {
     set_error("tn_contract_strided: bad arguments");
     return TN_E_INVALID_ARG;
@@ -244,7 +250,7 @@ tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *qu
                             void *const *outs, tn_dtype out_dtype, double *log2_scales,
                             tn_status *per_query, uint32_t flags) {
   if (!ctx || num_queries < 0 || (num_queries > 0 && (!queries || !outs)) ||
-      (flags & ~TN_FLAG_KEEP_SCALE)) {
+      (flags & ~(TN_FLAG_KEEP_SCALE | TN_FLAG_GRAPH))) {
     set_error("tn_contract_batch: bad arguments");
     return TN_E_INVALID_ARG;
   }

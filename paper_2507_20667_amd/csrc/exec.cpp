@@ -31,12 +31,20 @@ size_t result_elems(const tn_plan *p) {
   return p->closed ? 1 : (size_t)p->result_layout.size();
 }
 
+void release_graph(tn_ctx *ctx, GraphEntry &g) {
+  if (g.exec) hipGraphExecDestroy(g.exec);
+  if (g.ws >= 0) ctx->arena.release(g.ws, g.ws_bytes);
+  if (g.pinned) hipHostFree(g.pinned);
+  g = GraphEntry();
+}
+
 static size_t rnd(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static tn_status ensure_pinned(ExecRes &r, size_t bytes) {
+static tn_status ensure_pinned(ExecRes &r, size_t bytes, hipStream_t st) {
   if (*r.pinned_bytes >= bytes) return TN_OK;
-  // the previous staging may still feed a copy in flight on this stream
-  hipStreamSynchronize(r.st);
+  // the previous staging may still feed a copy in flight on the call's stream
+  hipStreamSynchronize(st);
+  if (st != r.st) hipStreamSynchronize(r.st);
   if (*r.pinned) hipHostFree(*r.pinned);
   *r.pinned = nullptr;
   *r.pinned_bytes = 0;
@@ -239,8 +247,29 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     chunk = std::max<size_t>(chunk, 1);
   }
   tn_status rc = TN_OK;
+  // TN_FLAG_GRAPH (the whole group in one chunk, not profiled, not serving):
+  // the call runs on the context's graph stream, after the caller's stream
+  bool want_graph = (flags & TN_FLAG_GRAPH) && rs.ws < 0 && !prof.on && !dbg_gemm &&
+                    chunk >= qs.size();
+  hipStream_t gst = nullptr;
+  if (want_graph) {
+    if (!ctx->graph_st &&
+        (hipStreamCreateWithFlags(&ctx->graph_st, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&ctx->graph_ev, hipEventDisableTiming) != hipSuccess)) {
+      (void)hipGetLastError();
+      if (ctx->graph_st) hipStreamDestroy(ctx->graph_st);
+      ctx->graph_st = nullptr;
+      ctx->graph_ev = nullptr;
+    }
+    if (ctx->graph_st && hipEventRecord(ctx->graph_ev, rs.st) == hipSuccess &&
+        hipStreamWaitEvent(ctx->graph_st, ctx->graph_ev, 0) == hipSuccess)
+      gst = ctx->graph_st;
+    else
+      want_graph = false;
+  }
   for (size_t q0 = 0; q0 < qs.size() && rc == TN_OK; q0 += chunk) {
     const int Q = (int)std::min(chunk, qs.size() - q0);
+    const hipStream_t st = gst ? gst : rs.st;
     // carve the workspace
     size_t o = 0;
     auto carve = [&](size_t b) {
@@ -256,14 +285,39 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     const size_t r_final = carve(final_bytes * Q);
     const size_t r_part = carve((size_t)max_blocks * 16 * Q);
     const size_t total = o;
-    const bool own_ws = rs.ws < 0;
+    // TN_FLAG_GRAPH: the whole group in one chunk, not profiled, not serving
+    // (a group whose workspace cannot be kept runs without a graph)
+    bool gmode = want_graph;
     const double t_carve = dbg ? ms_since(t_enter) : 0.0;
-    int64_t ws = own_ws ? ctx->arena.alloc(total) : rs.ws;
+    const size_t rb_bytes = (size_t)Q * (relems * 8 + sizeof(Slot) + sizeof(Result));
+    if (gmode) {
+      if (!p->graph) p->graph.reset(new GraphEntry());
+      GraphEntry &E = *p->graph;
+      if (E.layout != &L || E.Q != Q || E.ws_bytes != total) {
+        hipStreamSynchronize(st);
+        release_graph(ctx, E);
+        E.ws = ctx->arena.alloc(total);
+        E.ws_bytes = total;
+        if (E.ws < 0 || hipHostMalloc(&E.pinned, rb_bytes, hipHostMallocDefault) != hipSuccess) {
+          if (E.ws >= 0 && !E.pinned) (void)hipGetLastError();
+          E.pinned = nullptr;
+          release_graph(ctx, E);
+          gmode = false;
+        } else {
+          E.pinned_bytes = rb_bytes;
+          E.layout = &L;
+          E.Q = Q;
+        }
+      }
+    }
+    const bool own_ws = rs.ws < 0 && !gmode;
+    int64_t ws = gmode ? p->graph->ws : own_ws ? ctx->arena.alloc(total) : rs.ws;
     const double t_alloc = dbg ? ms_since(t_enter) : 0.0;
     if (ws < 0) {
       set_error("arena exhausted (%zu bytes requested)", total);
       return TN_E_NOMEM;
     }
+    bool capturing = false;
     uint8_t *base = ctx->arena.base() + ws;
     uint8_t *shared_base = base + r_shared, *perq_base = base + r_perq;
     Slot *slots = (Slot *)(base + r_slots);
@@ -338,7 +392,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           }
         }
         if (any_staged) {
-          rc = ensure_pinned(rs, ovr_bytes * Q);
+          rc = ensure_pinned(rs, ovr_bytes * Q, st);
           if (rc) goto done;
           uint8_t *h = (uint8_t *)*rs.pinned;
           for (int qi = 0; qi < Q; ++qi)
@@ -397,7 +451,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           }
         }
         if (any_staged) {
-          rc = ensure_pinned(rs, ovr_bytes * Q);
+          rc = ensure_pinned(rs, ovr_bytes * Q, st);
           if (rc) goto done;
           uint8_t *h = (uint8_t *)*rs.pinned;
           for (int qi = 0; qi < Q; ++qi)
@@ -425,6 +479,45 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
             }
         }
       }
+      // result staging on the host: the graph's own buffer, or the shared one
+      // (growing it synchronizes the stream first: the override copy above may
+      // still read it)
+      const bool root_shared = L.shared[p->root] != 0;
+      const bool dot_root = nv > 1 && p->nodes[p->root - nv].kind == NK_DOT;
+      size_t rb_vals = (size_t)Q * relems * 8, rb_slots = (size_t)Q * sizeof(Slot);
+      uint8_t *h = nullptr;
+      if (gmode) {
+        h = (uint8_t *)p->graph->pinned;
+      } else {
+        rc = ensure_pinned(rs, rb_bytes, st);
+        if (rc) goto done;
+        h = (uint8_t *)*rs.pinned;
+      }
+      float2 *hv = (float2 *)h;
+      Slot *hs = (Slot *)(h + rb_vals);
+      Result *hr = (Result *)(h + rb_vals + rb_slots);
+      const Operand R = operand(p->root);
+      // TN_FLAG_GRAPH: replay the launch sequence captured with the same
+      // workspace, layout and in-place overrides, or capture it now
+      bool replay = false;
+      if (gmode) {
+        GraphEntry &E = *p->graph;
+        std::vector<std::pair<const void *, int64_t>> dir;
+        for (int t : ovr) dir.push_back({direct_p[t], direct_bs[t]});
+        replay = E.exec && dir == E.direct;
+        if (!replay) {
+          if (E.exec) {
+            hipGraphExecDestroy(E.exec);
+            E.exec = nullptr;
+          }
+          E.direct = dir;
+          TN_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "graph capture");
+          capturing = true;
+        }
+      }
+      if (replay) {
+        TN_HIP(hipGraphLaunch(p->graph->exec, st), "graph launch");
+      } else {
       // scale records start at zero; not needed when the subtree kernel runs
       // every vertex (it keeps its scales in LDS and writes its results' records)
       if (!(trees && L.all_in_tree))
@@ -589,7 +682,6 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         }
       }
       // result into output-leg order
-      const Operand R = operand(p->root);
       if (p->fperm.needed) {
         const int nbf = L.shared[p->root] ? 1 : Q;
         TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, 16.0 * p->fperm.h.nelem * nbf, 0.0,
@@ -601,20 +693,9 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                "output permutation");
       }
       // read back
-      const bool root_shared = L.shared[p->root] != 0;
-      const bool dot_root = nv > 1 && p->nodes[p->root - nv].kind == NK_DOT;
-      size_t rb_vals = (size_t)Q * relems * 8, rb_slots = (size_t)Q * sizeof(Slot),
-             rb_res = (size_t)Q * sizeof(Result);
-      // (growing the staging synchronizes the stream first: the override copy
-      // above may still read it)
-      rc = ensure_pinned(rs, rb_vals + rb_slots + rb_res);
-      if (rc) goto done;
-      uint8_t *h = (uint8_t *)*rs.pinned;
-      float2 *hv = (float2 *)h;
-      Slot *hs = (Slot *)(h + rb_vals);
-      Result *hr = (Result *)(h + rb_vals + rb_slots);
       if (dot_root) {
-        TN_HIP(hipMemcpyAsync(hr, res, rb_res, hipMemcpyDeviceToHost, st), "result copy");
+        TN_HIP(hipMemcpyAsync(hr, res, (size_t)Q * sizeof(Result), hipMemcpyDeviceToHost, st),
+               "result copy");
       } else {
         const int rq = root_shared ? 1 : Q;
         if (p->fperm.needed) {
@@ -630,6 +711,17 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                                 sizeof(Slot), rq, hipMemcpyDeviceToHost, st),
                "scale copy");
       }
+      if (capturing) {
+        hipGraph_t g = nullptr;
+        capturing = false;
+        TN_HIP(hipStreamEndCapture(st, &g), "graph capture end");
+        hipError_t e = hipGraphInstantiate(&p->graph->exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) p->graph->exec = nullptr;
+        TN_HIP(e, "graph instantiate");
+        TN_HIP(hipGraphLaunch(p->graph->exec, st), "graph launch");
+      }
+      }  // not a replay
       const double t_launched = dbg ? ms_since(t_enter) : 0.0;
       TN_HIP(hipStreamSynchronize(st), "stream synchronize");
       if (dbg)
@@ -666,6 +758,11 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       }
     }
   done:
+    if (capturing) {  // an error while capturing: end the capture, keep nothing
+      hipGraph_t g = nullptr;
+      if (hipStreamEndCapture(st, &g) == hipSuccess && g) hipGraphDestroy(g);
+      p->graph->direct.clear();
+    }
     if (rc != TN_OK) {
       hipStreamSynchronize(st);
       prof.pend.clear();

@@ -258,7 +258,26 @@ struct tn_ctx {
   tn::ServeState *serve = nullptr;
   std::mutex serve_init_mu;
   tn::Profiler prof;
+  // TN_FLAG_GRAPH calls run on a stream of their own (graphs cannot be
+  // captured on the null stream), ordered after the caller's stream
+  hipStream_t graph_st = nullptr;
+  hipEvent_t graph_ev = nullptr;
 };
+
+namespace tn {
+// A captured launch sequence of one plan group (TN_FLAG_GRAPH) and what it
+// was captured with: replayed only when all of it matches.
+struct GraphEntry {
+  const ExecLayout *layout = nullptr;
+  int Q = 0;
+  size_t ws_bytes = 0;
+  int64_t ws = -1;                 // arena offset of the group's workspace (kept)
+  void *pinned = nullptr;          // result staging the graph copies into (kept)
+  size_t pinned_bytes = 0;
+  std::vector<std::pair<const void *, int64_t>> direct;  // in-place overrides
+  hipGraphExec_t exec = nullptr;
+};
+}  // namespace tn
 
 struct tn_plan {
   tn_ctx *ctx = nullptr;
@@ -291,6 +310,7 @@ struct tn_plan {
   tn::ExecLayout plain;          // nothing shared, one query
   std::mutex cache_mu;
   std::map<std::vector<int>, std::shared_ptr<tn::ExecLayout>> layouts;  // by override set
+  std::unique_ptr<tn::GraphEntry> graph;  // TN_FLAG_GRAPH: the captured launch sequence
 };
 
 namespace tn {
@@ -331,6 +351,8 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                     uint32_t flags, bool share, ExecRes &rs, const StridedOvr *so = nullptr);
 size_t group_workspace_bytes(const tn_plan *p, const ExecLayout &L, int Q);
 size_t result_elems(const tn_plan *p);
+// drops a captured graph with its workspace and pinned buffer (stream idle)
+void release_graph(tn_ctx *ctx, GraphEntry &g);
 
 // serve.cpp
 void serve_shutdown(tn_ctx *ctx);

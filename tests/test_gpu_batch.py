@@ -253,3 +253,51 @@ def test_strided_matches_batch(ctx, where):
         r = _ref(net, plan, amplitude_overrides(net, circ, xs[i]))
         assert err(got[i], r, circ.n) < TOL
     ctx.free_plan(p)
+
+
+def test_graph_replay_matches_eager(ctx):
+    """TN_FLAG_GRAPH: the first call captures the plan group's launch sequence,
+    later calls with the same group replay it.  Every replay (new bitstrings
+    staged into the same workspace, with eager calls and synchronizations in
+    between) equals the eager batch; in-place device overrides replay while
+    their buffer stays the same and are captured again when it changes; a
+    different query count replaces the graph."""
+    import torch
+    circ = random_circuit(16, 10, 31)
+    net = amplitude_network(circ, 0)
+    plan = _plan(net, 4)
+    p = ctx.load_network(net, plan.partition_of, 4, plan.tree)
+    ids = output_tensor_ids(net)
+    for rep in range(4):
+        xs = random_bitstrings(circ.n, 32, 100 + rep)
+        qs = [(p, amplitude_overrides(net, circ, x)) for x in xs]
+        ref, _, st = lib.tn_contract_batch(ctx.handle, qs, [()] * len(xs))
+        assert np.all(st == 0)
+        got, _, st = lib.tn_contract_batch(ctx.handle, qs, [()] * len(xs), flags=lib.TN_FLAG_GRAPH)
+        assert np.all(st == 0)
+        for a, b in zip(got, ref):
+            assert _c(a) == _c(b)
+        single, _ = lib.tn_contract(*qs[3])  # eager work between replays
+        assert abs(_c(single) - _c(ref[3])) <= 1e-6 * max(abs(_c(ref[3])), 2.0 ** -8)
+        torch.cuda.synchronize()
+    # device overrides read in place: one buffer (replay), then another (capture)
+    for rep in range(3):
+        xs = random_bitstrings(circ.n, 24, 200 + rep)
+        vec = {t: np.stack([amplitude_overrides(net, circ, x)[t] for x in xs]) for t in ids}
+        if rep < 2:
+            if rep == 0:
+                bufs = {t: torch.zeros((len(xs), 4), dtype=torch.float32, device="cuda") for t in ids}
+            for t in ids:
+                bufs[t].copy_(torch.from_numpy(vec[t].astype(np.complex64).view(np.float32)).reshape(len(xs), 4))
+        else:
+            bufs = {t: torch.from_numpy(vec[t].astype(np.complex64).view(np.float32)).reshape(len(xs), 4).cuda()
+                    for t in ids}
+        torch.cuda.synchronize()
+        ovr = [(t, bufs[t].data_ptr(), 16, lib.TN_C64_DEVICE) for t in ids]
+        eager, _ = lib.tn_contract_strided(p, len(xs), ovr)
+        graph, _ = lib.tn_contract_strided(p, len(xs), ovr, flags=lib.TN_FLAG_GRAPH)
+        assert np.array_equal(eager, graph)
+        refs = [_ref(net, plan, amplitude_overrides(net, circ, xs[i])) for i in (0, 11)]
+        for i, r in zip((0, 11), refs):
+            assert err(graph[i], r, circ.n) < TOL
+    ctx.free_plan(p)
