@@ -327,6 +327,13 @@ def gemm_phase_leg(lib, reps=3):
         for _ in range(reps):
             lib.tn_contract(p, ovr)
         amp_ms = (time.perf_counter() - t1) / reps * 1e3
+        # the same amplitude through the batched path (one query): the small
+        # vertices run in the subtree kernel instead of one launch each
+        lib.tn_contract_batch(ctx.handle, [(p, ovr)], [()])
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            bo, _, _ = lib.tn_contract_batch(ctx.handle, [(p, ovr)], [()])
+        bamp_ms = (time.perf_counter() - t1) / reps * 1e3
         lib.tn_profile_enable(ctx.handle, True)
         lib.tn_profile_read(ctx.handle, reset=True)
         for _ in range(reps):
@@ -339,12 +346,13 @@ def gemm_phase_leg(lib, reps=3):
                      "mfma_util": eff * mul / peak, "gemm_ms_per_amplitude": g["seconds"] / reps * 1e3,
                      "gemm_launches_per_amplitude": g["launches"] // reps,
                      "plain_ms_per_amplitude": amp_ms,
+                     "batched_ms_per_amplitude": bamp_ms,
                      "permute_ms_per_amplitude": st["permute"]["seconds"] / reps * 1e3,
                      "con_serial": costs["con_serial"],
                      "largest_intermediate": costs["largest_intermediate"],
                      "max_rel_err_vs_statevector": worst, "amplitudes_checked": len(gold["bitstrings"])}
         log(f"{name}: GEMM phase {eff:.1f} effective TFLOP/s ({out[name]['mfma_util']:.1%} of the "
-            f"MFMA peak), {amp_ms:.2f} ms per amplitude, max err {worst:.1e}")
+            f"MFMA peak), {amp_ms:.2f} ms per amplitude ({bamp_ms:.2f} batched), max err {worst:.1e}")
         ctx.free_plan(p)
     ctx.close()
     return out
@@ -588,9 +596,11 @@ def main():
     # executed work (vertices actually run, shared parts once) per unprofiled step time
     exec_tflops = sum(v["algo_flops"] for v in stats.values()) / K / (dt / K) / 1e12
 
-    serve = None
+    serve = serve_bf16 = None
     if args.serve_seconds > 0:
         serve = serve_bench(lib, ctx, args.serve_seconds, args.serve_rate, flags)
+        serve_bf16 = serve_bench(lib, ctx, args.serve_seconds, args.serve_rate,
+                                 lib.TN_PREC_BF16X3 | (lib.TN_FORM_3M if args.form == "3m" else 0))
 
     largest = None
     if not args.no_largest:
@@ -632,6 +642,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serve": serve,
+        "serve_bf16x3": serve_bf16,
         "largest_config_gemm_phase": largest,
         "uneven_batch": mix,
         "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},

@@ -2,6 +2,10 @@
 #include <cstring>
 #include <new>
 
+#include <atomic>
+#include <string>
+#include <thread>
+
 #include "tn_internal.h"
 
 using namespace tn;
@@ -60,6 +64,14 @@ tn_status tn_ctx_destroy(tn_ctx *ctx) {
     hipStreamDestroy(ctx->graph_st);
   }
   if (ctx->graph_ev) hipEventDestroy(ctx->graph_ev);
+  for (auto &l : ctx->lanes) {
+    if (l.st) {
+      hipStreamSynchronize(l.st);
+      hipStreamDestroy(l.st);
+    }
+    if (l.pinned) hipHostFree(l.pinned);
+  }
+  if (ctx->lanes_ev) hipEventDestroy(ctx->lanes_ev);
   ctx->prof.destroy();
   delete ctx;
   return TN_OK;
@@ -275,7 +287,7 @@ tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *qu
   }
   tn_status first = TN_OK;
   std::lock_guard<std::mutex> g(ctx->exec_mu);
-  for (size_t k = 0; k < plans.size(); ++k) {
+  auto group_io = [&](size_t k) {
     std::vector<QueryIO> qs;
     for (int i : members[k]) {
       QueryIO q;
@@ -286,12 +298,75 @@ tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *qu
       q.status = per_query ? &per_query[i] : nullptr;
       qs.push_back(q);
     }
-    ExecRes r = ctx_res(ctx);
-    tn_status st = run_group(ctx, plans[k], qs, out_dtype, flags, true, r);
-    if (st != TN_OK) {
+    return qs;
+  };
+  std::vector<tn_status> sts(plans.size(), TN_OK);
+  std::vector<std::string> msgs(plans.size());
+  std::vector<char> done(plans.size(), 0);
+  // Several plans: their groups run concurrently on up to four lanes (own
+  // stream and staging each, ordered after the caller's stream), so that one
+  // group's host work and small kernels overlap another's (with
+  // TN_FLAG_GRAPH each group captures on its lane).  Not while profiling.  A
+  // group that finds the arena taken by the others runs again, alone,
+  // afterwards.
+  const int W = (plans.size() > 1 && !ctx->prof.on)
+                    ? (int)std::min<size_t>(4, plans.size())
+                    : 1;
+  bool lanes_ok = W > 1;
+  if (lanes_ok) {
+    if (!ctx->lanes_ev && hipEventCreateWithFlags(&ctx->lanes_ev, hipEventDisableTiming) != hipSuccess) {
+      ctx->lanes_ev = nullptr;
+      lanes_ok = false;
+    }
+    while (lanes_ok && (int)ctx->lanes.size() < W) {
+      tn_ctx::Lane l;
+      if (hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking) != hipSuccess) {
+        lanes_ok = false;
+        break;
+      }
+      ctx->lanes.push_back(l);
+    }
+    if (lanes_ok && hipEventRecord(ctx->lanes_ev, ctx->stream) != hipSuccess) lanes_ok = false;
+    for (int w = 0; lanes_ok && w < W; ++w)
+      if (hipStreamWaitEvent(ctx->lanes[w].st, ctx->lanes_ev, 0) != hipSuccess) lanes_ok = false;
+    (void)hipGetLastError();
+  }
+  if (lanes_ok) {
+    std::atomic<size_t> next{0};
+    auto lane_main = [&](int w) {
+      tn_ctx::Lane &l = ctx->lanes[w];
+      ExecRes r;
+      r.st = l.st;
+      r.pinned = &l.pinned;
+      r.pinned_bytes = &l.pinned_bytes;
+      for (size_t k; (k = next.fetch_add(1)) < plans.size();) {
+        std::vector<QueryIO> qs = group_io(k);
+        sts[k] = run_group(ctx, plans[k], qs, out_dtype, flags, true, r);
+        if (sts[k] == TN_E_NOMEM) continue;  // retried alone below
+        done[k] = 1;
+        if (sts[k] != TN_OK) msgs[k] = last_error();
+      }
+      hipStreamSynchronize(l.st);
+    };
+    std::vector<std::thread> th;
+    for (int w = 1; w < W; ++w) th.emplace_back(lane_main, w);
+    lane_main(0);
+    for (auto &t : th) t.join();
+  }
+  for (size_t k = 0; k < plans.size(); ++k) {
+    if (!done[k]) {
+      std::vector<QueryIO> qs = group_io(k);
+      ExecRes r = ctx_res(ctx);
+      sts[k] = run_group(ctx, plans[k], qs, out_dtype, flags, true, r);
+      if (sts[k] != TN_OK) msgs[k] = last_error();
+    }
+    if (sts[k] != TN_OK) {
       if (per_query)
-        for (int i : members[k]) per_query[i] = st;
-      if (first == TN_OK) first = st;
+        for (int i : members[k]) per_query[i] = sts[k];
+      if (first == TN_OK) {
+        first = sts[k];
+        set_error("%s", msgs[k].c_str());
+      }
     }
   }
   return first;

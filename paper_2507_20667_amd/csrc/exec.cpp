@@ -252,7 +252,10 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   bool want_graph = (flags & TN_FLAG_GRAPH) && rs.ws < 0 && !prof.on && !dbg_gemm &&
                     chunk >= qs.size();
   hipStream_t gst = nullptr;
-  if (want_graph) {
+  // a caller's stream other than the context's (a batch lane, never the null
+  // stream) is captured on directly
+  if (want_graph && rs.st != ctx->stream && rs.st) gst = rs.st;
+  if (want_graph && !gst) {
     if (!ctx->graph_st &&
         (hipStreamCreateWithFlags(&ctx->graph_st, hipStreamNonBlocking) != hipSuccess ||
          hipEventCreateWithFlags(&ctx->graph_ev, hipEventDisableTiming) != hipSuccess)) {

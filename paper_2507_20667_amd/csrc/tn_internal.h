@@ -262,6 +262,15 @@ struct tn_ctx {
   // captured on the null stream), ordered after the caller's stream
   hipStream_t graph_st = nullptr;
   hipEvent_t graph_ev = nullptr;
+  // lanes of concurrent plan groups in tn_contract_batch: a stream and a
+  // pinned staging buffer each (created on first use)
+  struct Lane {
+    hipStream_t st = nullptr;
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+  };
+  std::vector<Lane> lanes;
+  hipEvent_t lanes_ev = nullptr;
 };
 
 namespace tn {

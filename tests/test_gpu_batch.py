@@ -301,3 +301,35 @@ def test_graph_replay_matches_eager(ctx):
         for i, r in zip((0, 11), refs):
             assert err(graph[i], r, circ.n) < TOL
     ctx.free_plan(p)
+
+
+def test_multi_plan_batch_concurrent(ctx):
+    """Queries of several plans in one call (their groups run concurrently on
+    separate streams) equal the same queries one at a time, interleaved in
+    any order, and match the oracle."""
+    circs = [random_circuit(12, 8, 41), random_circuit(14, 10, 42), brickwork_circuit(12, 8, 43),
+             phase_poly_circuit(10, 6, 44), random_circuit(16, 6, 45)]
+    loaded = []
+    for c in circs:
+        net = amplitude_network(c, 0)
+        plan = _plan(net, 2)
+        loaded.append((c, net, plan, ctx.load_network(net, plan.partition_of, 2, plan.tree)))
+    rng = np.random.default_rng(7)
+    qs, meta = [], []
+    for _ in range(60):
+        k = int(rng.integers(0, len(loaded)))
+        c, net, plan, p = loaded[k]
+        x = int(rng.integers(0, 1 << c.n))
+        qs.append((p, amplitude_overrides(net, c, x)))
+        meta.append((k, x))
+    outs, _, st = lib.tn_contract_batch(ctx.handle, qs, [()] * len(qs))
+    assert np.all(st == 0)
+    for (k, x), q, o in zip(meta, qs, outs):
+        single, _ = lib.tn_contract(*q)
+        assert abs(_c(o) - _c(single)) <= 1e-6 * max(abs(_c(single)), 2.0 ** -8)
+    for j in (0, 13, 59):
+        k, x = meta[j]
+        c, net, plan, p = loaded[k]
+        assert err(outs[j], _ref(net, plan, qs[j][1]), c.n) < TOL
+    for c, net, plan, p in loaded:
+        ctx.free_plan(p)
