@@ -702,7 +702,9 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       } else {
         const int rq = root_shared ? 1 : Q;
         if (p->fperm.needed) {
-          TN_HIP(hipMemcpyAsync(hv, fin, (size_t)rq * relems * 8, hipMemcpyDeviceToHost, st),
+          // the permuted results lie final_bytes apart (256-byte rounded)
+          TN_HIP(hipMemcpy2DAsync(hv, relems * 8, fin, final_bytes, relems * 8, rq,
+                                  hipMemcpyDeviceToHost, st),
                  "result copy");
         } else {
           const size_t pitch = R.bs ? (size_t)R.bs * 8 : relems * 8;

@@ -333,3 +333,27 @@ def test_multi_plan_batch_concurrent(ctx):
         assert err(outs[j], _ref(net, plan, qs[j][1]), c.n) < TOL
     for c, net, plan, p in loaded:
         ctx.free_plan(p)
+
+
+def test_batch_open_legs_each_query(ctx):
+    """Open legs in a batch: every query's result (several entries, permuted
+    into output-leg order) is its own, equal to the query run alone and to the
+    oracle."""
+    circ = random_circuit(13, 8, 51)
+    net = amplitude_network(circ, 0, open_qubits=(2, 7, 11))
+    plan = _plan(net, 3)
+    p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 3, plan.tree,
+                      net.output_legs)
+    xs = random_bitstrings(circ.n, 21, 52)
+    qs = [(p, amplitude_overrides(net, circ, x, open_qubits=(2, 7, 11))) for x in xs]
+    outs, _, st = lib.tn_contract_batch(ctx.handle, qs, [(2, 2, 2)] * len(qs))
+    assert np.all(st == 0)
+    for q, o in zip(qs, outs):
+        single, _ = lib.tn_contract(q[0], q[1], result_shape=(2, 2, 2))
+        scale = max(float(np.max(np.abs(single))), 2.0 ** -7)
+        assert np.max(np.abs(o - single)) <= 1e-6 * scale
+    for i in (0, 10, 20):
+        r = oracle.contract_tree(net.legs, net.dims, net.copy_with(qs[i][1]).tensors, plan.tree,
+                                 net.output_legs)
+        assert np.max(np.abs(outs[i] - r)) / max(float(np.max(np.abs(r))), 2.0 ** -7) < TOL
+    ctx.free_plan(p)
