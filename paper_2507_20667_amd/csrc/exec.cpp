@@ -538,6 +538,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         tl.steps = (const TreeStep *)(tb + L.tree_step_off);
         tl.loads = (const TreeLeafLoad *)(tb + L.tree_load_off);
         tl.sloads = (const TreeSharedLoad *)(tb + L.tree_sload_off);
+        tl.sgather = (const int2 *)(tb + L.tree_sg_off);
         tl.image = (const float2 *)(tb + L.tree_img_off);
         // overridden leaves in id order: read in place or from the staging block
         for (size_t k = 0; k < ovr.size() && k < (size_t)kTreeMaxOvr; ++k) {
@@ -567,9 +568,15 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         if (L.n_tree_perq) {
           tl.hdr = (const TreeHdr *)tb + L.n_tree_shared;
           tl.nq = Q;
-          tl.qw = L.tree_qw;
+          // a single query runs the level kernel (its waves share the query)
+          const bool wave = L.tree_wave && Q > 1, single = L.tree_wave && Q == 1;
+          tl.qw = single ? 1 : L.tree_qw;
+          const size_t lds = single ? L.lds_perq1 : L.lds_perq;
           TN_HIP(prof.timed(st, TN_KCLASS_TREE, tree_bytes_q * Q, tree_flops_q * Q,
-                            [&] { return launch_tree(st, tl, L.n_tree_perq, L.lds_perq); }),
+                            [&] {
+                              return wave ? launch_tree_wave(st, tl, L.n_tree_perq, lds)
+                                          : launch_tree(st, tl, L.n_tree_perq, lds);
+                            }),
                  "subtree kernel");
         }
       }

@@ -784,11 +784,14 @@ class Packer {
 
 // ------------------------------------------------------ subtree programs
 
-static size_t tree_lds_bytes(int qw, int nscale, int shared_elems, int perq_elems) {
+static size_t tree_lds_bytes(int qw, int nscale, int shared_elems, int perq_elems, bool wave = false) {
   auto r2 = [](int64_t x) { return (x + 1) & ~(int64_t)1; };
-  size_t b = (size_t)2 * kTreeChunk * kTreeStepWords * 4;  // two chunk buffers
-  b += 256 * 16;                                  // FP64 reduction buffer
-  b += 8 * (size_t)r2((int64_t)qw * nscale);       // scale records
+  size_t b = 0;
+  if (!wave) {
+    b += (size_t)2 * kTreeChunk * kTreeStepWords * 4;  // two chunk buffers
+    b += 256 * 16;                                      // FP64 reduction buffer
+  }
+  b += 8 * (size_t)r2((int64_t)qw * nscale);  // scale records
   b += 8 * (size_t)r2(shared_elems);
   b += 8 * (size_t)qw * (size_t)r2(perq_elems);
   return b;
@@ -1048,6 +1051,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     return;
   }
   std::vector<TreeSharedLoad> sloads;
+  std::vector<int2> sgather;  // (LDS offset, shared-part offset) per island entry
   std::vector<char> is_island(2 * nv - 1, 0);
   for (int u : L.islands) is_island[u] = 1;
   std::vector<int> order;  // shared subtrees (and islands) first
@@ -1123,6 +1127,17 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       sh += (int32_t)((n + 1) & ~(int64_t)1);
     }
     h.nsloads = (int32_t)sloads.size() - h.sload0;
+    h.nimg = h.nsloads ? sloads[h.sload0].lds : sh;
+    h.sg0 = (int32_t)sgather.size();
+    for (int i = h.sload0; i < h.sload0 + h.nsloads; ++i) {
+      const TreeSharedLoad &sl = sloads[i];
+      if (sl.off % 8 != 0 || sl.off / 8 + sl.n > INT32_MAX) {
+        L.tree_error = true;
+        return;
+      }
+      for (int32_t e = 0; e < sl.n; ++e) sgather.push_back(make_int2(sl.lds + e, (int32_t)(sl.off / 8) + e));
+    }
+    h.nsg = (int32_t)sgather.size() - h.sg0;
     h.shared_elems = sh;
     const int64_t base = pq;
     const LevelPlan lp = level_plan(p, nodes);
@@ -1156,6 +1171,8 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       chunks.push_back(tc);
     }
     h.nchunks = (int32_t)chunks.size() - h.chunk0;
+    h.step0 = h.nchunks ? chunks[h.chunk0].step0 : (int32_t)steps.size();
+    h.nsteps = (int32_t)steps.size() - h.step0;
     h.perq_elems = (int32_t)(base + lp.peak);
     h.nscale = (int32_t)scale.size();
     h.root_loc = loc[r];
@@ -1188,6 +1205,13 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       if (loc & kPerQuery) return (loc & ~kPerQuery) + r < h.perq_elems;
       return loc + r < h.shared_elems;
     };
+    // the chunks' steps are consecutive: [step0, step0 + nsteps)
+    int32_t next = h.step0;
+    for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c) {
+      ok = ok && chunks[c].step0 == next;
+      next += chunks[c].nsteps;
+    }
+    ok = ok && next == h.step0 + h.nsteps && h.step0 >= 0 && h.step0 + h.nsteps <= (int32_t)steps.size();
     for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c) {
       ok = ok && chunks[c].nsteps >= 1 && chunks[c].nsteps <= kTreeChunk;
       for (int k = chunks[c].step0; k < chunks[c].step0 + chunks[c].nsteps; ++k) {
@@ -1221,8 +1245,16 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
         if (st.kind == 1) ok = ok && chunks[c].nsteps == 1 && c == h.chunk0 + h.nchunks - 1;
       }
     }
+    // the islands' scale records are the first nsloads of the table, their
+    // entries follow the image
+    ok = ok && h.nsloads <= h.nscale && h.nimg >= 0 && h.nimg <= h.shared_elems &&
+         h.sg0 >= 0 && h.nsg >= 0 && h.sg0 + h.nsg <= (int32_t)sgather.size();
+    for (int i = h.sg0; ok && i < h.sg0 + h.nsg; ++i)
+      ok = sgather[i].x >= h.nimg && sgather[i].x < h.shared_elems && sgather[i].y >= 0 &&
+           8 * ((int64_t)sgather[i].y + 1) <= L.shared_bytes;
     for (int i = h.sload0; i < h.sload0 + h.nsloads; ++i)
-      ok = ok && sloads[i].lds >= 0 && sloads[i].lds + sloads[i].n <= h.shared_elems &&
+      ok = ok && sloads[i].scale == i - h.sload0 && sloads[i].lds >= h.nimg &&
+           sloads[i].lds >= 0 && sloads[i].lds + sloads[i].n <= h.shared_elems &&
            sloads[i].scale >= 0 && sloads[i].scale < h.nscale && sloads[i].slot >= nv &&
            sloads[i].slot < 2 * nv - 1 && sloads[i].off >= 0 &&
            sloads[i].off + 8 * (int64_t)sloads[i].n <= L.shared_bytes &&
@@ -1232,8 +1264,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
            loads[i].src >= 0 && loads[i].src < (int)ovr_list.size() &&
            p->leaf[ovr_list[loads[i].src]].size() == loads[i].n;
     // the image holds the shared leaves; the islands read in follow them in LDS
-    const int64_t nimg = h.nsloads ? sloads[h.sload0].lds : h.shared_elems;
-    ok = ok && h.image_off + nimg <= (int64_t)image.size() + 1;
+    ok = ok && h.image_off + h.nimg <= (int64_t)image.size();
     if (!h.final_dot) {
       const int64_t part = h.root_in_perq ? L.perq_bytes : L.shared_bytes;
       ok = ok && (h.root_loc & kPerQuery) && (h.root_loc & ~kPerQuery) + h.root_elems <= h.perq_elems &&
@@ -1245,20 +1276,36 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     return;
   }
   L.lds_shared = lds_sh;
-  // as many queries per workgroup as leave room for two workgroups per CU
+  // Batches run the wave kernel: four waves a workgroup, each with its own
+  // queries, so the queries per workgroup are a multiple of four; as many as
+  // leave room for two workgroups per CU, else four if one fits.  When not
+  // even that fits, the level kernel takes the batch.
+  const size_t lim = tree_lds_limit();
+  L.tree_wave = false;
   L.tree_qw = 1;
-  for (int qw : {16, 12, 8, 6, 5, 4, 3, 2}) {
-    if (tree_lds_bytes(qw, max_scale_q, max_sh_q, max_pq_q) <= tree_lds_limit() / 2) {
+  for (int qw : {16, 12, 8, 4})
+    if (tree_lds_bytes(qw, max_scale_q, max_sh_q, max_pq_q, true) <= lim / 2) {
       L.tree_qw = qw;
+      L.tree_wave = true;
       break;
     }
+  if (!L.tree_wave && tree_lds_bytes(4, max_scale_q, max_sh_q, max_pq_q, true) <= lim) {
+    L.tree_qw = 4;
+    L.tree_wave = true;
   }
+  if (!L.tree_wave)
+    for (int qw : {16, 12, 8, 6, 5, 4, 3, 2})
+      if (tree_lds_bytes(qw, max_scale_q, max_sh_q, max_pq_q) <= lim / 2) {
+        L.tree_qw = qw;
+        break;
+      }
   if (const char *e = getenv("TN_TREE_QW")) {  // tuning override
     const int qw = atoi(e);
-    if (qw >= 1 && qw <= 16 && tree_lds_bytes(qw, max_scale_q, max_sh_q, max_pq_q) <= tree_lds_limit())
+    if (qw >= 1 && qw <= 16 && tree_lds_bytes(qw, max_scale_q, max_sh_q, max_pq_q, L.tree_wave) <= lim)
       L.tree_qw = qw;
   }
-  L.lds_perq = tree_lds_bytes(L.tree_qw, max_scale_q, max_sh_q, max_pq_q);
+  L.lds_perq = tree_lds_bytes(L.tree_qw, max_scale_q, max_sh_q, max_pq_q, L.tree_wave);
+  L.lds_perq1 = tree_lds_bytes(1, max_scale_q, max_sh_q, max_pq_q);
   if (getenv("TN_DEBUG"))
     for (const TreeHdr &h : hdrs) {
       int gate = 0, nsteps = 0;
@@ -1283,6 +1330,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   L.tree_step_off = put(steps.data(), steps.size() * sizeof(TreeStep));
   L.tree_load_off = put(loads.data(), loads.size() * sizeof(TreeLeafLoad));
   L.tree_sload_off = put(sloads.data(), sloads.size() * sizeof(TreeSharedLoad));
+  L.tree_sg_off = put(sgather.data(), sgather.size() * sizeof(int2));
   L.tree_img_off = put(image.data(), image.size() * sizeof(float2));
 }
 
@@ -1411,9 +1459,10 @@ std::shared_ptr<ExecLayout> cached_layout(tn_plan *p, const std::vector<int> &ov
   if (getenv("TN_DEBUG"))
     fprintf(stderr,
             "[tn] layout: %zu overridden leaves, share %d, subtrees %d shared + %d per query, "
-            "%d queries/workgroup, LDS %zu / %zu bytes, per-query part %lld bytes, shared part "
-            "%lld bytes, tree error %d\n",
+            "%d queries/workgroup (wave kernel %d), LDS %zu / %zu bytes, per-query part %lld "
+            "bytes, shared part %lld bytes, tree error %d\n",
             overridden.size(), (int)share, L->n_tree_shared, L->n_tree_perq, L->tree_qw,
+            (int)L->tree_wave,
             L->lds_shared, L->lds_perq, (long long)L->perq_bytes, (long long)L->shared_bytes,
             (int)L->tree_error);
   p->layouts[key] = L;

@@ -191,8 +191,10 @@ struct TreeHdr {
   int64_t image_off;                 // shared leaves: offset in the leaf image
   int32_t root_slot;                 // tensor id (slot index) of the result
   int32_t sload0;                    // shared intermediates read from device memory
-  int32_t nsloads;
-  int32_t pad;
+  int32_t nsloads;                   // (their scale records are 0 .. nsloads-1)
+  int32_t nimg;                      // shared leaves copied from the image
+  int32_t step0, nsteps;             // the program: every step, chunk by chunk
+  int32_t sg0, nsg;                  // gather list of the shared intermediates
 };
 
 // A shared intermediate that a per-query subtree takes as an input: computed
@@ -217,6 +219,7 @@ struct TreeLaunch {
   const TreeStep *steps;
   const TreeLeafLoad *loads;
   const TreeSharedLoad *sloads;
+  const int2 *sgather;  // (LDS float2 offset, shared-part float2 offset) per entry
   const float2 *image;  // shared leaves of every subtree, each in its LDS order
   OvrSrc ovr[kTreeMaxOvr];
   uint8_t *shared_base;
@@ -268,6 +271,9 @@ hipError_t launch_dot(hipStream_t st, const DotDesc *d_desc, int64_t nelem, Oper
                       int nbatch);
 
 hipError_t launch_tree(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes);
+// Per-query launches: every wave takes ceil(qw / 4) queries of its workgroup
+// through the whole program on its own (no barrier after the leaves load).
+hipError_t launch_tree_wave(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes);
 size_t tree_lds_limit();
 
 // Tile shape variants of the GEMM (index into a table in the kernel file).

@@ -105,13 +105,15 @@ struct ExecLayout {
   // subtree programs: [TreeHdr...][TreeStep...][TreeLeafLoad...][image float2...]
   std::vector<uint8_t> tree_blob;
   size_t tree_chunk_off = 0, tree_step_off = 0, tree_load_off = 0, tree_img_off = 0;
-  size_t tree_sload_off = 0;
+  size_t tree_sload_off = 0, tree_sg_off = 0;
   // shared vertices inside per-query subtrees that run as shared subtrees of
   // their own (computed once, read by the per-query programs)
   std::vector<int> islands;
   int n_tree_shared = 0, n_tree_perq = 0;  // headers: shared subtrees first
   size_t lds_shared = 0, lds_perq = 0;     // dynamic LDS of the two launches
+  size_t lds_perq1 = 0;                    // the per-query launch of a single query
   int tree_qw = 1;                         // queries per workgroup (per-query launch)
+  bool tree_wave = false;                  // batches of queries run the wave kernel
   bool tree_reads_ovr = false;             // per-query subtrees load overridden leaves
   bool tree_error = false;                 // programs failed the bounds check
   bool all_in_tree = false;                // every vertex runs in the subtree kernel

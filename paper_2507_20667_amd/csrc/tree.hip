@@ -1,22 +1,34 @@
-// Subtree kernel: a whole subtree of small contractions in one workgroup.
+// Subtree kernels: a whole subtree of small contractions in one workgroup.
 //
 // The many small contractions near the leaves of a circuit network (gate
 // tensors of 2-16 entries meeting intermediates of up to a few thousand
 // entries) would each be a launch of their own.  Here one workgroup takes one
 // subtree for `qw` queries at once: it copies the subtree's leaves into LDS (a
-// shared copy of the leaves no query overrides, a per-query copy of the
-// overridden ones, read in place from the caller's buffers), then runs the
-// subtree level by level: the contractions of one level are independent, so
-// up to kTreeChunk of them share one barrier, with every operand and result in
-// LDS.  Finally it writes the subtree's result and its scale record to device
-// memory, or, when the subtree ends in the network's closed root, the FP64
-// inner product.
+// shared copy of the leaves no query overrides and of the shared
+// intermediates it reads, a per-query copy of the overridden leaves, read in
+// place from the caller's buffers), then runs the subtree's program with every
+// operand and result in LDS, and finally writes the subtree's result and its
+// scale record to device memory or, when the subtree ends in the network's
+// closed root, the FP64 inner product.
 //
-// The descriptors of the next chunk are fetched into registers while the
-// current chunk computes and stored to the second LDS buffer before the
-// barrier.  Scales: every intermediate keeps a running integer log2 scale and
-// the IEEE bits of its max |re|/|im|; a consumer multiplies its operands by
-// 2^-e (e = floor(log2 max)), exactly as the one-contraction kernels do.
+// Two ways to run the program:
+//  * k_tree (one query per launch: the shared subtrees, single queries): the
+//    four waves share the query.  The program runs level by level; the
+//    contractions of one level are independent, so up to kTreeChunk of them
+//    share one barrier.  The descriptors of the next chunk are fetched while
+//    the current one computes.
+//  * k_tree_wave (a batch of queries): every wave takes its own queries
+//    through the whole program, one step after the other, with no barrier
+//    after the leaves are in LDS: a wave's LDS accesses complete in order, so
+//    a step reads what the wave's earlier steps wrote.  The descriptors are
+//    uniform across the wave and are read with scalar loads.  A chain of
+//    small contractions (a gate sequence) then costs one wave's latency per
+//    step instead of a workgroup barrier and a descriptor round trip, and the
+//    other waves of the CU fill the gaps.
+//
+// Scales: every intermediate keeps a running integer log2 scale and the IEEE
+// bits of its max |re|/|im|; a consumer multiplies its operands by 2^-e
+// (e = floor(log2 max)), exactly as the one-contraction kernels do.
 #include "tn_device.h"
 
 namespace tn {
@@ -24,36 +36,21 @@ namespace tn {
 extern __shared__ __align__(16) unsigned char tree_lds[];
 
 typedef const TreeLaunch __attribute__((address_space(4))) *KernargLaunch;
+// step descriptors through the scalar cache (read only, uniform per wave)
+typedef const TreeStep __attribute__((address_space(4))) *CStep;
 
+// floor(log2 x) of the non-negative float with bits `bits`, without branches:
+// 0 for zero, infinity and NaN, -126 for subnormals
 __device__ __forceinline__ int tree_exp(uint32_t bits) {
-  if (bits == 0u) return 0;
   const int e = (int)((bits >> 23) & 0xffu);
-  if (e == 0xff) return 0;
-  if (e == 0) return -126;
-  return e - 127;
+  const int r = e == 0 ? -126 : e - 127;
+  return (bits == 0u || e == 0xff) ? 0 : r;
 }
 
-__device__ __forceinline__ void seg2(const int32_t *ext, const int32_t *s0, const int32_t *s1,
-                                     const int32_t *lg, int nseg, bool p2, int idx, int &o0,
-                                     int &o1) {
-  o0 = 0;
-  o1 = 0;
-  if (p2) {
-    for (int i = 0; i < nseg; ++i) {
-      const int v = idx & (ext[i] - 1);
-      idx >>= lg[i];
-      o0 += v * s0[i];
-      o1 += v * s1[i];
-    }
-  } else {
-    for (int i = 0; i < nseg; ++i) {
-      const int v = idx % ext[i];
-      idx /= ext[i];
-      o0 += v * s0[i];
-      o1 += v * s1[i];
-    }
-  }
-}
+// Index arithmetic: every offset, stride and index of a subtree is far below
+// 2^24, so the full-rate 24-bit multiply-add serves (the 32-bit integer
+// multiply runs at a quarter of the rate).
+__device__ __forceinline__ int mad24(int a, int b, int c) { return (int)__umul24((unsigned)a, (unsigned)b) + c; }
 
 // Decode with the map held in registers (unrolled over kTreeSeg); P2: every
 // extent a power of two (shifts and masks instead of divisions).
@@ -74,29 +71,265 @@ __device__ __forceinline__ void seg2r(const int32_t (&ext)[kTreeSeg], const int3
         v = idx % ext[i];
         idx /= ext[i];
       }
-      o0 += v * s0[i];
-      o1 += v * s1[i];
+      o0 = mad24(v, s0[i], o0);
+      o1 = mad24(v, s1[i], o1);
     }
   }
 }
 
-template <bool P2>
-__device__ __forceinline__ void tree_step_impl(const TreeStep *Sp, int lane, int nthr, int nqw,
-                                               float2 *pq, int perq, const float2 *shr, int2 *scl,
-                                               int nscale);
+// A step's result entries are dealt to threads in pairs of items (an item:
+// one result entry, or one fiber, of one query).  Every load of both items
+// (the operands' scale records, the operand entries) is issued before
+// anything is stored: a store to LDS ahead of a load keeps the compiler from
+// moving the load up, and each LDS round trip then costs its full latency.
+// Results, the result's log2 scale (by the thread of entry 0) and the running
+// max |re|/|im| (folded into the scale record with an LDS atomic when a
+// thread moves to another query, and at the end) follow.
+#ifndef TN_TREE_ITEMS
+#define TN_TREE_ITEMS 1
+#endif
+constexpr int kItems = TN_TREE_ITEMS;  // items per thread per pass
 
-template <bool P2, int NS, int NFY>
-__device__ __forceinline__ void tree_stream_impl(const TreeStep *Sp, int lane, int nthr, int nqw,
-                                                 float2 *pq, int perq, const float2 *shr,
-                                                 int2 *scl, int nscale);
+struct ItemScale {
+  int2 za, zb;
+  __device__ __forceinline__ int e() const { return tree_exp((uint32_t)za.y) + tree_exp((uint32_t)zb.y); }
+};
+
+__device__ __forceinline__ ItemScale item_scale(const int2 *sc, int asl, int bsl) {
+  ItemScale z;
+  z.za = asl >= 0 ? sc[asl] : make_int2(0, 0);
+  z.zb = bsl >= 0 ? sc[bsl] : make_int2(0, 0);
+  return z;
+}
+
+__device__ __forceinline__ void fold_max(int2 *scl, int nscale, int csl, int q, int &qprev, float &mx,
+                                         float m) {
+  if (q != qprev) {
+    if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
+    qprev = q;
+    mx = 0.f;
+  }
+  mx = fmaxf(mx, m);
+}
+
+// Kind 2: one thread per fiber of the large operand X (and query) reads the
+// fiber's ns entries once and writes nfy results; the small operand Y is
+// read into registers with the fiber.
+template <bool P2, int NS, int NFY, class SP>
+__device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int nqw, float2 *pq,
+                                                 int perq, const float2 *shr, int2 *scl,
+                                                 int nscale) {
+  const int a = Sp->a, b = Sp->b, c = Sp->c, asl = Sp->asl, bsl = Sp->bsl, csl = Sp->csl;
+  const int nfib = Sp->nc / NFY, ncs = Sp->ncs;
+  const int lgf = P2 ? __builtin_ctz((unsigned)nfib) : 0;
+  int32_t fext[kTreeSeg], fx[kTreeSeg], fc[kTreeSeg], flg[kTreeSeg];
+#pragma unroll
+  for (int i = 0; i < kTreeSeg; ++i) {
+    fext[i] = Sp->cext[i];
+    fx[i] = Sp->ca[i];
+    fc[i] = Sp->cb[i];
+    flg[i] = Sp->clg[i];
+  }
+  int xs[NS], cy[NFY], ym[NS * NFY];
+#pragma unroll
+  for (int v = 0; v < NS; ++v) xs[v] = Sp->xs[v];
+#pragma unroll
+  for (int v = 0; v < NFY; ++v) cy[v] = Sp->cy[v];
+#pragma unroll
+  for (int v = 0; v < NS * NFY; ++v) ym[v] = Sp->ymap[v];
+  const int total = nqw * nfib;
+  int qprev = -1;
+  float mx = 0.f;
+  for (int w0 = lane; w0 < total; w0 += kItems * nthr) {
+    int qv[kItems], fv[kItems], co[kItems];
+    bool ok[kItems];
+    ItemScale z[kItems];
+    float2 x[kItems][NS], y[kItems][NS * NFY];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+      const int w = w0 + u * nthr;
+      ok[u] = w < total;
+      const int ww = ok[u] ? w : w0;  // a missing second item repeats the first
+      const int q = P2 ? (ww >> lgf) : ww / nfib;
+      qv[u] = q;
+      fv[u] = P2 ? (ww & (nfib - 1)) : ww - mad24(q, nfib, 0);
+      const float2 *base = pq + mad24(q, perq, 0);
+      const float2 *X = (a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a;
+      const float2 *Y = (b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b;
+      z[u] = item_scale(scl + mad24(q, nscale, 0), asl, bsl);
+      int xo;
+      seg2r<P2>(fext, fx, fc, flg, ncs, fv[u], xo, co[u]);
+#pragma unroll
+      for (int v = 0; v < NS * NFY; ++v) y[u][v] = Y[ym[v]];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) x[u][s] = X[xo + xs[s]];
+    }
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+      if (!ok[u]) continue;
+      const int e = z[u].e();
+      const float f = ldexpf(1.0f, -e);
+      float2 *base = pq + mad24(qv[u], perq, 0);
+      float2 *C = base + (c & ~kPerQuery);
+      float m = 0.f;
+#pragma unroll
+      for (int j = 0; j < NFY; ++j) {
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const float2 yv = y[u][s * NFY + j];
+          re = fmaf(x[u][s].x, yv.x, re);
+          re = fmaf(-x[u][s].y, yv.y, re);
+          im = fmaf(x[u][s].x, yv.y, im);
+          im = fmaf(x[u][s].y, yv.x, im);
+        }
+        re *= f;
+        im *= f;
+        C[co[u] + cy[j]] = make_float2(re, im);
+        m = fmaxf(m, fmaxf(fabsf(re), fabsf(im)));
+      }
+      if (fv[u] == 0) scl[mad24(qv[u], nscale, csl)].x = z[u].za.x + z[u].zb.x + e;
+      fold_max(scl, nscale, csl, qv[u], qprev, mx, m);
+    }
+  }
+  if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
+}
+
+// Kind 0: one thread per result entry (and query); the shared index is summed
+// four terms at a time for both items of a pair.
+template <bool P2, class SP>
+__device__ __forceinline__ void tree_step_impl(SP Sp, int lane, int nthr, int nqw, float2 *pq,
+                                               int perq, const float2 *shr, int2 *scl, int nscale) {
+  const int a = Sp->a, b = Sp->b, c = Sp->c, asl = Sp->asl, bsl = Sp->bsl, csl = Sp->csl;
+  const int nc = Sp->nc, ns = Sp->ns, ncs = Sp->ncs, nss = Sp->nss;
+  const int lgnc = P2 ? __builtin_ctz((unsigned)nc) : 0;
+  int32_t cext[kTreeSeg], ca[kTreeSeg], cb[kTreeSeg], clg[kTreeSeg];
+  int32_t sext[kTreeSeg], sa[kTreeSeg], sb[kTreeSeg], slg[kTreeSeg];
+#pragma unroll
+  for (int i = 0; i < kTreeSeg; ++i) {
+    cext[i] = Sp->cext[i];
+    ca[i] = Sp->ca[i];
+    cb[i] = Sp->cb[i];
+    clg[i] = Sp->clg[i];
+    sext[i] = Sp->sext[i];
+    sa[i] = Sp->sa[i];
+    sb[i] = Sp->sb[i];
+    slg[i] = Sp->slg[i];
+  }
+  // shared-index offsets, computed once per wave: hardware lane l holds those
+  // of s = l (ns <= 64), read back in the inner loop with readlane (s is the
+  // same in every lane there); every lane of the wave is active here
+  const int hl = threadIdx.x & 63;
+  const bool stab = ns <= 64;
+  int soa = 0, sob = 0;
+  if (stab && hl < ns) seg2r<P2>(sext, sa, sb, slg, nss, hl, soa, sob);
+  const int total = nqw * nc;
+  int qprev = -1;
+  float mx = 0.f;
+  for (int w0 = lane; w0 < total; w0 += kItems * nthr) {
+    int qv[kItems], cv[kItems];
+    bool ok[kItems];
+    ItemScale z[kItems];
+    const float2 *A[kItems], *B[kItems];
+    float re[kItems][2], im[kItems][2];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+      const int w = w0 + u * nthr;
+      ok[u] = w < total;
+      const int ww = ok[u] ? w : w0;  // a missing second item repeats the first
+      const int q = P2 ? (ww >> lgnc) : ww / nc;
+      qv[u] = q;
+      cv[u] = P2 ? (ww & (nc - 1)) : ww - mad24(q, nc, 0);
+      const float2 *base = pq + mad24(q, perq, 0);
+      int ao, bo;
+      seg2r<P2>(cext, ca, cb, clg, ncs, cv[u], ao, bo);
+      A[u] = ((a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a) + ao;
+      B[u] = ((b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b) + bo;
+      z[u] = item_scale(scl + mad24(q, nscale, 0), asl, bsl);
+      re[u][0] = re[u][1] = im[u][0] = im[u][1] = 0.f;
+    }
+    if (stab) {
+      int s = 0;
+      for (; s + 4 <= ns; s += 4) {
+        float2 x[kItems][4], y[kItems][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int oa = __builtin_amdgcn_readlane(soa, s + t);
+          const int ob = __builtin_amdgcn_readlane(sob, s + t);
+#pragma unroll
+          for (int u = 0; u < kItems; ++u) {
+            x[u][t] = A[u][oa];
+            y[u][t] = B[u][ob];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kItems; ++u)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int r = t & 1;
+            re[u][r] = fmaf(x[u][t].x, y[u][t].x, re[u][r]);
+            re[u][r] = fmaf(-x[u][t].y, y[u][t].y, re[u][r]);
+            im[u][r] = fmaf(x[u][t].x, y[u][t].y, im[u][r]);
+            im[u][r] = fmaf(x[u][t].y, y[u][t].x, im[u][r]);
+          }
+      }
+      for (; s < ns; ++s) {
+        const int oa = __builtin_amdgcn_readlane(soa, s), ob = __builtin_amdgcn_readlane(sob, s);
+        float2 x[kItems], y[kItems];
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+          x[u] = A[u][oa];
+          y[u] = B[u][ob];
+        }
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+          re[u][0] = fmaf(x[u].x, y[u].x, re[u][0]);
+          re[u][0] = fmaf(-x[u].y, y[u].y, re[u][0]);
+          im[u][0] = fmaf(x[u].x, y[u].y, im[u][0]);
+          im[u][0] = fmaf(x[u].y, y[u].x, im[u][0]);
+        }
+      }
+    } else {
+      for (int s = 0; s < ns; ++s) {
+        int oa, ob;
+        seg2r<P2>(sext, sa, sb, slg, nss, s, oa, ob);
+        float2 x[kItems], y[kItems];
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+          x[u] = A[u][oa];
+          y[u] = B[u][ob];
+        }
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+          re[u][0] = fmaf(x[u].x, y[u].x, re[u][0]);
+          re[u][0] = fmaf(-x[u].y, y[u].y, re[u][0]);
+          im[u][0] = fmaf(x[u].x, y[u].y, im[u][0]);
+          im[u][0] = fmaf(x[u].y, y[u].x, im[u][0]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+      if (!ok[u]) continue;
+      const int e = z[u].e();
+      const float f = ldexpf(1.0f, -e);
+      const float rr = (re[u][0] + re[u][1]) * f, ii = (im[u][0] + im[u][1]) * f;
+      float2 *C = pq + mad24(qv[u], perq, c & ~kPerQuery);
+      C[cv[u]] = make_float2(rr, ii);
+      if (cv[u] == 0) scl[mad24(qv[u], nscale, csl)].x = z[u].za.x + z[u].zb.x + e;
+      fold_max(scl, nscale, csl, qv[u], qprev, mx, fmaxf(fabsf(rr), fabsf(ii)));
+    }
+  }
+  if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
+}
 
 // One contraction for every query of the group, by `nthr` threads starting at
 // `lane`.  The step's maps live in registers; each thread keeps the running
 // max of its results per query and folds it into the scale record once per
 // query.
-__device__ __forceinline__ void tree_step(const TreeStep *Sp, int lane, int nthr, int nqw,
-                                          float2 *pq, int perq, const float2 *shr, int2 *scl,
-                                          int nscale) {
+template <class SP>
+__device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
+                                          const float2 *shr, int2 *scl, int nscale) {
   if (Sp->kind == 2) {
     // a small operand along the fibers of a large one: ns, nfy in {1, 2, 4}
     const int sel = (Sp->ns >> 1) * 3 + (Sp->nss >> 1) + (Sp->pow2 ? 0 : 9);
@@ -130,163 +363,84 @@ __device__ __forceinline__ void tree_step(const TreeStep *Sp, int lane, int nthr
     tree_step_impl<false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale);
 }
 
-// Kind 2: one thread per fiber of the large operand X (and query) reads the
-// fiber's ns entries once and writes nfy results; the small operand Y sits in
-// registers, reloaded when a thread moves to another query.
-template <bool P2, int NS, int NFY>
-__device__ __forceinline__ void tree_stream_impl(const TreeStep *Sp, int lane, int nthr, int nqw,
-                                                 float2 *pq, int perq, const float2 *shr,
-                                                 int2 *scl, int nscale) {
-  const int a = Sp->a, b = Sp->b, c = Sp->c;
-  const int asl = Sp->asl, bsl = Sp->bsl, csl = Sp->csl;
-  const int nfib = Sp->nc / NFY, ncs = Sp->ncs;
-  const int lgf = P2 ? __builtin_ctz((unsigned)nfib) : 0;
-  int32_t fext[kTreeSeg], fx[kTreeSeg], fc[kTreeSeg], flg[kTreeSeg];
-#pragma unroll
-  for (int i = 0; i < kTreeSeg; ++i) {
-    fext[i] = Sp->cext[i];
-    fx[i] = Sp->ca[i];
-    fc[i] = Sp->cb[i];
-    flg[i] = Sp->clg[i];
+// Closed root of one query: the FP64 inner product and its result record
+// (mantissa pair normalised to [0.5, 1) in the larger part, exponent in log2s).
+__device__ __forceinline__ void tree_write_result(Result *r, double vr, double vi, int2 za, int2 zb) {
+  double log2s = (double)(za.x + zb.x);
+  const double m = fmax(fabs(vr), fabs(vi));
+  if (m > 0.0 && isfinite(m)) {
+    int e;
+    frexp(m, &e);
+    vr = ldexp(vr, -e);
+    vi = ldexp(vi, -e);
+    log2s += (double)e;
   }
-  int xs[NS], cy[NFY], ym[NS * NFY];
-#pragma unroll
-  for (int v = 0; v < NS; ++v) xs[v] = Sp->xs[v];
-#pragma unroll
-  for (int v = 0; v < NFY; ++v) cy[v] = Sp->cy[v];
-#pragma unroll
-  for (int v = 0; v < NS * NFY; ++v) ym[v] = Sp->ymap[v];
-  int qprev = -1;
-  float mx = 0.f, f = 1.f;
-  const float2 *X = nullptr;
-  float2 *C = nullptr;
-  int2 *sc = nullptr;
-  float2 y[NS * NFY];
-  for (int w = lane; w < nqw * nfib; w += nthr) {
-    const int q = P2 ? (w >> lgf) : w / nfib;
-    const int fi = w - q * nfib;
-    if (q != qprev) {
-      if (qprev >= 0) atomicMax((unsigned int *)&sc[csl].y, __float_as_uint(mx));
-      qprev = q;
-      mx = 0.f;
-      float2 *base = pq + q * perq;
-      X = (a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a;
-      const float2 *Y = (b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b;
-      C = base + (c & ~kPerQuery);
-      sc = scl + q * nscale;
-      const int2 za = asl >= 0 ? sc[asl] : make_int2(0, 0);
-      const int2 zb = bsl >= 0 ? sc[bsl] : make_int2(0, 0);
-      const int ea = tree_exp((uint32_t)za.y), eb = tree_exp((uint32_t)zb.y);
-      f = ldexpf(1.0f, -(ea + eb));
-      if (fi == 0) sc[csl].x = za.x + zb.x + ea + eb;
-#pragma unroll
-      for (int v = 0; v < NS * NFY; ++v) y[v] = Y[ym[v]];
-    }
-    int xo, co;
-    seg2r<P2>(fext, fx, fc, flg, ncs, fi, xo, co);
-    float2 x[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) x[s] = X[xo + xs[s]];
-#pragma unroll
-    for (int j = 0; j < NFY; ++j) {
-      float re = 0.f, im = 0.f;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const float2 yv = y[s * NFY + j];
-        re = fmaf(x[s].x, yv.x, re);
-        re = fmaf(-x[s].y, yv.y, re);
-        im = fmaf(x[s].x, yv.y, im);
-        im = fmaf(x[s].y, yv.x, im);
-      }
-      re *= f;
-      im *= f;
-      C[co + cy[j]] = make_float2(re, im);
-      mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
-    }
-  }
-  if (qprev >= 0) atomicMax((unsigned int *)&sc[csl].y, __float_as_uint(mx));
+  r->re = vr;
+  r->im = vi;
+  r->log2s = log2s;
+  r->pad = 0.0;
 }
 
-template <bool P2>
-__device__ __forceinline__ void tree_step_impl(const TreeStep *Sp, int lane, int nthr, int nqw,
-                                               float2 *pq, int perq, const float2 *shr, int2 *scl,
-                                               int nscale) {
-  const int a = Sp->a, b = Sp->b, c = Sp->c;
-  const int asl = Sp->asl, bsl = Sp->bsl, csl = Sp->csl;
-  const int nc = Sp->nc, ns = Sp->ns, ncs = Sp->ncs, nss = Sp->nss;
-  const int lgnc = P2 ? __builtin_ctz((unsigned)nc) : 0;
-  int32_t cext[kTreeSeg], ca[kTreeSeg], cb[kTreeSeg], clg[kTreeSeg];
-  int32_t sext[kTreeSeg], sa[kTreeSeg], sb[kTreeSeg], slg[kTreeSeg];
+// The leaves into LDS, by the whole workgroup: the shared leaves from the
+// image, the shared intermediates through the gather list, their scale
+// records into every query's table, the per-query scale records cleared and
+// the overridden leaves copied per query.  Loads are issued in groups of four
+// per thread before any of them is stored, so each part costs about one
+// round trip.  The caller places a barrier after it.
+__device__ __forceinline__ void tree_prologue(const TreeLaunch &t, KernargLaunch ka, const TreeHdr &h,
+                                              int tid, int qw, int nqw, int q0, int2 *scl,
+                                              float2 *shr, float2 *pq, int perq) {
+  // the shared intermediates' records (indices below nsloads) are written
+  // below, every other record starts at zero
+  for (int i = tid; i < qw * h.nscale; i += 256) {
+    const int r = i % h.nscale;
+    if (r >= h.nsloads) scl[i] = make_int2(0, 0);
+  }
+  const float2 *img = t.image + h.image_off;
+  for (int i0 = 0; i0 < h.nimg; i0 += 1024) {
+    float2 v[4];
 #pragma unroll
-  for (int i = 0; i < kTreeSeg; ++i) {
-    cext[i] = Sp->cext[i];
-    ca[i] = Sp->ca[i];
-    cb[i] = Sp->cb[i];
-    clg[i] = Sp->clg[i];
-    sext[i] = Sp->sext[i];
-    sa[i] = Sp->sa[i];
-    sb[i] = Sp->sb[i];
-    slg[i] = Sp->slg[i];
-  }
-  // shared-index offsets, computed once per wave: hardware lane l holds those
-  // of s = l (ns <= 64), read back in the inner loop with readlane (s is the
-  // same in every lane there); every lane of the wave is active here
-  const int hl = threadIdx.x & 63;
-  const bool stab = ns <= 64;
-  int soa = 0, sob = 0;
-  if (stab && hl < ns) seg2r<P2>(sext, sa, sb, slg, nss, hl, soa, sob);
-  int qprev = -1;
-  float mx = 0.f, f = 1.f;
-  const float2 *A = nullptr, *B = nullptr;
-  float2 *C = nullptr;
-  int2 *sc = nullptr;
-  for (int w = lane; w < nqw * nc; w += nthr) {
-    const int q = P2 ? (w >> lgnc) : w / nc;
-    const int ci = w - q * nc;
-    if (q != qprev) {
-      if (qprev >= 0) atomicMax((unsigned int *)&sc[csl].y, __float_as_uint(mx));
-      qprev = q;
-      mx = 0.f;
-      float2 *base = pq + q * perq;
-      A = (a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a;
-      B = (b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b;
-      C = base + (c & ~kPerQuery);
-      sc = scl + q * nscale;
-      const int2 za = asl >= 0 ? sc[asl] : make_int2(0, 0);
-      const int2 zb = bsl >= 0 ? sc[bsl] : make_int2(0, 0);
-      const int ea = tree_exp((uint32_t)za.y), eb = tree_exp((uint32_t)zb.y);
-      f = ldexpf(1.0f, -(ea + eb));
-      if (ci == 0) sc[csl].x = za.x + zb.x + ea + eb;
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + tid + 256 * j;
+      if (i < h.nimg) v[j] = img[i];
     }
-    int ao, bo;
-    seg2r<P2>(cext, ca, cb, clg, ncs, ci, ao, bo);
-    float re = 0.f, im = 0.f;
-    if (stab) {
-      for (int s = 0; s < ns; ++s) {
-        const int oa = __builtin_amdgcn_readlane(soa, s), ob = __builtin_amdgcn_readlane(sob, s);
-        const float2 x = A[ao + oa], y = B[bo + ob];
-        re = fmaf(x.x, y.x, re);
-        re = fmaf(-x.y, y.y, re);
-        im = fmaf(x.x, y.y, im);
-        im = fmaf(x.y, y.x, im);
-      }
-    } else {
-      for (int s = 0; s < ns; ++s) {
-        int oa, ob;
-        seg2r<P2>(sext, sa, sb, slg, nss, s, oa, ob);
-        const float2 x = A[ao + oa], y = B[bo + ob];
-        re = fmaf(x.x, y.x, re);
-        re = fmaf(-x.y, y.y, re);
-        im = fmaf(x.x, y.y, im);
-        im = fmaf(x.y, y.x, im);
-      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + tid + 256 * j;
+      if (i < h.nimg) shr[i] = v[j];
     }
-    re *= f;
-    im *= f;
-    C[ci] = make_float2(re, im);
-    mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
   }
-  if (qprev >= 0) atomicMax((unsigned int *)&sc[csl].y, __float_as_uint(mx));
+  const float2 *sbase = (const float2 *)t.shared_base;
+  for (int e0 = 0; e0 < h.nsg; e0 += 1024) {
+    int2 g[4];
+    float2 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = e0 + tid + 256 * j;
+      g[j] = e < h.nsg ? t.sgather[h.sg0 + e] : make_int2(-1, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (g[j].x >= 0) v[j] = sbase[g[j].y];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (g[j].x >= 0) shr[g[j].x] = v[j];
+  }
+  for (int e = tid; e < h.nsloads * nqw; e += 256) {
+    const int k = e / nqw, q = e - k * nqw;
+    const int slot = t.sloads[h.sload0 + k].slot;
+    const Slot z = t.slots_sh[slot];
+    scl[q * h.nscale + k] = make_int2((int)z.log2s, (int)z.maxbits);
+  }
+  for (int w = tid; w < h.nloads * nqw; w += 256) {
+    const int li = w / nqw, q = w - li * nqw;
+    const TreeLeafLoad L = t.loads[h.load0 + li];
+    const float2 *op = ka->ovr[L.src].p;
+    const int64_t ostride = ka->ovr[L.src].stride;
+    const float2 *src = op + (int64_t)(q0 + q) * ostride;
+    float2 *dst = pq + q * perq + (L.lds & ~kPerQuery);
+    for (int i = 0; i < L.n; ++i) dst[i] = src[i];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
@@ -312,57 +466,42 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
   const int perq = (h.perq_elems + 1) & ~1;
   const int32_t *gw = (const int32_t *)t.steps;
 
-  for (int i = tid; i < qw * h.nscale; i += 256) scl[i] = make_int2(0, 0);
-  // shared leaves from the image; shared intermediates (computed by the shared
-  // launch before this one) from the shared part, after them
-  const int nimg = h.nsloads ? t.sloads[h.sload0].lds : h.shared_elems;
-  for (int i = tid; i < nimg; i += 256) shr[i] = t.image[h.image_off + i];
-  if (h.nsloads) {
-    __syncthreads();  // the scale records are cleared
-    for (int k = 0; k < h.nsloads; ++k) {
-      const TreeSharedLoad S = t.sloads[h.sload0 + k];
-      const float2 *src = (const float2 *)(t.shared_base + S.off);
-      for (int i = tid; i < S.n; i += 256) shr[S.lds + i] = src[i];
-      if (tid < nqw) {
-        const Slot &z = t.slots_sh[S.slot];
-        scl[tid * h.nscale + S.scale] = make_int2((int)z.log2s, (int)z.maxbits);
-      }
-    }
-  }
-  for (int w = tid; w < h.nloads * nqw; w += 256) {
-    const int li = w / nqw, q = w - li * nqw;
-    const TreeLeafLoad L = t.loads[h.load0 + li];
-    const float2 *op = ka->ovr[L.src].p;
-    const int64_t ostride = ka->ovr[L.src].stride;
-    const float2 *src = op + (int64_t)(q0 + q) * ostride;
-    float2 *dst = pq + q * perq + (L.lds & ~kPerQuery);
-    for (int i = 0; i < L.n; ++i) dst[i] = src[i];
-  }
-  int cur = 0;
+  tree_prologue(t, ka, h, tid, qw, nqw, q0, scl, shr, pq, perq);
+  // the chunks' steps are consecutive from step0: the next chunk's size is
+  // fetched one chunk ahead, so no chunk waits on the chunk table
+  int cur = 0, nxt = 0, s_cur = h.step0;
   if (h.nchunks > 0) {
-    const TreeChunk c0 = t.chunks[h.chunk0];
-    cur = c0.nsteps;
-    for (int i = tid; i < c0.nsteps * W; i += 256) sbuf[i] = gw[(int64_t)c0.step0 * W + i];
+    cur = t.chunks[h.chunk0].nsteps;
+    if (h.nchunks > 1) nxt = t.chunks[h.chunk0 + 1].nsteps;
+    for (int i = tid; i < cur * W; i += 256) sbuf[i] = gw[(int64_t)s_cur * W + i];
   }
   __syncthreads();
 
   for (int k = 0; k < h.nchunks; ++k) {
     const TreeStep *S = (const TreeStep *)(sbuf + (k & 1) * CW);
-    int nxt = 0;
     int32_t pre[PRE];
+    int nxt2 = 0;
     if (k + 1 < h.nchunks) {
-      const TreeChunk cn = t.chunks[h.chunk0 + k + 1];
-      nxt = cn.nsteps;
+      const int64_t s_nxt = s_cur + cur;
 #pragma unroll
       for (int j = 0; j < PRE; ++j) {
         const int i = tid + 256 * j;
-        pre[j] = i < nxt * W ? gw[(int64_t)cn.step0 * W + i] : 0;
+        pre[j] = i < nxt * W ? gw[s_nxt * W + i] : 0;
       }
+      if (k + 2 < h.nchunks) nxt2 = t.chunks[h.chunk0 + k + 2].nsteps;
     }
     if (S[0].kind == 1) {
       // closed root: FP64 inner product over ns entries for every query
       const TreeStep &st = S[0];
       const bool p2 = st.pow2 != 0;
+      int32_t ext[kTreeSeg], s0[kTreeSeg], s1[kTreeSeg], lg[kTreeSeg];
+#pragma unroll
+      for (int i = 0; i < kTreeSeg; ++i) {
+        ext[i] = st.sext[i];
+        s0[i] = st.sa[i];
+        s1[i] = st.sb[i];
+        lg[i] = st.slg[i];
+      }
       for (int q = 0; q < nqw; ++q) {
         float2 *base = pq + q * perq;
         const float2 *A = (st.a & kPerQuery) ? base + (st.a & ~kPerQuery) : shr + st.a;
@@ -370,7 +509,10 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
         double re = 0.0, im = 0.0;
         for (int s = tid; s < st.ns; s += 256) {
           int sa, sb;
-          seg2(st.sext, st.sa, st.sb, st.slg, st.nss, p2, s, sa, sb);
+          if (p2)
+            seg2r<true>(ext, s0, s1, lg, st.nss, s, sa, sb);
+          else
+            seg2r<false>(ext, s0, s1, lg, st.nss, s, sa, sb);
           const float2 x = A[sa], y = B[sb];
           re += (double)x.x * y.x - (double)x.y * y.y;
           im += (double)x.x * y.y + (double)x.y * y.x;
@@ -388,21 +530,7 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
           const int2 *sc = scl + q * h.nscale;
           const int2 za = st.asl >= 0 ? sc[st.asl] : make_int2(0, 0);
           const int2 zb = st.bsl >= 0 ? sc[st.bsl] : make_int2(0, 0);
-          double vr = red[0].x, vi = red[0].y;
-          double log2s = (double)(za.x + zb.x);
-          const double m = fmax(fabs(vr), fabs(vi));
-          if (m > 0.0 && isfinite(m)) {
-            int e;
-            frexp(m, &e);
-            vr = ldexp(vr, -e);
-            vi = ldexp(vi, -e);
-            log2s += (double)e;
-          }
-          Result *r = t.res + (q0 + q);
-          r->re = vr;
-          r->im = vi;
-          r->log2s = log2s;
-          r->pad = 0.0;
+          tree_write_result(t.res + (q0 + q), red[0].x, red[0].y, za, zb);
         }
         __syncthreads();
       }
@@ -423,7 +551,9 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
         if (i < nxt * W) dst[i] = pre[j];
       }
     }
+    s_cur += cur;
     cur = nxt;
+    nxt = nxt2;
     __syncthreads();
   }
 
@@ -447,8 +577,101 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const TreeHdr h = t.hdr[blockIdx.x];
+  const int qw = t.qw;
+  const int qpw = (qw + 3) >> 2;
+  const int q0 = blockIdx.y * qw;
+  const int nqw = min(qw, t.nq - q0);
+  KernargLaunch ka = (KernargLaunch)__builtin_amdgcn_kernarg_segment_ptr();
+
+  // LDS: [scales: qw * nscale int2][shared region][qw per-query regions]
+  int2 *scl = (int2 *)tree_lds;
+  float2 *shr = (float2 *)(scl + ((qw * h.nscale + 1) & ~1));
+  float2 *pq = shr + ((h.shared_elems + 1) & ~1);
+  const int perq = (h.perq_elems + 1) & ~1;
+
+  tree_prologue(t, ka, h, tid, qw, nqw, q0, scl, shr, pq, perq);
+  __syncthreads();
+
+  // this wave's queries: [wq0, wq0 + wn) of the workgroup's
+  const int wq0 = wave * qpw;
+  const int wn = min(qpw, nqw - wq0);
+  if (wn <= 0) return;
+  float2 *wpq = pq + wq0 * perq;
+  int2 *wscl = scl + wq0 * h.nscale;
+  const CStep prog = (CStep)t.steps + h.step0;
+  for (int k = 0; k < h.nsteps; ++k) {
+    const CStep S = prog + k;
+    if (S->kind == 1) {
+      // closed root: FP64 inner product, reduced across the wave
+      const bool p2 = S->pow2 != 0;
+      const int ns = S->ns, nss = S->nss, a = S->a, b = S->b;
+      int32_t ext[kTreeSeg], s0[kTreeSeg], s1[kTreeSeg], lg[kTreeSeg];
+#pragma unroll
+      for (int i = 0; i < kTreeSeg; ++i) {
+        ext[i] = S->sext[i];
+        s0[i] = S->sa[i];
+        s1[i] = S->sb[i];
+        lg[i] = S->slg[i];
+      }
+      for (int q = 0; q < wn; ++q) {
+        float2 *base = wpq + q * perq;
+        const float2 *A = (a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a;
+        const float2 *B = (b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b;
+        double re = 0.0, im = 0.0;
+        for (int s = lane; s < ns; s += 64) {
+          int sa, sb;
+          if (p2)
+            seg2r<true>(ext, s0, s1, lg, nss, s, sa, sb);
+          else
+            seg2r<false>(ext, s0, s1, lg, nss, s, sa, sb);
+          const float2 x = A[sa], y = B[sb];
+          re += (double)x.x * y.x - (double)x.y * y.y;
+          im += (double)x.x * y.y + (double)x.y * y.x;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          re += __shfl_xor(re, off, 64);
+          im += __shfl_xor(im, off, 64);
+        }
+        if (lane == 0) {
+          const int2 *sc = wscl + q * h.nscale;
+          const int2 za = S->asl >= 0 ? sc[S->asl] : make_int2(0, 0);
+          const int2 zb = S->bsl >= 0 ? sc[S->bsl] : make_int2(0, 0);
+          tree_write_result(t.res + (q0 + wq0 + q), re, im, za, zb);
+        }
+      }
+    } else {
+      tree_step(S, lane, 64, wn, wpq, perq, shr, wscl, h.nscale);
+    }
+  }
+
+  if (!h.final_dot) {
+    const int rl = h.root_loc & ~kPerQuery;
+    for (int w = lane; w < wn * h.root_elems; w += 64) {
+      const int q = w / h.root_elems, i = w - q * h.root_elems;
+      uint8_t *part = h.root_in_perq ? t.perq_base + (int64_t)(q0 + wq0 + q) * t.perq_stride
+                                     : t.shared_base;
+      ((float2 *)(part + h.root_off))[i] = wpq[q * perq + rl + i];
+    }
+    if (lane < wn) {
+      const int q = lane;
+      const int2 z = wscl[q * h.nscale + h.root_scale];
+      Slot *s = h.root_in_perq ? t.slots_q + (int64_t)(q0 + wq0 + q) * t.slot_stride + h.root_slot
+                               : t.slots_sh + h.root_slot;
+      s->log2s = (double)z.x;
+      s->maxbits = (uint32_t)z.y;
+      s->pad = 0u;
+    }
+  }
+}
+
 // LDS a workgroup may use: the device's per-block limit (160 KiB on gfx950),
-// raised for k_tree once.
+// raised for both subtree kernels once.
 size_t tree_lds_limit() {
   static size_t limit = 0;
   if (limit == 0) {
@@ -460,8 +683,10 @@ size_t tree_lds_limit() {
       l = (size_t)v;
     if (l > 163840) l = 163840;
     if (l > 65536 &&
-        hipFuncSetAttribute((const void *)k_tree, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)l) != hipSuccess)
+        (hipFuncSetAttribute((const void *)k_tree, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)l) != hipSuccess ||
+         hipFuncSetAttribute((const void *)k_tree_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)l) != hipSuccess))
       l = 65536;
     limit = l;
   }
@@ -473,6 +698,14 @@ hipError_t launch_tree(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds
   if (lds_bytes > tree_lds_limit()) return hipErrorInvalidValue;
   const int groups = (t.nq + t.qw - 1) / t.qw;
   hipLaunchKernelGGL(k_tree, dim3(nsub, groups), dim3(256), lds_bytes, st, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_wave(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes) {
+  if (nsub <= 0 || t.nq <= 0) return hipSuccess;
+  if (lds_bytes > tree_lds_limit() || t.qw < 1 || t.qw > 16) return hipErrorInvalidValue;
+  const int groups = (t.nq + t.qw - 1) / t.qw;
+  hipLaunchKernelGGL(k_tree_wave, dim3(nsub, groups), dim3(256), lds_bytes, st, t);
   return hipGetLastError();
 }
 
