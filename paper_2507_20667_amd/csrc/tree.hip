@@ -77,19 +77,14 @@ __device__ __forceinline__ void seg2r(const int32_t (&ext)[kTreeSeg], const int3
   }
 }
 
-// A step's result entries are dealt to threads in pairs of items (an item:
-// one result entry, or one fiber, of one query).  Every load of both items
-// (the operands' scale records, the operand entries) is issued before
-// anything is stored: a store to LDS ahead of a load keeps the compiler from
-// moving the load up, and each LDS round trip then costs its full latency.
-// Results, the result's log2 scale (by the thread of entry 0) and the running
-// max |re|/|im| (folded into the scale record with an LDS atomic when a
-// thread moves to another query, and at the end) follow.
-#ifndef TN_TREE_ITEMS
-#define TN_TREE_ITEMS 1
-#endif
-constexpr int kItems = TN_TREE_ITEMS;  // items per thread per pass
-
+// A step's result entries are dealt to threads (an item: one result entry, or
+// one fiber, of one query).  Every load of an item (the operands' scale
+// records, the operand entries) is issued before anything is stored: a store
+// to LDS ahead of a load keeps the compiler from moving the load up, and each
+// LDS round trip then costs its full latency.  The results, the result's log2
+// scale and the running max |re|/|im| (folded into the scale record with an
+// LDS atomic) follow.  ONE: the group holds a single query, so its pointers
+// and operand scales are the same for every item (uniform, computed once).
 struct ItemScale {
   int2 za, zb;
   __device__ __forceinline__ int e() const { return tree_exp((uint32_t)za.y) + tree_exp((uint32_t)zb.y); }
@@ -99,6 +94,16 @@ __device__ __forceinline__ ItemScale item_scale(const int2 *sc, int asl, int bsl
   ItemScale z;
   z.za = asl >= 0 ? sc[asl] : make_int2(0, 0);
   z.zb = bsl >= 0 ? sc[bsl] : make_int2(0, 0);
+  return z;
+}
+
+// The operand scales of a single-query step, read once and made uniform.
+__device__ __forceinline__ ItemScale uniform_scale(const int2 *sc, int asl, int bsl) {
+  ItemScale z = item_scale(sc, asl, bsl);
+  z.za.x = __builtin_amdgcn_readfirstlane(z.za.x);
+  z.za.y = __builtin_amdgcn_readfirstlane(z.za.y);
+  z.zb.x = __builtin_amdgcn_readfirstlane(z.zb.x);
+  z.zb.y = __builtin_amdgcn_readfirstlane(z.zb.y);
   return z;
 }
 
@@ -113,9 +118,9 @@ __device__ __forceinline__ void fold_max(int2 *scl, int nscale, int csl, int q, 
 }
 
 // Kind 2: one thread per fiber of the large operand X (and query) reads the
-// fiber's ns entries once and writes nfy results; the small operand Y is
-// read into registers with the fiber.
-template <bool P2, int NS, int NFY, class SP>
+// fiber's ns entries once and writes nfy results; the small operand Y sits in
+// registers.
+template <bool ONE, bool P2, int NS, int NFY, class SP>
 __device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int nqw, float2 *pq,
                                                  int perq, const float2 *shr, int2 *scl,
                                                  int nscale) {
@@ -137,39 +142,63 @@ __device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int 
   for (int v = 0; v < NFY; ++v) cy[v] = Sp->cy[v];
 #pragma unroll
   for (int v = 0; v < NS * NFY; ++v) ym[v] = Sp->ymap[v];
-  const int total = nqw * nfib;
-  int qprev = -1;
-  float mx = 0.f;
-  for (int w0 = lane; w0 < total; w0 += kItems * nthr) {
-    int qv[kItems], fv[kItems], co[kItems];
-    bool ok[kItems];
-    ItemScale z[kItems];
-    float2 x[kItems][NS], y[kItems][NS * NFY];
+  if constexpr (ONE) {
+    const float2 *X = (a & kPerQuery) ? pq + (a & ~kPerQuery) : shr + a;
+    const float2 *Y = (b & kPerQuery) ? pq + (b & ~kPerQuery) : shr + b;
+    float2 *C = pq + (c & ~kPerQuery);
+    if (lane >= nfib) return;
+    float2 y[NS * NFY];
 #pragma unroll
-    for (int u = 0; u < kItems; ++u) {
-      const int w = w0 + u * nthr;
-      ok[u] = w < total;
-      const int ww = ok[u] ? w : w0;  // a missing second item repeats the first
-      const int q = P2 ? (ww >> lgf) : ww / nfib;
-      qv[u] = q;
-      fv[u] = P2 ? (ww & (nfib - 1)) : ww - mad24(q, nfib, 0);
-      const float2 *base = pq + mad24(q, perq, 0);
+    for (int v = 0; v < NS * NFY; ++v) y[v] = Y[ym[v]];
+    const ItemScale z = uniform_scale(scl, asl, bsl);
+    const int e = z.e();
+    const float f = ldexpf(1.0f, -e);
+    float mx = 0.f;
+    for (int fi = lane; fi < nfib; fi += nthr) {
+      int xo, co;
+      seg2r<P2>(fext, fx, fc, flg, ncs, fi, xo, co);
+      float2 x[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) x[s] = X[xo + xs[s]];
+#pragma unroll
+      for (int j = 0; j < NFY; ++j) {
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const float2 yv = y[s * NFY + j];
+          re = fmaf(x[s].x, yv.x, re);
+          re = fmaf(-x[s].y, yv.y, re);
+          im = fmaf(x[s].x, yv.y, im);
+          im = fmaf(x[s].y, yv.x, im);
+        }
+        re *= f;
+        im *= f;
+        C[co + cy[j]] = make_float2(re, im);
+        mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+      }
+    }
+    if (lane == 0) scl[csl].x = z.za.x + z.zb.x + e;
+    atomicMax((unsigned int *)&scl[csl].y, __float_as_uint(mx));
+  } else {
+    const int total = nqw * nfib;
+    int qprev = -1;
+    float mx = 0.f;
+    for (int w = lane; w < total; w += nthr) {
+      const int q = P2 ? (w >> lgf) : w / nfib;
+      const int fi = P2 ? (w & (nfib - 1)) : w - mad24(q, nfib, 0);
+      float2 *base = pq + mad24(q, perq, 0);
       const float2 *X = (a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a;
       const float2 *Y = (b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b;
-      z[u] = item_scale(scl + mad24(q, nscale, 0), asl, bsl);
-      int xo;
-      seg2r<P2>(fext, fx, fc, flg, ncs, fv[u], xo, co[u]);
+      const ItemScale z = item_scale(scl + mad24(q, nscale, 0), asl, bsl);
+      int xo, co;
+      seg2r<P2>(fext, fx, fc, flg, ncs, fi, xo, co);
+      float2 x[NS], y[NS * NFY];
 #pragma unroll
-      for (int v = 0; v < NS * NFY; ++v) y[u][v] = Y[ym[v]];
+      for (int v = 0; v < NS * NFY; ++v) y[v] = Y[ym[v]];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) x[u][s] = X[xo + xs[s]];
-    }
-#pragma unroll
-    for (int u = 0; u < kItems; ++u) {
-      if (!ok[u]) continue;
-      const int e = z[u].e();
+      for (int s = 0; s < NS; ++s) x[s] = X[xo + xs[s]];
+      const int e = z.e();
       const float f = ldexpf(1.0f, -e);
-      float2 *base = pq + mad24(qv[u], perq, 0);
       float2 *C = base + (c & ~kPerQuery);
       float m = 0.f;
 #pragma unroll
@@ -177,27 +206,76 @@ __device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int 
         float re = 0.f, im = 0.f;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          const float2 yv = y[u][s * NFY + j];
-          re = fmaf(x[u][s].x, yv.x, re);
-          re = fmaf(-x[u][s].y, yv.y, re);
-          im = fmaf(x[u][s].x, yv.y, im);
-          im = fmaf(x[u][s].y, yv.x, im);
+          const float2 yv = y[s * NFY + j];
+          re = fmaf(x[s].x, yv.x, re);
+          re = fmaf(-x[s].y, yv.y, re);
+          im = fmaf(x[s].x, yv.y, im);
+          im = fmaf(x[s].y, yv.x, im);
         }
         re *= f;
         im *= f;
-        C[co[u] + cy[j]] = make_float2(re, im);
+        C[co + cy[j]] = make_float2(re, im);
         m = fmaxf(m, fmaxf(fabsf(re), fabsf(im)));
       }
-      if (fv[u] == 0) scl[mad24(qv[u], nscale, csl)].x = z[u].za.x + z[u].zb.x + e;
-      fold_max(scl, nscale, csl, qv[u], qprev, mx, m);
+      if (fi == 0) scl[mad24(q, nscale, csl)].x = z.za.x + z.zb.x + e;
+      fold_max(scl, nscale, csl, q, qprev, mx, m);
     }
+    if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
   }
-  if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
 }
 
-// Kind 0: one thread per result entry (and query); the shared index is summed
-// four terms at a time for both items of a pair.
-template <bool P2, class SP>
+// The shared index of a kind 0 item summed four terms at a time (offsets of
+// term s in lane s of soa/sob when ns <= 64).
+template <bool P2>
+__device__ __forceinline__ float2 dot_terms(const float2 *A, const float2 *B, int ns, bool stab, int soa,
+                                            int sob, const int32_t (&sext)[kTreeSeg],
+                                            const int32_t (&sa)[kTreeSeg], const int32_t (&sb)[kTreeSeg],
+                                            const int32_t (&slg)[kTreeSeg], int nss) {
+  float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+  if (stab) {
+    int s = 0;
+    for (; s + 4 <= ns; s += 4) {
+      float2 x[4], y[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        x[t] = A[__builtin_amdgcn_readlane(soa, s + t)];
+        y[t] = B[__builtin_amdgcn_readlane(sob, s + t)];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; t += 2) {
+        re0 = fmaf(x[t].x, y[t].x, re0);
+        re0 = fmaf(-x[t].y, y[t].y, re0);
+        im0 = fmaf(x[t].x, y[t].y, im0);
+        im0 = fmaf(x[t].y, y[t].x, im0);
+        re1 = fmaf(x[t + 1].x, y[t + 1].x, re1);
+        re1 = fmaf(-x[t + 1].y, y[t + 1].y, re1);
+        im1 = fmaf(x[t + 1].x, y[t + 1].y, im1);
+        im1 = fmaf(x[t + 1].y, y[t + 1].x, im1);
+      }
+    }
+    for (; s < ns; ++s) {
+      const float2 x = A[__builtin_amdgcn_readlane(soa, s)], y = B[__builtin_amdgcn_readlane(sob, s)];
+      re0 = fmaf(x.x, y.x, re0);
+      re0 = fmaf(-x.y, y.y, re0);
+      im0 = fmaf(x.x, y.y, im0);
+      im0 = fmaf(x.y, y.x, im0);
+    }
+  } else {
+    for (int s = 0; s < ns; ++s) {
+      int oa, ob;
+      seg2r<P2>(sext, sa, sb, slg, nss, s, oa, ob);
+      const float2 x = A[oa], y = B[ob];
+      re0 = fmaf(x.x, y.x, re0);
+      re0 = fmaf(-x.y, y.y, re0);
+      im0 = fmaf(x.x, y.y, im0);
+      im0 = fmaf(x.y, y.x, im0);
+    }
+  }
+  return make_float2(re0 + re1, im0 + im1);
+}
+
+// Kind 0: one thread per result entry (and query).
+template <bool ONE, bool P2, class SP>
 __device__ __forceinline__ void tree_step_impl(SP Sp, int lane, int nthr, int nqw, float2 *pq,
                                                int perq, const float2 *shr, int2 *scl, int nscale) {
   const int a = Sp->a, b = Sp->b, c = Sp->c, asl = Sp->asl, bsl = Sp->bsl, csl = Sp->csl;
@@ -223,117 +301,61 @@ __device__ __forceinline__ void tree_step_impl(SP Sp, int lane, int nthr, int nq
   const bool stab = ns <= 64;
   int soa = 0, sob = 0;
   if (stab && hl < ns) seg2r<P2>(sext, sa, sb, slg, nss, hl, soa, sob);
-  const int total = nqw * nc;
-  int qprev = -1;
-  float mx = 0.f;
-  for (int w0 = lane; w0 < total; w0 += kItems * nthr) {
-    int qv[kItems], cv[kItems];
-    bool ok[kItems];
-    ItemScale z[kItems];
-    const float2 *A[kItems], *B[kItems];
-    float re[kItems][2], im[kItems][2];
-#pragma unroll
-    for (int u = 0; u < kItems; ++u) {
-      const int w = w0 + u * nthr;
-      ok[u] = w < total;
-      const int ww = ok[u] ? w : w0;  // a missing second item repeats the first
-      const int q = P2 ? (ww >> lgnc) : ww / nc;
-      qv[u] = q;
-      cv[u] = P2 ? (ww & (nc - 1)) : ww - mad24(q, nc, 0);
-      const float2 *base = pq + mad24(q, perq, 0);
+  if constexpr (ONE) {
+    const float2 *A0 = (a & kPerQuery) ? pq + (a & ~kPerQuery) : shr + a;
+    const float2 *B0 = (b & kPerQuery) ? pq + (b & ~kPerQuery) : shr + b;
+    float2 *C = pq + (c & ~kPerQuery);
+    if (lane >= nc) return;
+    const ItemScale z = uniform_scale(scl, asl, bsl);
+    const int e = z.e();
+    const float f = ldexpf(1.0f, -e);
+    float mx = 0.f;
+    for (int ci = lane; ci < nc; ci += nthr) {
       int ao, bo;
-      seg2r<P2>(cext, ca, cb, clg, ncs, cv[u], ao, bo);
-      A[u] = ((a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a) + ao;
-      B[u] = ((b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b) + bo;
-      z[u] = item_scale(scl + mad24(q, nscale, 0), asl, bsl);
-      re[u][0] = re[u][1] = im[u][0] = im[u][1] = 0.f;
+      seg2r<P2>(cext, ca, cb, clg, ncs, ci, ao, bo);
+      const float2 r = dot_terms<P2>(A0 + ao, B0 + bo, ns, stab, soa, sob, sext, sa, sb, slg, nss);
+      const float rr = r.x * f, ii = r.y * f;
+      C[ci] = make_float2(rr, ii);
+      mx = fmaxf(mx, fmaxf(fabsf(rr), fabsf(ii)));
     }
-    if (stab) {
-      int s = 0;
-      for (; s + 4 <= ns; s += 4) {
-        float2 x[kItems][4], y[kItems][4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int oa = __builtin_amdgcn_readlane(soa, s + t);
-          const int ob = __builtin_amdgcn_readlane(sob, s + t);
-#pragma unroll
-          for (int u = 0; u < kItems; ++u) {
-            x[u][t] = A[u][oa];
-            y[u][t] = B[u][ob];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kItems; ++u)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int r = t & 1;
-            re[u][r] = fmaf(x[u][t].x, y[u][t].x, re[u][r]);
-            re[u][r] = fmaf(-x[u][t].y, y[u][t].y, re[u][r]);
-            im[u][r] = fmaf(x[u][t].x, y[u][t].y, im[u][r]);
-            im[u][r] = fmaf(x[u][t].y, y[u][t].x, im[u][r]);
-          }
-      }
-      for (; s < ns; ++s) {
-        const int oa = __builtin_amdgcn_readlane(soa, s), ob = __builtin_amdgcn_readlane(sob, s);
-        float2 x[kItems], y[kItems];
-#pragma unroll
-        for (int u = 0; u < kItems; ++u) {
-          x[u] = A[u][oa];
-          y[u] = B[u][ob];
-        }
-#pragma unroll
-        for (int u = 0; u < kItems; ++u) {
-          re[u][0] = fmaf(x[u].x, y[u].x, re[u][0]);
-          re[u][0] = fmaf(-x[u].y, y[u].y, re[u][0]);
-          im[u][0] = fmaf(x[u].x, y[u].y, im[u][0]);
-          im[u][0] = fmaf(x[u].y, y[u].x, im[u][0]);
-        }
-      }
-    } else {
-      for (int s = 0; s < ns; ++s) {
-        int oa, ob;
-        seg2r<P2>(sext, sa, sb, slg, nss, s, oa, ob);
-        float2 x[kItems], y[kItems];
-#pragma unroll
-        for (int u = 0; u < kItems; ++u) {
-          x[u] = A[u][oa];
-          y[u] = B[u][ob];
-        }
-#pragma unroll
-        for (int u = 0; u < kItems; ++u) {
-          re[u][0] = fmaf(x[u].x, y[u].x, re[u][0]);
-          re[u][0] = fmaf(-x[u].y, y[u].y, re[u][0]);
-          im[u][0] = fmaf(x[u].x, y[u].y, im[u][0]);
-          im[u][0] = fmaf(x[u].y, y[u].x, im[u][0]);
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kItems; ++u) {
-      if (!ok[u]) continue;
-      const int e = z[u].e();
+    if (lane == 0) scl[csl].x = z.za.x + z.zb.x + e;
+    atomicMax((unsigned int *)&scl[csl].y, __float_as_uint(mx));
+  } else {
+    const int total = nqw * nc;
+    int qprev = -1;
+    float mx = 0.f;
+    for (int w = lane; w < total; w += nthr) {
+      const int q = P2 ? (w >> lgnc) : w / nc;
+      const int ci = P2 ? (w & (nc - 1)) : w - mad24(q, nc, 0);
+      float2 *base = pq + mad24(q, perq, 0);
+      int ao, bo;
+      seg2r<P2>(cext, ca, cb, clg, ncs, ci, ao, bo);
+      const float2 *A = ((a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a) + ao;
+      const float2 *B = ((b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b) + bo;
+      const ItemScale z = item_scale(scl + mad24(q, nscale, 0), asl, bsl);
+      const float2 r = dot_terms<P2>(A, B, ns, stab, soa, sob, sext, sa, sb, slg, nss);
+      const int e = z.e();
       const float f = ldexpf(1.0f, -e);
-      const float rr = (re[u][0] + re[u][1]) * f, ii = (im[u][0] + im[u][1]) * f;
-      float2 *C = pq + mad24(qv[u], perq, c & ~kPerQuery);
-      C[cv[u]] = make_float2(rr, ii);
-      if (cv[u] == 0) scl[mad24(qv[u], nscale, csl)].x = z[u].za.x + z[u].zb.x + e;
-      fold_max(scl, nscale, csl, qv[u], qprev, mx, fmaxf(fabsf(rr), fabsf(ii)));
+      const float rr = r.x * f, ii = r.y * f;
+      base[(c & ~kPerQuery) + ci] = make_float2(rr, ii);
+      if (ci == 0) scl[mad24(q, nscale, csl)].x = z.za.x + z.zb.x + e;
+      fold_max(scl, nscale, csl, q, qprev, mx, fmaxf(fabsf(rr), fabsf(ii)));
     }
+    if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
   }
-  if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
 }
 
 // One contraction for every query of the group, by `nthr` threads starting at
 // `lane`.  The step's maps live in registers; each thread keeps the running
 // max of its results per query and folds it into the scale record once per
 // query.
-template <class SP>
-__device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
-                                          const float2 *shr, int2 *scl, int nscale) {
+template <bool ONE, class SP>
+__device__ __forceinline__ void tree_step_q(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
+                                            const float2 *shr, int2 *scl, int nscale) {
   if (Sp->kind == 2) {
     // a small operand along the fibers of a large one: ns, nfy in {1, 2, 4}
     const int sel = (Sp->ns >> 1) * 3 + (Sp->nss >> 1) + (Sp->pow2 ? 0 : 9);
-#define TN_TS(P, A, B) tree_stream_impl<P, A, B>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale)
+#define TN_TS(P, A, B) tree_stream_impl<ONE, P, A, B>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale)
     switch (sel) {
       case 0: TN_TS(true, 1, 1); break;
       case 1: TN_TS(true, 1, 2); break;
@@ -358,9 +380,18 @@ __device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, fl
     return;
   }
   if (Sp->pow2)
-    tree_step_impl<true>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale);
+    tree_step_impl<ONE, true>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale);
   else
-    tree_step_impl<false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale);
+    tree_step_impl<ONE, false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale);
+}
+
+template <class SP>
+__device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
+                                          const float2 *shr, int2 *scl, int nscale) {
+  if (nqw == 1)
+    tree_step_q<true>(Sp, lane, nthr, 1, pq, perq, shr, scl, nscale);
+  else
+    tree_step_q<false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale);
 }
 
 // Closed root of one query: the FP64 inner product and its result record
