@@ -80,6 +80,18 @@ static void to_c64(const tn_leaf &l, int64_t n, float2 *dst) {
   }
 }
 
+// 2^e as a double: built from its bits in the normal range (multiplying by it
+// is exact there, as ldexp is), ldexp outside it
+static inline double pow2i(int e) {
+  if (e >= -1022 && e <= 1023) {
+    const uint64_t b = (uint64_t)(e + 1023) << 52;
+    double d;
+    memcpy(&d, &b, sizeof d);
+    return d;
+  }
+  return std::ldexp(1.0, e);
+}
+
 static void write_out(void *out, tn_dtype dt, size_t i, double re, double im) {
   if (dt == TN_C128) {
     ((double *)out)[2 * i] = re;
@@ -749,8 +761,13 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
             write_out(q.out, out_dtype, 0, r.re, r.im);
             if (q.log2s) *q.log2s = r.log2s;
           } else {
-            write_out(q.out, out_dtype, 0, std::ldexp(r.re, (int)r.log2s),
-                      std::ldexp(r.im, (int)r.log2s));
+            const int e = (int)r.log2s;
+            if (e >= -1022 && e <= 1023) {
+              const double sc = pow2i(e);
+              write_out(q.out, out_dtype, 0, r.re * sc, r.im * sc);
+            } else {
+              write_out(q.out, out_dtype, 0, std::ldexp(r.re, e), std::ldexp(r.im, e));
+            }
             if (q.log2s) *q.log2s = 0.0;
           }
         } else {
@@ -768,6 +785,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         }
         if (q.status) *q.status = TN_OK;
       }
+      if (dbg) fprintf(stderr, "[tn] run_group results written at %.3f ms\n", ms_since(t_enter));
     }
   done:
     if (capturing) {  // an error while capturing: end the capture, keep nothing

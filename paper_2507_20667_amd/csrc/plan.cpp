@@ -1325,6 +1325,23 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     if (bytes) memcpy(L.tree_blob.data() + off, src, bytes);
     return off;
   };
+  // device form of the steps (after the checks above, which read the plain
+  // form): power-of-two maps carry their masks (extent - 1) and the kind 2
+  // offsets are in bytes, which saves the kernels that arithmetic per step
+  for (TreeStep &st : steps) {
+    if (st.pow2) {
+      for (int i = 0; i < st.ncs; ++i) st.cext[i] -= 1;
+      if (st.kind != 2)
+        for (int i = 0; i < st.nss; ++i) st.sext[i] -= 1;
+    }
+    if (st.kind == 2) {
+      for (int v = 0; v < 4; ++v) {
+        st.xs[v] *= 8;
+        st.cy[v] *= 8;
+      }
+      for (int v = 0; v < 16; ++v) st.ymap[v] *= 8;
+    }
+  }
   put(hdrs.data(), hdrs.size() * sizeof(TreeHdr));
   L.tree_chunk_off = put(chunks.data(), chunks.size() * sizeof(TreeChunk));
   L.tree_step_off = put(steps.data(), steps.size() * sizeof(TreeStep));

@@ -50,10 +50,19 @@ __device__ __forceinline__ int tree_exp(uint32_t bits) {
 // Index arithmetic: every offset, stride and index of a subtree is far below
 // 2^24, so the full-rate 24-bit multiply-add serves (the 32-bit integer
 // multiply runs at a quarter of the rate).
-__device__ __forceinline__ int mad24(int a, int b, int c) { return (int)__umul24((unsigned)a, (unsigned)b) + c; }
+__device__ __forceinline__ int mad24(int a, int b, int c) {
+  __builtin_assume((unsigned)a < (1u << 24));
+  __builtin_assume((unsigned)b < (1u << 24));
+  return (int)__umul24((unsigned)a, (unsigned)b) + c;
+}
+
+// entry at a byte offset from p
+__device__ __forceinline__ const float2 &at_bytes(const float2 *p, int bytes) {
+  return *(const float2 *)((const char *)p + bytes);
+}
 
 // Decode with the map held in registers (unrolled over kTreeSeg); P2: every
-// extent a power of two (shifts and masks instead of divisions).
+// extent a power of two, and `ext` holds the masks (extent - 1).
 template <bool P2>
 __device__ __forceinline__ void seg2r(const int32_t (&ext)[kTreeSeg], const int32_t (&s0)[kTreeSeg],
                                       const int32_t (&s1)[kTreeSeg], const int32_t (&lg)[kTreeSeg],
@@ -65,7 +74,7 @@ __device__ __forceinline__ void seg2r(const int32_t (&ext)[kTreeSeg], const int3
     if (i < nseg) {
       int v;
       if (P2) {
-        v = idx & (ext[i] - 1);
+        v = idx & ext[i];
         idx >>= lg[i];
       } else {
         v = idx % ext[i];
@@ -149,7 +158,7 @@ __device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int 
     if (lane >= nfib) return;
     float2 y[NS * NFY];
 #pragma unroll
-    for (int v = 0; v < NS * NFY; ++v) y[v] = Y[ym[v]];
+    for (int v = 0; v < NS * NFY; ++v) y[v] = at_bytes(Y, ym[v]);
     const ItemScale z = uniform_scale(scl, asl, bsl);
     const int e = z.e();
     const float f = ldexpf(1.0f, -e);
@@ -159,7 +168,7 @@ __device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int 
       seg2r<P2>(fext, fx, fc, flg, ncs, fi, xo, co);
       float2 x[NS];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) x[s] = X[xo + xs[s]];
+      for (int s = 0; s < NS; ++s) x[s] = at_bytes(X + xo, xs[s]);
 #pragma unroll
       for (int j = 0; j < NFY; ++j) {
         float re = 0.f, im = 0.f;
@@ -173,7 +182,7 @@ __device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int 
         }
         re *= f;
         im *= f;
-        C[co + cy[j]] = make_float2(re, im);
+        *(float2 *)((char *)(C + co) + cy[j]) = make_float2(re, im);
         mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
       }
     }
@@ -194,9 +203,9 @@ __device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int 
       seg2r<P2>(fext, fx, fc, flg, ncs, fi, xo, co);
       float2 x[NS], y[NS * NFY];
 #pragma unroll
-      for (int v = 0; v < NS * NFY; ++v) y[v] = Y[ym[v]];
+      for (int v = 0; v < NS * NFY; ++v) y[v] = at_bytes(Y, ym[v]);
 #pragma unroll
-      for (int s = 0; s < NS; ++s) x[s] = X[xo + xs[s]];
+      for (int s = 0; s < NS; ++s) x[s] = at_bytes(X + xo, xs[s]);
       const int e = z.e();
       const float f = ldexpf(1.0f, -e);
       float2 *C = base + (c & ~kPerQuery);
@@ -214,7 +223,7 @@ __device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int 
         }
         re *= f;
         im *= f;
-        C[co + cy[j]] = make_float2(re, im);
+        *(float2 *)((char *)(C + co) + cy[j]) = make_float2(re, im);
         m = fmaxf(m, fmaxf(fabsf(re), fabsf(im)));
       }
       if (fi == 0) scl[mad24(q, nscale, csl)].x = z.za.x + z.zb.x + e;
