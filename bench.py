@@ -215,9 +215,9 @@ def serve_bench(lib, ctx, seconds, rate, flags, seed=0):
                 planning_s=plan_s)
 
 
-KERNEL_SOURCES = {"tree": "tree.hip", "stream": "kernels.hip", "permute": "kernels.hip",
-                  "dot": "kernels.hip", "gemm": "kernels.hip"}
-KERNEL_NAMES = {"tree": "k_tree"}
+KERNEL_SOURCES = {"tree": "tree.hip", "tree_batch": "tree.hip", "stream": "kernels.hip",
+                  "permute": "kernels.hip", "dot": "kernels.hip", "gemm": "kernels.hip"}
+KERNEL_NAMES = {"tree": "k_tree", "tree_batch": "k_tree_wave"}
 
 
 def measured_traffic(cls, launches):
@@ -248,7 +248,7 @@ def roofline(stats, prec):
         achieved = ds["algo_flops"] / ds["seconds"] / 1e12
         peak = MFMA_PEAK_TFLOPS[prec]
         roof = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s")
-    elif dom == "tree":
+    elif dom in ("tree", "tree_batch"):
         # every intermediate stays in LDS: its bound is arithmetic, not HBM
         achieved = ds["algo_flops"] / ds["seconds"] / 1e12
         peak = FP32_VECTOR_PEAK_TFLOPS

@@ -284,8 +284,11 @@ enum {
   TN_KCLASS_PERMUTE = 1,  /* leg permutation */
   TN_KCLASS_GEMM = 2,     /* complex GEMM */
   TN_KCLASS_DOT = 3,      /* FP64 inner product */
-  TN_KCLASS_TREE = 4,     /* whole small subtrees in one workgroup */
-  TN_KCLASS_COUNT = 5
+  TN_KCLASS_TREE = 4,     /* whole small subtrees in one workgroup: one query
+                             per launch (the shared subtrees, single queries) */
+  TN_KCLASS_TREE_BATCH = 5, /* the same for a batch of queries, every wave
+                               taking its own queries through the subtree */
+  TN_KCLASS_COUNT = 6
 };
 typedef struct {
   uint64_t launches;

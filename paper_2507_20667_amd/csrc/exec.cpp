@@ -584,7 +584,8 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           const bool wave = L.tree_wave && Q > 1, single = L.tree_wave && Q == 1;
           tl.qw = single ? 1 : L.tree_qw;
           const size_t lds = single ? L.lds_perq1 : L.lds_perq;
-          TN_HIP(prof.timed(st, TN_KCLASS_TREE, tree_bytes_q * Q, tree_flops_q * Q,
+          TN_HIP(prof.timed(st, wave ? TN_KCLASS_TREE_BATCH : TN_KCLASS_TREE, tree_bytes_q * Q,
+                            tree_flops_q * Q,
                             [&] {
                               return wave ? launch_tree_wave(st, tl, L.n_tree_perq, lds)
                                           : launch_tree(st, tl, L.n_tree_perq, lds);

@@ -327,7 +327,7 @@ class Context:
 
 # ------------------------------------------------------------------ timing
 
-KCLASS_NAMES = ["stream", "permute", "gemm", "dot", "tree"]
+KCLASS_NAMES = ["stream", "permute", "gemm", "dot", "tree", "tree_batch"]
 
 
 class tn_kernel_stats(ctypes.Structure):

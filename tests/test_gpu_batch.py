@@ -151,7 +151,9 @@ def test_profile_counts_subtree_kernel(ctx):
                           [()] * len(xs))
     stats = lib.tn_profile_read(ctx.handle, reset=True)
     lib.tn_profile_enable(ctx.handle, False)
+    # one launch for the shared subtrees, one for the batch of 16 queries
     assert stats["tree"]["launches"] >= 1 and stats["tree"]["seconds"] > 0
+    assert stats["tree_batch"]["launches"] >= 1 and stats["tree_batch"]["seconds"] > 0
     ctx.free_plan(p)
 
 
