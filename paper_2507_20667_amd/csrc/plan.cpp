@@ -1227,6 +1227,10 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
           for (int v = 0; v < nfy; ++v) mc = std::max<int64_t>(mc, st.cy[v]);
           for (int v = 0; v < ns * nfy; ++v) my = std::max<int64_t>(my, st.ymap[v]);
           const bool neg = std::min({st.xs[0], st.cy[0], st.ymap[0]}) < 0;
+          // Y's shared and free legs are apart: ymap[s nfy + j] = ymap[s nfy] + ymap[j] - ymap[0]
+          for (int a = 0; a < ns; ++a)
+            for (int b = 0; b < nfy; ++b)
+              ok = ok && st.ymap[a * nfy + b] == st.ymap[a * nfy] + st.ymap[b] - st.ymap[0];
           int64_t fib = 1;
           for (int i = 0; i < st.ncs; ++i) fib *= st.cext[i];
           ok = ok && !neg && fib * nfy == st.nc && inside(st.a, reach(st.cext, st.ca, st.ncs) + mx) &&

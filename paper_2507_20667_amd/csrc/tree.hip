@@ -155,6 +155,46 @@ __device__ __forceinline__ void tree_stream_impl(SP Sp, int lane, int nthr, int 
     const float2 *X = (a & kPerQuery) ? pq + (a & ~kPerQuery) : shr + a;
     const float2 *Y = (b & kPerQuery) ? pq + (b & ~kPerQuery) : shr + b;
     float2 *C = pq + (c & ~kPerQuery);
+    if (NFY > 1 && nfib * NFY <= nthr) {
+      // one result per thread, thread (fiber, j): a quarter (half) of the
+      // multiply-adds, loads and stores per thread of a fiber's nfy results.
+      // Y's shared and free legs are apart, so ymap[s * nfy + j] =
+      // ymap[s * nfy] + (ymap[j] - ymap[0]).
+      if (lane >= nfib * NFY) return;
+      const int j = lane & (NFY - 1), fi = lane >> (NFY == 4 ? 2 : 1);
+      int dj = 0, cj = cy[0];
+#pragma unroll
+      for (int v = 1; v < NFY; ++v)
+        if (j == v) {
+          dj = ym[v] - ym[0];
+          cj = cy[v];
+        }
+      int xo, co;
+      seg2r<P2>(fext, fx, fc, flg, ncs, fi, xo, co);
+      float2 x[NS], yv[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        x[s] = at_bytes(X + xo, xs[s]);
+        yv[s] = at_bytes(Y, ym[s * NFY] + dj);
+      }
+      const ItemScale z = uniform_scale(scl, asl, bsl);
+      const int e = z.e();
+      const float f = ldexpf(1.0f, -e);
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        re = fmaf(x[s].x, yv[s].x, re);
+        re = fmaf(-x[s].y, yv[s].y, re);
+        im = fmaf(x[s].x, yv[s].y, im);
+        im = fmaf(x[s].y, yv[s].x, im);
+      }
+      re *= f;
+      im *= f;
+      *(float2 *)((char *)(C + co) + cj) = make_float2(re, im);
+      if (lane == 0) scl[csl].x = z.za.x + z.zb.x + e;
+      atomicMax((unsigned int *)&scl[csl].y, __float_as_uint(fmaxf(fabsf(re), fabsf(im))));
+      return;
+    }
     if (lane >= nfib) return;
     float2 y[NS * NFY];
 #pragma unroll

@@ -359,3 +359,31 @@ def test_batch_open_legs_each_query(ctx):
                                  net.output_legs)
         assert np.max(np.abs(outs[i] - r)) / max(float(np.max(np.abs(r))), 2.0 ** -7) < TOL
     ctx.free_plan(p)
+
+
+@pytest.mark.parametrize("qw", [None, "8", "6"])
+def test_batch_sizes_and_query_grouping(ctx, qw, monkeypatch):
+    """Batches of 1 to 13 queries: workgroups with fewer queries than waves,
+    a last workgroup partly filled, and (through the queries-per-workgroup
+    override, read when a plan's layout is built) waves that take two queries
+    each; every amplitude against the oracle."""
+    if qw is None:
+        monkeypatch.delenv("TN_TREE_QW", raising=False)
+    else:
+        monkeypatch.setenv("TN_TREE_QW", qw)
+    circ = brickwork_circuit(14, 8, 5)
+    net = amplitude_network(circ, 0)
+    plan = _plan(net, 3)
+    p = ctx.load_network(net, plan.partition_of, 3, plan.tree)
+    xs_all = random_bitstrings(circ.n, 31, 7)
+    off = 0
+    for q in (1, 2, 3, 5, 7, 13):
+        xs = xs_all[off:off + q]
+        off += q
+        queries = [(p, amplitude_overrides(net, circ, x)) for x in xs]
+        outs, _, st = lib.tn_contract_batch(ctx.handle, queries, [()] * len(xs))
+        assert np.all(st == 0)
+        for x, o in zip(xs, outs):
+            e = err(o, _ref(net, plan, amplitude_overrides(net, circ, x)), circ.n)
+            assert e < TOL, (qw, q, x, o)
+    ctx.free_plan(p)
