@@ -1212,6 +1212,10 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       next += chunks[c].nsteps;
     }
     ok = ok && next == h.step0 + h.nsteps && h.step0 >= 0 && h.step0 + h.nsteps <= (int32_t)steps.size();
+    // a subtree ending in the closed root has it as its last step (the batch
+    // kernel runs that step after its loop)
+    ok = ok && h.nsteps >= 1 &&
+         (steps[h.step0 + h.nsteps - 1].kind == 1) == (h.final_dot != 0);
     for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c) {
       ok = ok && chunks[c].nsteps >= 1 && chunks[c].nsteps <= kTreeChunk;
       for (int k = chunks[c].step0; k < chunks[c].step0 + chunks[c].nsteps; ++k) {

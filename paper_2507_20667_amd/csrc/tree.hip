@@ -661,20 +661,30 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const TreeHdr h = t.hdr[blockIdx.x];
+  const TreeHdr *hp = t.hdr + blockIdx.x;
   const int qw = t.qw;
   const int qpw = (qw + 3) >> 2;
   const int q0 = blockIdx.y * qw;
   const int nqw = min(qw, t.nq - q0);
   KernargLaunch ka = (KernargLaunch)__builtin_amdgcn_kernarg_segment_ptr();
 
-  // LDS: [scales: qw * nscale int2][shared region][qw per-query regions]
-  int2 *scl = (int2 *)tree_lds;
-  float2 *shr = (float2 *)(scl + ((qw * h.nscale + 1) & ~1));
-  float2 *pq = shr + ((h.shared_elems + 1) & ~1);
-  const int perq = (h.perq_elems + 1) & ~1;
-
-  tree_prologue(t, ka, h, tid, qw, nqw, q0, scl, shr, pq, perq);
+  int nscale, nsteps, step0, final_dot;
+  int2 *scl;
+  float2 *shr, *pq;
+  int perq;
+  {
+    const TreeHdr h = *hp;
+    nscale = h.nscale;
+    nsteps = h.nsteps;
+    step0 = h.step0;
+    final_dot = h.final_dot;
+    // LDS: [scales: qw * nscale int2][shared region][qw per-query regions]
+    scl = (int2 *)tree_lds;
+    shr = (float2 *)(scl + ((qw * h.nscale + 1) & ~1));
+    pq = shr + ((h.shared_elems + 1) & ~1);
+    perq = (h.perq_elems + 1) & ~1;
+    tree_prologue(t, ka, h, tid, qw, nqw, q0, scl, shr, pq, perq);
+  }
   __syncthreads();
 
   // this wave's queries: [wq0, wq0 + wn) of the workgroup's
@@ -682,71 +692,74 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
   const int wn = min(qpw, nqw - wq0);
   if (wn <= 0) return;
   float2 *wpq = pq + wq0 * perq;
-  int2 *wscl = scl + wq0 * h.nscale;
-  const CStep prog = (CStep)t.steps + h.step0;
-  for (int k = 0; k < h.nsteps; ++k) {
-    const CStep S = prog + k;
-    if (S->kind == 1) {
-      // closed root: FP64 inner product, reduced across the wave
-      const bool p2 = S->pow2 != 0;
-      const int ns = S->ns, nss = S->nss, a = S->a, b = S->b;
-      int32_t ext[kTreeSeg], s0[kTreeSeg], s1[kTreeSeg], lg[kTreeSeg];
-#pragma unroll
-      for (int i = 0; i < kTreeSeg; ++i) {
-        ext[i] = S->sext[i];
-        s0[i] = S->sa[i];
-        s1[i] = S->sb[i];
-        lg[i] = S->slg[i];
-      }
-      for (int q = 0; q < wn; ++q) {
-        float2 *base = wpq + q * perq;
-        const float2 *A = (a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a;
-        const float2 *B = (b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b;
-        double re = 0.0, im = 0.0;
-        for (int s = lane; s < ns; s += 64) {
-          int sa, sb;
-          if (p2)
-            seg2r<true>(ext, s0, s1, lg, nss, s, sa, sb);
-          else
-            seg2r<false>(ext, s0, s1, lg, nss, s, sa, sb);
-          const float2 x = A[sa], y = B[sb];
-          re += (double)x.x * y.x - (double)x.y * y.y;
-          im += (double)x.x * y.y + (double)x.y * y.x;
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          re += __shfl_xor(re, off, 64);
-          im += __shfl_xor(im, off, 64);
-        }
-        if (lane == 0) {
-          const int2 *sc = wscl + q * h.nscale;
-          const int2 za = S->asl >= 0 ? sc[S->asl] : make_int2(0, 0);
-          const int2 zb = S->bsl >= 0 ? sc[S->bsl] : make_int2(0, 0);
-          tree_write_result(t.res + (q0 + wq0 + q), re, im, za, zb);
-        }
-      }
-    } else {
-      tree_step(S, lane, 64, wn, wpq, perq, shr, wscl, h.nscale);
-    }
-  }
+  int2 *wscl = scl + wq0 * nscale;
+  const CStep prog = (CStep)t.steps + step0;
+  // a closed root is the program's last step (checked on the host): it runs
+  // after the loop
+  const int nloop = nsteps - (final_dot ? 1 : 0);
+  for (int k = 0; k < nloop; ++k) tree_step(prog + k, lane, 64, wn, wpq, perq, shr, wscl, nscale);
 
-  if (!h.final_dot) {
-    const int rl = h.root_loc & ~kPerQuery;
-    for (int w = lane; w < wn * h.root_elems; w += 64) {
-      const int q = w / h.root_elems, i = w - q * h.root_elems;
-      uint8_t *part = h.root_in_perq ? t.perq_base + (int64_t)(q0 + wq0 + q) * t.perq_stride
-                                     : t.shared_base;
-      ((float2 *)(part + h.root_off))[i] = wpq[q * perq + rl + i];
+  if (final_dot) {
+    // closed root: FP64 inner product, reduced across the wave
+    const CStep S = prog + nloop;
+    const bool p2 = S->pow2 != 0;
+    const int ns = S->ns, nss = S->nss, a = S->a, b = S->b;
+    int32_t ext[kTreeSeg], s0[kTreeSeg], s1[kTreeSeg], lg[kTreeSeg];
+#pragma unroll
+    for (int i = 0; i < kTreeSeg; ++i) {
+      ext[i] = S->sext[i];
+      s0[i] = S->sa[i];
+      s1[i] = S->sb[i];
+      lg[i] = S->slg[i];
     }
-    if (lane < wn) {
-      const int q = lane;
-      const int2 z = wscl[q * h.nscale + h.root_scale];
-      Slot *s = h.root_in_perq ? t.slots_q + (int64_t)(q0 + wq0 + q) * t.slot_stride + h.root_slot
-                               : t.slots_sh + h.root_slot;
-      s->log2s = (double)z.x;
-      s->maxbits = (uint32_t)z.y;
-      s->pad = 0u;
+    for (int q = 0; q < wn; ++q) {
+      float2 *base = wpq + q * perq;
+      const float2 *A = (a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a;
+      const float2 *B = (b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b;
+      double re = 0.0, im = 0.0;
+      for (int s = lane; s < ns; s += 64) {
+        int sa, sb;
+        if (p2)
+          seg2r<true>(ext, s0, s1, lg, nss, s, sa, sb);
+        else
+          seg2r<false>(ext, s0, s1, lg, nss, s, sa, sb);
+        const float2 x = A[sa], y = B[sb];
+        re += (double)x.x * y.x - (double)x.y * y.y;
+        im += (double)x.x * y.y + (double)x.y * y.x;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 64);
+        im += __shfl_xor(im, off, 64);
+      }
+      if (lane == 0) {
+        const int2 *sc = wscl + q * nscale;
+        const int2 za = S->asl >= 0 ? sc[S->asl] : make_int2(0, 0);
+        const int2 zb = S->bsl >= 0 ? sc[S->bsl] : make_int2(0, 0);
+        tree_write_result(t.res + (q0 + wq0 + q), re, im, za, zb);
+      }
     }
+    return;
+  }
+  // the subtree's result and its scale record to device memory (the header
+  // fields read again here rather than kept through the loop)
+  const volatile TreeHdr *vh = hp;
+  const int root_elems = vh->root_elems, rl = vh->root_loc & ~kPerQuery, in_perq = vh->root_in_perq;
+  const int64_t root_off = vh->root_off;
+  const int root_scale = vh->root_scale, root_slot = vh->root_slot;
+  for (int w = lane; w < wn * root_elems; w += 64) {
+    const int q = w / root_elems, i = w - q * root_elems;
+    uint8_t *part = in_perq ? t.perq_base + (int64_t)(q0 + wq0 + q) * t.perq_stride : t.shared_base;
+    ((float2 *)(part + root_off))[i] = wpq[q * perq + rl + i];
+  }
+  if (lane < wn) {
+    const int q = lane;
+    const int2 z = wscl[q * nscale + root_scale];
+    Slot *sl = in_perq ? t.slots_q + (int64_t)(q0 + wq0 + q) * t.slot_stride + root_slot
+                       : t.slots_sh + root_slot;
+    sl->log2s = (double)z.x;
+    sl->maxbits = (uint32_t)z.y;
+    sl->pad = 0u;
   }
 }
 
