@@ -1338,6 +1338,19 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   // offsets are in bytes, which saves the kernels that arithmetic per step
   for (TreeStep &st : steps) {
     if (st.pow2) {
+      // the kernels run every segment of a power-of-two map: the unused ones
+      // must be all zero (mask, shift and strides)
+      for (int i = st.ncs; i < kTreeSeg; ++i)
+        if (st.cext[i] | st.ca[i] | st.cb[i] | st.clg[i]) {
+          L.tree_error = true;
+          return;
+        }
+      if (st.kind != 2)
+        for (int i = st.nss; i < kTreeSeg; ++i)
+          if (st.sext[i] | st.sa[i] | st.sb[i] | st.slg[i]) {
+            L.tree_error = true;
+            return;
+          }
       for (int i = 0; i < st.ncs; ++i) st.cext[i] -= 1;
       if (st.kind != 2)
         for (int i = 0; i < st.nss; ++i) st.sext[i] -= 1;

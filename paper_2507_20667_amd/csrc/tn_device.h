@@ -146,8 +146,8 @@ constexpr int kTreeMaxOvr = 64;    // overridden leaves read in place per launch
 // values) and j < nfy: C[cb(f) + cy[j]] = sum_{s < ns} X[ca(f) + xs[s]] *
 // Y[ymap[s * nfy + j]], with ns, nfy in {1, 2, 4}.
 // In the copy the kernels read, a map whose extents are all powers of two
-// (pow2) holds extent - 1 (the mask) in place of each extent, and xs, cy and
-// ymap are byte offsets.
+// (pow2) holds extent - 1 (the mask) in place of each extent and zeros in its
+// unused segments, and xs, cy and ymap are byte offsets.
 struct TreeStep {
   int32_t a, b, c;        // LDS locations of the operands and the result
   int32_t asl, bsl, csl;  // scale index of each (-1: a leaf, scale 1)

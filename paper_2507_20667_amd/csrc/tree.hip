@@ -71,7 +71,10 @@ __device__ __forceinline__ void seg2r(const int32_t (&ext)[kTreeSeg], const int3
   o1 = 0;
 #pragma unroll
   for (int i = 0; i < kTreeSeg; ++i) {
-    if (i < nseg) {
+    // power-of-two maps run every segment: an unused one has mask, shift and
+    // strides 0 and adds nothing, which spares the scalar unit a test per
+    // segment
+    if (P2 || i < nseg) {
       int v;
       if (P2) {
         v = idx & ext[i];
