@@ -37,14 +37,6 @@ typedef float v16f_b __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int slot_exp_b(uint32_t bits) {
-  if (bits == 0u) return 0;
-  const int e = (int)((bits >> 23) & 0xffu);
-  if (e == 0xff) return 0;
-  if (e == 0) return -126;
-  return e - 127;
-}
-
 constexpr int BT = 128;     // tile rows (M) and columns (N)
 constexpr int BKS = 32;     // k per stage
 constexpr int ROWE = BKS;   // bf16 per LDS row (no padding: swizzled chunks)
@@ -120,7 +112,7 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
   const int64_t m0 = (t % g.tiles_m) * BT, n0 = (t / g.tiles_m) * BT;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
-  const int ea = slot_exp_b(sa->maxbits), eb = slot_exp_b(sb->maxbits);
+  const int ea = tn_scale_exp(sa->maxbits), eb = tn_scale_exp(sb->maxbits);
   if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
 
   v16f_b acc[2][2][NACC];
@@ -358,7 +350,7 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
   const int64_t m0 = (t % g.tiles_m) * BT, n0 = (t / g.tiles_m) * BT;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
-  const int ea = slot_exp_b(sa->maxbits), eb = slot_exp_b(sb->maxbits);
+  const int ea = tn_scale_exp(sa->maxbits), eb = tn_scale_exp(sb->maxbits);
   if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
 
   v16f_b acc[2][2][2];

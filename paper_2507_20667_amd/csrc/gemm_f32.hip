@@ -40,14 +40,6 @@ constexpr int FBK = 16;               // k per stage
 constexpr int FPLANE = FT * FBK;      // floats per plane tile (8 KB)
 constexpr int FSTAGE = 4 * FPLANE;    // A re, A im, B re, B im (32 KB)
 
-__device__ __forceinline__ int slot_exp_f(uint32_t bits) {
-  if (bits == 0u) return 0;
-  const int e = (int)((bits >> 23) & 0xffu);
-  if (e == 0xff) return 0;
-  if (e == 0) return -126;
-  return e - 127;
-}
-
 // (b3 ^ b1, b2) of the row index: rows r..r+15 cover every (r % 4, chunk)
 // pair and rows r..r+7 every (r % 2, chunk) pair once
 __device__ __forceinline__ int fswz(int r) {
@@ -74,7 +66,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
   const int64_t m0 = (t % g.tiles_m) * FT, n0 = (t / g.tiles_m) * FT;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
-  const int ea = slot_exp_f(sa->maxbits), eb = slot_exp_f(sb->maxbits);
+  const int ea = tn_scale_exp(sa->maxbits), eb = tn_scale_exp(sb->maxbits);
   if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
 
   v16f_c acc[2][2][NACC];

@@ -17,14 +17,6 @@ namespace tn {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ int slot_exp(uint32_t bits) {
-  if (bits == 0u) return 0;
-  const int e = (int)((bits >> 23) & 0xffu);
-  if (e == 0xff) return 0;
-  if (e == 0) return -126;
-  return e - 127;
-}
-
 __device__ __forceinline__ void wave_atomic_max(uint32_t *p, float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
@@ -108,7 +100,7 @@ __global__ __launch_bounds__(256) void k_stream(const StreamDesc *__restrict__ d
   const int ns = d->ns, nfy = d->nfy, nseg = d->fib.nseg;
   const bool p2 = d->fib.pow2 != 0;
   const int64_t nfib = d->nfib;
-  const int ex = slot_exp(xsl->maxbits), ey = slot_exp(ysl->maxbits);
+  const int ex = tn_scale_exp(xsl->maxbits), ey = tn_scale_exp(ysl->maxbits);
   const float fx = ldexpf(1.0f, -ex), fy = ldexpf(1.0f, -ey);
   if (tid < ns * nfy) {
     const float2 v = yp[d->ymap[tid]];
@@ -230,7 +222,7 @@ __device__ __forceinline__ int64_t ktile_index(const KTile &t, int64_t o) {
 // the GEMM that reads them expects; complex64 output is copied unscaled.
 template <int NP>
 __device__ __forceinline__ float perm_scale(const Slot *sl, int64_t sbs, int q) {
-  return NP == 0 ? 1.0f : ldexpf(1.0f, -slot_exp(sl[q * sbs].maxbits));
+  return NP == 0 ? 1.0f : ldexpf(1.0f, -tn_scale_exp(sl[q * sbs].maxbits));
 }
 
 // Generic: one thread per output element; writes are contiguous, reads follow
@@ -445,7 +437,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
   const int64_t m0 = (tile % g.tiles_m) * BM, n0 = (tile / g.tiles_m) * BN;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
-  const int ea = slot_exp(sa->maxbits), eb = slot_exp(sb->maxbits);
+  const int ea = tn_scale_exp(sa->maxbits), eb = tn_scale_exp(sb->maxbits);
   const float fa = ldexpf(1.0f, -ea), fb = ldexpf(1.0f, -eb);
   if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
 

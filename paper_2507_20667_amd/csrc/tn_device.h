@@ -236,6 +236,15 @@ struct TreeLaunch {
   int32_t qw;           // queries per workgroup
 };
 
+// Exponent of a scale record's max: floor(log2 x) of the non-negative float
+// with bits `bits`; -126 for subnormals, 0 for zero (an all-zero operand is
+// scaled by 1, never by an overflowing power of two), 127 for infinity and
+// NaN.  A consumer multiplies its operand by 2^-e (exact).
+__device__ __forceinline__ int tn_scale_exp(uint32_t bits) {
+  const int e = min(max((int)(bits >> 23) - 127, -126), 127);
+  return bits == 0u ? 0 : e;
+}
+
 // Split x = h + l with h = bf16(x) and l = bf16(x - h), both rounded to nearest
 // even (finite inputs): the two terms carry 16 significant bits of x.
 __device__ __forceinline__ uint32_t tn_bf16_rne(float x) {

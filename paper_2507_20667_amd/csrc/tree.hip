@@ -39,14 +39,6 @@ typedef const TreeLaunch __attribute__((address_space(4))) *KernargLaunch;
 // step descriptors through the scalar cache (read only, uniform per wave)
 typedef const TreeStep __attribute__((address_space(4))) *CStep;
 
-// floor(log2 x) of the non-negative float with bits `bits`, without branches:
-// 0 for zero, infinity and NaN, -126 for subnormals
-__device__ __forceinline__ int tree_exp(uint32_t bits) {
-  const int e = (int)((bits >> 23) & 0xffu);
-  const int r = e == 0 ? -126 : e - 127;
-  return (bits == 0u || e == 0xff) ? 0 : r;
-}
-
 // Index arithmetic: every offset, stride and index of a subtree is far below
 // 2^24, so the full-rate 24-bit multiply-add serves (the 32-bit integer
 // multiply runs at a quarter of the rate).
@@ -99,7 +91,7 @@ __device__ __forceinline__ void seg2r(const int32_t (&ext)[kTreeSeg], const int3
 // and operand scales are the same for every item (uniform, computed once).
 struct ItemScale {
   int2 za, zb;
-  __device__ __forceinline__ int e() const { return tree_exp((uint32_t)za.y) + tree_exp((uint32_t)zb.y); }
+  __device__ __forceinline__ int e() const { return tn_scale_exp((uint32_t)za.y) + tn_scale_exp((uint32_t)zb.y); }
 };
 
 __device__ __forceinline__ ItemScale item_scale(const int2 *sc, int asl, int bsl) {
