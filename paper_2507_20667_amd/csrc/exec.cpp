@@ -511,6 +511,10 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       float2 *hv = (float2 *)h;
       Slot *hs = (Slot *)(h + rb_vals);
       Result *hr = (Result *)(h + rb_vals + rb_slots);
+      // a closed root's records go straight to the pinned staging buffer
+      // (host memory the device writes to; visible after the synchronize
+      // below), which saves the copy back
+      Result *res_out = dot_root ? hr : res;
       const Operand R = operand(p->root);
       // TN_FLAG_GRAPH: replay the launch sequence captured with the same
       // workspace, layout and in-place overrides, or capture it now
@@ -569,7 +573,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         tl.slots_sh = slots_sh;
         tl.slots_q = slots_q;
         tl.slot_stride = perq_sl;
-        tl.res = res;
+        tl.res = res_out;
         if (L.n_tree_shared) {
           tl.nq = 1;
           tl.qw = 1;
@@ -698,7 +702,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                             [&] {
                               return launch_dot(st, (const DotDesc *)(desc_base + n.ddesc_off),
                                                 n.nelem, operand(n.c1), operand(n.c2), outop(n.id),
-                                                is_root ? res : nullptr, 1, partials,
+                                                is_root ? res_out : nullptr, 1, partials,
                                                 n.dot_blocks, nb);
                             }),
                  "dot");
@@ -716,10 +720,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                "output permutation");
       }
       // read back
-      if (dot_root) {
-        TN_HIP(hipMemcpyAsync(hr, res, (size_t)Q * sizeof(Result), hipMemcpyDeviceToHost, st),
-               "result copy");
-      } else {
+      if (!dot_root) {
         const int rq = root_shared ? 1 : Q;
         if (p->fperm.needed) {
           // the permuted results lie final_bytes apart (256-byte rounded)
