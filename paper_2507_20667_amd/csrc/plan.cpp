@@ -1092,11 +1092,29 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     h.image_off = (int64_t)image.size();
     h.load0 = (int32_t)loads.size();
     int32_t sh = 0, pq = 0;
+    // leaves with the same entries (a circuit's repeated gates) share one copy:
+    // leaves are only read, and each step addresses a leaf through its own maps
+    std::map<std::pair<int64_t, uint64_t>, std::vector<std::pair<int32_t, int>>> same;
     for (int t : leaves) {
       const int64_t n = p->leaf[t].size();
       if (!ovr[t]) {
+        const float2 *src = p->leaf_host.data() + p->leaf_off[t];
+        uint64_t hsh = 1469598103934665603ull;  // FNV-1a over the entries' bytes
+        for (int64_t i = 0; i < n * 8; ++i) hsh = (hsh ^ ((const uint8_t *)src)[i]) * 1099511628211ull;
+        auto &cands = same[{n, hsh}];
+        int32_t at = -1;
+        for (const auto &c : cands)
+          if (memcmp(p->leaf_host.data() + p->leaf_off[c.second], src, (size_t)n * 8) == 0) {
+            at = c.first;
+            break;
+          }
+        if (at >= 0) {
+          loc[t] = at;
+          continue;
+        }
         loc[t] = sh;
-        for (int64_t i = 0; i < n; ++i) image.push_back(p->leaf_host[p->leaf_off[t] + i]);
+        cands.push_back({sh, t});
+        for (int64_t i = 0; i < n; ++i) image.push_back(src[i]);
         if (n & 1) image.push_back(make_float2(0.f, 0.f));
         sh += (int32_t)((n + 1) & ~(int64_t)1);
       } else {
