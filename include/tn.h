@@ -75,9 +75,11 @@ enum {
   TN_FORM_4M = 0,          /* four real products per complex product */
   TN_FORM_3M = 1 << 4,     /* three real products (Gauss) */
   TN_FLAG_KEEP_SCALE = 1 << 8, /* return mantissa and log2 scale separately */
-  TN_FLAG_GRAPH = 1 << 9       /* batched calls: capture each plan group's launch
+  TN_FLAG_GRAPH = 1 << 9,      /* batched calls: capture each plan group's launch
                                   sequence as a HIP graph and replay it (see
                                   tn_contract_batch) */
+  TN_FLAG_CONCURRENT = 1 << 10 /* tn_contract: run the partitions' subtrees side
+                                  by side, one stream each (see tn_contract) */
 };
 
 typedef struct tn_ctx tn_ctx;   /* arena, stream, caches, scheduler */
@@ -195,8 +197,16 @@ tn_status tn_plan_free(tn_plan *plan);
  * written and *log2_scale receives the FP64 exponent (value = out *
  * 2^log2_scale); otherwise the scale is folded in and log2_scale, if not
  * NULL, receives 0.
- * Errors: TN_E_INVALID_ARG (host-only plan, bad override), TN_E_NOMEM (the
- * arena cannot hold the workspace), TN_E_DEVICE.
+ * TN_FLAG_CONCURRENT: the partitions are independent until the
+ * cross-partition tree (§3, eqs. con_par and con_dist), so each partition's
+ * subtree runs on a stream of its own, side by side, and the cross-partition
+ * vertices run on the context's stream once the partitions they read are
+ * done.  Each partition takes memory of its own (the workspace is the sum of
+ * the partitions' live peaks plus the reduction path's, not their maximum).
+ * The results are bit-identical to the serial order: every vertex computes
+ * the same values either way.  Without effect on a plan of one partition.
+ * Errors: TN_E_INVALID_ARG (host-only plan, bad override or flag), TN_E_NOMEM
+ * (the arena cannot hold the workspace), TN_E_DEVICE.
  */
 tn_status tn_contract(tn_plan *plan, int32_t num_overrides, const tn_leaf *overrides, void *out,
                       tn_dtype out_dtype, double *log2_scale, uint32_t flags);

@@ -72,6 +72,12 @@ tn_status tn_ctx_destroy(tn_ctx *ctx) {
     if (l.pinned) hipHostFree(l.pinned);
   }
   if (ctx->lanes_ev) hipEventDestroy(ctx->lanes_ev);
+  for (size_t k = 0; k < ctx->part_st.size(); ++k) {
+    hipStreamSynchronize(ctx->part_st[k]);
+    hipStreamDestroy(ctx->part_st[k]);
+    hipEventDestroy(ctx->part_ev[k]);
+  }
+  if (ctx->part_ev0) hipEventDestroy(ctx->part_ev0);
   ctx->prof.destroy();
   delete ctx;
   return TN_OK;
@@ -210,7 +216,8 @@ tn_status tn_contract(tn_plan *p, int32_t num_overrides, const tn_leaf *override
     set_error("tn_contract: plan is NULL or host-only (loaded without a context)");
     return TN_E_INVALID_ARG;
   }
-  if (num_overrides < 0 || (num_overrides > 0 && !overrides) || (flags & ~TN_FLAG_KEEP_SCALE)) {
+  if (num_overrides < 0 || (num_overrides > 0 && !overrides) ||
+      (flags & ~(TN_FLAG_KEEP_SCALE | TN_FLAG_CONCURRENT))) {
     set_error("tn_contract: bad overrides or flags");
     return TN_E_INVALID_ARG;
   }

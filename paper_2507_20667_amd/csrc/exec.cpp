@@ -40,6 +40,32 @@ void release_graph(tn_ctx *ctx, GraphEntry &g) {
 
 static size_t rnd(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Streams and events for TN_FLAG_CONCURRENT: one stream per partition (default
+// priority, not synchronizing with the null stream), created on first use.
+static tn_status ensure_part_streams(tn_ctx *ctx, int K) {
+  if (!ctx->part_ev0 && hipEventCreateWithFlags(&ctx->part_ev0, hipEventDisableTiming) != hipSuccess) {
+    ctx->part_ev0 = nullptr;
+    set_error("partition streams: event creation failed");
+    return TN_E_DEVICE;
+  }
+  while ((int)ctx->part_st.size() < K) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      set_error("partition streams: stream creation failed");
+      return TN_E_DEVICE;
+    }
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      hipStreamDestroy(s);
+      set_error("partition streams: event creation failed");
+      return TN_E_DEVICE;
+    }
+    ctx->part_st.push_back(s);
+    ctx->part_ev.push_back(e);
+  }
+  return TN_OK;
+}
+
 static tn_status ensure_pinned(ExecRes &r, size_t bytes, hipStream_t st) {
   if (*r.pinned_bytes >= bytes) return TN_OK;
   // the previous staging may still feed a copy in flight on the call's stream
@@ -165,7 +191,15 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   auto ms_since = [](std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   };
-  std::shared_ptr<ExecLayout> Lp = cached_layout(p, ovr, share);
+  // TN_FLAG_CONCURRENT (single calls): partitions side by side, each on a
+  // stream of its own, in a layout that gives each its own memory
+  const bool conc = (flags & TN_FLAG_CONCURRENT) && !share && qs.size() == 1 && p->K > 1 &&
+                    !(flags & TN_FLAG_GRAPH) && rs.st == ctx->stream;
+  if (conc) {
+    tn_status cs = ensure_part_streams(ctx, p->K);
+    if (cs != TN_OK) return cs;
+  }
+  std::shared_ptr<ExecLayout> Lp = cached_layout(p, ovr, share, conc);
   const ExecLayout &L = *Lp;
   const double t_layout = dbg ? ms_since(t_enter) : 0.0;
   Profiler idle_prof;
@@ -597,9 +631,35 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                  "subtree kernel");
         }
       }
+      if (conc) {
+        // every partition stream starts after the uploads and slot set-up above
+        TN_HIP(hipEventRecord(ctx->part_ev0, st), "partition start");
+        for (int k = 0; k < p->K; ++k) TN_HIP(hipStreamWaitEvent(ctx->part_st[k], ctx->part_ev0, 0), "partition start");
+      }
+      std::vector<char> part_dirty(conc ? p->K : 0, 0);
+      // the reduction path (and the read-back) waits for the partitions with
+      // work launched since it last waited
+      auto join_parts = [&]() -> hipError_t {
+        for (int k = 0; k < (int)part_dirty.size(); ++k)
+          if (part_dirty[k]) {
+            hipError_t e = hipEventRecord(ctx->part_ev[k], ctx->part_st[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->part_ev[k], 0);
+            if (e != hipSuccess) return e;
+            part_dirty[k] = 0;
+          }
+        return hipSuccess;
+      };
       for (int j : p->order) {
         const Node &n = p->nodes[j];
         if (trees && p->in_tree[n.id]) continue;
+        // TN_FLAG_CONCURRENT: a partition's vertices on its own stream
+        hipStream_t xs = st;
+        if (conc && n.part >= 0) {
+          xs = ctx->part_st[n.part];
+          part_dirty[n.part] = 1;
+        } else if (conc) {
+          TN_HIP(join_parts(), "partition join");
+        }
         const bool sh = L.shared[n.id] != 0;
         const int nb = sh ? 1 : Q;
         const double wflops = 8.0 * (double)n.weight * nb;
@@ -609,9 +669,9 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                                                     : p->nodes[n.c2 - nv].out.size());
         const double nodeb = (c1b + c2b + 8.0 * (double)std::max<int64_t>(n.out.size(), 1)) * nb;
         if (n.kind == NK_STREAM) {
-          TN_HIP(prof.timed(st, TN_KCLASS_STREAM, nodeb, wflops,
+          TN_HIP(prof.timed(xs, TN_KCLASS_STREAM, nodeb, wflops,
                             [&] {
-                              return launch_stream(st,
+                              return launch_stream(xs,
                                                    (const StreamDesc *)(desc_base + n.sdesc_off),
                                                    n.nfib, n.ns, operand(n.x), operand(n.y),
                                                    outop(n.id), nb);
@@ -628,10 +688,10 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           const double pbytes = n.planes > 2 ? 8.0 + 2.0 * n.planes : 16.0;
           if (n.pa.needed) {
             void *dst = pbase + L.scr_a[j];
-            TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, pbytes * n.pa.h.nelem * nb, 0.0,
+            TN_HIP(prof.timed(xs, TN_KCLASS_PERMUTE, pbytes * n.pa.h.nelem * nb, 0.0,
                               [&] {
                                 return launch_permute(
-                                    st, (const PermDesc *)(desc_base + n.pa.desc_off), n.pa.h,
+                                    xs, (const PermDesc *)(desc_base + n.pa.desc_off), n.pa.h,
                                     A.p, A.bs, dst, pst, nb, n.planes, n.pa.h.nelem, A.slot,
                                     A.sbs, ktile_of(n, n.M));
                               }),
@@ -641,10 +701,10 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           }
           if (n.pb.needed) {
             void *dst = pbase + L.scr_b[j];
-            TN_HIP(prof.timed(st, TN_KCLASS_PERMUTE, pbytes * n.pb.h.nelem * nb, 0.0,
+            TN_HIP(prof.timed(xs, TN_KCLASS_PERMUTE, pbytes * n.pb.h.nelem * nb, 0.0,
                               [&] {
                                 return launch_permute(
-                                    st, (const PermDesc *)(desc_base + n.pb.desc_off), n.pb.h,
+                                    xs, (const PermDesc *)(desc_base + n.pb.desc_off), n.pb.h,
                                     B.p, B.bs, dst, pst, nb, n.planes, n.pb.h.nelem, B.slot,
                                     B.sbs, ktile_of(n, n.N));
                               }),
@@ -688,19 +748,19 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           const int prec = (p->flags & TN_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
           const int form = (p->flags & TN_FORM_3M) ? kForm3M : kForm4M;
           const auto tg = std::chrono::steady_clock::now();
-          TN_HIP(prof.timed(st, TN_KCLASS_GEMM, nodeb, wflops,
-                            [&] { return launch_gemm(st, g, prec, form, n.variant, nb); }),
+          TN_HIP(prof.timed(xs, TN_KCLASS_GEMM, nodeb, wflops,
+                            [&] { return launch_gemm(xs, g, prec, form, n.variant, nb); }),
                  "complex GEMM");
           if (dbg_gemm) {
-            hipStreamSynchronize(st);
+            hipStreamSynchronize(xs);
             fprintf(stderr, "[tn] gemm M %lld N %lld K %lld batch %d: %.3f ms\n", (long long)n.M,
                     (long long)n.N, (long long)n.K, nb, ms_since(tg));
           }
         } else {
           const bool is_root = n.id == p->root;
-          TN_HIP(prof.timed(st, TN_KCLASS_DOT, nodeb, wflops,
+          TN_HIP(prof.timed(xs, TN_KCLASS_DOT, nodeb, wflops,
                             [&] {
-                              return launch_dot(st, (const DotDesc *)(desc_base + n.ddesc_off),
+                              return launch_dot(xs, (const DotDesc *)(desc_base + n.ddesc_off),
                                                 n.nelem, operand(n.c1), operand(n.c2), outop(n.id),
                                                 is_root ? res_out : nullptr, 1, partials,
                                                 n.dot_blocks, nb);
@@ -708,6 +768,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                  "dot");
         }
       }
+      if (conc) TN_HIP(join_parts(), "partition join");
       // result into output-leg order
       if (p->fperm.needed) {
         const int nbf = L.shared[p->root] ? 1 : Q;
@@ -797,6 +858,8 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     }
     if (rc != TN_OK) {
       hipStreamSynchronize(st);
+      if (conc)  // partitions still running read and write this workspace
+        for (int k = 0; k < p->K; ++k) hipStreamSynchronize(ctx->part_st[k]);
       prof.pend.clear();
       prof.used = 0;
     }

@@ -1391,9 +1391,14 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
 }
 
 ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden, bool share,
-                            bool allow_trees) {
+                            bool allow_trees, bool conc) {
   const int nv = p->nv, nn = 2 * nv - 1;
   ExecLayout L;
+  // concurrent partitions: the vertices of partition k's subtree (and their
+  // scratch) take memory from a packer of their own, laid out after the
+  // reduction path's, so partitions running side by side never share memory
+  conc = conc && !share && p->K > 1;
+  L.conc = conc;
   L.off.assign(nn, -1);
   L.shared.assign(nn, 1);
   L.scr_a.assign(nv > 1 ? nv - 1 : 0, -1);
@@ -1419,6 +1424,12 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
     return std::find(p->tree_roots.begin(), p->tree_roots.end(), v) != p->tree_roots.end();
   };
   Packer pk[2];  // 0: per-query, 1: shared
+  std::vector<Packer> pkp(conc ? p->K : 0);  // concurrent partitions
+  auto packer_of = [&](const Node &n) -> Packer & {
+    if (conc && n.part >= 0) return pkp[n.part];
+    return pk[L.shared[n.id] ? 1 : 0];
+  };
+  std::vector<int8_t> in_part(nn, -1);  // partition packer a vertex's memory came from
   // Islands: the largest vertices that no override reaches inside a per-query
   // subtree.  They run once, as shared subtrees of their own, and the
   // per-query programs read their results instead of recomputing them for
@@ -1450,8 +1461,8 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
   for (int j : p->order) {
     const Node &n = p->nodes[j];
     if (trees && p->in_tree[n.id]) continue;
-    const int part = L.shared[n.id] ? 1 : 0;
-    Packer &P = pk[part];
+    Packer &P = packer_of(n);
+    if (conc && n.part >= 0) in_part[n.id] = (int8_t)n.part;
     int64_t out_bytes = std::max<int64_t>(n.out.size(), 1) * 8;
     L.off[n.id] = P.alloc(out_bytes);
     std::vector<std::pair<int64_t, int64_t>> tmp;
@@ -1481,6 +1492,9 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
     // feeding per-query vertices stay for the whole execution)
     for (int c : {n.c1, n.c2}) {
       if (c < nv || L.off[c] < 0) continue;
+      // (a partition's result read by the reduction path stays: it lives in
+      // the partition's own region)
+      if (in_part[c] != in_part[n.id]) continue;
       if (L.shared[c] == L.shared[n.id]) {
         const Node &cn = p->nodes[c - nv];
         P.release(L.off[c], std::max<int64_t>(cn.out.size(), 1) * 8);
@@ -1491,6 +1505,26 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
   L.peak_intermediate = pk[0].peak();
   L.perq_bytes = pk[0].peak();
   L.shared_bytes = pk[1].peak();
+  if (conc) {
+    // partition regions after the reduction path's, each 256-byte aligned
+    std::vector<int64_t> base(p->K);
+    int64_t top = (L.perq_bytes + 255) & ~(int64_t)255;
+    for (int k = 0; k < p->K; ++k) {
+      base[k] = top;
+      top += (pkp[k].peak() + 255) & ~(int64_t)255;
+    }
+    for (const Node &n : p->nodes) {
+      if (in_part[n.id] < 0) continue;
+      const int64_t b = base[in_part[n.id]];
+      const int j = n.id - nv;
+      L.off[n.id] += b;
+      if (L.scr_a[j] >= 0) L.scr_a[j] += b;
+      if (L.scr_b[j] >= 0) L.scr_b[j] += b;
+      if (L.partial[j] >= 0) L.partial[j] += b;
+    }
+    L.perq_bytes = top;
+    L.peak_intermediate = top;
+  }
   if (trees) {
     L.all_in_tree = true;
     for (const Node &n : p->nodes) L.all_in_tree = L.all_in_tree && p->in_tree[n.id];
@@ -1503,15 +1537,15 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
 }
 
 std::shared_ptr<ExecLayout> cached_layout(tn_plan *p, const std::vector<int> &overridden,
-                                          bool share) {
+                                          bool share, bool conc) {
   std::lock_guard<std::mutex> g(p->cache_mu);
   std::vector<int> key = overridden;
-  key.push_back(share ? -1 : -2);
+  key.push_back(share ? -1 : conc ? -3 : -2);
   auto it = p->layouts.find(key);
   if (it != p->layouts.end()) return it->second;
-  auto L = std::make_shared<ExecLayout>(make_exec_layout(p, overridden, share, true));
+  auto L = std::make_shared<ExecLayout>(make_exec_layout(p, overridden, share, true, conc));
   if (L->tree_error)  // fall back to one launch per vertex
-    L = std::make_shared<ExecLayout>(make_exec_layout(p, overridden, share, false));
+    L = std::make_shared<ExecLayout>(make_exec_layout(p, overridden, share, false, conc));
   if (getenv("TN_DEBUG"))
     fprintf(stderr,
             "[tn] layout: %zu overridden leaves, share %d, subtrees %d shared + %d per query, "

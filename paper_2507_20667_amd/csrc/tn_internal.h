@@ -114,6 +114,7 @@ struct ExecLayout {
   size_t lds_perq1 = 0;                    // the per-query launch of a single query
   int tree_qw = 1;                         // queries per workgroup (per-query launch)
   bool tree_wave = false;                  // batches of queries run the wave kernel
+  bool conc = false;                       // partitions in regions of their own (concurrent)
   bool tree_reads_ovr = false;             // per-query subtrees load overridden leaves
   bool tree_error = false;                 // programs failed the bounds check
   bool all_in_tree = false;                // every vertex runs in the subtree kernel
@@ -273,6 +274,11 @@ struct tn_ctx {
   };
   std::vector<Lane> lanes;
   hipEvent_t lanes_ev = nullptr;
+  // TN_FLAG_CONCURRENT: a stream and an event per partition, and the event
+  // that starts them (created on first use)
+  std::vector<hipStream_t> part_st;
+  std::vector<hipEvent_t> part_ev;
+  hipEvent_t part_ev0 = nullptr;
 };
 
 namespace tn {
@@ -329,9 +335,9 @@ namespace tn {
 // plan.cpp
 tn_status build_plan(tn_plan *p, const tn_plan_desc *d);
 ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden, bool share,
-                            bool allow_trees);
+                            bool allow_trees, bool conc = false);
 std::shared_ptr<ExecLayout> cached_layout(tn_plan *p, const std::vector<int> &overridden,
-                                          bool share);
+                                          bool share, bool conc = false);
 const char *last_error();
 
 // exec.cpp

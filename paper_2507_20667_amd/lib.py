@@ -25,6 +25,7 @@ TN_PREC_FP32, TN_PREC_BF16X3 = 0, 1
 TN_FORM_4M, TN_FORM_3M = 0, 1 << 4
 TN_FLAG_KEEP_SCALE = 1 << 8
 TN_FLAG_GRAPH = 1 << 9
+TN_FLAG_CONCURRENT = 1 << 10
 
 STATUS_NAMES = {0: "TN_OK", 1: "TN_PENDING", -1: "TN_E_INVALID_ARG", -2: "TN_E_INVALID_PLAN",
                 -3: "TN_E_NOMEM", -4: "TN_E_DEVICE", -5: "TN_E_AGAIN", -6: "TN_E_CANCELLED",
