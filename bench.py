@@ -391,7 +391,8 @@ def batch_mix_leg(lib, queries=512, reps=3):
     ctx = lib.Context(32 << 30)
     handles = [ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 4, plan.tree, None, 0)
                for _, net, plan in circs]
-    cs = [lib.tn_plan_costs_get(h)["con_serial"] for h in handles]
+    costs = [lib.tn_plan_costs_get(h) for h in handles]
+    cs = [c["con_serial"] for c in costs]
     qs = [(handles[i], amplitude_overrides(circs[i][1], circs[i][0], x)) for i, x in zip(idx, bits)]
     shapes = [()] * queries
     work = 8.0 * sum(cs[i] for i in idx)
@@ -430,6 +431,17 @@ def batch_mix_leg(lib, queries=512, reps=3):
         plain.append(lib.tn_contract(*q))
         per_q.append(time.perf_counter() - t3)
     pt = time.perf_counter() - t2
+    # the same single calls with the partitions side by side (TN_FLAG_CONCURRENT)
+    for q in qs[:8]:
+        lib.tn_contract(*q, flags=lib.TN_FLAG_CONCURRENT)
+    conc, per_qc = [], []
+    t2 = time.perf_counter()
+    for q in qs:
+        t3 = time.perf_counter()
+        conc.append(lib.tn_contract(*q, flags=lib.TN_FLAG_CONCURRENT))
+        per_qc.append(time.perf_counter() - t3)
+    ptc = time.perf_counter() - t2
+    conc_diff = max(float(np.max(np.abs(np.asarray(a[0]) - np.asarray(b[0])))) for a, b in zip(conc, plain))
     # the paper's cost model against measured time: per circuit, mean plain
     # time per amplitude against con_serial (Pearson r, linear and log-log)
     by_c = {}
@@ -439,6 +451,15 @@ def batch_mix_leg(lib, queries=512, reps=3):
     ys_ = np.array([float(np.median(v)) for v in by_c.values()])
     r_lin = float(np.corrcoef(xs_, ys_)[0, 1]) if len(by_c) > 2 else None
     r_log = float(np.corrcoef(np.log(xs_), np.log(ys_))[0, 1]) if len(by_c) > 2 else None
+    # concurrency (f4): per circuit, the serial-over-concurrent time ratio
+    # against the cost model's bound con_serial / con_par
+    by_cc = {}
+    for k, i in enumerate(idx):
+        by_cc.setdefault(i, []).append(per_qc[k])
+    tc_ = np.array([float(np.median(by_cc[i])) for i in by_c])
+    bound = np.array([float(costs[i]["con_serial"]) / float(costs[i]["con_par"]) for i in by_c])
+    cpar = np.array([float(costs[i]["con_par"]) for i in by_c])
+    speed = ys_ / tc_
     diff = max(abs(amp(outs[k], l2s[k]) - amp(*plain[k])) / max(abs(amp(*plain[k])), 2.0 ** (-circs[i][0].n / 2))
                for k, i in enumerate(idx))
     # the oracle on the queries of the smallest circuits
@@ -464,6 +485,17 @@ def batch_mix_leg(lib, queries=512, reps=3):
            "kernel_seconds_batched": kern_s, "wall_seconds_batched": bt,
            "max_rel_diff_batched_vs_plain": diff,
            "max_rel_err_vs_oracle": max(errs) if errs else None, "oracle_checked": len(errs),
+           "concurrent_partitions": {
+               "plain_amplitudes_per_s": queries / pt, "concurrent_amplitudes_per_s": queries / ptc,
+               "speedup": pt / ptc, "max_abs_diff_vs_serial": conc_diff,
+               "per_circuit_speedup_median": float(np.median(speed)),
+               "per_circuit_speedup_range": [float(speed.min()), float(speed.max())],
+               "con_serial_over_con_par_median": float(np.median(bound)),
+               "con_serial_over_con_par_range": [float(bound.min()), float(bound.max())],
+               "pearson_r_log_con_par_vs_concurrent_time":
+                   float(np.corrcoef(np.log(cpar), np.log(tc_))[0, 1]) if len(by_c) > 2 else None,
+               "pearson_r_log_con_serial_vs_concurrent_time":
+                   float(np.corrcoef(np.log(xs_), np.log(tc_))[0, 1]) if len(by_c) > 2 else None},
            "cost_model_vs_time": {"circuits": len(by_c), "pearson_r_con_serial_vs_plain_time": r_lin,
                                   "pearson_r_log": r_log,
                                   "con_serial_range": [float(xs_.min()), float(xs_.max())],
@@ -472,6 +504,11 @@ def batch_mix_leg(lib, queries=512, reps=3):
         f"({out['batched_graph_amplitudes_per_s']:.0f} with graphs) vs "
         f"{out['plain_amplitudes_per_s']:.0f} plain (x{out['speedup_vs_plain']:.1f}), "
         f"max diff {diff:.1e}, oracle err {out['max_rel_err_vs_oracle']}")
+    cp = out["concurrent_partitions"]
+    log(f"concurrent partitions: {cp['concurrent_amplitudes_per_s']:.0f} amplitudes/s vs "
+        f"{cp['plain_amplitudes_per_s']:.0f} serial (x{cp['speedup']:.2f}; per circuit median "
+        f"x{cp['per_circuit_speedup_median']:.2f}, con_serial/con_par median "
+        f"{cp['con_serial_over_con_par_median']:.2f}), max diff {cp['max_abs_diff_vs_serial']}")
     return out
 
 
