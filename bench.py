@@ -304,7 +304,7 @@ def gemm_phase_leg(lib, reps=3):
     plan = simulated_annealing(net.legs, net.dims, tree_partition(net.legs, net.dims, 8), 8,
                                SAConfig(iterations=8, seed=0))
     plan_s = time.perf_counter() - t0
-    ctx = lib.Context(16 << 30)
+    ctx = lib.Context(48 << 30)  # the concurrent layout holds every partition's peak at once
     out = {"workload": f"random circuit {c['n']} qubits depth {c['depth']} seed {c['seed']}, "
                        f"{c['cx_per_layer']} CX pairs per layer (p_nn {c['p_nn']}), single-amplitude "
                        "networks, 8 SA partitions", "planning_s": plan_s}
@@ -327,6 +327,12 @@ def gemm_phase_leg(lib, reps=3):
         for _ in range(reps):
             lib.tn_contract(p, ovr)
         amp_ms = (time.perf_counter() - t1) / reps * 1e3
+        # the same plain call with the partitions side by side (TN_FLAG_CONCURRENT)
+        lib.tn_contract(p, ovr, flags=lib.TN_FLAG_CONCURRENT)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            lib.tn_contract(p, ovr, flags=lib.TN_FLAG_CONCURRENT)
+        camp_ms = (time.perf_counter() - t1) / reps * 1e3
         # the same amplitude through the batched path (one query): the small
         # vertices run in the subtree kernel instead of one launch each
         lib.tn_contract_batch(ctx.handle, [(p, ovr)], [()])
@@ -346,13 +352,16 @@ def gemm_phase_leg(lib, reps=3):
                      "mfma_util": eff * mul / peak, "gemm_ms_per_amplitude": g["seconds"] / reps * 1e3,
                      "gemm_launches_per_amplitude": g["launches"] // reps,
                      "plain_ms_per_amplitude": amp_ms,
+                     "plain_concurrent_ms_per_amplitude": camp_ms,
+                     "con_serial_over_con_par": float(costs["con_serial"]) / float(costs["con_par"]),
                      "batched_ms_per_amplitude": bamp_ms,
                      "permute_ms_per_amplitude": st["permute"]["seconds"] / reps * 1e3,
                      "con_serial": costs["con_serial"],
                      "largest_intermediate": costs["largest_intermediate"],
                      "max_rel_err_vs_statevector": worst, "amplitudes_checked": len(gold["bitstrings"])}
         log(f"{name}: GEMM phase {eff:.1f} effective TFLOP/s ({out[name]['mfma_util']:.1%} of the "
-            f"MFMA peak), {amp_ms:.2f} ms per amplitude ({bamp_ms:.2f} batched), max err {worst:.1e}")
+            f"MFMA peak), {amp_ms:.2f} ms per amplitude ({camp_ms:.2f} concurrent partitions, "
+            f"{bamp_ms:.2f} batched), max err {worst:.1e}")
         ctx.free_plan(p)
     ctx.close()
     return out
