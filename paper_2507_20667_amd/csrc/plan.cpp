@@ -921,8 +921,10 @@ struct LevelPlan {
   int64_t peak = 0;
 };
 
-static LevelPlan level_plan(const tn_plan *p, const std::vector<int> &nodes) {
+static LevelPlan level_plan(const tn_plan *p, const std::vector<int> &nodes,
+                            const std::vector<char> *spilled = nullptr) {
   const int nv = p->nv;
+  auto in_lds = [&](int u) { return !spilled || !(*spilled)[u]; };
   std::map<int, int> lvl;
   for (int u : nodes) {  // nodes are in SSA order, children first
     const Node &n = p->nodes[u - nv];
@@ -947,7 +949,8 @@ static LevelPlan level_plan(const tn_plan *p, const std::vector<int> &nodes) {
   }
   Packer P(2);
   for (const auto &ch : lp.chunks) {
-    for (int u : ch) lp.at[u] = P.alloc(std::max<int64_t>(p->nodes[u - nv].out.size(), 1));
+    for (int u : ch)
+      if (in_lds(u)) lp.at[u] = P.alloc(std::max<int64_t>(p->nodes[u - nv].out.size(), 1));
     for (int u : ch)
       for (int c : {p->nodes[u - nv].c1, p->nodes[u - nv].c2})
         if (c >= nv && lp.at.count(c))  // (inputs from outside the subtree live elsewhere)
@@ -1052,8 +1055,9 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   }
   std::vector<TreeSharedLoad> sloads;
   std::vector<int2> sgather;  // (LDS offset, shared-part offset) per island entry
-  std::vector<char> is_island(2 * nv - 1, 0);
+  std::vector<char> is_island(2 * nv - 1, 0), is_spill(2 * nv - 1, 0);
   for (int u : L.islands) is_island[u] = 1;
+  for (int u : L.spill) is_spill[u] = 1;
   std::vector<int> order;  // shared subtrees (and islands) first
   for (int r : p->tree_roots)
     if (L.shared[r]) order.push_back(r);
@@ -1158,28 +1162,36 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     h.nsg = (int32_t)sgather.size() - h.sg0;
     h.shared_elems = sh;
     const int64_t base = pq;
-    const LevelPlan lp = level_plan(p, nodes);
+    const LevelPlan lp = level_plan(p, nodes, &is_spill);
     for (int u : nodes) scale[u] = (int)scale.size();
     h.chunk0 = (int32_t)chunks.size();
     for (const auto &ch : lp.chunks) {
       TreeChunk tc;
       tc.step0 = (int32_t)steps.size();
       tc.nsteps = (int32_t)ch.size();
-      for (int u : ch) loc[u] = kPerQuery | (int32_t)(base + lp.at.at(u));
+      for (int u : ch)
+        if (!is_spill[u]) loc[u] = kPerQuery | (int32_t)(base + lp.at.at(u));
       for (int u : ch) {
         const Node &n = p->nodes[u - nv];
         TreeStep st;
         const bool final_dot = n.kind == NK_DOT && u == p->root;
+        // an operand or the result in the query's device workspace: kind 3
+        const int glob = (is_spill[n.c1] ? 1 : 0) | (is_spill[n.c2] ? 2 : 0) | (is_spill[u] ? 4 : 0);
         bool swap = false;
         memset(&st, 0, sizeof(st));
-        if (final_dot || !tree_stream_step(n, lay, st, swap)) {
+        if (final_dot || glob || !tree_stream_step(n, lay, st, swap)) {
           swap = false;
           tree_step(p, n, lay, final_dot, st);
         }
         const int ca_ = swap ? n.c2 : n.c1, cb_ = swap ? n.c1 : n.c2;
-        st.a = loc[ca_];
-        st.b = loc[cb_];
-        st.c = loc[u];
+        auto dev_loc = [&](int v) { return (int32_t)(L.off[v] / 8); };
+        st.a = (glob & 1) ? dev_loc(ca_) : loc[ca_];
+        st.b = (glob & 2) ? dev_loc(cb_) : loc[cb_];
+        st.c = (glob & 4) ? dev_loc(u) : loc[u];
+        if (glob) {
+          st.kind = 3;
+          st.glob = glob;
+        }
         st.asl = ca_ >= nv ? scale[ca_] : -1;
         st.bsl = cb_ >= nv ? scale[cb_] : -1;
         st.csl = scale[u];
@@ -1264,9 +1276,18 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
         }
         const int64_t ra = reach(st.cext, st.ca, st.ncs) + reach(st.sext, st.sa, st.nss);
         const int64_t rb = reach(st.cext, st.cb, st.ncs) + reach(st.sext, st.sb, st.nss);
-        ok = ok && inside(st.a, ra) && inside(st.b, rb) && (st.c & kPerQuery) &&
-             (st.c & ~kPerQuery) + st.nc <= h.perq_elems && st.csl >= 0 && st.csl < h.nscale &&
-             st.asl < h.nscale && st.bsl < h.nscale && st.nc >= 1 && st.ns >= 1;
+        // kind 3: an operand in the query's device workspace stays inside it
+        const int g = st.kind == 3 ? st.glob : 0;
+        auto in_dev = [&](int32_t off, int64_t r) {
+          return off >= 0 && 8 * ((int64_t)off + r + 1) <= L.perq_bytes;
+        };
+        ok = ok && (st.kind != 3 || (g > 0 && g < 8)) && (st.kind == 3 || st.glob == 0);
+        ok = ok && ((g & 1) ? in_dev(st.a, ra) : inside(st.a, ra)) &&
+             ((g & 2) ? in_dev(st.b, rb) : inside(st.b, rb)) &&
+             ((g & 4) ? in_dev(st.c, st.nc - 1)
+                      : (st.c & kPerQuery) && (st.c & ~kPerQuery) + st.nc <= h.perq_elems) &&
+             st.csl >= 0 && st.csl < h.nscale && st.asl < h.nscale && st.bsl < h.nscale && st.nc >= 1 &&
+             st.ns >= 1;
         // a closed-root inner product runs alone in the last chunk
         if (st.kind == 1) ok = ok && chunks[c].nsteps == 1 && c == h.chunk0 + h.nchunks - 1;
       }
@@ -1302,20 +1323,13 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     return;
   }
   L.lds_shared = lds_sh;
-  // Batches run the wave kernel: four waves a workgroup, each with its own
-  // queries, so the queries per workgroup are a multiple of four; as many as
-  // leave room for two workgroups per CU, else four if one fits.  When not
-  // even that fits, the level kernel takes the batch.
+  // Batches run the wave kernel: four waves a workgroup, one query each (the
+  // single-query step forms), as many workgroups per CU as the LDS allows.
+  // When four queries do not fit, the level kernel takes the batch.
   const size_t lim = tree_lds_limit();
   L.tree_wave = false;
   L.tree_qw = 1;
-  for (int qw : {16, 12, 8, 4})
-    if (tree_lds_bytes(qw, max_scale_q, max_sh_q, max_pq_q, true) <= lim / 2) {
-      L.tree_qw = qw;
-      L.tree_wave = true;
-      break;
-    }
-  if (!L.tree_wave && tree_lds_bytes(4, max_scale_q, max_sh_q, max_pq_q, true) <= lim) {
+  if (tree_lds_bytes(4, max_scale_q, max_sh_q, max_pq_q, true) <= lim) {
     L.tree_qw = 4;
     L.tree_wave = true;
   }
@@ -1457,6 +1471,25 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
     for (int r : p->tree_roots)
       L.off[r] = pk[L.shared[r] ? 1 : 0].alloc(std::max<int64_t>(p->nodes[r - nv].out.size(), 1) * 8);
     for (int u : L.islands) L.off[u] = pk[1].alloc(std::max<int64_t>(p->nodes[u - nv].out.size(), 1) * 8);
+    // the large intermediates of per-query subtrees stay in the query's part
+    // of the workspace (their whole lifetime), which keeps each query's LDS
+    // small enough for more queries per CU
+    L.spill.clear();
+    for (int r : p->tree_roots) {
+      if (L.shared[r]) continue;
+      std::vector<int> stack{p->nodes[r - nv].c1, p->nodes[r - nv].c2};
+      while (!stack.empty()) {
+        const int u = stack.back();
+        stack.pop_back();
+        if (u < nv || L.shared[u]) continue;  // leaves, islands
+        const Node &n = p->nodes[u - nv];
+        if (n.out.size() >= kTreeSpillElems) L.spill.push_back(u);
+        stack.push_back(n.c1);
+        stack.push_back(n.c2);
+      }
+    }
+    std::sort(L.spill.begin(), L.spill.end());
+    for (int u : L.spill) L.off[u] = pk[0].alloc(p->nodes[u - nv].out.size() * 8);
   }
   for (int j : p->order) {
     const Node &n = p->nodes[j];

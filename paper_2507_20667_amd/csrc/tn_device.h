@@ -137,9 +137,14 @@ constexpr int32_t kPerQuery = 1 << 30;
 constexpr int kTreeMaxElems = 4096;
 constexpr int kTreeChunk = 16;     // steps of one level run between two barriers
 constexpr int kTreeMaxOvr = 64;    // overridden leaves read in place per launch
+// a per-query subtree's intermediates of at least this many entries live in
+// the query's device workspace instead of LDS (kind 3 steps reach them)
+constexpr int kTreeSpillElems = 512;
 
 // kind 0, a contraction: C[i] = sum_s A[ca(i) + sa(s)] B[cb(i) + sb(s)].
 // kind 1, the closed root: the FP64 inner product sum_s A[sa(s)] B[sb(s)].
+// kind 3, kind 0 with some of A, B, C (bits 0, 1, 2 of glob) in the query's
+// device workspace: their locations are float2 offsets from its start.
 // kind 2, a small operand (a gate) applied along the fibers of a large one:
 // A is the large operand X, B the small one Y (<= 16 entries); for every value
 // f of X's free index (the map: f -> (X offset ca, C offset cb), nc / nfy
@@ -165,6 +170,8 @@ struct TreeStep {
       int32_t xs[4], cy[4], ymap[16];
     };
   };
+  int32_t glob;           // kind 3: operands in the query's device workspace
+  int32_t pad;
 };
 constexpr int kTreeStepWords = (int)(sizeof(TreeStep) / 4);
 

@@ -115,6 +115,7 @@ struct ExecLayout {
   int tree_qw = 1;                         // queries per workgroup (per-query launch)
   bool tree_wave = false;                  // batches of queries run the wave kernel
   bool conc = false;                       // partitions in regions of their own (concurrent)
+  std::vector<int> spill;                  // per-query subtree vertices kept in device memory
   bool tree_reads_ovr = false;             // per-query subtrees load overridden leaves
   bool tree_error = false;                 // programs failed the bounds check
   bool all_in_tree = false;                // every vertex runs in the subtree kernel

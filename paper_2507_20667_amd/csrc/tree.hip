@@ -429,9 +429,70 @@ __device__ __forceinline__ void tree_step_q(SP Sp, int lane, int nthr, int nqw, 
     tree_step_impl<ONE, false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale);
 }
 
+// Kind 3: the kind 0 form with some operands in the query's device workspace
+// (a large intermediate of a per-query subtree), reached through generic
+// pointers.  gq: the device workspace of the group's first query, gstride
+// float2 apart.
+template <bool P2, class SP>
+__device__ void tree_dev_impl(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
+                              const float2 *shr, int2 *scl, int nscale, float2 *gq, int64_t gstride) {
+  const int a = Sp->a, b = Sp->b, c = Sp->c, asl = Sp->asl, bsl = Sp->bsl, csl = Sp->csl;
+  const int nc = Sp->nc, ns = Sp->ns, ncs = Sp->ncs, nss = Sp->nss, glob = Sp->glob;
+  int32_t cext[kTreeSeg], ca[kTreeSeg], cb[kTreeSeg], clg[kTreeSeg];
+  int32_t sext[kTreeSeg], sa[kTreeSeg], sb[kTreeSeg], slg[kTreeSeg];
+#pragma unroll
+  for (int i = 0; i < kTreeSeg; ++i) {
+    cext[i] = Sp->cext[i];
+    ca[i] = Sp->ca[i];
+    cb[i] = Sp->cb[i];
+    clg[i] = Sp->clg[i];
+    sext[i] = Sp->sext[i];
+    sa[i] = Sp->sa[i];
+    sb[i] = Sp->sb[i];
+    slg[i] = Sp->slg[i];
+  }
+  const int hl = threadIdx.x & 63;
+  const bool stab = ns <= 64;
+  int soa = 0, sob = 0;
+  if (stab && hl < ns) seg2r<P2>(sext, sa, sb, slg, nss, hl, soa, sob);
+  const int total = nqw * nc;
+  int qprev = -1;
+  float mx = 0.f;
+  for (int w = lane; w < total; w += nthr) {
+    const int q = w / nc;
+    const int ci = w - q * nc;
+    float2 *base = pq + mad24(q, perq, 0);
+    float2 *dev = gq + (int64_t)q * gstride;
+    const float2 *A = (glob & 1) ? dev + a : ((a & kPerQuery) ? base + (a & ~kPerQuery) : shr + a);
+    const float2 *B = (glob & 2) ? dev + b : ((b & kPerQuery) ? base + (b & ~kPerQuery) : shr + b);
+    float2 *C = (glob & 4) ? dev + c : base + (c & ~kPerQuery);
+    int ao, bo;
+    seg2r<P2>(cext, ca, cb, clg, ncs, ci, ao, bo);
+    const ItemScale z = item_scale(scl + mad24(q, nscale, 0), asl, bsl);
+    const float2 r = dot_terms<P2>(A + ao, B + bo, ns, stab, soa, sob, sext, sa, sb, slg, nss);
+    const int e = z.e();
+    const float f = ldexpf(1.0f, -e);
+    const float rr = r.x * f, ii = r.y * f;
+    C[ci] = make_float2(rr, ii);
+    if (ci == 0) scl[mad24(q, nscale, csl)].x = z.za.x + z.zb.x + e;
+    fold_max(scl, nscale, csl, q, qprev, mx, fmaxf(fabsf(rr), fabsf(ii)));
+  }
+  if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
+}
+
 template <class SP>
 __device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
-                                          const float2 *shr, int2 *scl, int nscale) {
+                                          const float2 *shr, int2 *scl, int nscale, float2 *gq,
+                                          int64_t gstride) {
+  if (Sp->kind == 3) {
+    if (Sp->pow2)
+      tree_dev_impl<true>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
+    else
+      tree_dev_impl<false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
+    // a later step of this wave reads what this one stored to device memory
+    __builtin_amdgcn_s_waitcnt(0);
+    return;
+  }
   if (nqw == 1)
     tree_step_q<true>(Sp, lane, nthr, 1, pq, perq, shr, scl, nscale);
   else
@@ -540,6 +601,9 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
   float2 *pq = shr + ((h.shared_elems + 1) & ~1);
   const int perq = (h.perq_elems + 1) & ~1;
   const int32_t *gw = (const int32_t *)t.steps;
+  // the queries' device workspaces (large per-query intermediates)
+  float2 *gq = (float2 *)(t.perq_base + (int64_t)q0 * t.perq_stride);
+  const int64_t gstride = t.perq_stride / 8;
 
   tree_prologue(t, ka, h, tid, qw, nqw, q0, scl, shr, pq, perq);
   // the chunks' steps are consecutive from step0: the next chunk's size is
@@ -611,12 +675,13 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
       }
     } else if (cur == 1) {
       // one step (a spine contraction): the whole workgroup on it
-      tree_step(S, tid, 256, nqw, pq, perq, shr, scl, h.nscale);
+      tree_step(S, tid, 256, nqw, pq, perq, shr, scl, h.nscale, gq, gstride);
     } else {
       // several independent steps of one level (largest first): one wave per
       // step, round robin
       const int wave = tid >> 6, lane = tid & 63;
-      for (int i = wave; i < cur; i += 4) tree_step(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale);
+      for (int i = wave; i < cur; i += 4)
+        tree_step(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale, gq, gstride);
     }
     if (k + 1 < h.nchunks) {
       int32_t *dst = sbuf + ((k + 1) & 1) * CW;
@@ -692,7 +757,10 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
   // a closed root is the program's last step (checked on the host): it runs
   // after the loop
   const int nloop = nsteps - (final_dot ? 1 : 0);
-  for (int k = 0; k < nloop; ++k) tree_step(prog + k, lane, 64, wn, wpq, perq, shr, wscl, nscale);
+  float2 *wgq = (float2 *)(t.perq_base + (int64_t)(q0 + wq0) * t.perq_stride);
+  const int64_t gstride = t.perq_stride / 8;
+  for (int k = 0; k < nloop; ++k)
+    tree_step(prog + k, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride);
 
   if (final_dot) {
     // closed root: FP64 inner product, reduced across the wave
