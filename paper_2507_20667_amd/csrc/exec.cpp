@@ -612,7 +612,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           tl.nq = 1;
           tl.qw = 1;
           TN_HIP(prof.timed(st, TN_KCLASS_TREE, tree_bytes_sh, tree_flops_sh,
-                            [&] { return launch_tree(st, tl, L.n_tree_shared, L.lds_shared); }),
+                            [&] { return launch_tree(st, tl, L.n_tree_shared, L.lds_shared, false); }),
                  "subtree kernel (shared)");
         }
         if (L.n_tree_perq) {
@@ -626,7 +626,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                             tree_flops_q * Q,
                             [&] {
                               return wave ? launch_tree_wave(st, tl, L.n_tree_perq, lds)
-                                          : launch_tree(st, tl, L.n_tree_perq, lds);
+                                          : launch_tree(st, tl, L.n_tree_perq, lds, true);
                             }),
                  "subtree kernel");
         }

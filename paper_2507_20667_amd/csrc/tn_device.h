@@ -289,7 +289,8 @@ hipError_t launch_dot(hipStream_t st, const DotDesc *d_desc, int64_t nelem, Oper
                       OutOperand C, Result *res, int64_t rbs, double2 *partials, int nblocks,
                       int nbatch);
 
-hipError_t launch_tree(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes);
+// dev: the subtrees may hold kind 3 steps (per-query subtrees)
+hipError_t launch_tree(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes, bool dev);
 // Per-query launches: every wave takes ceil(qw / 4) queries of its workgroup
 // through the whole program on its own (no barrier after the leaves load).
 hipError_t launch_tree_wave(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes);

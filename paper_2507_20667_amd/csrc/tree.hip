@@ -480,11 +480,13 @@ __device__ void tree_dev_impl(SP Sp, int lane, int nthr, int nqw, float2 *pq, in
   if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
 }
 
-template <class SP>
+// DEV: the program may hold kind 3 steps (per-query subtrees; a shared
+// subtree never does, and its launch leaves that code out)
+template <bool DEV, class SP>
 __device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
                                           const float2 *shr, int2 *scl, int nscale, float2 *gq,
                                           int64_t gstride) {
-  if (Sp->kind == 3) {
+  if (DEV && Sp->kind == 3) {
     if (Sp->pow2)
       tree_dev_impl<true>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
     else
@@ -579,6 +581,7 @@ __device__ __forceinline__ void tree_prologue(const TreeLaunch &t, KernargLaunch
   }
 }
 
+template <bool DEV>
 __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
   constexpr int W = kTreeStepWords;
   constexpr int CW = kTreeChunk * W;
@@ -675,13 +678,13 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
       }
     } else if (cur == 1) {
       // one step (a spine contraction): the whole workgroup on it
-      tree_step(S, tid, 256, nqw, pq, perq, shr, scl, h.nscale, gq, gstride);
+      tree_step<DEV>(S, tid, 256, nqw, pq, perq, shr, scl, h.nscale, gq, gstride);
     } else {
       // several independent steps of one level (largest first): one wave per
       // step, round robin
       const int wave = tid >> 6, lane = tid & 63;
       for (int i = wave; i < cur; i += 4)
-        tree_step(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale, gq, gstride);
+        tree_step<DEV>(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale, gq, gstride);
     }
     if (k + 1 < h.nchunks) {
       int32_t *dst = sbuf + ((k + 1) & 1) * CW;
@@ -760,7 +763,7 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
   float2 *wgq = (float2 *)(t.perq_base + (int64_t)(q0 + wq0) * t.perq_stride);
   const int64_t gstride = t.perq_stride / 8;
   for (int k = 0; k < nloop; ++k)
-    tree_step(prog + k, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride);
+    tree_step<true>(prog + k, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride);
 
   if (final_dot) {
     // closed root: FP64 inner product, reduced across the wave
@@ -839,7 +842,9 @@ size_t tree_lds_limit() {
       l = (size_t)v;
     if (l > 163840) l = 163840;
     if (l > 65536 &&
-        (hipFuncSetAttribute((const void *)k_tree, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (hipFuncSetAttribute((const void *)k_tree<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)l) != hipSuccess ||
+         hipFuncSetAttribute((const void *)k_tree<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)l) != hipSuccess ||
          hipFuncSetAttribute((const void *)k_tree_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)l) != hipSuccess))
@@ -849,11 +854,14 @@ size_t tree_lds_limit() {
   return limit;
 }
 
-hipError_t launch_tree(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes) {
+hipError_t launch_tree(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes, bool dev) {
   if (nsub <= 0 || t.nq <= 0) return hipSuccess;
   if (lds_bytes > tree_lds_limit()) return hipErrorInvalidValue;
   const int groups = (t.nq + t.qw - 1) / t.qw;
-  hipLaunchKernelGGL(k_tree, dim3(nsub, groups), dim3(256), lds_bytes, st, t);
+  if (dev)
+    hipLaunchKernelGGL(k_tree<true>, dim3(nsub, groups), dim3(256), lds_bytes, st, t);
+  else
+    hipLaunchKernelGGL(k_tree<false>, dim3(nsub, groups), dim3(256), lds_bytes, st, t);
   return hipGetLastError();
 }
 
