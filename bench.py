@@ -92,11 +92,13 @@ def strided_call(lib, plan, dev, net, n):
         arr[i] = lib.tn_leaf(t, base + i * 16, lib.TN_C64_DEVICE)
         strides[i] = n * 16
     outs = np.zeros((Q, 2), dtype=np.float64)
+    # the call's arguments, marshalled once
+    fn = lib.load().tn_contract_strided
+    args = (ctypes.c_void_p(plan), Q, n, ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(strides, ctypes.c_void_p),
+            outs.ctypes.data_as(ctypes.c_void_p), 1, lib.TN_C128, None, 0)
 
     def call():
-        rc = lib.load().tn_contract_strided(ctypes.c_void_p(plan), Q, n, ctypes.cast(arr, ctypes.c_void_p),
-                                            ctypes.cast(strides, ctypes.c_void_p),
-                                            outs.ctypes.data_as(ctypes.c_void_p), 1, lib.TN_C128, None, 0)
+        rc = fn(*args)
         if rc != 0:
             raise lib.TnError(rc, lib.tn_last_error())
         return outs
