@@ -1357,6 +1357,15 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       fprintf(stderr, "[tn]   subtree root %d: %d chunks, %d steps (%d gate form), %d shared leaf "
               "entries, %d per-query entries, %d scale records, %d loads\n", h.root_slot, h.nchunks,
               nsteps, gate, h.shared_elems, h.perq_elems, h.nscale, h.nloads);
+      // TN_DEBUG=steps: one line per step (kind, result and shared-index
+      // entries, gate fibers, device-workspace operands)
+      if (strcmp(getenv("TN_DEBUG"), "steps") == 0)
+        for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c)
+          for (int k = chunks[c].step0; k < chunks[c].step0 + chunks[c].nsteps; ++k) {
+            const TreeStep &s = steps[k];
+            fprintf(stderr, "[tn]     chunk %d step %d: kind %d nc %d ns %d nss %d ncs %d pow2 %d glob %d\n",
+                    c - h.chunk0, k, s.kind, s.nc, s.ns, s.nss, s.ncs, s.pow2, s.glob);
+          }
     }
   // blob
   auto put = [&](const void *src, size_t bytes) {

@@ -434,7 +434,7 @@ __device__ __forceinline__ void tree_step_q(SP Sp, int lane, int nthr, int nqw, 
 // pointers.  gq: the device workspace of the group's first query, gstride
 // float2 apart.
 template <bool P2, class SP>
-__device__ void tree_dev_impl(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
+__device__ __forceinline__ void tree_dev_impl(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
                               const float2 *shr, int2 *scl, int nscale, float2 *gq, int64_t gstride) {
   const int a = Sp->a, b = Sp->b, c = Sp->c, asl = Sp->asl, bsl = Sp->bsl, csl = Sp->csl;
   const int nc = Sp->nc, ns = Sp->ns, ncs = Sp->ncs, nss = Sp->nss, glob = Sp->glob;
@@ -480,6 +480,65 @@ __device__ void tree_dev_impl(SP Sp, int lane, int nthr, int nqw, float2 *pq, in
   if (qprev >= 0) atomicMax((unsigned int *)&scl[mad24(qprev, nscale, csl)].y, __float_as_uint(mx));
 }
 
+// Kind 3 for a single query with power-of-two maps.  GLOB (bit 1: A, 2: B,
+// 4: C in the device workspace) is a template argument here, so that every
+// operand has one memory space the compiler knows: LDS operands are read with
+// LDS instructions and the device workspace with global ones (a pointer that
+// may point at either compiles to the slower flat instructions).  The items
+// are dealt as in the single-query kind 0 form: operand scales read once,
+// no division per item.
+template <int GLOB, class SP>
+__device__ __forceinline__ void tree_dev_one(SP Sp, int lane, int nthr, float2 *pq, const float2 *shr,
+                                             int2 *scl, float2 *gq) {
+  const int a = Sp->a, b = Sp->b, c = Sp->c, asl = Sp->asl, bsl = Sp->bsl, csl = Sp->csl;
+  const int nc = Sp->nc, ns = Sp->ns, ncs = Sp->ncs, nss = Sp->nss;
+  int32_t cext[kTreeSeg], ca[kTreeSeg], cb[kTreeSeg], clg[kTreeSeg];
+  int32_t sext[kTreeSeg], sa[kTreeSeg], sb[kTreeSeg], slg[kTreeSeg];
+#pragma unroll
+  for (int i = 0; i < kTreeSeg; ++i) {
+    cext[i] = Sp->cext[i];
+    ca[i] = Sp->ca[i];
+    cb[i] = Sp->cb[i];
+    clg[i] = Sp->clg[i];
+    sext[i] = Sp->sext[i];
+    sa[i] = Sp->sa[i];
+    sb[i] = Sp->sb[i];
+    slg[i] = Sp->slg[i];
+  }
+  const int hl = threadIdx.x & 63;
+  const bool stab = ns <= 64;
+  int soa = 0, sob = 0;
+  if (stab && hl < ns) seg2r<true>(sext, sa, sb, slg, nss, hl, soa, sob);
+  const float2 *A0, *B0;
+  float2 *C;
+  if constexpr ((GLOB & 1) != 0)
+    A0 = gq + a;
+  else
+    A0 = (a & kPerQuery) ? pq + (a & ~kPerQuery) : shr + a;
+  if constexpr ((GLOB & 2) != 0)
+    B0 = gq + b;
+  else
+    B0 = (b & kPerQuery) ? pq + (b & ~kPerQuery) : shr + b;
+  if constexpr ((GLOB & 4) != 0)
+    C = gq + c;
+  else
+    C = pq + (c & ~kPerQuery);
+  const ItemScale z = uniform_scale(scl, asl, bsl);
+  const int e = z.e();
+  const float f = ldexpf(1.0f, -e);
+  float mx = 0.f;
+  for (int ci = lane; ci < nc; ci += nthr) {
+    int ao, bo;
+    seg2r<true>(cext, ca, cb, clg, ncs, ci, ao, bo);
+    const float2 r = dot_terms<true>(A0 + ao, B0 + bo, ns, stab, soa, sob, sext, sa, sb, slg, nss);
+    const float rr = r.x * f, ii = r.y * f;
+    C[ci] = make_float2(rr, ii);
+    mx = fmaxf(mx, fmaxf(fabsf(rr), fabsf(ii)));
+  }
+  if (lane == 0) scl[csl].x = z.za.x + z.zb.x + e;
+  atomicMax((unsigned int *)&scl[csl].y, __float_as_uint(mx));
+}
+
 // DEV: the program may hold kind 3 steps (per-query subtrees; a shared
 // subtree never does, and its launch leaves that code out)
 template <bool DEV, class SP>
@@ -487,10 +546,21 @@ __device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, fl
                                           const float2 *shr, int2 *scl, int nscale, float2 *gq,
                                           int64_t gstride) {
   if (DEV && Sp->kind == 3) {
-    if (Sp->pow2)
+    if (nqw == 1 && Sp->pow2) {
+      switch (Sp->glob) {  // 1 .. 7 (checked on the host)
+        case 1: tree_dev_one<1>(Sp, lane, nthr, pq, shr, scl, gq); break;
+        case 2: tree_dev_one<2>(Sp, lane, nthr, pq, shr, scl, gq); break;
+        case 3: tree_dev_one<3>(Sp, lane, nthr, pq, shr, scl, gq); break;
+        case 4: tree_dev_one<4>(Sp, lane, nthr, pq, shr, scl, gq); break;
+        case 5: tree_dev_one<5>(Sp, lane, nthr, pq, shr, scl, gq); break;
+        case 6: tree_dev_one<6>(Sp, lane, nthr, pq, shr, scl, gq); break;
+        default: tree_dev_one<7>(Sp, lane, nthr, pq, shr, scl, gq); break;
+      }
+    } else if (Sp->pow2) {
       tree_dev_impl<true>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
-    else
+    } else {
       tree_dev_impl<false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
+    }
     // a later step of this wave reads what this one stored to device memory
     __builtin_amdgcn_s_waitcnt(0);
     return;
