@@ -590,6 +590,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         tl.sloads = (const TreeSharedLoad *)(tb + L.tree_sload_off);
         tl.sgather = (const int2 *)(tb + L.tree_sg_off);
         tl.image = (const float2 *)(tb + L.tree_img_off);
+        tl.lanes = (const TreeLaneRec *)(tb + L.tree_lane_off);
         // overridden leaves in id order: read in place or from the staging block
         for (size_t k = 0; k < ovr.size() && k < (size_t)kTreeMaxOvr; ++k) {
           const int t = ovr[k];

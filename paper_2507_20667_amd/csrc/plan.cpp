@@ -1346,17 +1346,140 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   }
   L.lds_perq = tree_lds_bytes(L.tree_qw, max_scale_q, max_sh_q, max_pq_q, L.tree_wave);
   L.lds_perq1 = tree_lds_bytes(1, max_scale_q, max_sh_q, max_pq_q);
+  // blob
+  auto put = [&](const void *src, size_t bytes) {
+    size_t off = (L.tree_blob.size() + 255) & ~(size_t)255;
+    L.tree_blob.resize(off + bytes);
+    if (bytes) memcpy(L.tree_blob.data() + off, src, bytes);
+    return off;
+  };
+  // Kind 4: the small kind 2 steps of a level (result entries <= 64) packed
+  // into steps of up to 64 entries, one lane record per entry, for programs
+  // that only single-query groups run: the shared subtrees (one query per
+  // launch) and, when their groups hold one query each, the per-query ones.
+  // TN_TREE_PACK (tuning): 0 packs nothing, 1 only levels with several such
+  // steps of one ns, 2 (the default) every such step.
+  std::vector<TreeLaneRec> lanes;
+  {
+    int mode = 2;
+    if (const char *e = getenv("TN_TREE_PACK")) mode = atoi(e);
+    const bool one_q = (L.tree_wave && L.tree_qw <= 4) || L.tree_qw == 1;
+    std::vector<TreeStep> out;
+    out.reserve(steps.size());
+    for (size_t hi = 0; hi < hdrs.size(); ++hi) {
+      TreeHdr &h = hdrs[hi];
+      const bool can = mode > 0 && ((int)hi < L.n_tree_shared || one_q);
+      const int32_t s0 = (int32_t)out.size();
+      for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c) {
+        const int32_t c0 = (int32_t)out.size();
+        std::vector<int> cand[3];  // ns = 1, 2, 4
+        for (int k = chunks[c].step0; k < chunks[c].step0 + chunks[c].nsteps; ++k) {
+          const TreeStep &st = steps[k];
+          if (can && st.kind == 2 && st.nc <= 64 && (st.c & kPerQuery))
+            cand[st.ns == 1 ? 0 : st.ns == 2 ? 1 : 2].push_back(k);
+          else
+            out.push_back(st);
+        }
+        for (int g = 0; g < 3; ++g) {
+          if (cand[g].empty()) continue;
+          if (mode == 1 && cand[g].size() == 1) {
+            out.push_back(steps[cand[g][0]]);
+            continue;
+          }
+          const int ns = g == 0 ? 1 : g == 1 ? 2 : 4;
+          // one record per result entry, in the steps' order
+          std::vector<TreeLaneRec> recs;
+          std::vector<std::pair<int32_t, bool>> reads;  // query-region X and Y offsets
+          std::vector<int32_t> writes;
+          bool ok2 = true;
+          for (int k : cand[g]) {
+            const TreeStep &st = steps[k];
+            const int nfy = st.nss;
+            auto addr = [&](int32_t loc, int64_t off) -> uint32_t {
+              const bool q = (loc & kPerQuery) != 0;
+              const int64_t i = (int64_t)(loc & ~kPerQuery) + off;
+              const int64_t lim = q ? h.perq_elems : h.shared_elems;
+              if (i < 0 || i >= lim || i >= 0x8000) ok2 = false;
+              if (q) reads.push_back({(int32_t)i, true});
+              return (uint32_t)(i & 0x7fff) | (q ? 0u : 0x8000u);
+            };
+            for (int i = 0; i < st.nc; ++i) {
+              const int j = i % nfy;
+              int64_t f = i / nfy, xo = 0, co = 0;
+              for (int d = 0; d < st.ncs; ++d) {
+                const int64_t v = f % st.cext[d];
+                f /= st.cext[d];
+                xo += v * st.ca[d];
+                co += v * st.cb[d];
+              }
+              uint32_t xa[4] = {0, 0, 0, 0}, ya[4] = {0, 0, 0, 0};
+              for (int v = 0; v < ns; ++v) {
+                xa[v] = addr(st.a, xo + st.xs[v]);
+                ya[v] = addr(st.b, st.ymap[v * nfy + j]);
+              }
+              const int64_t ci = (int64_t)(st.c & ~kPerQuery) + co + st.cy[j];
+              if (ci < 0 || ci >= h.perq_elems || ci >= 0x8000 || st.csl < 0 || st.csl >= h.nscale ||
+                  st.csl >= 0x8000 || st.asl >= h.nscale || st.bsl >= h.nscale || st.asl >= 0xffff ||
+                  st.bsl >= 0xffff)
+                ok2 = false;
+              writes.push_back((int32_t)ci);
+              TreeLaneRec r;
+              memset(&r, 0, sizeof(r));
+              r.w[0] = xa[0] | xa[1] << 16;
+              r.w[1] = ya[0] | ya[1] << 16;
+              r.w[2] = (uint32_t)(ci & 0xffff) | (uint32_t)st.csl << 16 | (i == 0 ? 1u << 31 : 0u);
+              r.w[3] = (uint32_t)(st.asl < 0 ? 0xffff : st.asl) | (uint32_t)(st.bsl < 0 ? 0xffff : st.bsl) << 16;
+              r.w[4] = xa[2] | xa[3] << 16;
+              r.w[5] = ya[2] | ya[3] << 16;
+              recs.push_back(r);
+            }
+          }
+          // the packed steps are independent: no entry one of them writes is
+          // read by another (or by itself), and no two write the same entry
+          std::vector<int32_t> w2(writes);
+          std::sort(w2.begin(), w2.end());
+          ok2 = ok2 && std::adjacent_find(w2.begin(), w2.end()) == w2.end();
+          for (const auto &rd : reads)
+            if (std::binary_search(w2.begin(), w2.end(), rd.first)) ok2 = false;
+          if (!ok2) {  // keep the steps as they were
+            for (int k : cand[g]) out.push_back(steps[k]);
+            continue;
+          }
+          for (size_t r0 = 0; r0 < recs.size(); r0 += 64) {
+            TreeStep ps;
+            memset(&ps, 0, sizeof(ps));
+            ps.kind = 4;
+            ps.nc = (int32_t)std::min<size_t>(64, recs.size() - r0);
+            ps.ns = ns;
+            ps.tab = (int32_t)lanes.size();
+            for (int l = 0; l < ps.nc; ++l) lanes.push_back(recs[r0 + l]);
+            out.push_back(ps);
+          }
+        }
+        chunks[c].step0 = c0;
+        chunks[c].nsteps = (int32_t)out.size() - c0;
+        if (chunks[c].nsteps > kTreeChunk) {
+          L.tree_error = true;
+          return;
+        }
+      }
+      h.step0 = s0;
+      h.nsteps = (int32_t)out.size() - s0;
+    }
+    steps.swap(out);
+  }
   if (getenv("TN_DEBUG"))
     for (const TreeHdr &h : hdrs) {
-      int gate = 0, nsteps = 0;
+      int gate = 0, packed = 0, nsteps = 0;
       for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c)
         for (int k = chunks[c].step0; k < chunks[c].step0 + chunks[c].nsteps; ++k) {
           ++nsteps;
           gate += steps[k].kind == 2;
+          packed += steps[k].kind == 4;
         }
-      fprintf(stderr, "[tn]   subtree root %d: %d chunks, %d steps (%d gate form), %d shared leaf "
-              "entries, %d per-query entries, %d scale records, %d loads\n", h.root_slot, h.nchunks,
-              nsteps, gate, h.shared_elems, h.perq_elems, h.nscale, h.nloads);
+      fprintf(stderr, "[tn]   subtree root %d: %d chunks, %d steps (%d gate form, %d packed), %d shared "
+              "leaf entries, %d per-query entries, %d scale records, %d loads\n", h.root_slot,
+              h.nchunks, nsteps, gate, packed, h.shared_elems, h.perq_elems, h.nscale, h.nloads);
       // TN_DEBUG=steps: one line per step (kind, result and shared-index
       // entries, gate fibers, device-workspace operands)
       if (strcmp(getenv("TN_DEBUG"), "steps") == 0)
@@ -1367,17 +1490,11 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
                     c - h.chunk0, k, s.kind, s.nc, s.ns, s.nss, s.ncs, s.pow2, s.glob);
           }
     }
-  // blob
-  auto put = [&](const void *src, size_t bytes) {
-    size_t off = (L.tree_blob.size() + 255) & ~(size_t)255;
-    L.tree_blob.resize(off + bytes);
-    if (bytes) memcpy(L.tree_blob.data() + off, src, bytes);
-    return off;
-  };
   // device form of the steps (after the checks above, which read the plain
   // form): power-of-two maps carry their masks (extent - 1) and the kind 2
   // offsets are in bytes, which saves the kernels that arithmetic per step
   for (TreeStep &st : steps) {
+    if (st.kind == 4) continue;
     if (st.pow2) {
       // the kernels run every segment of a power-of-two map: the unused ones
       // must be all zero (mask, shift and strides)
@@ -1411,6 +1528,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   L.tree_sload_off = put(sloads.data(), sloads.size() * sizeof(TreeSharedLoad));
   L.tree_sg_off = put(sgather.data(), sgather.size() * sizeof(int2));
   L.tree_img_off = put(image.data(), image.size() * sizeof(float2));
+  L.tree_lane_off = put(lanes.data(), lanes.size() * sizeof(TreeLaneRec));
 }
 
 ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden, bool share,

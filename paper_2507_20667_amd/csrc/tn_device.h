@@ -150,6 +150,11 @@ constexpr int kTreeSpillElems = 512;
 // f of X's free index (the map: f -> (X offset ca, C offset cb), nc / nfy
 // values) and j < nfy: C[cb(f) + cy[j]] = sum_{s < ns} X[ca(f) + xs[s]] *
 // Y[ymap[s * nfy + j]], with ns, nfy in {1, 2, 4}.
+// kind 4, result entries of kind 2 steps of one level (one step or several
+// independent ones), one entry per lane: lane l < nc reads lane record tab + l
+// of the launch's lane table (TreeLaneRec) and computes
+// C[c] = sum_{s < ns} X[xa_s] * Y[ya_s] with the scales of its own step.  Only
+// single-query groups run kind 4 (every group of a program that holds one).
 // In the copy the kernels read, a map whose extents are all powers of two
 // (pow2) holds extent - 1 (the mask) in place of each extent and zeros in its
 // unused segments, and xs, cy and ymap are byte offsets.
@@ -171,7 +176,17 @@ struct TreeStep {
     };
   };
   int32_t glob;           // kind 3: operands in the query's device workspace
-  int32_t pad;
+  int32_t tab;            // kind 4: the first lane's record in the lane table
+};
+
+// A kind 4 lane's record (32 bytes).  Each address is 16 bits: bit 15 set for
+// the shared region, clear for the query's region, bits 0-14 the float2 offset
+// in it.  w[0]: xa_0 | xa_1 << 16, w[1]: ya_0 | ya_1 << 16, w[2]: c (query
+// region) | csl << 16 | (the step's first entry) << 31, w[3]: asl | bsl << 16
+// (0xffff: a leaf, scale 1), w[4]: xa_2 | xa_3 << 16, w[5]: ya_2 | ya_3 << 16
+// (ns = 4 only), w[6], w[7]: 0.
+struct TreeLaneRec {
+  uint32_t w[8];
 };
 constexpr int kTreeStepWords = (int)(sizeof(TreeStep) / 4);
 
@@ -231,6 +246,7 @@ struct TreeLaunch {
   const TreeSharedLoad *sloads;
   const int2 *sgather;  // (LDS float2 offset, shared-part float2 offset) per entry
   const float2 *image;  // shared leaves of every subtree, each in its LDS order
+  const TreeLaneRec *lanes;  // kind 4 lane records
   OvrSrc ovr[kTreeMaxOvr];
   uint8_t *shared_base;
   uint8_t *perq_base;

@@ -105,6 +105,7 @@ struct ExecLayout {
   // subtree programs: [TreeHdr...][TreeStep...][TreeLeafLoad...][image float2...]
   std::vector<uint8_t> tree_blob;
   size_t tree_chunk_off = 0, tree_step_off = 0, tree_load_off = 0, tree_img_off = 0;
+  size_t tree_lane_off = 0;  // kind 4 lane records
   size_t tree_sload_off = 0, tree_sg_off = 0;
   // shared vertices inside per-query subtrees that run as shared subtrees of
   // their own (computed once, read by the per-query programs)

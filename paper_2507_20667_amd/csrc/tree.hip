@@ -539,12 +539,71 @@ __device__ __forceinline__ void tree_dev_one(SP Sp, int lane, int nthr, float2 *
   atomicMax((unsigned int *)&scl[csl].y, __float_as_uint(mx));
 }
 
+// Kind 4: up to 64 result entries of a level's small gate steps, one per
+// lane.  A lane reads its addresses and scale records from its lane record
+// (one global load of 16 bytes, two for ns = 4, from a table every wave of the
+// launch reads) instead of decoding a step's maps, so several independent
+// small steps cost one step of the wave.  Single-query groups only.
+template <int NS>
+__device__ __forceinline__ void tree_lane_step(const TreeLaneRec *rec, int lane, int nl, float2 *pq,
+                                               const float2 *shr, int2 *scl) {
+  if (lane >= nl) return;
+  const uint4 *r = (const uint4 *)(rec + lane);
+  const uint4 r0 = r[0];
+  uint4 r1 = make_uint4(0u, 0u, 0u, 0u);
+  if (NS == 4) r1 = r[1];
+  // bit 15: the shared region, else the query's
+  auto at = [&](uint32_t v) -> float2 { return ((v & 0x8000u) ? shr : pq)[v & 0x7fffu]; };
+  float2 x[NS], y[NS];
+  x[0] = at(r0.x & 0xffffu);
+  y[0] = at(r0.y & 0xffffu);
+  if (NS >= 2) {
+    x[1] = at(r0.x >> 16);
+    y[1] = at(r0.y >> 16);
+  }
+  if (NS == 4) {
+    x[2] = at(r1.x & 0xffffu);
+    x[3] = at(r1.x >> 16);
+    y[2] = at(r1.y & 0xffffu);
+    y[3] = at(r1.y >> 16);
+  }
+  const uint32_t asl = r0.w & 0xffffu, bsl = r0.w >> 16;
+  const int2 za = asl != 0xffffu ? scl[asl] : make_int2(0, 0);
+  const int2 zb = bsl != 0xffffu ? scl[bsl] : make_int2(0, 0);
+  const int e = tn_scale_exp((uint32_t)za.y) + tn_scale_exp((uint32_t)zb.y);
+  const float f = ldexpf(1.0f, -e);
+  float re = 0.f, im = 0.f;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    re = fmaf(x[s].x, y[s].x, re);
+    re = fmaf(-x[s].y, y[s].y, re);
+    im = fmaf(x[s].x, y[s].y, im);
+    im = fmaf(x[s].y, y[s].x, im);
+  }
+  re *= f;
+  im *= f;
+  pq[r0.z & 0xffffu] = make_float2(re, im);
+  const int csl = (int)((r0.z >> 16) & 0x7fffu);
+  if (r0.z >> 31) scl[csl].x = za.x + zb.x + e;
+  atomicMax((unsigned int *)&scl[csl].y, __float_as_uint(fmaxf(fabsf(re), fabsf(im))));
+}
+
 // DEV: the program may hold kind 3 steps (per-query subtrees; a shared
 // subtree never does, and its launch leaves that code out)
 template <bool DEV, class SP>
 __device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
                                           const float2 *shr, int2 *scl, int nscale, float2 *gq,
-                                          int64_t gstride) {
+                                          int64_t gstride, const TreeLaneRec *lanes) {
+  if (Sp->kind == 4) {
+    const TreeLaneRec *rec = lanes + Sp->tab;
+    if (Sp->ns == 1)
+      tree_lane_step<1>(rec, lane, Sp->nc, pq, shr, scl);
+    else if (Sp->ns == 2)
+      tree_lane_step<2>(rec, lane, Sp->nc, pq, shr, scl);
+    else
+      tree_lane_step<4>(rec, lane, Sp->nc, pq, shr, scl);
+    return;
+  }
   if (DEV && Sp->kind == 3) {
     if (nqw == 1 && Sp->pow2) {
       switch (Sp->glob) {  // 1 .. 7 (checked on the host)
@@ -748,13 +807,13 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
       }
     } else if (cur == 1) {
       // one step (a spine contraction): the whole workgroup on it
-      tree_step<DEV>(S, tid, 256, nqw, pq, perq, shr, scl, h.nscale, gq, gstride);
+      tree_step<DEV>(S, tid, 256, nqw, pq, perq, shr, scl, h.nscale, gq, gstride, t.lanes);
     } else {
       // several independent steps of one level (largest first): one wave per
       // step, round robin
       const int wave = tid >> 6, lane = tid & 63;
       for (int i = wave; i < cur; i += 4)
-        tree_step<DEV>(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale, gq, gstride);
+        tree_step<DEV>(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale, gq, gstride, t.lanes);
     }
     if (k + 1 < h.nchunks) {
       int32_t *dst = sbuf + ((k + 1) & 1) * CW;
@@ -833,7 +892,7 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
   float2 *wgq = (float2 *)(t.perq_base + (int64_t)(q0 + wq0) * t.perq_stride);
   const int64_t gstride = t.perq_stride / 8;
   for (int k = 0; k < nloop; ++k)
-    tree_step<true>(prog + k, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride);
+    tree_step<true>(prog + k, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride, t.lanes);
 
   if (final_dot) {
     // closed root: FP64 inner product, reduced across the wave
