@@ -1204,7 +1204,9 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     h.step0 = h.nchunks ? chunks[h.chunk0].step0 : (int32_t)steps.size();
     h.nsteps = (int32_t)steps.size() - h.step0;
     h.perq_elems = (int32_t)(base + lp.peak);
-    h.nscale = (int32_t)scale.size();
+    // one record more than the vertices: it stays zero, and a kind 4 lane
+    // reads it for an operand that is a leaf (scale 1)
+    h.nscale = (int32_t)scale.size() + 1;
     h.root_loc = loc[r];
     h.root_scale = scale[r];
     h.root_elems = (int32_t)std::max<int64_t>(p->nodes[r - nv].out.size(), 1);
@@ -1358,11 +1360,14 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   // that only single-query groups run: the shared subtrees (one query per
   // launch) and, when their groups hold one query each, the per-query ones.
   // TN_TREE_PACK (tuning): 0 packs nothing, 1 only levels with several such
-  // steps of one ns, 2 (the default) every such step.
+  // steps of one ns, 2 (the default) every such step.  TN_TREE_PACK_NC
+  // (tuning) sets the size limit; a step above 64 entries takes several kind
+  // 4 steps.
   std::vector<TreeLaneRec> lanes;
   {
-    int mode = 2;
+    int mode = 2, most = 64;
     if (const char *e = getenv("TN_TREE_PACK")) mode = atoi(e);
+    if (const char *e = getenv("TN_TREE_PACK_NC")) most = std::max(1, atoi(e));  // tuning
     const bool one_q = (L.tree_wave && L.tree_qw <= 4) || L.tree_qw == 1;
     std::vector<TreeStep> out;
     out.reserve(steps.size());
@@ -1375,7 +1380,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
         std::vector<int> cand[3];  // ns = 1, 2, 4
         for (int k = chunks[c].step0; k < chunks[c].step0 + chunks[c].nsteps; ++k) {
           const TreeStep &st = steps[k];
-          if (can && st.kind == 2 && st.nc <= 64 && (st.c & kPerQuery))
+          if (can && st.kind == 2 && st.nc <= most && (st.c & kPerQuery))
             cand[st.ns == 1 ? 0 : st.ns == 2 ? 1 : 2].push_back(k);
           else
             out.push_back(st);
@@ -1395,13 +1400,14 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
           for (int k : cand[g]) {
             const TreeStep &st = steps[k];
             const int nfy = st.nss;
+            // byte offset in the operand's region
             auto addr = [&](int32_t loc, int64_t off) -> uint32_t {
               const bool q = (loc & kPerQuery) != 0;
               const int64_t i = (int64_t)(loc & ~kPerQuery) + off;
               const int64_t lim = q ? h.perq_elems : h.shared_elems;
-              if (i < 0 || i >= lim || i >= 0x8000) ok2 = false;
+              if (i < 0 || i >= lim || 8 * i >= 0x10000) ok2 = false;
               if (q) reads.push_back({(int32_t)i, true});
-              return (uint32_t)(i & 0x7fff) | (q ? 0u : 0x8000u);
+              return (uint32_t)(8 * i) & 0xffffu;
             };
             for (int i = 0; i < st.nc; ++i) {
               const int j = i % nfy;
@@ -1418,17 +1424,19 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
                 ya[v] = addr(st.b, st.ymap[v * nfy + j]);
               }
               const int64_t ci = (int64_t)(st.c & ~kPerQuery) + co + st.cy[j];
-              if (ci < 0 || ci >= h.perq_elems || ci >= 0x8000 || st.csl < 0 || st.csl >= h.nscale ||
-                  st.csl >= 0x8000 || st.asl >= h.nscale || st.bsl >= h.nscale || st.asl >= 0xffff ||
-                  st.bsl >= 0xffff)
+              if (ci < 0 || ci >= h.perq_elems || 8 * ci >= 0x10000 || st.csl < 0 ||
+                  st.csl >= h.nscale - 1 || h.nscale > 0x7fff || st.asl >= h.nscale - 1 ||
+                  st.bsl >= h.nscale - 1)
                 ok2 = false;
               writes.push_back((int32_t)ci);
               TreeLaneRec r;
               memset(&r, 0, sizeof(r));
               r.w[0] = xa[0] | xa[1] << 16;
               r.w[1] = ya[0] | ya[1] << 16;
-              r.w[2] = (uint32_t)(ci & 0xffff) | (uint32_t)st.csl << 16 | (i == 0 ? 1u << 31 : 0u);
-              r.w[3] = (uint32_t)(st.asl < 0 ? 0xffff : st.asl) | (uint32_t)(st.bsl < 0 ? 0xffff : st.bsl) << 16;
+              r.w[2] = (uint32_t)(8 * ci) | (uint32_t)st.csl << 16 | (i == 0 ? 1u << 31 : 0u);
+              const int32_t zero = h.nscale - 1;  // the record no step writes
+              r.w[3] = (uint32_t)(st.asl < 0 ? zero : st.asl) | ((st.a & kPerQuery) ? 0u : 1u << 15) |
+                       (uint32_t)(st.bsl < 0 ? zero : st.bsl) << 16 | ((st.b & kPerQuery) ? 0u : 1u << 31);
               r.w[4] = xa[2] | xa[3] << 16;
               r.w[5] = ya[2] | ya[3] << 16;
               recs.push_back(r);

@@ -179,12 +179,13 @@ struct TreeStep {
   int32_t tab;            // kind 4: the first lane's record in the lane table
 };
 
-// A kind 4 lane's record (32 bytes).  Each address is 16 bits: bit 15 set for
-// the shared region, clear for the query's region, bits 0-14 the float2 offset
-// in it.  w[0]: xa_0 | xa_1 << 16, w[1]: ya_0 | ya_1 << 16, w[2]: c (query
-// region) | csl << 16 | (the step's first entry) << 31, w[3]: asl | bsl << 16
-// (0xffff: a leaf, scale 1), w[4]: xa_2 | xa_3 << 16, w[5]: ya_2 | ya_3 << 16
-// (ns = 4 only), w[6], w[7]: 0.
+// A kind 4 lane's record (32 bytes).  Each address is a 16-bit byte offset in
+// its operand's LDS region.  w[0]: xa_0 | xa_1 << 16, w[1]: ya_0 | ya_1 << 16,
+// w[2]: c (query region) | csl << 16 | (the step's first entry) << 31,
+// w[3]: asl | (X in the shared region) << 15 | bsl << 16 | (Y in the shared
+// region) << 31 (scale indices of 15 bits; a leaf operand has the program's
+// last record, which no step writes and the prologue clears),
+// w[4]: xa_2 | xa_3 << 16, w[5]: ya_2 | ya_3 << 16 (ns = 4 only), w[6], w[7]: 0.
 struct TreeLaneRec {
   uint32_t w[8];
 };

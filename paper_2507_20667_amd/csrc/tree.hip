@@ -544,32 +544,29 @@ __device__ __forceinline__ void tree_dev_one(SP Sp, int lane, int nthr, float2 *
 // (one global load of 16 bytes, two for ns = 4, from a table every wave of the
 // launch reads) instead of decoding a step's maps, so several independent
 // small steps cost one step of the wave.  Single-query groups only.
+// r0, r1: the lane's record (r1 for ns = 4 only).
 template <int NS>
-__device__ __forceinline__ void tree_lane_step(const TreeLaneRec *rec, int lane, int nl, float2 *pq,
-                                               const float2 *shr, int2 *scl) {
-  if (lane >= nl) return;
-  const uint4 *r = (const uint4 *)(rec + lane);
-  const uint4 r0 = r[0];
-  uint4 r1 = make_uint4(0u, 0u, 0u, 0u);
-  if (NS == 4) r1 = r[1];
-  // bit 15: the shared region, else the query's
-  auto at = [&](uint32_t v) -> float2 { return ((v & 0x8000u) ? shr : pq)[v & 0x7fffu]; };
+__device__ __forceinline__ void tree_lane_exec(uint4 r0, uint4 r1, float2 *pq, const float2 *shr,
+                                               int2 *scl) {
+  // each operand's region once (bits 15 and 31 of w[3]), then byte offsets
+  const char *xb = (const char *)((r0.w & 0x8000u) ? shr : pq);
+  const char *yb = (const char *)((r0.w >> 31) ? shr : pq);
+  auto at = [](const char *base, uint32_t off) -> float2 { return *(const float2 *)(base + off); };
   float2 x[NS], y[NS];
-  x[0] = at(r0.x & 0xffffu);
-  y[0] = at(r0.y & 0xffffu);
+  x[0] = at(xb, r0.x & 0xffffu);
+  y[0] = at(yb, r0.y & 0xffffu);
   if (NS >= 2) {
-    x[1] = at(r0.x >> 16);
-    y[1] = at(r0.y >> 16);
+    x[1] = at(xb, r0.x >> 16);
+    y[1] = at(yb, r0.y >> 16);
   }
   if (NS == 4) {
-    x[2] = at(r1.x & 0xffffu);
-    x[3] = at(r1.x >> 16);
-    y[2] = at(r1.y & 0xffffu);
-    y[3] = at(r1.y >> 16);
+    x[2] = at(xb, r1.x & 0xffffu);
+    x[3] = at(xb, r1.x >> 16);
+    y[2] = at(yb, r1.y & 0xffffu);
+    y[3] = at(yb, r1.y >> 16);
   }
-  const uint32_t asl = r0.w & 0xffffu, bsl = r0.w >> 16;
-  const int2 za = asl != 0xffffu ? scl[asl] : make_int2(0, 0);
-  const int2 zb = bsl != 0xffffu ? scl[bsl] : make_int2(0, 0);
+  // a leaf operand's index is that of a record that stays zero
+  const int2 za = scl[r0.w & 0x7fffu], zb = scl[(r0.w >> 16) & 0x7fffu];
   const int e = tn_scale_exp((uint32_t)za.y) + tn_scale_exp((uint32_t)zb.y);
   const float f = ldexpf(1.0f, -e);
   float re = 0.f, im = 0.f;
@@ -582,10 +579,18 @@ __device__ __forceinline__ void tree_lane_step(const TreeLaneRec *rec, int lane,
   }
   re *= f;
   im *= f;
-  pq[r0.z & 0xffffu] = make_float2(re, im);
+  *(float2 *)((char *)pq + (r0.z & 0xffffu)) = make_float2(re, im);
   const int csl = (int)((r0.z >> 16) & 0x7fffu);
   if (r0.z >> 31) scl[csl].x = za.x + zb.x + e;
   atomicMax((unsigned int *)&scl[csl].y, __float_as_uint(fmaxf(fabsf(re), fabsf(im))));
+}
+
+template <int NS>
+__device__ __forceinline__ void tree_lane_step(const TreeLaneRec *rec, int lane, int nl, float2 *pq,
+                                               const float2 *shr, int2 *scl) {
+  if (lane >= nl) return;
+  const uint4 *r = (const uint4 *)(rec + lane);
+  tree_lane_exec<NS>(r[0], NS == 4 ? r[1] : make_uint4(0u, 0u, 0u, 0u), pq, shr, scl);
 }
 
 // DEV: the program may hold kind 3 steps (per-query subtrees; a shared
@@ -891,8 +896,35 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
   const int nloop = nsteps - (final_dot ? 1 : 0);
   float2 *wgq = (float2 *)(t.perq_base + (int64_t)(q0 + wq0) * t.perq_stride);
   const int64_t gstride = t.perq_stride / 8;
-  for (int k = 0; k < nloop; ++k)
-    tree_step<true>(prog + k, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride, t.lanes);
+  // a kind 4 step's lane record is loaded one step ahead, so that its
+  // latency overlaps the step before
+  uint4 n0 = make_uint4(0u, 0u, 0u, 0u), n1 = n0;
+  auto fetch = [&](int k) {
+    const CStep S = prog + k;
+    if (S->kind == 4 && lane < S->nc) {
+      const uint4 *r = (const uint4 *)(t.lanes + S->tab + lane);
+      n0 = r[0];
+      if (S->ns == 4) n1 = r[1];
+    }
+  };
+  if (nloop > 0) fetch(0);
+  for (int k = 0; k < nloop; ++k) {
+    const CStep S = prog + k;
+    const uint4 c0 = n0, c1 = n1;
+    if (k + 1 < nloop) fetch(k + 1);
+    if (S->kind == 4) {
+      if (lane < S->nc) {
+        if (S->ns == 1)
+          tree_lane_exec<1>(c0, c1, wpq, shr, wscl);
+        else if (S->ns == 2)
+          tree_lane_exec<2>(c0, c1, wpq, shr, wscl);
+        else
+          tree_lane_exec<4>(c0, c1, wpq, shr, wscl);
+      }
+    } else {
+      tree_step<true>(S, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride, t.lanes);
+    }
+  }
 
   if (final_dot) {
     // closed root: FP64 inner product, reduced across the wave
