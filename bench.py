@@ -91,7 +91,10 @@ def strided_call(lib, plan, dev, net, n):
     for i, t in enumerate(ids):
         arr[i] = lib.tn_leaf(t, base + i * 16, lib.TN_C64_DEVICE)
         strides[i] = n * 16
-    outs = np.zeros((Q, 2), dtype=np.float64)
+    # the results go to pinned host memory, which the subtree kernel writes itself
+    import torch
+    outs_t = torch.zeros((Q, 2), dtype=torch.float64, pin_memory=True)
+    outs = outs_t.numpy()
     # the call's arguments, marshalled once
     fn = lib.load().tn_contract_strided
     args = (ctypes.c_void_p(plan), Q, n, ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(strides, ctypes.c_void_p),
@@ -102,7 +105,7 @@ def strided_call(lib, plan, dev, net, n):
         if rc != 0:
             raise lib.TnError(rc, lib.tn_last_error())
         return outs
-    call.keep = (arr, strides, dev)
+    call.keep = (arr, strides, dev, outs_t)
     return call
 
 

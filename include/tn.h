@@ -246,7 +246,12 @@ tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *qu
  *                  and unchanged until the call returns.
  *   out            host memory; query q's result (the product of the output
  *                  dimensions elements of out_dtype) starts out_stride
- *                  elements after query q - 1's.
+ *                  elements after query q - 1's.  When out is pinned host
+ *                  memory (hipHostMalloc), 16-byte aligned, the results are
+ *                  TN_C128 closed amplitudes without TN_FLAG_KEEP_SCALE or
+ *                  TN_FLAG_GRAPH, the kernel that computes them writes each
+ *                  value into out itself (no staging or conversion on the
+ *                  host); the values are the same either way.
  *   log2_scales    num_queries values (TN_FLAG_KEEP_SCALE) or NULL.
  * Errors: TN_E_INVALID_ARG (bad ids, dtypes, strides, out_stride smaller
  * than a result, host-only plan), TN_E_NOMEM, TN_E_DEVICE.  Synchronous.

@@ -255,6 +255,27 @@ tn_status tn_contract_strided(tn_plan *p, int32_t num_queries, int32_t num_overr
   so.leaves.assign(overrides, overrides + num_overrides);
   so.strides.assign(strides, strides + num_overrides);
   const size_t esz = out_dtype == TN_C128 ? 16 : 8;
+  // complex128 results in pinned host memory (the first and the last result
+  // pinned, with one host-to-device mapping): the kernels may write them
+  // there themselves
+  so.log2s = log2_scales != nullptr;
+  if (out_dtype == TN_C128 && (uintptr_t)out % 16 == 0) {
+    const char *o0 = (const char *)out;
+    const char *o1 = o0 + ((size_t)num_queries - 1) * (size_t)out_stride * esz;
+    hipPointerAttribute_t a0, a1;
+    memset(&a0, 0, sizeof(a0));
+    memset(&a1, 0, sizeof(a1));
+    const bool got = hipPointerGetAttributes(&a0, o0) == hipSuccess &&
+                     hipPointerGetAttributes(&a1, o1) == hipSuccess;
+    if (!got) (void)hipGetLastError();  // pageable memory: not the caller's error
+    if (got && a0.type == hipMemoryTypeHost && a1.type == hipMemoryTypeHost && a0.hostPointer &&
+        a0.devicePointer && a1.hostPointer && a1.devicePointer &&
+        (const char *)a0.devicePointer - (const char *)a0.hostPointer ==
+            (const char *)a1.devicePointer - (const char *)a1.hostPointer) {
+      so.dout = (double2 *)((char *)a0.devicePointer + (o0 - (const char *)a0.hostPointer));
+      so.dout_stride = out_stride;
+    }
+  }
   std::vector<QueryIO> qs((size_t)num_queries);
   for (int32_t i = 0; i < num_queries; ++i) {
     qs[i].out = (char *)out + (size_t)i * (size_t)out_stride * esz;

@@ -549,6 +549,10 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       // (host memory the device writes to; visible after the synchronize
       // below), which saves the copy back
       Result *res_out = dot_root ? hr : res;
+      // results straight into the caller's pinned array: complex128 values
+      // scaled to 1, a closed root computed by the subtree kernel, no graph
+      const bool direct = so && so->dout && out_dtype == TN_C128 && !(flags & TN_FLAG_KEEP_SCALE) &&
+                          dot_root && !root_shared && trees && p->in_tree[p->root] && !gmode;
       const Operand R = operand(p->root);
       // TN_FLAG_GRAPH: replay the launch sequence captured with the same
       // workspace, layout and in-place overrides, or capture it now
@@ -609,6 +613,8 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         tl.slots_q = slots_q;
         tl.slot_stride = perq_sl;
         tl.res = res_out;
+        tl.dres = direct ? so->dout + (int64_t)q0 * so->dout_stride : nullptr;
+        tl.dres_stride = so ? so->dout_stride : 0;
         if (L.n_tree_shared) {
           tl.nq = 1;
           tl.qw = 1;
@@ -813,10 +819,13 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       const double t_launched = dbg ? ms_since(t_enter) : 0.0;
       TN_HIP(hipStreamSynchronize(st), "stream synchronize");
       if (dbg)
-        fprintf(stderr, "[tn] run_group %d queries: host prep+launch %.3f ms, device done at %.3f ms\n",
-                Q, t_launched, ms_since(t_enter));
+        fprintf(stderr, "[tn] run_group %d queries: host prep+launch %.3f ms, device done at %.3f ms%s\n",
+                Q, t_launched, ms_since(t_enter), direct ? " (results written by the kernel)" : "");
       if (prof.on) prof.collect();
-      for (int qi = 0; qi < Q; ++qi) {
+      // written by the kernel: only the scales (1) remain, if asked for
+      for (int qi = 0; qi < Q && direct && so->log2s; ++qi)
+        if (qs[q0 + qi].log2s) *qs[q0 + qi].log2s = 0.0;
+      for (int qi = 0; qi < Q && !direct; ++qi) {
         const QueryIO &q = qs[q0 + qi];
         const bool keep = (flags & TN_FLAG_KEEP_SCALE) != 0;
         if (dot_root) {

@@ -256,6 +256,10 @@ struct TreeLaunch {
   Slot *slots_q;
   int64_t slot_stride;  // Slot records per query
   Result *res;
+  // when set, a closed root's value goes straight to dres[q * dres_stride]
+  // as complex128 (scaled to 1) instead of a Result record
+  double2 *dres;
+  int64_t dres_stride;
   int32_t nq;           // queries in this launch
   int32_t qw;           // queries per workgroup
 };

@@ -355,6 +355,12 @@ struct QueryIO {
 struct StridedOvr {
   std::vector<tn_leaf> leaves;
   std::vector<int64_t> strides;
+  // the results' complex128 array when the device can write it (pinned host
+  // memory): its device address and the stride in complex128 elements; the
+  // subtree kernel then writes a closed root's values there itself
+  double2 *dout = nullptr;
+  int64_t dout_stride = 0;
+  bool log2s = false;  // the caller asked for scales (written on the host)
 };
 // Resources of one executing thread: its stream, its pinned staging, an
 // optional profiler and optionally a workspace reserved beforehand.

@@ -653,6 +653,21 @@ __device__ __forceinline__ void tree_write_result(Result *r, double vr, double v
   r->pad = 0.0;
 }
 
+// Query q's closed root: its Result record, or (dres set) the value itself,
+// the record's mantissas scaled by 2^log2s exactly as a reader of the record
+// would.
+__device__ __forceinline__ void tree_emit_result(const TreeLaunch &t, int q, double vr, double vi,
+                                                 int2 za, int2 zb) {
+  if (t.dres == nullptr) {
+    tree_write_result(t.res + q, vr, vi, za, zb);
+    return;
+  }
+  Result r;
+  tree_write_result(&r, vr, vi, za, zb);
+  const int e = (int)r.log2s;
+  t.dres[(int64_t)q * t.dres_stride] = make_double2(ldexp(r.re, e), ldexp(r.im, e));
+}
+
 // The leaves into LDS, by the whole workgroup: the shared leaves from the
 // image, the shared intermediates through the gather list, their scale
 // records into every query's table, the per-query scale records cleared and
@@ -806,7 +821,7 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
           const int2 *sc = scl + q * h.nscale;
           const int2 za = st.asl >= 0 ? sc[st.asl] : make_int2(0, 0);
           const int2 zb = st.bsl >= 0 ? sc[st.bsl] : make_int2(0, 0);
-          tree_write_result(t.res + (q0 + q), red[0].x, red[0].y, za, zb);
+          tree_emit_result(t, q0 + q, red[0].x, red[0].y, za, zb);
         }
         __syncthreads();
       }
@@ -963,7 +978,7 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
         const int2 *sc = wscl + q * nscale;
         const int2 za = S->asl >= 0 ? sc[S->asl] : make_int2(0, 0);
         const int2 zb = S->bsl >= 0 ? sc[S->bsl] : make_int2(0, 0);
-        tree_write_result(t.res + (q0 + wq0 + q), re, im, za, zb);
+        tree_emit_result(t, q0 + wq0 + q, re, im, za, zb);
       }
     }
     return;

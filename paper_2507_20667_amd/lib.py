@@ -226,11 +226,16 @@ def tn_contract_batch(ctx, queries, result_shapes, out_dtype=TN_C128, flags=0):
     return outs, l2[:n], st[:n]
 
 
-def tn_contract_strided(plan, num_queries, overrides, result_shape=(), out_dtype=TN_C128, flags=0):
+def tn_contract_strided(plan, num_queries, overrides, result_shape=(), out_dtype=TN_C128, flags=0,
+                        out=None, out_stride=None, scales=True):
     """overrides: list of (tensor id, data, stride bytes, dtype) where data is a
     numpy array holding every query's copy (its base address is query 0's) or
     a device address (int) with dtype TN_C64_DEVICE.  Returns (results of
-    shape (num_queries,) + result_shape, log2 scales)."""
+    shape (num_queries,) + result_shape, log2 scales).  out: an array to write
+    the results into instead (query q's at element q * out_stride, out_stride
+    defaulting to a result's size; pinned host memory lets the kernels write
+    complex128 results there themselves), returned as given; scales=False asks
+    for no log2 scales (None returned)."""
     n = len(overrides)
     arr = (tn_leaf * max(1, n))()
     strides = (ctypes.c_int64 * max(1, n))()
@@ -245,13 +250,21 @@ def tn_contract_strided(plan, num_queries, overrides, result_shape=(), out_dtype
         arr[i] = tn_leaf(int(t), ptr, dt)
         strides[i] = int(stride)
     res = int(np.prod(result_shape)) if result_shape else 1
-    out = np.zeros((num_queries,) + tuple(result_shape),
-                   dtype=np.complex128 if out_dtype == TN_C128 else np.complex64)
-    l2 = np.zeros(max(1, num_queries), dtype=np.float64)
+    stride = res if out_stride is None else int(out_stride)
+    if out is None:
+        out = np.zeros((num_queries,) + tuple(result_shape),
+                       dtype=np.complex128 if out_dtype == TN_C128 else np.complex64)
+        stride = res
+    else:
+        want = np.complex128 if out_dtype == TN_C128 else np.complex64
+        if out.dtype != want or not out.flags.c_contiguous or out.size < max(0, num_queries - 1) * stride + res:
+            raise ValueError("out: wrong dtype, not contiguous or too small")
+    l2 = np.zeros(max(1, num_queries), dtype=np.float64) if scales else None
     _check(load().tn_contract_strided(ctypes.c_void_p(plan), int(num_queries), n,
                                       ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(strides, ctypes.c_void_p),
-                                      _p(out), ctypes.c_int64(res), out_dtype, _p(l2), flags))
-    return out, l2[:num_queries]
+                                      _p(out), ctypes.c_int64(stride), out_dtype,
+                                      _p(l2) if scales else None, flags))
+    return out, (l2[:num_queries] if scales else None)
 
 
 def tn_serve_submit(ctx, plan, overrides=None) -> int:

@@ -257,6 +257,42 @@ def test_strided_matches_batch(ctx, where):
     ctx.free_plan(p)
 
 
+@pytest.mark.parametrize("stride", [1, 3])
+def test_strided_pinned_output(ctx, capfd, monkeypatch, stride):
+    """Complex128 results into pinned host memory: the subtree kernel writes each
+    closed root's value there itself (the call says so under TN_DEBUG), bit for
+    bit what the host writes into pageable memory from the result records, the
+    results `stride` elements apart (the elements between left alone), with and
+    without the scales asked for; and the values agree with the oracle."""
+    import torch
+    circ = brickwork_circuit(16, 10, 3)
+    net = amplitude_network(circ, 0)
+    plan = _plan(net, 4)
+    p = ctx.load_network(net, plan.partition_of, 4, plan.tree)
+    xs = random_bitstrings(circ.n, 48, 12)
+    ids = output_tensor_ids(net)
+    vec = {t: np.stack([amplitude_overrides(net, circ, x)[t] for x in xs]) for t in ids}
+    ovr = [(t, vec[t].astype(np.complex128), 16 * vec[t].shape[1], lib.TN_C128) for t in ids]
+    ref, _ = lib.tn_contract_strided(p, len(xs), ovr)  # pageable: converted on the host
+    pinned = torch.zeros((len(xs), stride), dtype=torch.complex128, pin_memory=True)
+    out = pinned.numpy()
+    out[:] = np.nan
+    monkeypatch.setenv("TN_DEBUG", "1")
+    got, l2 = lib.tn_contract_strided(p, len(xs), ovr, out=out, out_stride=stride)
+    monkeypatch.delenv("TN_DEBUG")
+    assert "results written by the kernel" in capfd.readouterr().err
+    assert np.array_equal(got[:, 0], ref)
+    assert np.all(l2 == 0.0)
+    assert np.all(np.isnan(got[:, 1:]))
+    out[:, 0] = np.nan
+    got2, none = lib.tn_contract_strided(p, len(xs), ovr, out=out, out_stride=stride, scales=False)
+    assert none is None and np.array_equal(got2[:, 0], ref)
+    for i in (0, 23, 47):
+        r = _ref(net, plan, amplitude_overrides(net, circ, xs[i]))
+        assert err(got[i, 0], r, circ.n) < TOL
+    ctx.free_plan(p)
+
+
 def test_graph_replay_matches_eager(ctx):
     """TN_FLAG_GRAPH: the first call captures the plan group's launch sequence,
     later calls with the same group replay it.  Every replay (new bitstrings
