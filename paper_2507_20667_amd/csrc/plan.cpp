@@ -1459,6 +1459,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
             ps.kind = 4;
             ps.nc = (int32_t)std::min<size_t>(64, recs.size() - r0);
             ps.ns = ns;
+            ps.nss = cand[g].size() == 1 ? 1 : 0;  // one whole step (its nc <= 64)
             ps.tab = (int32_t)lanes.size();
             for (int l = 0; l < ps.nc; ++l) lanes.push_back(recs[r0 + l]);
             out.push_back(ps);

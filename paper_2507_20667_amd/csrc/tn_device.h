@@ -153,8 +153,9 @@ constexpr int kTreeSpillElems = 512;
 // kind 4, result entries of kind 2 steps of one level (one step or several
 // independent ones), one entry per lane: lane l < nc reads lane record tab + l
 // of the launch's lane table (TreeLaneRec) and computes
-// C[c] = sum_{s < ns} X[xa_s] * Y[ya_s] with the scales of its own step.  Only
-// single-query groups run kind 4 (every group of a program that holds one).
+// C[c] = sum_{s < ns} X[xa_s] * Y[ya_s] with the scales of its own step
+// (nss = 1: the entries of one whole step).  Only single-query groups run
+// kind 4 (every group of a program that holds one).
 // In the copy the kernels read, a map whose extents are all powers of two
 // (pow2) holds extent - 1 (the mask) in place of each extent and zeros in its
 // unused segments, and xs, cy and ymap are byte offsets.

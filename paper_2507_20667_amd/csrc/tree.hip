@@ -585,6 +585,71 @@ __device__ __forceinline__ void tree_lane_exec(uint4 r0, uint4 r1, float2 *pq, c
   atomicMax((unsigned int *)&scl[csl].y, __float_as_uint(fmaxf(fabsf(re), fabsf(im))));
 }
 
+// The largest of v over the wave, in a scalar register (every lane of the
+// wave active): a butterfly inside each row of 16 lanes by DPP moves, then the
+// four rows' values read out.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // lane ^ 1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // lane ^ 2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // 7 - lane in 8
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // 15 - lane in 16
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+  const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+// Kind 4 holding one whole kind 2 step (nss = 1), run by a whole wave (lanes
+// past nc inactive in the arithmetic only): the operand scales are the same
+// for every lane, and the wave writes the result's scale record with one
+// store, its max reduced across the wave, instead of one LDS atomic per lane
+// on one word.
+template <int NS>
+__device__ __forceinline__ void tree_lane_whole(uint4 r0, uint4 r1, bool act, int lane, float2 *pq,
+                                                const float2 *shr, int2 *scl) {
+  const uint32_t w3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)r0.w);  // lane 0 is active
+  const uint32_t wz = (uint32_t)__builtin_amdgcn_readfirstlane((int)r0.z);
+  const int2 za = scl[w3 & 0x7fffu], zb = scl[(w3 >> 16) & 0x7fffu];
+  const int zax = __builtin_amdgcn_readfirstlane(za.x), zay = __builtin_amdgcn_readfirstlane(za.y);
+  const int zbx = __builtin_amdgcn_readfirstlane(zb.x), zby = __builtin_amdgcn_readfirstlane(zb.y);
+  const int e = tn_scale_exp((uint32_t)zay) + tn_scale_exp((uint32_t)zby);
+  float m = 0.f;
+  if (act) {
+    const char *xb = (const char *)((w3 & 0x8000u) ? shr : pq);
+    const char *yb = (const char *)((w3 >> 31) ? shr : pq);
+    auto at = [](const char *base, uint32_t off) -> float2 { return *(const float2 *)(base + off); };
+    float2 x[NS], y[NS];
+    x[0] = at(xb, r0.x & 0xffffu);
+    y[0] = at(yb, r0.y & 0xffffu);
+    if (NS >= 2) {
+      x[1] = at(xb, r0.x >> 16);
+      y[1] = at(yb, r0.y >> 16);
+    }
+    if (NS == 4) {
+      x[2] = at(xb, r1.x & 0xffffu);
+      x[3] = at(xb, r1.x >> 16);
+      y[2] = at(yb, r1.y & 0xffffu);
+      y[3] = at(yb, r1.y >> 16);
+    }
+    const float f = ldexpf(1.0f, -e);
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      re = fmaf(x[s].x, y[s].x, re);
+      re = fmaf(-x[s].y, y[s].y, re);
+      im = fmaf(x[s].x, y[s].y, im);
+      im = fmaf(x[s].y, y[s].x, im);
+    }
+    re *= f;
+    im *= f;
+    *(float2 *)((char *)pq + (r0.z & 0xffffu)) = make_float2(re, im);
+    m = fmaxf(fabsf(re), fabsf(im));
+  }
+  const unsigned mx = wave_max_u32(__float_as_uint(m));
+  if (lane == 0) scl[(wz >> 16) & 0x7fffu] = make_int2(zax + zbx + e, (int)mx);
+}
+
 template <int NS>
 __device__ __forceinline__ void tree_lane_step(const TreeLaneRec *rec, int lane, int nl, float2 *pq,
                                                const float2 *shr, int2 *scl) {
@@ -928,7 +993,15 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
     const uint4 c0 = n0, c1 = n1;
     if (k + 1 < nloop) fetch(k + 1);
     if (S->kind == 4) {
-      if (lane < S->nc) {
+      if (S->nss) {  // one whole step: the whole wave, one scale store
+        const bool act = lane < S->nc;
+        if (S->ns == 1)
+          tree_lane_whole<1>(c0, c1, act, lane, wpq, shr, wscl);
+        else if (S->ns == 2)
+          tree_lane_whole<2>(c0, c1, act, lane, wpq, shr, wscl);
+        else
+          tree_lane_whole<4>(c0, c1, act, lane, wpq, shr, wscl);
+      } else if (lane < S->nc) {
         if (S->ns == 1)
           tree_lane_exec<1>(c0, c1, wpq, shr, wscl);
         else if (S->ns == 2)
