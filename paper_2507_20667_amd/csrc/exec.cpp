@@ -230,14 +230,14 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       return TN_E_DEVICE;
     }
   }
-  upload_lock.unlock();
-  // algorithmic traffic and work of the subtree kernel (for the profiler)
+  // algorithmic traffic and work of the subtree kernel (for the profiler),
+  // once per layout
   // (a vertex counts as its subtree runs: once when the subtree's root is
   // shared, once per query otherwise, whatever the vertex itself depends on)
-  double tree_bytes_sh = 0, tree_flops_sh = 0, tree_bytes_q = 0, tree_flops_q = 0;
-  std::vector<int> troots(p->tree_roots);
-  troots.insert(troots.end(), L.islands.begin(), L.islands.end());
-  if (trees)
+  if (trees && !L.tree_acct) {
+    ExecLayout &Lm = const_cast<ExecLayout &>(L);
+    std::vector<int> troots(p->tree_roots);
+    troots.insert(troots.end(), L.islands.begin(), L.islands.end());
     for (int r : troots) {
       const bool shr = L.shared[r] != 0;
       std::vector<int> stack{r};
@@ -254,15 +254,15 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           return (double)(t < nv ? p->leaf[t].size() : std::max<int64_t>(p->nodes[t - nv].out.size(), 1));
         };
         const double b = 8.0 * (sz(n.c1) + sz(n.c2) + sz(n.id)), f = 8.0 * (double)n.weight;
-        if (shr) {
-          tree_bytes_sh += b;
-          tree_flops_sh += f;
-        } else {
-          tree_bytes_q += b;
-          tree_flops_q += f;
-        }
+        (shr ? Lm.tree_bytes_sh : Lm.tree_bytes_q) += b;
+        (shr ? Lm.tree_flops_sh : Lm.tree_flops_q) += f;
       }
     }
+    Lm.tree_acct = true;
+  }
+  upload_lock.unlock();
+  const double tree_bytes_sh = L.tree_bytes_sh, tree_flops_sh = L.tree_flops_sh;
+  const double tree_bytes_q = L.tree_bytes_q, tree_flops_q = L.tree_flops_q;
   const size_t perq = rnd(L.perq_bytes);
   const size_t relems = result_elems(p);
   const size_t final_bytes = p->fperm.needed ? rnd(relems * 8) : 0;

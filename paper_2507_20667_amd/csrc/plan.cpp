@@ -1373,7 +1373,8 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
     out.reserve(steps.size());
     for (size_t hi = 0; hi < hdrs.size(); ++hi) {
       TreeHdr &h = hdrs[hi];
-      const bool can = mode > 0 && ((int)hi < L.n_tree_shared || one_q);
+      static const bool pack_shared = !getenv("TN_TREE_PACK_SHARED") || atoi(getenv("TN_TREE_PACK_SHARED")) != 0;
+      const bool can = mode > 0 && ((int)hi < L.n_tree_shared ? pack_shared : one_q);
       const int32_t s0 = (int32_t)out.size();
       for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c) {
         const int32_t c0 = (int32_t)out.size();
@@ -1611,6 +1612,10 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
     // of the workspace (their whole lifetime), which keeps each query's LDS
     // small enough for more queries per CU
     L.spill.clear();
+    static const int64_t spill_at = [] {  // tuning: TN_TREE_SPILL entries
+      const char *e = getenv("TN_TREE_SPILL");
+      return e && atoll(e) > 0 ? (int64_t)atoll(e) : (int64_t)kTreeSpillElems;
+    }();
     for (int r : p->tree_roots) {
       if (L.shared[r]) continue;
       std::vector<int> stack{p->nodes[r - nv].c1, p->nodes[r - nv].c2};
@@ -1619,7 +1624,7 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
         stack.pop_back();
         if (u < nv || L.shared[u]) continue;  // leaves, islands
         const Node &n = p->nodes[u - nv];
-        if (n.out.size() >= kTreeSpillElems) L.spill.push_back(u);
+        if ((int64_t)n.out.size() >= spill_at) L.spill.push_back(u);
         stack.push_back(n.c1);
         stack.push_back(n.c2);
       }

@@ -106,6 +106,10 @@ struct ExecLayout {
   std::vector<uint8_t> tree_blob;
   size_t tree_chunk_off = 0, tree_step_off = 0, tree_load_off = 0, tree_img_off = 0;
   size_t tree_lane_off = 0;  // kind 4 lane records
+  // algorithmic bytes and flops of the shared and of one query's subtree
+  // launch (profiler), filled on first use under the plan's cache lock
+  bool tree_acct = false;
+  double tree_bytes_sh = 0, tree_flops_sh = 0, tree_bytes_q = 0, tree_flops_q = 0;
   size_t tree_sload_off = 0, tree_sg_off = 0;
   // shared vertices inside per-query subtrees that run as shared subtrees of
   // their own (computed once, read by the per-query programs)
