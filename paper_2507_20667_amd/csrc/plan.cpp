@@ -1376,6 +1376,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       static const bool pack_shared = !getenv("TN_TREE_PACK_SHARED") || atoi(getenv("TN_TREE_PACK_SHARED")) != 0;
       const bool can = mode > 0 && ((int)hi < L.n_tree_shared ? pack_shared : one_q);
       const int32_t s0 = (int32_t)out.size();
+      h.rec0 = (int32_t)lanes.size();
       for (int c = h.chunk0; c < h.chunk0 + h.nchunks; ++c) {
         const int32_t c0 = (int32_t)out.size();
         std::vector<int> cand[3];  // ns = 1, 2, 4
@@ -1475,8 +1476,39 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       }
       h.step0 = s0;
       h.nsteps = (int32_t)out.size() - s0;
+      h.nrec = (int32_t)lanes.size() - h.rec0;
     }
     steps.swap(out);
+    // the level kernel keeps a program's lane records in LDS (after the
+    // query regions, 16-byte aligned) when they fit: one copy at the start
+    // instead of a device-memory round trip in every level
+    const size_t lim = tree_lds_limit();
+    size_t rec_q = 0;
+    bool fit_q = true;
+    for (size_t hi = 0; hi < hdrs.size(); ++hi) {
+      TreeHdr &h = hdrs[hi];
+      const size_t rb = h.nrec ? 16 + 32 * (size_t)h.nrec : 0;
+      h.rec_lds = 0;
+      if (!h.nrec) continue;
+      if ((int)hi < L.n_tree_shared) {
+        const size_t need = tree_lds_bytes(1, h.nscale, h.shared_elems, h.perq_elems) + rb;
+        if (need <= lim) {
+          h.rec_lds = 1;
+          L.lds_shared = std::max(L.lds_shared, need);
+        }
+      } else {
+        rec_q = std::max(rec_q, rb);
+      }
+    }
+    // per-query programs: single queries run the level kernel with one query
+    // per workgroup (lds_perq1; lds_perq too when there is no batch kernel)
+    fit_q = L.lds_perq1 + rec_q <= lim && (L.tree_wave || L.lds_perq + rec_q <= lim);
+    if (rec_q && fit_q) {
+      for (size_t hi = (size_t)L.n_tree_shared; hi < hdrs.size(); ++hi)
+        if (hdrs[hi].nrec) hdrs[hi].rec_lds = 1;
+      L.lds_perq1 += rec_q;
+      if (!L.tree_wave) L.lds_perq += rec_q;
+    }
   }
   if (getenv("TN_DEBUG"))
     for (const TreeHdr &h : hdrs) {

@@ -222,6 +222,9 @@ struct TreeHdr {
   int32_t nimg;                      // shared leaves copied from the image
   int32_t step0, nsteps;             // the program: every step, chunk by chunk
   int32_t sg0, nsg;                  // gather list of the shared intermediates
+  int32_t rec0, nrec;                // kind 4 lane records [rec0, rec0 + nrec)
+  int32_t rec_lds;                   // the level kernel copies them into LDS
+  int32_t pad;
 };
 
 // A shared intermediate that a per-query subtree takes as an input: computed

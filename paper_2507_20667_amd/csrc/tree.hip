@@ -663,9 +663,11 @@ __device__ __forceinline__ void tree_lane_step(const TreeLaneRec *rec, int lane,
 template <bool DEV, class SP>
 __device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
                                           const float2 *shr, int2 *scl, int nscale, float2 *gq,
-                                          int64_t gstride, const TreeLaneRec *lanes) {
+                                          int64_t gstride, const TreeLaneRec *lanes, int lane0) {
   if (Sp->kind == 4) {
-    const TreeLaneRec *rec = lanes + Sp->tab;
+    // lanes: the launch's records (lane0 = 0) or the program's copy in LDS
+    // (lane0 = its first record's index)
+    const TreeLaneRec *rec = lanes + (Sp->tab - lane0);
     if (Sp->ns == 1)
       tree_lane_step<1>(rec, lane, Sp->nc, pq, shr, scl);
     else if (Sp->ns == 2)
@@ -823,6 +825,18 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
   const int64_t gstride = t.perq_stride / 8;
 
   tree_prologue(t, ka, h, tid, qw, nqw, q0, scl, shr, pq, perq);
+  // the program's kind 4 lane records: copied after the query regions
+  // (16-byte aligned; the host sized the LDS for it) or read from device memory
+  const TreeLaneRec *lrec = t.lanes;
+  int lrec0 = 0;
+  if (h.rec_lds) {
+    const size_t off = ((size_t)((const unsigned char *)(pq + qw * perq) - tree_lds) + 15) & ~(size_t)15;
+    uint4 *dst = (uint4 *)(tree_lds + off);
+    const uint4 *src = (const uint4 *)(t.lanes + h.rec0);
+    for (int i = tid; i < 2 * h.nrec; i += 256) dst[i] = src[i];
+    lrec = (const TreeLaneRec *)dst;
+    lrec0 = h.rec0;
+  }
   // the chunks' steps are consecutive from step0: the next chunk's size is
   // fetched one chunk ahead, so no chunk waits on the chunk table
   int cur = 0, nxt = 0, s_cur = h.step0;
@@ -892,13 +906,13 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
       }
     } else if (cur == 1) {
       // one step (a spine contraction): the whole workgroup on it
-      tree_step<DEV>(S, tid, 256, nqw, pq, perq, shr, scl, h.nscale, gq, gstride, t.lanes);
+      tree_step<DEV>(S, tid, 256, nqw, pq, perq, shr, scl, h.nscale, gq, gstride, lrec, lrec0);
     } else {
       // several independent steps of one level (largest first): one wave per
       // step, round robin
       const int wave = tid >> 6, lane = tid & 63;
       for (int i = wave; i < cur; i += 4)
-        tree_step<DEV>(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale, gq, gstride, t.lanes);
+        tree_step<DEV>(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale, gq, gstride, lrec, lrec0);
     }
     if (k + 1 < h.nchunks) {
       int32_t *dst = sbuf + ((k + 1) & 1) * CW;
@@ -1010,7 +1024,7 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
           tree_lane_exec<4>(c0, c1, wpq, shr, wscl);
       }
     } else {
-      tree_step<true>(S, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride, t.lanes);
+      tree_step<true>(S, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride, t.lanes, 0);
     }
   }
 

@@ -293,6 +293,41 @@ def test_strided_pinned_output(ctx, capfd, monkeypatch, stride):
     ctx.free_plan(p)
 
 
+def test_packed_gate_steps_match_unpacked(ctx, monkeypatch):
+    """Small gate vertices packed into lane-record steps (the default) give the
+    same amplitudes, bit for bit, as the same programs with packing off
+    (TN_TREE_PACK=0, read when a plan's layouts are built): on a batch (the
+    batch kernel) and on single queries (the level kernel); and they agree
+    with the oracle."""
+    circ = brickwork_circuit(16, 10, 7)
+    net = amplitude_network(circ, 0)
+    plan = _plan(net, 4)
+    xs = random_bitstrings(circ.n, 40, 77)
+    ids = output_tensor_ids(net)
+    vec = {t: np.stack([amplitude_overrides(net, circ, x)[t] for x in xs]) for t in ids}
+    ovr = [(t, vec[t].astype(np.complex128), 16 * vec[t].shape[1], lib.TN_C128) for t in ids]
+
+    def run():
+        p = ctx.load_network(net, plan.partition_of, 4, plan.tree)
+        batch, _ = lib.tn_contract_strided(p, len(xs), ovr)
+        singles = [lib.tn_contract(p, amplitude_overrides(net, circ, xs[i]))[0] for i in (0, 5)]
+        ctx.free_plan(p)
+        return batch, singles
+
+    monkeypatch.setenv("TN_TREE_PACK", "0")
+    b0, s0 = run()
+    monkeypatch.delenv("TN_TREE_PACK")
+    b1, s1 = run()
+    assert np.array_equal(b0, b1)
+    for a, b in zip(s0, s1):
+        assert _c(a) == _c(b)
+    for i in (0, 5, 39):
+        r = _ref(net, plan, amplitude_overrides(net, circ, xs[i]))
+        assert err(b1[i], r, circ.n) < TOL
+    for i, sq in zip((0, 5), s1):  # single queries (level kernel) against the batch
+        assert abs(_c(sq) - _c(b1[i])) <= 1e-6 * max(abs(_c(b1[i])), 2.0 ** -8)
+
+
 def test_graph_replay_matches_eager(ctx):
     """TN_FLAG_GRAPH: the first call captures the plan group's launch sequence,
     later calls with the same group replay it.  Every replay (new bitstrings
