@@ -839,19 +839,25 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
   }
   // the chunks' steps are consecutive from step0: the next chunk's size is
   // fetched one chunk ahead, so no chunk waits on the chunk table
+  // A program of at most 2 kTreeChunk steps is copied whole into the two
+  // chunk buffers here, and no level waits on device memory for its steps.
+  const bool whole = h.nsteps <= 2 * kTreeChunk;
   int cur = 0, nxt = 0, s_cur = h.step0;
   if (h.nchunks > 0) {
     cur = t.chunks[h.chunk0].nsteps;
     if (h.nchunks > 1) nxt = t.chunks[h.chunk0 + 1].nsteps;
-    for (int i = tid; i < cur * W; i += 256) sbuf[i] = gw[(int64_t)s_cur * W + i];
+    const int n = (whole ? h.nsteps : cur) * W;
+    for (int i = tid; i < n; i += 256) sbuf[i] = gw[(int64_t)s_cur * W + i];
   }
   __syncthreads();
 
   for (int k = 0; k < h.nchunks; ++k) {
-    const TreeStep *S = (const TreeStep *)(sbuf + (k & 1) * CW);
+    const TreeStep *S = (const TreeStep *)(sbuf + (whole ? (s_cur - h.step0) * W : (k & 1) * CW));
     int32_t pre[PRE];
     int nxt2 = 0;
-    if (k + 1 < h.nchunks) {
+    if (k + 1 < h.nchunks && whole) {
+      if (k + 2 < h.nchunks) nxt2 = t.chunks[h.chunk0 + k + 2].nsteps;
+    } else if (k + 1 < h.nchunks) {
       const int64_t s_nxt = s_cur + cur;
 #pragma unroll
       for (int j = 0; j < PRE; ++j) {
@@ -914,7 +920,7 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
       for (int i = wave; i < cur; i += 4)
         tree_step<DEV>(S + i, lane, 64, nqw, pq, perq, shr, scl, h.nscale, gq, gstride, lrec, lrec0);
     }
-    if (k + 1 < h.nchunks) {
+    if (k + 1 < h.nchunks && !whole) {
       int32_t *dst = sbuf + ((k + 1) & 1) * CW;
 #pragma unroll
       for (int j = 0; j < PRE; ++j) {
