@@ -842,6 +842,8 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
   // A program of at most 2 kTreeChunk steps is copied whole into the two
   // chunk buffers here, and no level waits on device memory for its steps.
   const bool whole = h.nsteps <= 2 * kTreeChunk;
+  // (its chunk sizes too, one per lane of every wave: nchunks <= nsteps <= 32)
+  const int csz = whole && (tid & 63) < h.nchunks ? t.chunks[h.chunk0 + (tid & 63)].nsteps : 0;
   int cur = 0, nxt = 0, s_cur = h.step0;
   if (h.nchunks > 0) {
     cur = t.chunks[h.chunk0].nsteps;
@@ -856,7 +858,7 @@ __global__ __launch_bounds__(256) void k_tree(TreeLaunch t) {
     int32_t pre[PRE];
     int nxt2 = 0;
     if (k + 1 < h.nchunks && whole) {
-      if (k + 2 < h.nchunks) nxt2 = t.chunks[h.chunk0 + k + 2].nsteps;
+      if (k + 2 < h.nchunks) nxt2 = __builtin_amdgcn_readlane(csz, k + 2);
     } else if (k + 1 < h.nchunks) {
       const int64_t s_nxt = s_cur + cur;
 #pragma unroll
