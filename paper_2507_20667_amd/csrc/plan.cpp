@@ -1396,7 +1396,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
           const int ns = g == 0 ? 1 : g == 1 ? 2 : 4;
           // one record per result entry, in the steps' order
           std::vector<TreeLaneRec> recs;
-          std::vector<std::pair<int32_t, bool>> reads;  // query-region X and Y offsets
+          std::vector<int32_t> reads;  // query-region X and Y offsets
           std::vector<int32_t> writes;
           bool ok2 = true;
           for (int k : cand[g]) {
@@ -1408,7 +1408,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
               const int64_t i = (int64_t)(loc & ~kPerQuery) + off;
               const int64_t lim = q ? h.perq_elems : h.shared_elems;
               if (i < 0 || i >= lim || 8 * i >= 0x10000) ok2 = false;
-              if (q) reads.push_back({(int32_t)i, true});
+              if (q) reads.push_back((int32_t)i);
               return (uint32_t)(8 * i) & 0xffffu;
             };
             for (int i = 0; i < st.nc; ++i) {
@@ -1449,8 +1449,8 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
           std::vector<int32_t> w2(writes);
           std::sort(w2.begin(), w2.end());
           ok2 = ok2 && std::adjacent_find(w2.begin(), w2.end()) == w2.end();
-          for (const auto &rd : reads)
-            if (std::binary_search(w2.begin(), w2.end(), rd.first)) ok2 = false;
+          for (const int32_t rd : reads)
+            if (std::binary_search(w2.begin(), w2.end(), rd)) ok2 = false;
           if (!ok2) {  // keep the steps as they were
             for (int k : cand[g]) out.push_back(steps[k]);
             continue;
@@ -1461,7 +1461,9 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
             ps.kind = 4;
             ps.nc = (int32_t)std::min<size_t>(64, recs.size() - r0);
             ps.ns = ns;
-            ps.nss = cand[g].size() == 1 ? 1 : 0;  // one whole step (its nc <= 64)
+            // one whole step in one kind 4 step (a larger one, TN_TREE_PACK_NC
+            // above 64, spans several, which fold their maxes atomically)
+            ps.nss = cand[g].size() == 1 && recs.size() <= 64 ? 1 : 0;
             ps.tab = (int32_t)lanes.size();
             for (int l = 0; l < ps.nc; ++l) lanes.push_back(recs[r0 + l]);
             out.push_back(ps);

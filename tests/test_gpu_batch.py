@@ -296,9 +296,10 @@ def test_strided_pinned_output(ctx, capfd, monkeypatch, stride):
 def test_packed_gate_steps_match_unpacked(ctx, monkeypatch):
     """Small gate vertices packed into lane-record steps (the default) give the
     same amplitudes, bit for bit, as the same programs with packing off
-    (TN_TREE_PACK=0, read when a plan's layouts are built): on a batch (the
-    batch kernel) and on single queries (the level kernel); and they agree
-    with the oracle."""
+    (TN_TREE_PACK=0, read when a plan's layouts are built) and with vertices
+    of up to 256 entries packed (TN_TREE_PACK_NC=256: one vertex over several
+    steps): on a batch (the batch kernel) and on single queries (the level
+    kernel); and they agree with the oracle."""
     circ = brickwork_circuit(16, 10, 7)
     net = amplitude_network(circ, 0)
     plan = _plan(net, 4)
@@ -317,10 +318,14 @@ def test_packed_gate_steps_match_unpacked(ctx, monkeypatch):
     monkeypatch.setenv("TN_TREE_PACK", "0")
     b0, s0 = run()
     monkeypatch.delenv("TN_TREE_PACK")
+    # vertices up to 256 entries packed too (one vertex spanning several steps)
+    monkeypatch.setenv("TN_TREE_PACK_NC", "256")
+    b2, s2 = run()
+    monkeypatch.delenv("TN_TREE_PACK_NC")
     b1, s1 = run()
-    assert np.array_equal(b0, b1)
-    for a, b in zip(s0, s1):
-        assert _c(a) == _c(b)
+    assert np.array_equal(b0, b1) and np.array_equal(b0, b2)
+    for a, b, c in zip(s0, s1, s2):
+        assert _c(a) == _c(b) == _c(c)
     for i in (0, 5, 39):
         r = _ref(net, plan, amplitude_overrides(net, circ, xs[i]))
         assert err(b1[i], r, circ.n) < TOL
