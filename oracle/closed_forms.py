@@ -12,6 +12,11 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
     CX gates.  RZ(t) = diag(e^{-it/2}, e^{it/2}).
   * Single-qubit: <0|RX(t)|0> = cos(t/2), <1|RX(t)|0> = -i sin(t/2),
     <0|RZ(t)|0> = e^{-it/2}.
+  * Graph state (H on every qubit, then CZ on the edges of a graph): H^n|0>
+    is the uniform superposition and each CZ(i, j) multiplies basis state x
+    by (-1)^(x_i x_j), so <x|U|0^n> = 2^(-n/2) (-1)^(sum over edges of
+    x_i x_j).  It fixes the CZ matrix, and it does not depend on the
+    orientation or the order of the CZ gates.
 """
 from __future__ import annotations
 
@@ -63,3 +68,20 @@ def rx_amplitudes(theta: float):
 
 def rz_amplitude0(theta: float) -> complex:
     return cmath.exp(-1j * theta / 2.0)
+
+
+def graph_state_amplitude(circ, x: int) -> complex:
+    """Exact amplitude of an H layer followed by CZ gates only (a graph state)
+    for bitstring x: 2^(-n/2) times -1 for every CZ whose two qubits are 1 in x."""
+    n = circ.n
+    gates = list(circ.gates)
+    if [g.name for g in gates[:n]] != ["H"] * n or sorted(g.qubits[0] for g in gates[:n]) != list(range(n)):
+        raise ValueError("not a graph-state circuit: it must start with H on every qubit")
+    sign = 1
+    for g in gates[n:]:
+        if g.name != "CZ":
+            raise ValueError("not a graph-state circuit: only CZ after the H layer")
+        i, j = g.qubits
+        if (x >> i) & 1 and (x >> j) & 1:
+            sign = -sign
+    return sign * 2.0 ** (-n / 2.0)

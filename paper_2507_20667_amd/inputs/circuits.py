@@ -97,6 +97,26 @@ def hadamard_layer(n: int) -> Circuit:
     return c
 
 
+def graph_state_circuit(n: int, edges) -> Circuit:
+    """H on every qubit, then CZ on each edge (i, j) in the order given."""
+    c = Circuit(n, name=f"graph{n}_e{len(edges)}")
+    for q in range(n):
+        c.add("H", (q,))
+    for i, j in edges:
+        c.add("CZ", (i, j))
+    return c
+
+
+def brick_edges(n: int, layers: int) -> list:
+    """The CZ bricks of brickwork_circuit's CZ layers: (2i, 2i+1) on even
+    layers, (2i+1, 2i+2) on odd ones."""
+    out = []
+    for layer in range(layers):
+        start = 0 if layer % 2 == 0 else 1
+        out.extend((q, q + 1) for q in range(start, n - 1, 2))
+    return out
+
+
 def phase_poly_circuit(n: int, depth: int, seed: int) -> Circuit:
     """H on every qubit, then per layer: CX on the disjoint consecutive pairs
     of a random permutation (first of a pair is the control), then RZ(theta)

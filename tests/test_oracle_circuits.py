@@ -7,7 +7,8 @@
     each seeded family;
   * closed forms: GHZ amplitudes 1/sqrt2, Hadamard-layer amplitudes
     2^(-n/2), the exact phase-polynomial amplitudes (configuration-1 family,
-    also at 20 qubits where no state vector is needed), sum |amp|^2 = 1;
+    also at 20 qubits where no state vector is needed), graph-state signs
+    (the CZ convention of the brickwork family), sum |amp|^2 = 1;
   * <Z_i Z_j>: light-cone-pruned network = unpruned network = state-vector
     expectation; GHZ gives 1 and a Hadamard layer 0.
 """
@@ -18,8 +19,8 @@ import pytest
 
 import oracle
 from oracle import closed_forms as cf
-from paper_2507_20667_amd.inputs import (Circuit, amplitude_network, brickwork_circuit, ghz,
-                                         hadamard_layer, phase_poly_circuit, random_circuit,
+from paper_2507_20667_amd.inputs import (Circuit, amplitude_network, brick_edges, brickwork_circuit,
+                                         ghz, graph_state_circuit, hadamard_layer, phase_poly_circuit, random_circuit,
                                          zz_network)
 from paper_2507_20667_amd.planner import contiguous_partition, plan_from_partition
 
@@ -111,6 +112,34 @@ def test_phase_polynomial_closed_form_small_and_large():
     for x in rng.integers(0, 1 << 20, size=3):
         got = sv_amplitude_via_network(c, int(x))
         assert abs(got - cf.phase_poly_amplitude(c, int(x))) < 1e-13
+
+
+def test_graph_state_closed_form_pins_cz():
+    """CZ-only circuits: the state vector and the network contraction equal
+    2^(-n/2) (-1)^(sum over edges of x_i x_j) on every amplitude (brickwork
+    CZ bricks, and a random graph with long-range edges in both orientations),
+    and on sampled amplitudes of the 20-qubit brickwork layout through the
+    network alone.  A wrong CZ matrix or leg convention flips some sign."""
+    n = 10
+    for edges in (brick_edges(n, 6),
+                  [(0, 7), (7, 0), (3, 9), (2, 5), (9, 1), (4, 6), (6, 8), (5, 3)]):
+        c = graph_state_circuit(n, edges)
+        psi = oracle.statevector(c)
+        want = np.array([cf.graph_state_amplitude(c, x) for x in range(1 << n)])
+        assert np.allclose(psi, want, atol=1e-13)
+        # the closed form is not trivial: both signs occur
+        assert (want > 0).any() and (want < 0).any()
+        for x in np.random.default_rng(5).integers(0, 1 << n, size=12):
+            assert abs(sv_amplitude_via_network(c, int(x)) - want[int(x)]) < 1e-13
+    c = graph_state_circuit(20, brick_edges(20, 7))
+    for x in np.random.default_rng(12).integers(0, 1 << 20, size=4):
+        got = sv_amplitude_via_network(c, int(x))
+        assert abs(got - cf.graph_state_amplitude(c, int(x))) < 1e-13
+    # a CZ that acted as diag(1, 1, -1, 1) would be caught: the closed form
+    # with the sign on x_i (1 - x_j) differs from the state vector
+    c = graph_state_circuit(4, [(0, 1)])
+    psi = oracle.statevector(c)
+    assert abs(psi[0b01] - (-0.25)) > 0.4 and abs(psi[0b11] - (-0.25)) < 1e-15
 
 
 def test_norm_over_all_bitstrings():
