@@ -316,6 +316,7 @@ def gemm_phase_leg(lib, reps=3):
     # bf16 MFMA operations per effective complex flop: 4M = 12 products of
     # 2 flops per 8 effective flops, 3M = 9 products
     for name, flags, peak, mul in [("fp32_4m", 0, MFMA_PEAK_TFLOPS["fp32"], 1.0),
+                                   ("fp32_3m", lib.TN_FORM_3M, MFMA_PEAK_TFLOPS["fp32"], 0.75),
                                    ("bf16x3_4m", lib.TN_PREC_BF16X3, MFMA_PEAK_TFLOPS["bf16x3"], 3.0),
                                    ("bf16x3_3m", lib.TN_PREC_BF16X3 | lib.TN_FORM_3M,
                                     MFMA_PEAK_TFLOPS["bf16x3"], 2.25)]:

@@ -131,11 +131,11 @@ tn_status tn_plan_load(tn_ctx *ctx, const tn_plan_desc *desc, uint32_t flags, tn
     p->ctx = ctx;
     p->dev_leaf_bytes = std::max<size_t>(p->leaf_host.size() * sizeof(float2), 256);
     p->dev_desc_bytes = std::max<size_t>(p->desc_blob.size(), 256);
-    p->dev_leaf = ctx->arena.alloc(p->dev_leaf_bytes);
-    p->dev_desc = ctx->arena.alloc(p->dev_desc_bytes);
+    p->dev_leaf = ctx->arena.alloc(p->dev_leaf_bytes, true);
+    p->dev_desc = ctx->arena.alloc(p->dev_desc_bytes, true);
     if (p->dev_leaf < 0 || p->dev_desc < 0) {
-      ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes);
-      ctx->arena.release(p->dev_desc, p->dev_desc_bytes);
+      ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes, true);
+      ctx->arena.release(p->dev_desc, p->dev_desc_bytes, true);
       delete p;
       set_error("tn_plan_load: arena cannot hold the leaves and descriptors");
       return TN_E_NOMEM;
@@ -148,8 +148,8 @@ tn_status tn_plan_load(tn_ctx *ctx, const tn_plan_desc *desc, uint32_t flags, tn
                          hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
-      ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes);
-      ctx->arena.release(p->dev_desc, p->dev_desc_bytes);
+      ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes, true);
+      ctx->arena.release(p->dev_desc, p->dev_desc_bytes, true);
       delete p;
       set_error("tn_plan_load: upload failed: %s", hipGetErrorString(e));
       return TN_E_DEVICE;
@@ -199,10 +199,11 @@ tn_status tn_plan_free(tn_plan *p) {
     tn_ctx *ctx = p->ctx;
     std::lock_guard<std::mutex> g(ctx->exec_mu);
     hipStreamSynchronize(ctx->stream);
-    ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes);
-    ctx->arena.release(p->dev_desc, p->dev_desc_bytes);
+    ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes, true);
+    ctx->arena.release(p->dev_desc, p->dev_desc_bytes, true);
     for (auto &kv : p->layouts)
-      if (kv.second->tree_dev >= 0) ctx->arena.release(kv.second->tree_dev, kv.second->tree_dev_bytes);
+      if (kv.second->tree_dev >= 0)
+        ctx->arena.release(kv.second->tree_dev, kv.second->tree_dev_bytes, true);
     if (p->graph) release_graph(ctx, *p->graph);
     ctx->live_plans--;
   }

@@ -33,7 +33,7 @@ size_t result_elems(const tn_plan *p) {
 
 void release_graph(tn_ctx *ctx, GraphEntry &g) {
   if (g.exec) hipGraphExecDestroy(g.exec);
-  if (g.ws >= 0) ctx->arena.release(g.ws, g.ws_bytes);
+  if (g.ws >= 0) ctx->arena.release(g.ws, g.ws_bytes, true);
   if (g.pinned) hipHostFree(g.pinned);
   g = GraphEntry();
 }
@@ -215,7 +215,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     // first use of this layout: upload its subtree programs
     ExecLayout &Lm = const_cast<ExecLayout &>(L);
     Lm.tree_dev_bytes = std::max<size_t>(L.tree_blob.size(), 256);
-    Lm.tree_dev = ctx->arena.alloc(Lm.tree_dev_bytes);
+    Lm.tree_dev = ctx->arena.alloc(Lm.tree_dev_bytes, true);
     if (Lm.tree_dev < 0) {
       set_error("arena cannot hold the subtree programs (%zu bytes)", Lm.tree_dev_bytes);
       return TN_E_NOMEM;
@@ -224,7 +224,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                                   L.tree_blob.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-      ctx->arena.release(Lm.tree_dev, Lm.tree_dev_bytes);
+      ctx->arena.release(Lm.tree_dev, Lm.tree_dev_bytes, true);
       Lm.tree_dev = -1;
       set_error("subtree program upload: %s", hipGetErrorString(e));
       return TN_E_DEVICE;
@@ -317,35 +317,40 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       want_graph = false;
   }
   for (size_t q0 = 0; q0 < qs.size() && rc == TN_OK; q0 += chunk) {
-    const int Q = (int)std::min(chunk, qs.size() - q0);
+    int Q = (int)std::min(chunk, qs.size() - q0);
     const hipStream_t st = gst ? gst : rs.st;
-    // carve the workspace
-    size_t o = 0;
-    auto carve = [&](size_t b) {
-      size_t r = o;
-      o += rnd(b);
-      return r;
+    // carve the workspace of Q queries
+    size_t r_shared = 0, r_perq = 0, r_slots = 0, r_ovr = 0, r_res = 0, r_final = 0, r_part = 0,
+           total = 0;
+    auto carve_all = [&](int nq) {
+      size_t o = 0;
+      auto carve = [&](size_t b) {
+        size_t r = o;
+        o += rnd(b);
+        return r;
+      };
+      r_shared = carve(L.shared_bytes);
+      r_perq = carve(perq * nq);
+      r_slots = carve(slot_bytes * (nq + 1));
+      r_ovr = carve(ovr_bytes * nq);
+      r_res = carve(sizeof(Result) * nq);
+      r_final = carve(final_bytes * nq);
+      r_part = carve((size_t)max_blocks * 16 * nq);
+      total = o;
     };
-    const size_t r_shared = carve(L.shared_bytes);
-    const size_t r_perq = carve(perq * Q);
-    const size_t r_slots = carve(slot_bytes * (Q + 1));
-    const size_t r_ovr = carve(ovr_bytes * Q);
-    const size_t r_res = carve(sizeof(Result) * Q);
-    const size_t r_final = carve(final_bytes * Q);
-    const size_t r_part = carve((size_t)max_blocks * 16 * Q);
-    const size_t total = o;
+    carve_all(Q);
     // TN_FLAG_GRAPH: the whole group in one chunk, not profiled, not serving
     // (a group whose workspace cannot be kept runs without a graph)
     bool gmode = want_graph;
     const double t_carve = dbg ? ms_since(t_enter) : 0.0;
-    const size_t rb_bytes = (size_t)Q * (relems * 8 + sizeof(Slot) + sizeof(Result));
+    size_t rb_bytes = (size_t)Q * (relems * 8 + sizeof(Slot) + sizeof(Result));
     if (gmode) {
       if (!p->graph) p->graph.reset(new GraphEntry());
       GraphEntry &E = *p->graph;
       if (E.layout != &L || E.Q != Q || E.ws_bytes != total) {
         hipStreamSynchronize(st);
         release_graph(ctx, E);
-        E.ws = ctx->arena.alloc(total);
+        E.ws = ctx->arena.alloc(total, true);
         E.ws_bytes = total;
         if (E.ws < 0 || hipHostMalloc(&E.pinned, rb_bytes, hipHostMallocDefault) != hipSuccess) {
           if (E.ws >= 0 && !E.pinned) (void)hipGetLastError();
@@ -361,6 +366,15 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     }
     const bool own_ws = rs.ws < 0 && !gmode;
     int64_t ws = gmode ? p->graph->ws : own_ws ? ctx->arena.alloc(total) : rs.ws;
+    // the free space measured above may have been taken meanwhile (serve
+    // workers share the arena): fewer queries per chunk
+    while (ws < 0 && own_ws && Q > 1) {
+      Q = (Q + 1) / 2;
+      chunk = (size_t)Q;
+      carve_all(Q);
+      rb_bytes = (size_t)Q * (relems * 8 + sizeof(Slot) + sizeof(Result));
+      ws = ctx->arena.alloc(total);
+    }
     const double t_alloc = dbg ? ms_since(t_enter) : 0.0;
     if (ws < 0) {
       set_error("arena exhausted (%zu bytes requested)", total);

@@ -75,6 +75,14 @@ __device__ constexpr int prod_4m(int i, int f) {
                             {0, 2, 3, 1}, {1, 2, 1, 0}, {0, 3, 2, 1}, {1, 3, 0, 0}};
   return t[i][f];
 }
+// 3M products grouped by plane pair (re, im, sum), for the direct-to-LDS
+// kernel, which reads one group's fragments while the previous group's
+// products run
+__device__ constexpr int prod_3m_g(int i, int f) {
+  constexpr int t[9][4] = {{0, 0, 0, 0}, {0, 0, 1, 0}, {0, 1, 0, 0}, {1, 2, 2, 0}, {1, 2, 3, 0},
+                           {1, 3, 2, 0}, {2, 4, 4, 0}, {2, 4, 5, 0}, {2, 5, 4, 0}};
+  return t[i][f];
+}
 __device__ constexpr int prod_3m(int i, int f) {
   constexpr int t[9][4] = {{0, 0, 0, 0}, {1, 2, 2, 0}, {2, 4, 4, 0}, {0, 0, 1, 0}, {1, 2, 3, 0},
                            {2, 4, 5, 0}, {0, 1, 0, 0}, {1, 3, 2, 0}, {2, 5, 4, 0}};
@@ -307,34 +315,49 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
   }
 }
 
-// ------------------------------------------------- direct-to-LDS form (4M)
+// ------------------------------------------------------- direct-to-LDS form
 // For k a multiple of 16 the permutation writes the planes k-tiled (16
 // consecutive k of consecutive rows contiguous), so one stage of a tile is a
-// contiguous 4 KB block of each plane, and the 4M product streams it straight
-// from global memory into LDS (global_load_lds_dwordx4: each lane's 16 bytes land
-// at the wave's LDS segment base + 16 * lane), with no staging registers and
-// no LDS stores.  Four 32 KB stages of 16 k form a ring, filled three stages
-// ahead; a wave waits for its own loads of a stage (vmcnt) and the barrier
-// that follows publishes everyone's.  Past the last stage the requests repeat
-// the last stage into the free slot, so the count of loads in flight, and the
-// wait, are the same in every iteration.  The four slots are distinct arrays
-// named statically (the loop is unrolled by four), which lets the compiler
-// see that a read of one slot does not depend on loads into another.
+// contiguous 4 KB block of each plane, streamed straight from global memory
+// into LDS (global_load_lds_dwordx4: each lane's 16 bytes land at the wave's
+// LDS segment base + 16 * lane), with no staging registers and no LDS
+// stores.  The stages form a ring of NSLOT slots, filled NSLOT - 1 stages
+// ahead: 4M (four planes, 32 KB a stage) keeps four slots, 3M (six planes,
+// 48 KB a stage) three, within the 160 KB of LDS.  A wave waits for its own
+// loads of a stage (vmcnt, the later stages' loads may stay in flight) and
+// the barrier that follows publishes everyone's.  Past the last stage the
+// requests repeat the last stage into the free slot, so the count of loads
+// in flight, and the wait, are the same in every iteration.  The slots are
+// distinct arrays named statically (the loop is unrolled by the least common
+// multiple of NSLOT and the two fragment sets), which lets the compiler see
+// that a read of one slot does not depend on loads into another.
 //
-// LDS layout of a slot: [A planes 0-3][B planes 0-3], each 128 rows x 32
-// bytes; row r's 16-byte chunk c sits at position c ^ dswz(r), so the 16
-// rows read together fall on distinct banks.  While the fragments of stage
-// kt are read, the last two thirds of stage kt-1's products run.
+// LDS layout of a slot: [A planes][B planes], each 128 rows x 32 bytes; row
+// r's 16-byte chunk c sits at position c ^ dswz(r), so the 16 rows read
+// together fall on distinct banks.  While the fragments of stage kt are read,
+// the products of stage kt - 1 that did not run before the barrier run.
 constexpr int DBK = 16;               // k per stage
-constexpr int DSPLIT = 4;             // products of a stage run before the next barrier
 constexpr int DPLANE = BT * DBK;      // bf16 per plane tile (4 KB)
-constexpr int DSTAGE = 8 * DPLANE;    // A and B, four planes each (32 KB)
 typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 
+// s_waitcnt immediate: vmcnt(v) expcnt(7) lgkmcnt(0)
+__host__ __device__ constexpr int dma_wait_imm(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4); }
+
+template <int FORM>
 __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
-  __shared__ __align__(16) uint16_t ring0[DSTAGE], ring1[DSTAGE], ring2[DSTAGE], ring3[DSTAGE];
+  constexpr int NP = FORM == kForm3M ? 6 : 4;        // planes per operand
+  constexpr int NSLOT = FORM == kForm3M ? 3 : 4;     // ring slots
+  constexpr int NACC = FORM == kForm3M ? 3 : 2;
+  constexpr int NPROD = FORM == kForm3M ? 9 : 12;
+  constexpr int SPLIT = FORM == kForm3M ? 3 : 4;     // products of a stage before the next barrier
+  constexpr int UNROLL = NSLOT == 4 ? 4 : 6;         // lcm(NSLOT, 2)
+  constexpr int STAGE = 2 * NP * DPLANE;
+  // loads of a wave per stage: one 1 KB instruction per plane of A and of B
+  constexpr int LOADS = 2 * NP;
+  __shared__ __align__(16) uint16_t ring0[STAGE], ring1[STAGE], ring2[STAGE];
+  __shared__ __align__(16) uint16_t ring3[NSLOT == 4 ? STAGE : 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int q = blockIdx.y;
@@ -353,13 +376,13 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
   const int ea = tn_scale_exp(sa->maxbits), eb = tn_scale_exp(sb->maxbits);
   if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
 
-  v16f_b acc[2][2][2];
+  v16f_b acc[2][2][NACC];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < NACC; ++c)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[a][b][c][v] = 0.0f;
 
@@ -385,34 +408,42 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
     const int64_t kb = kbeg / DBK + (stg < nk ? stg : nk - 1);
     const uint8_t *ak = abase + kb * g.M * DBK * 2, *bk = bbase + kb * g.N * DBK * 2;
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) {
+    for (int pl = 0; pl < NP; ++pl) {
       __builtin_amdgcn_global_load_lds((const void *)(ak + pl * g.pa * 2 + aoff),
                                        (lds_void *)(rb + pl * DPLANE), 16, 0, 0);
       __builtin_amdgcn_global_load_lds((const void *)(bk + pl * g.pb * 2 + boff),
-                                       (lds_void *)(rb + (4 + pl) * DPLANE), 16, 0, 0);
+                                       (lds_void *)(rb + (NP + pl) * DPLANE), 16, 0, 0);
     }
   };
   const int fr = lane & 31, fpos = ((lane >> 5) ^ dswz(fr)) * 8;
-  auto fread = [&](auto slot, v4u (&a)[2][4], v4u (&b)[2][4]) {
+  // fragments in plane-pair order (A and B of pair 0, then pair 1, ...), so
+  // that the products of one pair can start while the next pair is read
+  auto fread = [&](auto slot, v4u (&a)[2][NP], v4u (&b)[2][NP]) {
     constexpr int S = decltype(slot)::value;
     const uint16_t *rb = TN_RING(S);
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int pp = 0; pp < NP; pp += 2) {
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl)
-        a[mb][pl] = *(const v4u *)(rb + pl * DPLANE + (wm * 64 + mb * 32 + fr) * DBK + fpos);
+      for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+        for (int pl = pp; pl < pp + 2; ++pl)
+          a[mb][pl] = *(const v4u *)(rb + pl * DPLANE + (wm * 64 + mb * 32 + fr) * DBK + fpos);
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl)
-        b[nb][pl] = *(const v4u *)(rb + (4 + pl) * DPLANE + (wn * 64 + nb * 32 + fr) * DBK + fpos);
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int pl = pp; pl < pp + 2; ++pl)
+          b[nb][pl] = *(const v4u *)(rb + (NP + pl) * DPLANE + (wn * 64 + nb * 32 + fr) * DBK + fpos);
+    }
   };
 #undef TN_RING
-  auto mma = [&](const v4u (&a)[2][4], const v4u (&b)[2][4], int p0, int p1) {
+  auto mma = [&](const v4u (&a)[2][NP], const v4u (&b)[2][NP], int p0, int p1) {
 #pragma unroll
-    for (int pi = 0; pi < 12; ++pi) {
+    for (int pi = 0; pi < NPROD; ++pi) {
       if (pi < p0 || pi >= p1) continue;
-      const int c = prod_4m(pi, 0), ap = prod_4m(pi, 1), bp = prod_4m(pi, 2), ng = prod_4m(pi, 3);
+      const int c = FORM == kForm3M ? prod_3m_g(pi, 0) : prod_4m(pi, 0);
+      const int ap = FORM == kForm3M ? prod_3m_g(pi, 1) : prod_4m(pi, 1);
+      const int bp = FORM == kForm3M ? prod_3m_g(pi, 2) : prod_4m(pi, 2);
+      const int ng = FORM == kForm3M ? prod_3m_g(pi, 3) : prod_4m(pi, 3);
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb) {
         const v8bf av = as_bf(ng ? neg4(a[mb][ap]) : a[mb][ap]);
@@ -423,56 +454,80 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
       }
     }
   };
-  v4u fa0[2][4], fb0[2][4], fa1[2][4], fb1[2][4];
-  // one stage: wait for it (two stages of loads may stay in flight; every
-  // fragment read done), barrier, request stage kt + 3 into the slot freed by
-  // stage kt - 1, read stage kt's fragments, then the remaining products of
-  // stage kt - 1 and the first DSPLIT of stage kt's
-  auto stage = [&](auto slot, int64_t kt, bool first) {
+  // 4M: two fragment sets (stage kt's are read while stage kt - 1's last
+  // products run); 3M: one set (its six planes and third accumulator set
+  // leave no room for a second), read pair by pair ahead of the products
+  constexpr int NFS = FORM == kForm3M ? 1 : 2;
+  v4u fa0[2][NP], fb0[2][NP], fa1[NFS][2][NP], fb1[NFS][2][NP];
+  // one stage (ring slot S, fragment set F = kt % 2): wait for it (the loads
+  // of the NSLOT - 2 stages after it may stay in flight; every fragment read
+  // done), barrier, request stage kt + NSLOT - 1 into the slot freed by stage
+  // kt - 1, read stage kt's fragments, then the remaining products of stage
+  // kt - 1 and the first SPLIT of stage kt's
+  auto run_stage = [&](auto slot, auto fset, int64_t kt, bool first) {
     constexpr int S = decltype(slot)::value;
-    __builtin_amdgcn_s_waitcnt((1 << 14) | (7 << 4));  // vmcnt(16) expcnt(7) lgkmcnt(0)
+    constexpr int F = decltype(fset)::value;
+    __builtin_amdgcn_s_waitcnt(dma_wait_imm((NSLOT - 2) * LOADS));
     __builtin_amdgcn_s_barrier();
-    issue(std::integral_constant<int, (S + 3) % 4>(), kt + 3);
-    if (S % 2 == 0)
+    issue(std::integral_constant<int, (S + NSLOT - 1) % NSLOT>(), kt + NSLOT - 1);
+    if constexpr (NFS == 1) {
       fread(slot, fa0, fb0);
-    else
-      fread(slot, fa1, fb1);
-    __builtin_amdgcn_sched_barrier(0);
-    if (!first) {
-      if (S % 2 == 0)
-        mma(fa1, fb1, DSPLIT, 12);
+      mma(fa0, fb0, 0, NPROD);
+    } else {
+      if (F == 0)
+        fread(slot, fa0, fb0);
       else
-        mma(fa0, fb0, DSPLIT, 12);
+        fread(slot, fa1[0], fb1[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      if (!first) {
+        if (F == 0)
+          mma(fa1[0], fb1[0], SPLIT, NPROD);
+        else
+          mma(fa0, fb0, SPLIT, NPROD);
+      }
+      if (F == 0)
+        mma(fa0, fb0, 0, SPLIT);
+      else
+        mma(fa1[0], fb1[0], 0, SPLIT);
     }
-    if (S % 2 == 0)
-      mma(fa0, fb0, 0, DSPLIT);
-    else
-      mma(fa1, fb1, 0, DSPLIT);
     __builtin_amdgcn_sched_barrier(0);
   };
-  const std::integral_constant<int, 0> s0;
-  const std::integral_constant<int, 1> s1;
-  const std::integral_constant<int, 2> s2;
-  const std::integral_constant<int, 3> s3;
+  // stage j of an unrolled block that starts at kt = 1 (mod UNROLL): slot
+  // (1 + j) % NSLOT, fragment set (1 + j) % 2
+  auto nth = [&](auto j, int64_t kt) {
+    constexpr int J = decltype(j)::value;
+    run_stage(std::integral_constant<int, (1 + J) % NSLOT>(), std::integral_constant<int, (1 + J) % 2>(),
+              kt, false);
+  };
   __builtin_amdgcn_s_waitcnt(0);  // nothing else in flight when the ring starts
-  issue(s0, 0);
-  issue(s1, 1);
-  issue(s2, 2);
-  stage(s0, 0, true);
+  issue(std::integral_constant<int, 0>(), 0);
+  issue(std::integral_constant<int, 1>(), 1);
+  if constexpr (NSLOT == 4) issue(std::integral_constant<int, 2>(), 2);
+  run_stage(std::integral_constant<int, 0>(), std::integral_constant<int, 0>(), 0, true);
   int64_t kt = 1;
-  for (; kt + 4 <= nk; kt += 4) {
-    stage(s1, kt, false);
-    stage(s2, kt + 1, false);
-    stage(s3, kt + 2, false);
-    stage(s0, kt + 3, false);
+  for (; kt + UNROLL <= nk; kt += UNROLL) {
+    nth(std::integral_constant<int, 0>(), kt);
+    nth(std::integral_constant<int, 1>(), kt + 1);
+    nth(std::integral_constant<int, 2>(), kt + 2);
+    nth(std::integral_constant<int, 3>(), kt + 3);
+    if constexpr (UNROLL == 6) {
+      nth(std::integral_constant<int, 4>(), kt + 4);
+      nth(std::integral_constant<int, 5>(), kt + 5);
+    }
   }
-  if (kt < nk) stage(s1, kt, false);
-  if (kt + 1 < nk) stage(s2, kt + 1, false);
-  if (kt + 2 < nk) stage(s3, kt + 2, false);
-  if ((nk - 1) & 1)
-    mma(fa1, fb1, DSPLIT, 12);
-  else
-    mma(fa0, fb0, DSPLIT, 12);
+  if (kt < nk) nth(std::integral_constant<int, 0>(), kt);
+  if (kt + 1 < nk) nth(std::integral_constant<int, 1>(), kt + 1);
+  if (kt + 2 < nk) nth(std::integral_constant<int, 2>(), kt + 2);
+  if constexpr (UNROLL == 6) {
+    if (kt + 3 < nk) nth(std::integral_constant<int, 3>(), kt + 3);
+    if (kt + 4 < nk) nth(std::integral_constant<int, 4>(), kt + 4);
+  }
+  if constexpr (NFS == 2) {
+    if ((nk - 1) & 1)
+      mma(fa1[0], fb1[0], SPLIT, NPROD);
+    else
+      mma(fa0, fb0, SPLIT, NPROD);
+  }
   __builtin_amdgcn_s_waitcnt(0);  // no load may still write LDS when the block ends
 
   const bool partial = g.ksplit > 1;
@@ -488,7 +543,15 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
         const int row = wm * 64 + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
         const int col = wn * 64 + nb * 32 + (lane & 31);
         const int64_t cm = m0 + row, cn = n0 + col;
-        const float re = acc[mb][nb][0][v], im = acc[mb][nb][1][v];
+        float re, im;
+        if (FORM == kForm4M) {
+          re = acc[mb][nb][0][v];
+          im = acc[mb][nb][1][v];
+        } else {
+          const float t1 = acc[mb][nb][0][v], t2 = acc[mb][nb][1][v], t3 = acc[mb][nb][NACC - 1][v];
+          re = t1 - t2;
+          im = t3 - t1 - t2;
+        }
         if (cm < g.M && cn < g.N) {
           C[cm * ldc + cn] = make_float2(re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
@@ -515,8 +578,11 @@ hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g0, int form, int 
   const dim3 grid((unsigned)blocks, nbatch);
   const bool exact = g.K % BKS == 0 && g.kchunk % BKS == 0;
   if (g.ktile) {
-    if (form != kForm4M || g.K % DBK != 0 || g.kchunk % DBK != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cgemm_bf16x3_dma, grid, dim3(256), 0, st, g);
+    if (g.K % DBK != 0 || g.kchunk % DBK != 0) return hipErrorInvalidValue;
+    if (form == kForm4M)
+      hipLaunchKernelGGL(k_cgemm_bf16x3_dma<kForm4M>, grid, dim3(256), 0, st, g);
+    else
+      hipLaunchKernelGGL(k_cgemm_bf16x3_dma<kForm3M>, grid, dim3(256), 0, st, g);
   } else if (form == kForm4M) {
     if (exact)
       hipLaunchKernelGGL((k_cgemm_bf16x3<kForm4M, true>), grid, dim3(256), 0, st, g);

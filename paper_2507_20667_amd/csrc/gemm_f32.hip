@@ -22,9 +22,13 @@
 // 64 bytes; row r's chunk c sits at position c ^ swz(r), so the rows one LDS
 // access touches fall on distinct banks.  A stage is 128 MFMAs per wave (4M),
 // so the fragments of stage kt are read while stage kt-1 multiplies.
-// 4M form only (Re = ArBr - AiBi, Im = ArBi + AiBr): the 3M form's third
-// accumulator set does not fit beside two fragment sets, and takes the
-// complex64 kernel.
+// FORM = 4M: Re = ArBr - AiBi, Im = ArBi + AiBr (four products per complex
+// one).  FORM = 3M (Gauss): T1 = ArBr, T2 = AiBi, T3 = (Ar + Ai)(Br + Bi),
+// Re = T1 - T2, Im = T3 - T1 - T2; the sums are formed in registers from the
+// fragments (one add per value), so the planes and the LDS traffic are the
+// same as 4M's and the MFMA work is three quarters of it.  The third
+// accumulator set lives beside the two fragment sets (the kernel runs one
+// wave per SIMD, with the accumulation registers).
 #include <type_traits>
 
 #include "tn_device.h"
@@ -46,8 +50,9 @@ __device__ __forceinline__ int fswz(int r) {
   return ((((r >> 3) ^ (r >> 1)) & 1) << 1) | ((r >> 2) & 1);
 }
 
+template <int FORM>
 __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
-  constexpr int NACC = 2;
+  constexpr int NACC = FORM == kForm3M ? 3 : 2;
   __shared__ __align__(16) float ring0[FSTAGE], ring1[FSTAGE], ring2[FSTAGE], ring3[FSTAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -149,47 +154,82 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
         br[x] = b[x][0][s >> 2][s & 3];
         bi[x] = b[x][1][s >> 2][s & 3];
       }
+      if (FORM == kForm4M) {
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[mb][nb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[mb], br[nb], acc[mb][nb][0], 0, 0, 0);
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[mb], br[nb], acc[mb][nb][0], 0, 0, 0);
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[mb][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[mb], bi[nb], acc[mb][nb][1], 0, 0, 0);
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[mb], bi[nb], acc[mb][nb][1], 0, 0, 0);
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[mb][nb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[mb], bi[nb], acc[mb][nb][0], 0, 0, 0);
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[mb], bi[nb], acc[mb][nb][0], 0, 0, 0);
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[mb][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[mb], br[nb], acc[mb][nb][1], 0, 0, 0);
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[mb], br[nb], acc[mb][nb][1], 0, 0, 0);
+      } else {
+        float as[2], bs[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          as[x] = ar[x] + ai[x];
+          bs[x] = br[x] + bi[x];
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[mb], br[nb], acc[mb][nb][0], 0, 0, 0);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[mb], bi[nb], acc[mb][nb][1], 0, 0, 0);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[mb], bs[nb], acc[mb][nb][NACC - 1], 0, 0, 0);
+      }
     }
   };
-  v4f fa0[2][2][2], fb0[2][2][2], fa1[2][2][2], fb1[2][2][2];
+  // 4M: two fragment sets (stage kt's are read while stage kt - 1's
+  // multiply); 3M: one set, whose third accumulator set takes the registers
+  // of the second (a stage is 96 MFMAs of 64 cycles per wave, so the LDS
+  // latency it exposes is small)
+  constexpr int NFS = FORM == kForm3M ? 1 : 2;
+  v4f fa0[2][2][2], fb0[2][2][2], fa1[NFS][2][2][2], fb1[NFS][2][2][2];
   // one stage: wait for it (two stages of loads may stay in flight, every
   // fragment read done), barrier, request stage kt + 3 into the slot stage
-  // kt - 1 used, read stage kt's fragments, multiply stage kt - 1's
+  // kt - 1 used, read stage kt's fragments, multiply stage kt - 1's (4M) or
+  // stage kt's (3M)
   auto stage = [&](auto slot, int64_t kt, bool first) {
     constexpr int S = decltype(slot)::value;
     __builtin_amdgcn_s_waitcnt((1 << 14) | (7 << 4));  // vmcnt(16) expcnt(7) lgkmcnt(0)
     __builtin_amdgcn_s_barrier();
     issue(std::integral_constant<int, (S + 3) % 4>(), kt + 3);
-    if (S % 2 == 0)
+    if constexpr (FORM == kForm3M) {
       fread(slot, fa0, fb0);
-    else
-      fread(slot, fa1, fb1);
-    __builtin_amdgcn_sched_barrier(0);
-    if (!first) {
+      mma(fa0, fb0);
+    } else {
       if (S % 2 == 0)
-        mma(fa1, fb1);
+        fread(slot, fa0, fb0);
       else
-        mma(fa0, fb0);
+        fread(slot, fa1[0], fb1[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      if (!first) {
+        if (S % 2 == 0)
+          mma(fa1[0], fb1[0]);
+        else
+          mma(fa0, fb0);
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -212,10 +252,12 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
   if (kt < nk) stage(s1, kt, false);
   if (kt + 1 < nk) stage(s2, kt + 1, false);
   if (kt + 2 < nk) stage(s3, kt + 2, false);
-  if ((nk - 1) & 1)
-    mma(fa1, fb1);
-  else
-    mma(fa0, fb0);
+  if constexpr (FORM == kForm4M) {
+    if ((nk - 1) & 1)
+      mma(fa1[0], fb1[0]);
+    else
+      mma(fa0, fb0);
+  }
   __builtin_amdgcn_s_waitcnt(0);  // no load may still write LDS when the block ends
 
   const bool partial = g.ksplit > 1;
@@ -231,7 +273,15 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
         const int row = wm * 64 + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
         const int col = wn * 64 + nb * 32 + (lane & 31);
         const int64_t cm = m0 + row, cn = n0 + col;
-        const float re = acc[mb][nb][0][v], im = acc[mb][nb][1][v];
+        float re, im;
+        if (FORM == kForm4M) {
+          re = acc[mb][nb][0][v];
+          im = acc[mb][nb][1][v];
+        } else {
+          const float t1 = acc[mb][nb][0][v], t2 = acc[mb][nb][1][v], t3 = acc[mb][nb][NACC - 1][v];
+          re = t1 - t2;
+          im = t3 - t1 - t2;
+        }
         if (cm < g.M && cn < g.N) {
           C[cm * ldc + cn] = make_float2(re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
@@ -246,7 +296,8 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
 
 hipError_t launch_gemm_f32_planes(hipStream_t st, const GemmArgs &g0, int form, int nbatch) {
   GemmArgs g = g0;
-  if (g.opA != 0 || g.opB != 1 || g.planes != 2 || !g.ktile || g.K % FBK != 0 || form != kForm4M)
+  if (g.opA != 0 || g.opB != 1 || g.planes != 2 || !g.ktile || g.K % FBK != 0 ||
+      (form != kForm4M && form != kForm3M))
     return hipErrorInvalidValue;
   g.tiles_m = (int)((g.M + FT - 1) / FT);
   g.tiles_n = (int)((g.N + FT - 1) / FT);
@@ -258,7 +309,10 @@ hipError_t launch_gemm_f32_planes(hipStream_t st, const GemmArgs &g0, int form, 
   const int64_t blocks = (int64_t)g.tiles_m * g.tiles_n * g.ksplit;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks, nbatch);
-  hipLaunchKernelGGL(k_cgemm_f32_planes, grid, dim3(256), 0, st, g);
+  if (form == kForm4M)
+    hipLaunchKernelGGL(k_cgemm_f32_planes<kForm4M>, grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL(k_cgemm_f32_planes<kForm3M>, grid, dim3(256), 0, st, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.ksplit == 1) return e;
   return launch_splitk_reduce(st, g, nbatch);

@@ -254,7 +254,7 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   int bMode = block_at_start(B, S) ? 0 : (block_at_end(B, S) ? 1 : -1);   // 0: N, 1: T
   std::vector<int64_t> sorder;
   bool permA = aMode < 0, permB = bMode < 0;
-  // The split-BF16 GEMM, and the FP32 4M GEMM when k is a multiple of 16,
+  // The split-BF16 GEMM, and the FP32 GEMM when k is a multiple of 16,
   // read both operands as planes that the permutation kernel writes (an
   // identity map where the order is right).
   int64_t k_all = 1;
@@ -262,7 +262,7 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   n.planes = 0;
   if (p->flags & TN_PREC_BF16X3)
     n.planes = (p->flags & TN_FORM_3M) ? 6 : 4;
-  else if (!(p->flags & TN_FORM_3M) && k_all % 16 == 0)
+  else if (k_all % 16 == 0)
     n.planes = 2;
   if (n.planes > 0) {
     sorder = !permA || permB ? sA : sB;
@@ -331,7 +331,7 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
     const int tile = n.planes > 0 ? 128 : gemm_variant_tile_m(n.variant);
     n.ksplit = gemm_ksplit(n.M, n.N, n.K, tile, tile, &n.kchunk);
   }
-  n.ktile = (n.planes == 4 || n.planes == 2) && n.K % 16 == 0 &&
+  n.ktile = n.planes > 0 && n.K % 16 == 0 &&
             (n.ksplit == 1 || n.kchunk % 16 == 0);
   p->num_perm += (int)permA + (int)permB;
   return TN_OK;

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/tn.h"
+#include "arena.h"
 #include "tn_device.h"
 
 namespace tn {
@@ -129,72 +130,6 @@ struct ExecLayout {
 };
 
 struct tn_plan_impl;
-
-// Device arena: first-fit over a borrowed device range, 256-byte granules.
-class Arena {
- public:
-  void init(uint8_t *base, size_t bytes) {
-    base_ = base;
-    bytes_ = bytes;
-    free_.clear();
-    if (bytes) free_[0] = bytes;
-  }
-  // returns offset or -1
-  int64_t alloc(size_t bytes) {
-    std::lock_guard<std::mutex> g(mu_);
-    bytes = round(bytes);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        int64_t off = it->first;
-        size_t rem = it->second - bytes;
-        free_.erase(it);
-        if (rem) free_[off + (int64_t)bytes] = rem;
-        used_ += bytes;
-        return off;
-      }
-    }
-    return -1;
-  }
-  void release(int64_t off, size_t bytes) {
-    if (off < 0) return;
-    std::lock_guard<std::mutex> g(mu_);
-    bytes = round(bytes);
-    used_ -= bytes;
-    auto it = free_.emplace((int64_t)off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + (int64_t)it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + (int64_t)pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t largest_free() {
-    std::lock_guard<std::mutex> g(mu_);
-    size_t m = 0;
-    for (auto &kv : free_) m = kv.second > m ? kv.second : m;
-    return m;
-  }
-  size_t used() {
-    std::lock_guard<std::mutex> g(mu_);
-    return used_;
-  }
-  uint8_t *base() const { return base_; }
-  size_t bytes() const { return bytes_; }
-  static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
-
- private:
-  std::mutex mu_;
-  uint8_t *base_ = nullptr;
-  size_t bytes_ = 0;
-  size_t used_ = 0;
-  std::map<int64_t, size_t> free_;
-};
 
 struct ServeState;  // serve.cpp
 

@@ -180,7 +180,12 @@ def test_permutation_is_bit_exact(ctx, shape, perm):
                                          # few output tiles, deep k: split into k chunks
                                          (64, 4100, 96, lib.TN_FORM_4M), (100, 8192, 70, lib.TN_FORM_3M),
                                          # k a multiple of 16: float planes, k-tiled, ragged M and N
-                                         (130, 48, 300, lib.TN_FORM_4M), (200, 4096, 72, lib.TN_FORM_4M)])
+                                         (130, 48, 300, lib.TN_FORM_4M), (200, 4096, 72, lib.TN_FORM_4M),
+                                         (130, 48, 300, lib.TN_FORM_3M), (200, 4096, 72, lib.TN_FORM_3M),
+                                         (1024, 512, 1024, lib.TN_FORM_3M)]
+                         # 1, 3, 5, 7 and 11 stages of 16 k: every tail of the four-slot ring
+                         + [(130, k, 200, f) for k in (16, 48, 80, 112, 176)
+                            for f in (lib.TN_FORM_4M, lib.TN_FORM_3M)])
 def test_gemm_vertex_against_fp64(ctx, M, K, N, form):
     """Two tensors A(m, k) and B(k, n) with an open output: one GEMM vertex.
     Error bound |dC| <= gamma * |A||B| with gamma = 4 * K * 2^-24 (FP32 inputs
@@ -239,7 +244,14 @@ def test_keep_scale_and_open_legs(ctx):
                                          (1024, 512, 1024, lib.TN_FORM_4M),
                                          # split into k chunks (aligned, ragged and unaligned k)
                                          (64, 4096, 96, lib.TN_FORM_4M), (200, 3000, 130, lib.TN_FORM_3M),
-                                         (64, 2050, 64, lib.TN_FORM_4M)])
+                                         (64, 2050, 64, lib.TN_FORM_4M),
+                                         # k a multiple of 16: k-tiled planes streamed into LDS
+                                         (1024, 512, 1024, lib.TN_FORM_3M), (64, 4096, 96, lib.TN_FORM_3M),
+                                         (300, 64, 129, lib.TN_FORM_3M)]
+                         # 1 to 11 stages of 16 k: every tail of the four-slot (4M) and
+                         # three-slot (3M, unrolled by six) rings
+                         + [(130, k, 200, f) for k in (16, 32, 48, 80, 96, 112, 176, 208)
+                            for f in (lib.TN_FORM_4M, lib.TN_FORM_3M)])
 def test_gemm_vertex_bf16x3_against_fp64(ctx, M, K, N, form):
     """Three-term split BF16: each real product a*b is carried as
     ha*hb + ha*lb + la*hb with h = bf16(a), l = bf16(a - h), so the dropped
