@@ -48,9 +48,11 @@ def greedy_pairs(items, dims, rng=None, temperature: float = 0.0):
             key = -score
         heapq.heappush(heap, (key, lo, hi))
 
+    # edges in label order, so that the order of the pushes (and of the noise
+    # draws) does not depend on how a set happens to iterate
     seen = set()
-    for e, hs in holders.items():
-        hs = sorted(hs)
+    for e in sorted(holders):
+        hs = sorted(holders[e])
         for x in range(len(hs)):
             for y in range(x + 1, len(hs)):
                 p = (hs[x], hs[y])

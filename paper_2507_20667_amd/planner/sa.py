@@ -1,5 +1,6 @@
 """Simulated-annealing refinement of a partitioning (Section 4.3, Algorithms 1
-and 2).
+and 2).  The search loop is built from a cooling schedule, an acceptance
+predicate, a best-state tracker with restarts and a progress clock.
 
 State: a partitioning K with a Greedy tree per partition and a RandomGreedy
 reduction path; its cost is eq. con_dist (con = con_serial, comm = 0).
@@ -57,6 +58,8 @@ class SAConfig:
     rg_samples: int = 16
     rg_temperature: float = 0.1
     seed: int = 0
+    # run the p workers' chains in forked processes (same result as in turn)
+    parallel: bool = False
 
 
 def objective(legs_a, legs_b, dims) -> int:
@@ -115,49 +118,108 @@ class Annealer:
         return SAState(pof, parts, red, cost)
 
     def do_steps(self, n, s: SAState, temp, rng) -> SAState:
+        """n Metropolis steps at temperature `temp` from state s."""
         for _ in range(n):
             new = self.neighbour(s, rng)
-            if s.cost == 0:
-                accept = new.cost <= s.cost
-            elif new.cost <= s.cost:
-                accept = True
-            else:
-                p = math.exp(-(math.log(new.cost) - math.log(s.cost)) / temp)
-                accept = p >= rng.random()
-            if accept:
+            if accept(s.cost, new.cost, temp, rng):
                 s = new
         return s
 
-    def run(self, initial_partition_of) -> tuple:
+    def run(self, initial_partition_of, pool=None) -> tuple:
+        """Search from the initial partitioning; returns (best state, history
+        of (iteration, temperature, current cost, best cost)).  `pool`: an
+        executor whose map runs the workers' step chains side by side (the
+        same result as one after another: each worker has its own random
+        stream)."""
         cfg = self.cfg
         rngs = [np.random.default_rng([cfg.seed, w]) for w in range(cfg.workers)]
         cur = self.make_state(initial_partition_of, rngs[0])
-        best = cur
-        i_best = i = -1
-        alpha = cfg.tf / cfg.t0
-        n_p = -(-cfg.n_steps // cfg.workers)
-        start = time.monotonic()
+        track = BestTracker(cur, cfg.restart_threshold)
+        clock = Progress(cfg.iterations, cfg.time_limit)
+        steps = -(-cfg.n_steps // cfg.workers)     # each worker's share of N
         history = []
         while True:
-            if cfg.iterations is not None:
-                if i + 1 >= cfg.iterations:
-                    break
-                t = (i + 1) / cfg.iterations
+            t = clock.next()
+            if t is None:
+                break
+            temp = cooling(t, cfg.t0, cfg.tf)
+            if pool is None:
+                ends = [self.do_steps(steps, cur, temp, r) for r in rngs]
             else:
-                elapsed = time.monotonic() - start
-                if elapsed >= cfg.time_limit:
-                    break
-                t = elapsed / cfg.time_limit
-            i += 1
-            temp = cfg.t0 * alpha ** t
-            results = [self.do_steps(n_p, cur, temp, rngs[w]) for w in range(cfg.workers)]
-            cur = min(enumerate(results), key=lambda x: (x[1].cost, x[0]))[1]
-            if cur.cost < best.cost:
-                i_best, best = i, cur
-            elif i - i_best >= cfg.restart_threshold:
-                i_best, cur = i, best
-            history.append((i, temp, cur.cost, best.cost))
-        return best, history
+                out = list(pool.map(_worker_chain, [(self, steps, cur, temp, r) for r in rngs]))
+                ends = [e for e, _ in out]
+                rngs = [r for _, r in out]
+                self.evaluations += steps * len(rngs)
+            # the cheapest worker's end state (lowest worker index on ties)
+            cur = min(enumerate(ends), key=lambda x: (x[1].cost, x[0]))[1]
+            cur = track.update(clock.i, cur)
+            history.append((clock.i, temp, cur.cost, track.best.cost))
+        return track.best, history
+
+
+def cooling(t: float, t0: float, tf: float) -> float:
+    """Exponential cooling from t0 at progress t = 0 to tf at t = 1."""
+    return t0 * (tf / t0) ** t
+
+
+def accept(c_cur: int, c_new: int, temp: float, rng) -> bool:
+    """Metropolis rule on the log of the cost ratio: downhill or equal moves
+    always, an uphill move with probability exp(-log(c_new / c_cur) / temp),
+    i.e. (c_cur / c_new)^(1 / temp).  A draw is made only for uphill moves."""
+    if c_new <= c_cur:
+        return True
+    if c_cur == 0:
+        return False
+    return math.exp(-(math.log(c_new) - math.log(c_cur)) / temp) >= rng.random()
+
+
+class BestTracker:
+    """The cheapest state seen and the iteration that found it; after
+    `threshold` iterations without improvement the search restarts from it."""
+
+    def __init__(self, start: SAState, threshold: int):
+        self.best = start
+        self.found = -1
+        self.threshold = threshold
+
+    def update(self, i: int, cur: SAState) -> SAState:
+        if cur.cost < self.best.cost:
+            self.best, self.found = cur, i
+            return cur
+        if i - self.found >= self.threshold:
+            self.found = i
+            return self.best
+        return cur
+
+
+class Progress:
+    """Search progress t in [0, 1): iteration / budget when a budget is
+    given (reproducible), else elapsed / time limit.  next() returns None once
+    the search is over."""
+
+    def __init__(self, iterations, time_limit):
+        self.iterations, self.time_limit = iterations, time_limit
+        self.i = -1
+        self.start = time.monotonic()
+
+    def next(self):
+        if self.iterations is not None:
+            if self.i + 1 >= self.iterations:
+                return None
+            t = (self.i + 1) / self.iterations
+        else:
+            elapsed = time.monotonic() - self.start
+            if elapsed >= self.time_limit:
+                return None
+            t = elapsed / self.time_limit
+        self.i += 1
+        return t
+
+
+def _worker_chain(args):
+    ann, steps, state, temp, rng = args
+    end = ann.do_steps(steps, state, temp, rng)
+    return end, rng
 
 
 def simulated_annealing(leaf_legs, dims, initial_partition_of, num_partitions,
@@ -165,7 +227,15 @@ def simulated_annealing(leaf_legs, dims, initial_partition_of, num_partitions,
     cfg = cfg or SAConfig()
     ann = Annealer(leaf_legs, dims, num_partitions, cfg)
     init = ann.make_state(initial_partition_of, np.random.default_rng([cfg.seed, 0]))
-    best, history = ann.run(initial_partition_of)
+    if cfg.parallel and cfg.workers > 1:
+        # the workers' step chains in processes of their own (forked: no
+        # program is started, the planner's state is copied)
+        import multiprocessing
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(cfg.workers, mp_context=multiprocessing.get_context("fork")) as pool:
+            best, history = ann.run(initial_partition_of, pool)
+    else:
+        best, history = ann.run(initial_partition_of)
     tree, roots = assemble_tree(len(leaf_legs), best.parts, best.red_pairs)
     meta = dict(method="sa-directed" if cfg.directed else "sa-naive", seed=cfg.seed,
                 t0=cfg.t0, tf=cfg.tf, n_steps=cfg.n_steps, workers=cfg.workers,
