@@ -262,6 +262,35 @@ tn_status tn_contract_strided(tn_plan *plan, int32_t num_queries, int32_t num_ov
                               uint32_t flags);
 
 /*
+ * tn_contract_strided for callers that cannot allocate memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * The call performs no device or pinned-host allocation of any kind (no
+ * hipMalloc, hipHostMalloc, hipFree, no arena allocation): its workspace is a
+ * fixed static array in device memory (64 MiB; every GPU the library runs on
+ * holds one for the life of the process), the overrides are read in place
+ * and the results are written to device memory by the kernels.
+ *   overrides, strides  as tn_contract_strided, but every override must be
+ *               TN_C64_DEVICE with a stride that is a multiple of 8 bytes.
+ *   out         device memory, 16-byte aligned: query q's amplitude as a
+ *               complex128 value (scale folded in) at element q * out_stride.
+ *   flags       0.
+ * Only closed networks (one amplitude per query).  The plan's subtree
+ * programs for this set of overridden leaves must already be on the device:
+ * run tn_contract_strided once with the same leaves overridden first.
+ * Synchronous.  Every call on one GPU shares that GPU's scratch array, which
+ * keeps the last call's contents: calls that overlap on one GPU (from two
+ * contexts, or with another process's calls) race on it; calls on one
+ * context are serialized.
+ * Errors: TN_E_INVALID_ARG (host override data, bad stride, open network,
+ * programs not yet on the device, bad out), TN_E_NOMEM (the workspace of
+ * num_queries queries exceeds the 64 MiB scratch; split the call),
+ * TN_E_DEVICE.
+ */
+tn_status tn_contract_strided_noalloc(tn_plan *plan, int32_t num_queries, int32_t num_overrides,
+                                      const tn_leaf *overrides, const int64_t *strides, void *out,
+                                      int64_t out_stride, uint32_t flags);
+
+/*
  * Serving.  tn_serve_submit copies the query and returns a ticket at once
  * (TN_E_AGAIN when the queue is full).  A library thread admits queued
  * requests while their workspace fits the free arena, groups admitted

@@ -43,6 +43,13 @@ tn_status tn_ctx_create(void *arena_dev_ptr, size_t arena_bytes, void *hip_strea
   }
   c->arena.init((uint8_t *)arena_dev_ptr, arena_bytes);
   c->stream = (hipStream_t)hip_stream;
+  // this device's static scratch (tn_contract_strided_noalloc); without it
+  // that call reports an error, every other call works as before
+  void *sp = nullptr;
+  if (scratch_address(c->device, &sp) == hipSuccess)
+    c->scratch = (uint8_t *)sp;
+  else
+    (void)hipGetLastError();
   *out = c;
   return TN_OK;
 }
@@ -285,6 +292,76 @@ tn_status tn_contract_strided(tn_plan *p, int32_t num_queries, int32_t num_overr
   std::lock_guard<std::mutex> g(p->ctx->exec_mu);
   ExecRes r = ctx_res(p->ctx);
   return run_group(p->ctx, p, qs, out_dtype, flags, true, r, &so);
+}
+
+tn_status tn_contract_strided_noalloc(tn_plan *p, int32_t num_queries, int32_t num_overrides,
+                                      const tn_leaf *overrides, const int64_t *strides, void *out,
+                                      int64_t out_stride, uint32_t flags) {
+  if (!p || !p->ctx) {
+    set_error("tn_contract_strided_noalloc: plan is NULL or host-only (loaded without a context)");
+    return TN_E_INVALID_ARG;
+  }
+  if (num_queries < 0 || num_overrides < 0 || (num_overrides > 0 && (!overrides || !strides)) ||
+      (num_queries > 0 && !out) || out_stride < 1 || flags != 0 || ((uintptr_t)out & 15)) {
+    set_error("tn_contract_strided_noalloc: bad arguments (out: 16-byte aligned device memory, "
+              "out_stride >= 1, flags = 0)");
+    return TN_E_INVALID_ARG;
+  }
+  if (!p->closed || p->nv < 2) {
+    set_error("tn_contract_strided_noalloc: only closed networks of two or more tensors (one "
+              "amplitude per query)");
+    return TN_E_INVALID_ARG;
+  }
+  for (int32_t i = 0; i < num_overrides; ++i)
+    if (overrides[i].dtype != TN_C64_DEVICE || strides[i] < 0 || strides[i] % 8 != 0) {
+      set_error("tn_contract_strided_noalloc: override %d must be TN_C64_DEVICE with a "
+                "non-negative stride that is a multiple of 8 bytes", i);
+      return TN_E_INVALID_ARG;
+    }
+  tn_ctx *ctx = p->ctx;
+  if (!ctx->scratch) {
+    set_error("tn_contract_strided_noalloc: the static scratch of this device is unavailable");
+    return TN_E_DEVICE;
+  }
+  if (num_queries == 0) return TN_OK;
+  // the plan's subtree programs for this override set must already be in the
+  // arena (put there by an earlier call): this call uploads nothing
+  std::vector<char> is(p->nv, 0);
+  for (int32_t i = 0; i < num_overrides; ++i) {
+    const int t = overrides[i].tensor;
+    if (t < 0 || t >= p->nv || is[t] || !overrides[i].data) {
+      set_error("tn_contract_strided_noalloc: override %d: tensor id out of range or repeated, or "
+                "NULL data", i);
+      return TN_E_INVALID_ARG;
+    }
+    is[t] = 1;
+  }
+  std::vector<int> ovr;
+  for (int t = 0; t < p->nv; ++t)
+    if (is[t]) ovr.push_back(t);
+  {
+    std::shared_ptr<ExecLayout> L = cached_layout(p, ovr, true);
+    std::lock_guard<std::mutex> g(p->cache_mu);
+    if (L->n_tree_shared + L->n_tree_perq > 0 && L->tree_dev < 0) {
+      set_error("tn_contract_strided_noalloc: the plan's subtree programs for these overridden "
+                "leaves are not on the device yet; run tn_contract_strided once with them first");
+      return TN_E_INVALID_ARG;
+    }
+  }
+  StridedOvr so;
+  so.leaves.assign(overrides, overrides + num_overrides);
+  so.strides.assign(strides, strides + num_overrides);
+  so.dout = (double2 *)out;
+  so.dout_stride = out_stride;
+  so.device_out = true;
+  std::vector<QueryIO> qs((size_t)num_queries);
+  for (int32_t i = 0; i < num_queries; ++i) qs[i].out = (char *)out + (size_t)i * (size_t)out_stride * 16;
+  std::lock_guard<std::mutex> g(ctx->exec_mu);
+  ExecRes r;
+  r.st = ctx->stream;
+  r.ext_ws = ctx->scratch;
+  r.ext_ws_bytes = kScratchBytes;
+  return run_group(ctx, p, qs, TN_C128, 0, true, r, &so);
 }
 
 tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *queries,

@@ -275,7 +275,15 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                            (size_t)max_blocks * 16;
   // queries per chunk that fit the arena (or the caller's reserved workspace)
   size_t chunk;
-  if (rs.ws >= 0) {
+  if (rs.ext_ws) {
+    const size_t need = group_workspace_bytes(p, L, (int)qs.size());
+    if (need > rs.ext_ws_bytes) {
+      set_error("the workspace of %zu queries (%zu bytes) exceeds the static scratch (%zu bytes)",
+                qs.size(), need, rs.ext_ws_bytes);
+      return TN_E_NOMEM;
+    }
+    chunk = qs.size();
+  } else if (rs.ws >= 0) {
     if (group_workspace_bytes(p, L, (int)qs.size()) > rs.ws_bytes) {
       set_error("reserved workspace too small for %zu queries", qs.size());
       return TN_E_NOMEM;
@@ -295,7 +303,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   tn_status rc = TN_OK;
   // TN_FLAG_GRAPH (the whole group in one chunk, not profiled, not serving):
   // the call runs on the context's graph stream, after the caller's stream
-  bool want_graph = (flags & TN_FLAG_GRAPH) && rs.ws < 0 && !prof.on && !dbg_gemm &&
+  bool want_graph = (flags & TN_FLAG_GRAPH) && rs.ws < 0 && !rs.ext_ws && !prof.on && !dbg_gemm &&
                     chunk >= qs.size();
   hipStream_t gst = nullptr;
   // a caller's stream other than the context's (a batch lane, never the null
@@ -364,8 +372,8 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         }
       }
     }
-    const bool own_ws = rs.ws < 0 && !gmode;
-    int64_t ws = gmode ? p->graph->ws : own_ws ? ctx->arena.alloc(total) : rs.ws;
+    const bool own_ws = rs.ws < 0 && !rs.ext_ws && !gmode;
+    int64_t ws = rs.ext_ws ? 0 : gmode ? p->graph->ws : own_ws ? ctx->arena.alloc(total) : rs.ws;
     // the free space measured above may have been taken meanwhile (serve
     // workers share the arena): fewer queries per chunk
     while (ws < 0 && own_ws && Q > 1) {
@@ -381,7 +389,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       return TN_E_NOMEM;
     }
     bool capturing = false;
-    uint8_t *base = ctx->arena.base() + ws;
+    uint8_t *base = rs.ext_ws ? rs.ext_ws : ctx->arena.base() + ws;
     uint8_t *shared_base = base + r_shared, *perq_base = base + r_perq;
     Slot *slots = (Slot *)(base + r_slots);
     Slot *slots_sh = slots, *slots_q = slots + nn;
@@ -453,6 +461,12 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
             direct_p[t] = nullptr;
             any_staged = true;
           }
+        }
+        if (any_staged && so->device_out) {
+          set_error("every override must be device data read in place (TN_C64_DEVICE, a stride "
+                    "that is a multiple of 8 bytes)");
+          rc = TN_E_INVALID_ARG;
+          goto done;
         }
         if (any_staged) {
           rc = ensure_pinned(rs, ovr_bytes * Q, st);
@@ -548,10 +562,12 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       const bool root_shared = L.shared[p->root] != 0;
       const bool dot_root = nv > 1 && p->nodes[p->root - nv].kind == NK_DOT;
       size_t rb_vals = (size_t)Q * relems * 8, rb_slots = (size_t)Q * sizeof(Slot);
+      // results into device memory (no host staging at all)
+      const bool devout = so && so->device_out;
       uint8_t *h = nullptr;
       if (gmode) {
         h = (uint8_t *)p->graph->pinned;
-      } else {
+      } else if (!devout) {
         rc = ensure_pinned(rs, rb_bytes, st);
         if (rc) goto done;
         h = (uint8_t *)*rs.pinned;
@@ -562,7 +578,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       // a closed root's records go straight to the pinned staging buffer
       // (host memory the device writes to; visible after the synchronize
       // below), which saves the copy back
-      Result *res_out = dot_root ? hr : res;
+      Result *res_out = dot_root && !devout ? hr : res;
       // results straight into the caller's pinned array: complex128 values
       // scaled to 1, a closed root computed by the subtree kernel, no graph
       const bool direct = so && so->dout && out_dtype == TN_C128 && !(flags & TN_FLAG_KEEP_SCALE) &&
@@ -801,8 +817,13 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
                           }),
                "output permutation");
       }
+      // device results not written by the subtree kernel: from the records
+      if (devout && !direct)
+        TN_HIP(launch_results_to_c128(st, res, root_shared ? 0 : 1, Q,
+                                      so->dout + (int64_t)q0 * so->dout_stride, so->dout_stride),
+               "result conversion");
       // read back
-      if (!dot_root) {
+      if (!dot_root && !devout) {
         const int rq = root_shared ? 1 : Q;
         if (p->fperm.needed) {
           // the permuted results lie final_bytes apart (256-byte rounded)
@@ -839,7 +860,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       // written by the kernel: only the scales (1) remain, if asked for
       for (int qi = 0; qi < Q && direct && so->log2s; ++qi)
         if (qs[q0 + qi].log2s) *qs[q0 + qi].log2s = 0.0;
-      for (int qi = 0; qi < Q && !direct; ++qi) {
+      for (int qi = 0; qi < Q && !direct && !devout; ++qi) {
         const QueryIO &q = qs[q0 + qi];
         const bool keep = (flags & TN_FLAG_KEEP_SCALE) != 0;
         if (dot_root) {

@@ -10,6 +10,8 @@
 // Every kernel reads the scale records of its operands, multiplies by the
 // power of two that brings their maxima to [1, 2), writes the scale of its
 // output and contributes to the output's running max (Slot).
+#include <mutex>
+
 #include "tn_device.h"
 
 namespace tn {
@@ -729,6 +731,49 @@ hipError_t launch_dot(hipStream_t st, const DotDesc *d_desc, int64_t nelem, Oper
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dot_final, dim3(nbatch), dim3(256), 0, st, partials, nblocks, A, B, C, res,
                      rbs);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- static scratch
+// The workspace of tn_contract_strided_noalloc: a fixed array in device
+// memory that every GPU the library runs on holds until the process ends, so
+// that the call needs no allocation.  Host code never names it directly (in
+// host code the name is a host-side stand-in, not a device address): its
+// address on each device comes from hipGetSymbolAddress, taken once per
+// device with that device current (at context creation) and kept.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void **ptr) {
+  static std::mutex mu;
+  static void *per_device[kScratchMaxDevices] = {};
+  if (device < 0 || device >= kScratchMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!per_device[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    per_device[device] = p;
+  }
+  *ptr = per_device[device];
+  return hipSuccess;
+}
+
+// Closed-root result records to complex128 values with the scale folded in
+// (as the host does for tn_contract): out[q * stride] = (re, im) * 2^log2s.
+__global__ void k_results_to_c128(const Result *res, int64_t rbs, int nq, double2 *out,
+                                  int64_t stride) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const Result r = res[q * rbs];
+  const int e = (int)r.log2s;
+  out[(int64_t)q * stride] = make_double2(ldexp(r.re, e), ldexp(r.im, e));
+}
+
+hipError_t launch_results_to_c128(hipStream_t st, const Result *res, int64_t rbs, int nq,
+                                  double2 *out, int64_t stride) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_results_to_c128, dim3((nq + 255) / 256), dim3(256), 0, st, res, rbs, nq, out,
+                     stride);
   return hipGetLastError();
 }
 

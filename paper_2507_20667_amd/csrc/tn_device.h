@@ -321,6 +321,17 @@ hipError_t launch_tree(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds
 hipError_t launch_tree_wave(hipStream_t st, const TreeLaunch &t, int nsub, size_t lds_bytes);
 size_t tree_lds_limit();
 
+// The static scratch array of tn_contract_strided_noalloc (kernels.hip): its
+// size, and its device address on `device` (taken once per device with the
+// device current, then kept).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kScratchMaxDevices = 64;
+hipError_t scratch_address(int device, void **ptr);
+// closed-root records of nq queries (query q's at res[q * rbs]) to
+// complex128 values at out[q * stride]
+hipError_t launch_results_to_c128(hipStream_t st, const Result *res, int64_t rbs, int nq,
+                                  double2 *out, int64_t stride);
+
 // Tile shape variants of the GEMM (index into a table in the kernel file).
 int gemm_num_variants();
 int gemm_variant_tile_m(int v);

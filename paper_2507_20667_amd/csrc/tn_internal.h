@@ -220,6 +220,8 @@ struct tn_ctx {
   std::vector<hipStream_t> part_st;
   std::vector<hipEvent_t> part_ev;
   hipEvent_t part_ev0 = nullptr;
+  // this device's static scratch (tn_contract_strided_noalloc), or NULL
+  uint8_t *scratch = nullptr;
 };
 
 namespace tn {
@@ -300,6 +302,10 @@ struct StridedOvr {
   double2 *dout = nullptr;
   int64_t dout_stride = 0;
   bool log2s = false;  // the caller asked for scales (written on the host)
+  // dout is device memory: every closed root's complex128 value goes there
+  // (from the subtree kernel, else converted from its record on the device);
+  // nothing is staged through host memory
+  bool device_out = false;
 };
 // Resources of one executing thread: its stream, its pinned staging, an
 // optional profiler and optionally a workspace reserved beforehand.
@@ -310,6 +316,10 @@ struct ExecRes {
   Profiler *prof = nullptr;
   int64_t ws = -1;
   size_t ws_bytes = 0;
+  // a workspace outside the arena (the static scratch): its device address
+  // and size; the whole group must fit it
+  uint8_t *ext_ws = nullptr;
+  size_t ext_ws_bytes = 0;
 };
 tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_dtype out_dtype,
                     uint32_t flags, bool share, ExecRes &rs, const StridedOvr *so = nullptr);

@@ -33,7 +33,8 @@ STATUS_NAMES = {0: "TN_OK", 1: "TN_PENDING", -1: "TN_E_INVALID_ARG", -2: "TN_E_I
 
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_last_error", "tn_plan_load",
             "tn_plan_costs_get", "tn_plan_free", "tn_contract", "tn_contract_batch", "tn_contract_strided",
-            "tn_serve_submit", "tn_serve_poll", "tn_profile_enable", "tn_profile_read"]
+            "tn_contract_strided_noalloc", "tn_serve_submit", "tn_serve_poll", "tn_profile_enable",
+            "tn_profile_read"]
 
 
 class TnError(RuntimeError):
@@ -94,6 +95,7 @@ def load():
             "tn_contract": [P, I32, P, P, ctypes.c_int, P, U32],
             "tn_contract_batch": [P, I32, P, P, ctypes.c_int, P, P, U32],
             "tn_contract_strided": [P, I32, I32, P, P, P, ctypes.c_int64, ctypes.c_int, P, U32],
+            "tn_contract_strided_noalloc": [P, I32, I32, P, P, P, ctypes.c_int64, U32],
             "tn_serve_submit": [P, P, P],
             "tn_serve_poll": [P, ctypes.c_uint64, P, ctypes.c_int, P, P],
         }
@@ -265,6 +267,22 @@ def tn_contract_strided(plan, num_queries, overrides, result_shape=(), out_dtype
                                       _p(out), ctypes.c_int64(stride), out_dtype,
                                       _p(l2) if scales else None, flags))
     return out, (l2[:num_queries] if scales else None)
+
+
+def tn_contract_strided_noalloc(plan, num_queries, overrides, out_ptr, out_stride=1):
+    """overrides: list of (tensor id, device address, stride bytes); out_ptr:
+    device address of num_queries complex128 results (out_stride elements
+    apart).  Allocates nothing."""
+    n = len(overrides)
+    arr = (tn_leaf * max(1, n))()
+    strides = (ctypes.c_int64 * max(1, n))()
+    for i, (t, ptr, stride) in enumerate(overrides):
+        arr[i] = tn_leaf(int(t), int(ptr), TN_C64_DEVICE)
+        strides[i] = int(stride)
+    _check(load().tn_contract_strided_noalloc(ctypes.c_void_p(plan), int(num_queries), n,
+                                              ctypes.cast(arr, ctypes.c_void_p),
+                                              ctypes.cast(strides, ctypes.c_void_p),
+                                              ctypes.c_void_p(int(out_ptr)), ctypes.c_int64(out_stride), 0))
 
 
 def tn_serve_submit(ctx, plan, overrides=None) -> int:
