@@ -1,24 +1,26 @@
 """Throughput of partitioned tensor-network contraction on one MI355X.
 
-Workload (default): the 20-qubit brickwork circuit of depth 14 (CZ brick
-layers alternating with RX/RZ rotation layers, seed 0), one closed network per
-output bitstring, 4 partitions refined by simulated annealing.  One step
-contracts a batch of `--queries` amplitude queries (random bitstrings) through
-the whole path: leaf overrides, every partition's tree in turn, the reduction
-path and the FP64 final contraction.  The overrides of all steps are placed in
-device memory before the timed region.
+Headline workload (the largest configuration): the 30-qubit random circuit of
+depth 20 (seed 0, 7 CX pairs per layer, 70 % nearest-neighbour), one closed
+network per output bitstring, 8 partitions refined by simulated annealing,
+largest intermediate 2^27 complex64.  One step contracts `--queries`
+amplitudes (seeded random bitstrings) through the whole path in one
+tn_contract_strided call: leaf overrides (basis vectors read in place from
+device memory), every partition's tree in turn (leg permutations, complex
+GEMMs, the subtree kernels for the small vertices), the reduction path and
+the FP64 closed root.  `value` is amplitudes/s of that path in the chosen
+precision and form (default FP32 3M); beside it: the plain FP32 4M path
+(tn_contract one query at a time, the denominator of the speed-up), effective
+complex TFLOP/s (8 * con_serial per amplitude), the roofline position of the
+dominant kernel (the GEMM, event-timed inside this run), the permutation
+kernels' HBM GB/s, and the error of nine amplitudes against stored
+state-vector values.  The CPU oracle is timed on a bounded sample.
 
-Printed: one JSON line with amplitudes/s of the batched path (`value`:
-tn_contract_strided, the overridden output vectors read in place from one
-device buffer; tn_contract_batch with per-query descriptors beside it), the
-plain per-query path (tn_contract, one query at a time) for the same
-workload, effective complex TFLOP/s (8 * con_serial per amplitude), the
-roofline position of the dominant kernel class (event-timed inside this run)
-the CPU oracle timed on a bounded sample, and (unless --no-largest) the GEMM
-phase of the 30-qubit configuration in FP32 and three-term split BF16 with its
-MFMA utilisation and its error against stored state-vector amplitudes.
+Secondary legs (each can be skipped): the 20-qubit brickwork batch of 4096
+queries per step, the GEMM phase of the 30-qubit plan in every precision and
+form, the uneven 512-query batch over 64 circuits, and serving.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--queries 4096]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--queries 8]
 """
 from __future__ import annotations
 
@@ -39,23 +41,13 @@ METRIC = "amplitudes/s + effective complex TFLOP/s vs plain FP32 path; serve p50
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
+# FP32 vector rate without the packed FP32 instructions, which this build
+# keeps off: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+FP32_VALU_ATTAINABLE_TFLOPS = 78.6
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def make_workload(args):
-    from paper_2507_20667_amd.inputs import amplitude_network, brickwork_circuit
-    from paper_2507_20667_amd.planner import SAConfig, simulated_annealing
-    from paper_2507_20667_amd.planner.plan import tree_partition
-    circ = brickwork_circuit(20, 14, 0)
-    net = amplitude_network(circ, 0)
-    t0 = time.perf_counter()
-    init = tree_partition(net.legs, net.dims, 4)
-    plan = simulated_annealing(net.legs, net.dims, init, 4,
-                               SAConfig(iterations=20, n_steps=32, workers=4, rg_samples=8, seed=0))
-    return circ, net, plan, time.perf_counter() - t0
 
 
 def device_overrides(torch, net, n, bitstrings):
@@ -128,166 +120,153 @@ def batch_call(lib, ctx, plan, leaves, n):
     return call
 
 
-def serve_bench(lib, ctx, seconds, rate, flags, seed=0):
-    """Poisson arrivals of amplitude and <Z_i Z_j> requests over a pool of
-    seeded random circuits (12-22 qubits, depth 8-16, the 30-qubit family's
-    generator with n/4 CX pairs per layer): p50/p99 of submit-to-ready latency,
-    offered and achieved rates; then the same requests all at once
-    (saturation throughput)."""
-    import threading
-    from paper_2507_20667_amd.inputs import (amplitude_network, amplitude_overrides,
-                                             random_circuit, zz_network)
-    from paper_2507_20667_amd.planner import SAConfig, simulated_annealing
+SERVE_MAX_LARGEST = 1 << 32     # planned largest intermediate (entries)
+SERVE_MAX_WORK = 1 << 36        # con_serial (complex multiply-adds) of one request
+
+
+def _serve_circuit(args):
+    """Circuit c of the serving pool and its three planned networks."""
+    c, seed = args
+    from paper_2507_20667_amd.inputs import amplitude_network, random_circuit, zz_network
+    from paper_2507_20667_amd.planner import cost, plan_from_partition
     from paper_2507_20667_amd.planner.plan import tree_partition
-    rng = np.random.default_rng(seed)
-    pool = []
-    t0 = time.perf_counter()
-    for c in range(8):
-        n = int(rng.integers(12, 23))
-        d = int(rng.integers(8, 17))
-        circ = random_circuit(n, d, 100 + c)
-        nets = [("amp", amplitude_network(circ, 0), None)]
-        for _ in range(2):
-            i, j = sorted(int(v) for v in rng.choice(n, 2, replace=False))
-            nets.append(("zz", zz_network(circ, i, j), (i, j)))
+    rng = np.random.default_rng([seed, c])
+    for r in range(1000):
+        # a draw out of bounds is replaced by a new draw of size, depth,
+        # circuit and pairs
+        n = int(rng.integers(12, 33))
+        d = int(rng.integers(8, 25))
+        pairs = [tuple(sorted(int(v) for v in rng.choice(n, 2, replace=False))) for _ in range(2)]
+        circ = random_circuit(n, d, 7000 + 1000 * c + r)
+        nets = [("amp", amplitude_network(circ, 0), None)] + \
+               [("zz", zz_network(circ, i, j), (i, j)) for i, j in pairs]
+        planned = []
         for kind, net, ij in nets:
-            k = 2 if net.num_tensors < 200 else 4
-            pl = simulated_annealing(net.legs, net.dims, tree_partition(net.legs, net.dims, k), k,
-                                     SAConfig(iterations=3, n_steps=8, workers=2, rg_samples=4))
-            p = ctx.plan_load(net.legs, net.dims, net.tensors, pl.partition_of, k, pl.tree, None,
-                              flags)
-            pool.append((kind, circ, net, p))
-    plan_s = time.perf_counter() - t0
-    amp_plans = [x for x in pool if x[0] == "amp"]
-    zz_plans = [x for x in pool if x[0] == "zz"]
-    nreq = max(1, int(seconds * rate))
-    reqs = []
-    for _ in range(nreq):
-        if rng.random() < 0.5:
-            kind, circ, net, p = amp_plans[int(rng.integers(0, len(amp_plans)))]
-            x = int(rng.integers(0, 1 << circ.n))
-            reqs.append((p, amplitude_overrides(net, circ, x)))
-        else:
-            kind, circ, net, p = zz_plans[int(rng.integers(0, len(zz_plans)))]
-            reqs.append((p, {}))
-    gaps = rng.exponential(1.0 / rate, size=nreq)
-
-    def run(paced):
-        tickets = [None] * nreq
-
-        def submitter():
-            t_next = time.perf_counter()
-            for i, (p, ovr) in enumerate(reqs):
-                if paced:
-                    t_next += gaps[i]
-                    while time.perf_counter() < t_next:
-                        time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
-                tickets[i] = lib.tn_serve_submit(ctx.handle, p, ovr)
-
-        th = threading.Thread(target=submitter)
-        start = time.perf_counter()
-        th.start()
-        lat = []
-        done = 0
-        while done < nreq:
-            progressed = False
-            for i in range(nreq):
-                t = tickets[i]
-                if t is None or t < 0:
-                    continue
-                st, out, _, l = lib.tn_serve_poll(ctx.handle, t)
-                if st == lib.TN_PENDING:
-                    continue
-                tickets[i] = -1
-                lat.append(l)
-                done += 1
-                progressed = True
-            if not progressed:
-                time.sleep(2e-4)
-        th.join()
-        wall = time.perf_counter() - start
-        return np.array(lat), wall
-
-    lat, wall = run(True)
-    lat_s, wall_s = run(False)
-    return dict(requests=nreq, offered_per_s=rate, achieved_per_s=nreq / wall,
-                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                saturated_per_s=nreq / wall_s,
-                saturated_p50_ms=float(np.percentile(lat_s, 50) * 1e3),
-                saturated_p99_ms=float(np.percentile(lat_s, 99) * 1e3),
-                pool="8 random circuits 12-22 qubits depth 8-16 (n/4 CX per layer, 70% nearest-"
-                     "neighbour), amplitude + 2 <ZZ> networks each, 50/50 mix",
-                planning_s=plan_s)
+            k = 4 if net.num_tensors >= 8 else 1
+            pl = plan_from_partition(net.legs, net.dims, tree_partition(net.legs, net.dims, k), k)
+            li = cost.largest_intermediate(net.legs, net.dims, pl.tree)
+            cs = cost.con_serial(net.legs, net.dims, pl.tree)
+            if li > SERVE_MAX_LARGEST or cs > SERVE_MAX_WORK:
+                break
+            planned.append((kind, net, ij, pl, k, cs, li))
+        if len(planned) == len(nets):
+            return circ, planned
+    raise RuntimeError(f"no draw of circuit {c} fits the bounds")
 
 
-KERNEL_SOURCES = {"tree": "tree.hip", "tree_batch": "tree.hip", "stream": "kernels.hip",
-                  "permute": "kernels.hip", "dot": "kernels.hip", "gemm": "kernels.hip"}
-KERNEL_NAMES = {"tree": "k_tree", "tree_batch": "k_tree_wave"}
-
-
-def measured_traffic(cls, launches):
-    """HBM bytes per launch from the committed counter record, if the kernel
-    source is unchanged since the counters were taken (else None)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    name = KERNEL_NAMES.get(cls)
-    if not name or not os.path.exists(path):
-        return None
-    rec = json.load(open(path)).get(name)
-    if not rec:
-        return None
-    src = os.path.join(ROOT, rec["source"])
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if sha != rec["source_sha256_16"]:
-        return None
-    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
-
-
-def roofline(stats, prec):
-    """Roofline position of the kernel class with the largest event-timed
-    share: achieved = algorithmic work per launch / average launch time."""
-    dom = max(stats, key=lambda k: stats[k]["seconds"])
-    ds = stats[dom]
-    n = max(ds["launches"], 1)
-    if dom == "gemm":
-        achieved = ds["algo_flops"] / ds["seconds"] / 1e12
-        peak = MFMA_PEAK_TFLOPS[prec]
-        roof = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s")
-    elif dom in ("tree", "tree_batch"):
-        # every intermediate stays in LDS: its bound is arithmetic, not HBM
-        achieved = ds["algo_flops"] / ds["seconds"] / 1e12
-        peak = FP32_VECTOR_PEAK_TFLOPS
-        roof = dict(bound="alu", achieved=achieved, peak=peak, unit="TFLOP/s")
-    else:
-        achieved = ds["algo_bytes"] / ds["seconds"] / 1e9
-        peak = HBM_PEAK_GBS
-        roof = dict(bound="hbm", achieved=achieved, peak=peak, unit="GB/s")
-    roof["frac"] = achieved / peak
-    roof["traffic"] = measured_traffic(dom, n)
-    roof["kernel_class"] = dom
-    roof["launches"] = ds["launches"]
-    roof["avg_launch_us"] = ds["seconds"] / n * 1e6
-    roof["algo_bytes_per_launch"] = ds["algo_bytes"] / n
-    roof["algo_flops_per_launch"] = ds["algo_flops"] / n
-    return roof
-
-
-def cpu_baseline(net, plan, circ, budget_s):
-    import oracle
-    from paper_2507_20667_amd.inputs import amplitude_overrides, random_bitstrings
-    threads = oracle.default_threads()
-    xs = random_bitstrings(circ.n, 100000, 99)
-    done = 0
+def serve_pool(n_circuits=128, seed=2024, processes=8):
+    """The serving pool: circuit c of the random family (n/4 CX pairs per
+    layer, 70 % nearest-neighbour) with n ~ U{12..32} and depth ~ U{8..24}
+    drawn from (seed, c), the circuit itself from seed 7000 + 1000 c + r, r
+    counting the draws (size, depth, pairs and circuit drawn again until the
+    networks are in bounds); per circuit its amplitude
+    network and the light-cone-pruned networks of <Z_i Z_j> for two pairs
+    i < j drawn uniformly.  Each network is planned with 4 partitions (the
+    tree split, Greedy inside) and must keep its largest intermediate within
+    2^32 entries and its con_serial within 2^36 multiply-adds.  The circuits
+    are planned in forked processes (before this process touches the GPU)."""
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and done < len(xs):
-        ovr = amplitude_overrides(net, circ, xs[done])
-        oracle.contract_tree(net.legs, net.dims, net.copy_with(ovr).tensors, plan.tree,
-                             nthreads=threads)
-        done += 1
-    dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="amplitudes/s", cores=threads, kind="oracle",
-                sample=f"{done} amplitudes of the same 20-qubit brickwork network and plan, "
-                       f"complex128 loop-nest contraction, {dt:.1f} s")
+    jobs = [(c, seed) for c in range(n_circuits)]
+    if processes > 1:
+        import multiprocessing
+        with multiprocessing.get_context("fork").Pool(processes) as mp:
+            pool = mp.map(_serve_circuit, jobs)
+    else:
+        pool = [_serve_circuit(j) for j in jobs]
+    return pool, time.perf_counter() - t0
+
+
+def serve_bench(lib, ctx, pool, flags, rate, warmup_s, seconds, seed=0, check=32):
+    """Poisson arrivals (rate per second) of amplitude and <Z_i Z_j> requests:
+    circuit ~ truncated Zipf(1.1) over the pool, amplitude (uniform bitstring)
+    or one of the circuit's two <Z_i Z_j> networks with probability 1/2 each.
+    Requests arrive for warmup_s + seconds; latencies (submit to ready) and
+    the achieved rate are over the requests of the measured window.  Then
+    `check` requests of the window are run again alone (tn_contract) and
+    compared with what serving returned."""
+    import threading
+    from paper_2507_20667_amd.inputs import amplitude_overrides, zipf_indices
+    rng = np.random.default_rng(seed)
+    plans = []
+    for circ, nets in pool:
+        plans.append([(kind, net, ij, ctx.plan_load(net.legs, net.dims, net.tensors, pl.partition_of, k,
+                                                     pl.tree, None, flags), cs)
+                      for kind, net, ij, pl, k, cs, li in nets])
+    nreq = max(1, int((warmup_s + seconds) * rate))
+    which = zipf_indices(len(pool), nreq, 1.1, seed + 1)
+    reqs = []
+    for c in which:
+        circ = pool[c][0]
+        if rng.random() < 0.5:
+            kind, net, ij, p, cs = plans[c][0]
+            x = int(rng.integers(0, 1 << circ.n))
+            reqs.append((c, 0, p, amplitude_overrides(net, circ, x), cs))
+        else:
+            z = 1 + int(rng.integers(0, 2))
+            kind, net, ij, p, cs = plans[c][z]
+            reqs.append((c, z, p, {}, cs))
+    gaps = rng.exponential(1.0 / rate, size=nreq)
+    tickets = [None] * nreq
+    t_sub = [0.0] * nreq
+    results = [None] * nreq
+    lat = [None] * nreq
+    done_at = [None] * nreq
+
+    def submitter():
+        t_next = time.perf_counter()
+        for i, (c, z, p, ovr, cs) in enumerate(reqs):
+            t_next += gaps[i]
+            while time.perf_counter() < t_next:
+                time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
+            t_sub[i] = time.perf_counter()
+            tickets[i] = lib.tn_serve_submit(ctx.handle, p, ovr)
+
+    start = time.perf_counter()
+    th = threading.Thread(target=submitter)
+    th.start()
+    remaining = nreq
+    while remaining:
+        progressed = False
+        for i in range(nreq):
+            t = tickets[i]
+            if t is None or lat[i] is not None:
+                continue
+            st, out, _, l = lib.tn_serve_poll(ctx.handle, t)
+            if st == lib.TN_PENDING:
+                continue
+            assert st == lib.TN_OK, (i, st)
+            lat[i] = l
+            done_at[i] = time.perf_counter()
+            results[i] = complex(np.asarray(out).reshape(-1)[0])
+            remaining -= 1
+            progressed = True
+        if not progressed:
+            time.sleep(2e-4)
+    th.join()
+    w0 = start + warmup_s
+    win = [i for i in range(nreq) if t_sub[i] >= w0]
+    lw = np.array([lat[i] for i in win])
+    achieved = len(win) / (max(done_at[i] for i in win) - w0)
+    work = sum(reqs[i][4] for i in win)
+    # alone against the mix, on requests spread over the window
+    pick = [win[int(k)] for k in np.linspace(0, len(win) - 1, min(check, len(win)))]
+    worst = 0.0
+    for i in pick:
+        c, z, p, ovr, cs = reqs[i]
+        alone = complex(np.asarray(lib.tn_contract(p, ovr)[0]).reshape(-1)[0])
+        n = pool[c][0].n
+        floor = 2.0 ** (-n / 2) if z == 0 else 1.0
+        worst = max(worst, abs(results[i] - alone) / max(abs(alone) if z == 0 else 0.0, floor))
+    for row in plans:
+        for kind, net, ij, p, cs in row:
+            ctx.free_plan(p)
+    return dict(offered_per_s=rate, requests_measured=len(win), warmup_s=warmup_s, measured_s=seconds,
+                achieved_per_s=achieved, p50_ms=float(np.percentile(lw, 50) * 1e3),
+                p99_ms=float(np.percentile(lw, 99) * 1e3), max_ms=float(lw.max() * 1e3),
+                effective_tflops=8.0 * work / (max(done_at[i] for i in win) - w0) / 1e12,
+                amplitude_share=float(np.mean([reqs[i][1] == 0 for i in win])),
+                alone_vs_mix_checked=len(pick), alone_vs_mix_max_err=worst,
+                error_metric="amplitudes: |a - a_alone| / max(|a_alone|, 2^(-n/2)); <ZZ>: absolute")
 
 
 def gemm_phase_leg(lib, reps=3):
@@ -383,26 +362,9 @@ def batch_mix_leg(lib, queries=512, reps=3):
     executed flops of the batched call (shared parts once) come from the
     event-timed kernel classes."""
     import oracle
-    from paper_2507_20667_amd.inputs import amplitude_network, amplitude_overrides, circuit_mix, zipf_indices
-    from paper_2507_20667_amd.planner import SAConfig, simulated_annealing
-    from paper_2507_20667_amd.planner.cost import largest_intermediate
-    from paper_2507_20667_amd.planner.plan import tree_partition
-    t0 = time.perf_counter()
-    circs, seed = [], 0
-    while len(circs) < 64:
-        (s, circ), = circuit_mix(1, seed)
-        seed += 1
-        net = amplitude_network(circ, 0)
-        plan = simulated_annealing(net.legs, net.dims, tree_partition(net.legs, net.dims, 4), 4,
-                                   SAConfig(iterations=4, n_steps=16, workers=2, rg_samples=4, seed=s))
-        li = largest_intermediate(net.legs, net.dims, plan.tree)
-        if li > 1 << 24 or li < 1 << 4:
-            continue
-        circs.append((circ, net, plan))
-    plan_s = time.perf_counter() - t0
-    idx = zipf_indices(len(circs), queries, 1.2, 7)
-    rng = np.random.default_rng(8)
-    bits = [int(rng.integers(0, 1 << circs[i][0].n)) for i in idx]
+    from paper_2507_20667_amd.inputs import amplitude_overrides
+    from paper_2507_20667_amd.planner.workloads import uneven_mix
+    circs, idx, bits, plan_s = uneven_mix(queries)
     ctx = lib.Context(32 << 30)
     handles = [ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 4, plan.tree, None, 0)
                for _, net, plan in circs]
@@ -511,6 +473,9 @@ def batch_mix_leg(lib, queries=512, reps=3):
                    float(np.corrcoef(np.log(cpar), np.log(tc_))[0, 1]) if len(by_c) > 2 else None,
                "pearson_r_log_con_serial_vs_concurrent_time":
                    float(np.corrcoef(np.log(xs_), np.log(tc_))[0, 1]) if len(by_c) > 2 else None},
+           "cost_points": [(f"uneven circuit {i} ({circs[i][0].n} qubits, {len(circs[i][0].gates)} gates)",
+                            int(cs[i]), roofline_seconds(circs[i][1], circs[i][2]),
+                            float(np.median(by_c[i]))) for i in by_c],
            "cost_model_vs_time": {"circuits": len(by_c), "pearson_r_con_serial_vs_plain_time": r_lin,
                                   "pearson_r_log": r_log,
                                   "con_serial_range": [float(xs_.min()), float(xs_.max())],
@@ -527,55 +492,287 @@ def batch_mix_leg(lib, queries=512, reps=3):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--queries", type=int, default=4096)
-    ap.add_argument("--plain-queries", type=int, default=64)
-    ap.add_argument("--prec", choices=["fp32", "bf16x3"], default="fp32")
-    ap.add_argument("--form", choices=["4m", "3m"], default="4m")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain 512 MiB device-to-device copy (known traffic) so "
-                         "that hardware byte counters can be scaled against it")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
-    ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--no-largest", action="store_true",
-                    help="skip the 30-qubit GEMM-phase leg")
-    ap.add_argument("--no-mix", action="store_true",
-                    help="skip the uneven 64-circuit batch leg")
-    args = ap.parse_args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}, WORLD_SIZE={world}): "
-              "this build measures a single MI355X; see DESIGN.md for how the path shards.",
-              file=sys.stderr)
-        sys.exit(2)
+# bf16 (or f32) MFMA flops executed per effective complex flop (8 per complex
+# multiply-add): FP32 4M 8, FP32 3M 6; BF16x3 4M twelve bf16 products of 2
+# flops, 3M nine
+EXEC_PER_EFFECTIVE = {("fp32", "4m"): 1.0, ("fp32", "3m"): 0.75, ("bf16x3", "4m"): 3.0,
+                      ("bf16x3", "3m"): 2.25}
+GEMM_KERNEL = {("fp32", "4m"): "k_cgemm_f32_planes<0>", ("fp32", "3m"): "k_cgemm_f32_planes<1>",
+               ("bf16x3", "4m"): "k_cgemm_bf16x3_dma<0>", ("bf16x3", "3m"): "k_cgemm_bf16x3_dma<1>"}
+GEMM_SOURCE = {"fp32": "gemm_f32.hip", "bf16x3": "gemm_bf16.hip"}
 
-    import torch
-    from paper_2507_20667_amd import lib
+
+def traffic_record(name):
+    """HBM bytes per launch of kernel `name` from the committed counter record
+    (profiles/traffic.json), if its source is unchanged since the counters
+    were taken; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(name)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def roofline_seconds(net, plan):
+    """Sum over the plan's vertices of the roofline time max(8 * 2^vc / P,
+    8 (|c1| + |c2| + |v|) / BW): P the FP32 matrix peak, BW the HBM peak
+    (complex64 operands read once, the result written once)."""
+    from paper_2507_20667_amd.planner.cost import node_legs, node_weights, size_of
+    legs = node_legs(net.legs, plan.tree)
+    w = node_weights(net.legs, net.dims, plan.tree)
+    nv = len(net.legs)
+    t = 0.0
+    for j, (a, b) in enumerate(plan.tree):
+        nbytes = 8.0 * (size_of(legs[a], net.dims) + size_of(legs[b], net.dims) + size_of(legs[nv + j], net.dims))
+        t += max(8.0 * w[j] / (MFMA_PEAK_TFLOPS["fp32"] * 1e12), nbytes / (HBM_PEAK_GBS * 1e9))
+    return t
+
+
+def cost_model_fit(points):
+    """Pearson r of measured plain time per amplitude against con_serial and
+    against the summed per-vertex roofline time (linear and log-log), over
+    (name, con_serial, roofline seconds, measured seconds) points."""
+    cs = np.array([float(p[1]) for p in points])
+    rt = np.array([p[2] for p in points])
+    tm = np.array([p[3] for p in points])
+
+    def r(x, y):
+        return float(np.corrcoef(x, y)[0, 1]) if len(x) > 2 else None
+    return {"plans": len(points), "pearson_r_con_serial": r(cs, tm), "pearson_r_log_con_serial": r(np.log(cs), np.log(tm)),
+            "pearson_r_roofline_time": r(rt, tm), "pearson_r_log_roofline_time": r(np.log(rt), np.log(tm)),
+            "measured_over_roofline_median": float(np.median(tm / rt)),
+            "points": [{"plan": p[0], "con_serial": p[1], "roofline_s": p[2], "plain_s": p[3]} for p in points]}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_random30(w, seconds):
+    """The oracle (complex128 loop-nest contraction of the same network and
+    tree) on a bounded sample of one 30-qubit amplitude: bound legs fixed
+    (sliced) so that a slice holds 1/16 of the work, timed on all host cores;
+    a slice of 1/128 of the work timed on one core.  Amplitudes/s = the
+    measured multiply-add rate / con_serial of the whole amplitude (the rate
+    of a slice, whose intermediates are 16 times smaller, taken as the rate of
+    the whole; a whole amplitude takes minutes on the host)."""
     import oracle
     from paper_2507_20667_amd.inputs import amplitude_overrides, random_bitstrings
+    from paper_2507_20667_amd.planner import cost
+    from paper_2507_20667_amd.planner.slicing import choose_slices, sliced_problem
+    net, plan, circ = w.net, w.plan, w.circ
+    full = cost.con_serial(net.legs, net.dims, plan.tree)
+    x = random_bitstrings(circ.n, 1, 4242)[0]
+    tensors = net.copy_with(amplitude_overrides(net, circ, x)).tensors
 
-    if args.copy_calibration:
-        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    circ, net, plan, plan_s = make_workload(args)
+    def slice_rate(target, threads):
+        sl = choose_slices(net.legs, net.dims, plan.tree, target)
+        d, base, ovrs = sliced_problem(net.legs, net.dims, tensors, sl)
+        work = cost.con_serial(net.legs, d, plan.tree)
+        ts = [ovrs[0].get(i, t) for i, t in enumerate(base)]
+        t0 = time.perf_counter()
+        oracle.contract_tree(net.legs, d, ts, plan.tree, nthreads=threads)
+        dt = time.perf_counter() - t0
+        return work / dt, len(sl), work, dt
+
+    threads = oracle.default_threads()
+    rate, nsl, work, dt = slice_rate(1 << 23, threads)
+    rate1, nsl1, work1, dt1 = slice_rate(1 << 20, 1)
+    return dict(value=rate / full, unit="amplitudes/s", cores=threads, kind="oracle",
+                sample=f"one 30-qubit amplitude (bitstring {x}) with {nsl} bound legs fixed: one slice of "
+                       f"{work} multiply-adds of the amplitude's {full} ({dt:.1f} s on {threads} threads), "
+                       "complex128 loop-nest contraction of the same network and tree; amplitudes/s = "
+                       "multiply-adds per second / con_serial",
+                gmac_per_s=rate / 1e9, cpu_model=cpu_model(),
+                single_thread={"value": rate1 / full, "unit": "amplitudes/s", "gmac_per_s": rate1 / 1e9,
+                               "sample": f"{nsl1} legs fixed, {work1} multiply-adds, {dt1:.1f} s on 1 thread"})
+
+
+def headline_random30(lib, torch, args):
+    """The 30-qubit amplitudes through tn_contract_strided, `args.queries` per
+    step, in the requested precision and form; the plain FP32 4M path on the
+    same plan; event-timed kernel classes; state-vector parity."""
+    from paper_2507_20667_amd.inputs import amplitude_overrides, output_tensor_ids, random_bitstrings
+    from paper_2507_20667_amd.planner.workloads import random30
+    w = random30()
+    circ, net, plan = w.circ, w.net, w.plan
     n = circ.n
-    log(f"planned in {plan_s:.1f}s: {plan.meta.get('con_dist')}")
-    flags = (lib.TN_PREC_BF16X3 if args.prec == "bf16x3" else 0) | \
-            (lib.TN_FORM_3M if args.form == "3m" else 0)
-    ctx = lib.Context(16 << 30)
-    p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 4, plan.tree, None, flags)
+    log(f"30-qubit plan in {w.planning_s:.1f} s")
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "config3_amplitudes.json")))
+    assert gold["circuit"]["n"] == n and gold["circuit"]["seed"] == 0
+    prec, form = args.prec, args.form
+    flags = (lib.TN_PREC_BF16X3 if prec == "bf16x3" else 0) | (lib.TN_FORM_3M if form == "3m" else 0)
+    ctx = lib.Context(args.arena_gib << 30)
+    p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 8, plan.tree, None, flags)
     costs = lib.tn_plan_costs_get(p)
     con_serial = costs["con_serial"]
+    ids = output_tensor_ids(net)
     Q, K, W = args.queries, args.steps, args.warmup
+
+    def basis(xs):
+        bits = np.array([[(x >> q) & 1 for q in range(n)] for x in xs], dtype=np.int64)
+        h = np.zeros((len(xs), n, 2), dtype=np.complex64)
+        h[np.arange(len(xs))[:, None], np.arange(n)[None, :], bits] = 1.0
+        return torch.from_numpy(h).pin_memory()
+
+    def make_call(dev, nq):
+        arr = (lib.tn_leaf * n)()
+        strides = (ctypes.c_int64 * n)()
+        for i, t in enumerate(ids):
+            arr[i] = lib.tn_leaf(t, dev.data_ptr() + i * 16, lib.TN_C64_DEVICE)
+            strides[i] = n * 16
+        out_t = torch.zeros((nq, 2), dtype=torch.float64, pin_memory=True)
+        fn = lib.load().tn_contract_strided
+        a = (ctypes.c_void_p(p), nq, n, ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(strides, ctypes.c_void_p),
+             ctypes.c_void_p(out_t.data_ptr()), 1, lib.TN_C128, None, 0)
+
+        def call():
+            rc = fn(*a)
+            if rc != 0:
+                raise lib.TnError(rc, lib.tn_last_error())
+            return out_t.numpy()
+        call.keep = (arr, strides, out_t)
+        return call
+
+    # parity: the nine stored state-vector amplitudes through the same call
+    gx = gold["bitstrings"]
+    gdev = basis(gx).to("cuda")
+    res = make_call(gdev, len(gx))()
+    errs = []
+    for i, x in enumerate(gx):
+        ref = complex(*gold["amplitudes"][str(x)])
+        errs.append(abs(complex(res[i, 0], res[i, 1]) - ref) / max(abs(ref), 2.0 ** (-n / 2)))
+    max_err = max(errs)
+    tol = 1e-5 if prec == "fp32" else 1e-3
+    log(f"30-qubit {prec} {form}: max error {max_err:.2e} over {len(gx)} stored amplitudes")
+    # the timed steps: the basis vectors of each step go host -> device inside
+    # the step (pinned host memory, the context's stream), then one call
+    hosts = [basis(random_bitstrings(n, Q, 5000 + s)) for s in range(K + W)]
+    devs = [torch.empty_like(h, device="cuda") for h in hosts]
+    calls = [make_call(d, Q) for d in devs]
+    for s in range(W):
+        devs[s].copy_(hosts[s], non_blocking=True)
+        calls[s]()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(W, W + K):
+        devs[s].copy_(hosts[s], non_blocking=True)
+        calls[s]()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    amps = Q * K / dt
+    # the same steps on the plan loaded without the tuning table (the
+    # built-in launch heuristics)
+    os.environ["TN_TUNE_OFF"] = "1"
+    try:
+        p_tuned = p
+        p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 8, plan.tree, None, flags)
+    finally:
+        del os.environ["TN_TUNE_OFF"]
+    calls_off = [make_call(d, Q) for d in devs]
+    for s in range(W):
+        calls_off[s]()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(W, W + K):
+        devs[s].copy_(hosts[s], non_blocking=True)
+        calls_off[s]()
+    torch.cuda.synchronize()
+    amps_untuned = Q * K / (time.perf_counter() - t0)
+    ctx.free_plan(p)
+    p = p_tuned
+    # the same steps with every kernel launch bracketed by events
+    lib.tn_profile_enable(ctx.handle, True)
+    lib.tn_profile_read(ctx.handle, reset=True)
+    for s in range(W, W + K):
+        calls[s]()
+    lib.tn_profile_enable(ctx.handle, False)
+    stats = lib.tn_profile_read(ctx.handle, reset=True)
+    g = stats["gemm"]
+    mul = EXEC_PER_EFFECTIVE[(prec, form)]
+    peak = MFMA_PEAK_TFLOPS[prec]
+    eff = g["algo_flops"] / g["seconds"] / 1e12
+    achieved = eff * mul
+    nl = max(g["launches"], 1)
+    kname = GEMM_KERNEL[(prec, form)]
+    traffic = traffic_record(kname)
+    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic, "kernel": kname,
+            "launches": g["launches"], "avg_launch_us": g["seconds"] / nl * 1e6,
+            "algo_flops_per_launch": g["algo_flops"] / nl * mul,
+            "algo_bytes_per_launch": g["algo_bytes"] / nl,
+            "effective_tflops": eff,
+            "note": "achieved = MFMA flops of the form (8 M N K for 4M, 6 M N K for 3M, times 3 or 2.25 "
+                    "bf16 products for BF16x3) per launch / event-timed average launch, the split-k "
+                    "reduction of the one split vertex included"}
+    perm = stats["permute"]
+    perm_gbs = perm["algo_bytes"] / perm["seconds"] / 1e9 if perm["seconds"] else None
+    kern_s = sum(v["seconds"] for v in stats.values())
+    # the plain FP32 4M path (tn_contract, one query at a time, one launch per
+    # vertex) on the same network and plan
+    pp = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 8, plan.tree, None, 0)
+    ovr0 = amplitude_overrides(net, circ, gx[1])
+    lib.tn_contract(pp, ovr0)
+    t1 = time.perf_counter()
+    for x in gx[1:4]:
+        lib.tn_contract(pp, amplitude_overrides(net, circ, x))
+    plain = 3 / (time.perf_counter() - t1)
+    ctx.free_plan(pp)
+    cost_point = (w.name, int(con_serial), roofline_seconds(net, plan), 1.0 / plain)
+    ctx.close()
+    from paper_2507_20667_amd.tune import DEFAULT_OUT
+    rec = {"amplitudes_per_s": amps, "ms_per_step": dt / K * 1e3, "queries_per_step": Q,
+           "untuned_amplitudes_per_s": amps_untuned, "tuning_table": os.path.exists(DEFAULT_OUT),
+           "effective_tflops": 8.0 * con_serial * amps / 1e12,
+           "executed_tflops": sum(v["algo_flops"] for v in stats.values()) * mul / K / (dt / K) / 1e12,
+           "plain_fp32_amplitudes_per_s": plain, "speedup_vs_plain_fp32": amps / plain,
+           "max_rel_err_vs_statevector": max_err, "tolerance": tol, "amplitudes_checked": len(gx),
+           "roofline": roof,
+           "permute": {"hbm_gbs": perm_gbs, "frac_of_hbm": perm_gbs / HBM_PEAK_GBS if perm_gbs else None,
+                       "launches": perm["launches"], "ms_per_step": perm["seconds"] / K * 1e3,
+                       "algo_bytes_per_step": perm["algo_bytes"] / K,
+                       "note": "algorithmic bytes: 8 read + 8 written per complex entry for float "
+                               "planes, 8 + 2 per bf16 plane"},
+           "kernel_seconds_per_step": kern_s / K,
+           "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},
+           "con_serial": con_serial, "con_dist": costs["con_dist"],
+           "largest_intermediate": costs["largest_intermediate"], "planning_s": w.planning_s,
+           "workload": w.name, "overrides": "host basis vectors copied to the device inside each step",
+           "cost_point": cost_point}
+    log(f"30-qubit {prec} {form}: {amps:.1f} amplitudes/s ({dt / K * 1e3:.1f} ms per step of {Q}), "
+        f"plain FP32 {plain:.1f}/s, GEMM {achieved:.1f} TFLOP/s ({achieved / peak:.1%}), "
+        f"permutations {perm_gbs or 0:.0f} GB/s")
+    return w, rec
+
+
+def brickwork_leg(lib, torch, args):
+    """20-qubit brickwork, `args.bw_queries` amplitudes per step through
+    tn_contract_strided (overrides resident in device memory before the timed
+    region; the same with the host-to-device upload inside the step beside
+    it), tn_contract_batch and the plain path; every result of the first step
+    against the state vector; the batch subtree kernel's roofline position."""
+    import oracle
+    from paper_2507_20667_amd.inputs import random_bitstrings
+    from paper_2507_20667_amd.planner.workloads import brickwork20
+    w = brickwork20()
+    circ, net, plan = w.circ, w.net, w.plan
+    n = circ.n
+    ctx = lib.Context(16 << 30)
+    p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 4, plan.tree, None, 0)
+    costs = lib.tn_plan_costs_get(p)
+    Q, K, W = args.bw_queries, args.bw_steps, 3
     steps_bits = [random_bitstrings(n, Q, 1000 + s) for s in range(K + W)]
     devs, calls, bcalls = [], [], []
     for s in range(K + W):
@@ -584,41 +781,28 @@ def main():
         calls.append(strided_call(lib, p, dev, net, n))
         bcalls.append(batch_call(lib, ctx.handle, p, leaves, n))
     torch.cuda.synchronize()
-
-    # parity spot check outside the timed region
     res = calls[0]()
-    errs = []
-    for qi in range(0, Q, max(1, Q // 8)):
-        x = steps_bits[0][qi]
-        ovr = amplitude_overrides(net, circ, x)
-        ref = complex(oracle.contract_tree(net.legs, net.dims, net.copy_with(ovr).tensors,
-                                           plan.tree))
-        got = complex(res[qi, 0], res[qi, 1])
-        errs.append(abs(got - ref) / max(abs(ref), 2.0 ** (-n / 2)))
-    max_err = max(errs)
-    log(f"spot-check max relative error {max_err:.2e}")
+    psi = oracle.statevector(circ)
+    ref = psi[np.array(steps_bits[0], dtype=np.int64)]
+    got = res[:, 0] + 1j * res[:, 1]
+    max_err = float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 2.0 ** (-n / 2))))
 
-    for s in range(W):
-        calls[s]()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(W, W + K):
-        calls[s]()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    amps = Q * K / dt
-    eff_tflops = 8.0 * con_serial * Q * K / dt / 1e12
-    # the same steps through tn_contract_batch (one descriptor per query and leaf)
-    for s in range(W):
-        bcalls[s]()
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    for s in range(W, W + K):
-        bcalls[s]()
-    torch.cuda.synchronize()
-    batch_api_amps = Q * K / (time.perf_counter() - tb)
+    def timed(fns, pre=None):
+        for s in range(W):
+            fns[s]()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(W, W + K):
+            if pre:
+                pre(s)
+            fns[s]()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
-    # plain path: tn_contract, one query at a time, device-resident overrides
+    dt = timed(calls)
+    hosts = [d[0].cpu().pin_memory() for d in devs]
+    dtu = timed(calls, lambda s: devs[s][0].copy_(hosts[s], non_blocking=True))
+    dtb = timed(bcalls)
     dev0, leaves0 = devs[W]
     P = min(args.plain_queries, Q)
     plain_out = np.zeros(2, dtype=np.float64)
@@ -631,75 +815,167 @@ def main():
     t1 = time.perf_counter()
     for qi in range(P):
         rc = L.tn_contract(ctypes.c_void_p(p), n, ctypes.cast(leaves0[qi], ctypes.c_void_p),
-                           plain_out.ctypes.data_as(ctypes.c_void_p), lib.TN_C128,
-                           ctypes.byref(l2), 0)
+                           plain_out.ctypes.data_as(ctypes.c_void_p), lib.TN_C128, ctypes.byref(l2), 0)
         assert rc == 0, lib.tn_last_error()
     torch.cuda.synchronize()
     plain_amps = P / (time.perf_counter() - t1)
-
-    # event-timed kernel classes over the same steps
     lib.tn_profile_enable(ctx.handle, True)
     lib.tn_profile_read(ctx.handle, reset=True)
     for s in range(W, W + K):
         calls[s]()
     lib.tn_profile_enable(ctx.handle, False)
     stats = lib.tn_profile_read(ctx.handle, reset=True)
-    roof = roofline(stats, args.prec)
-    # executed work (vertices actually run, shared parts once) per unprofiled step time
-    exec_tflops = sum(v["algo_flops"] for v in stats.values()) / K / (dt / K) / 1e12
+    ctx.close()
+    tb = stats["tree_batch"]
+    nl = max(tb["launches"], 1)
+    t_launch = tb["seconds"] / nl
+    bytes_l, flops_l = tb["algo_bytes"] / nl, tb["algo_flops"] / nl
+    # roofline bound of the batch subtree kernel: the larger of its byte time
+    # at the HBM peak and its flop time at the attainable FP32 vector rate
+    t_bytes = bytes_l / (HBM_PEAK_GBS * 1e9)
+    t_flops = flops_l / (FP32_VALU_ATTAINABLE_TFLOPS * 1e12)
+    roof = {"bound": "hbm" if t_bytes >= t_flops else "alu",
+            "achieved": bytes_l / t_launch / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": max(t_bytes, t_flops) / t_launch, "traffic": traffic_record("k_tree_wave"),
+            "kernel": "k_tree_wave", "launches": tb["launches"], "avg_launch_us": t_launch * 1e6,
+            "algo_bytes_per_launch": bytes_l, "algo_flops_per_launch": flops_l,
+            "alu_tflops": flops_l / t_launch / 1e12,
+            "alu_frac_of_attainable": flops_l / t_launch / 1e12 / FP32_VALU_ATTAINABLE_TFLOPS}
+    rec = {"workload": w.name + f", {Q} bitstrings per step", "amplitudes_per_s": Q * K / dt,
+           "ms_per_step": dt / K * 1e3, "steps": K,
+           "overrides": "device-resident before the timed region (basis vectors read in place)",
+           "amplitudes_per_s_with_upload": Q * K / dtu,
+           "batch_api_amplitudes_per_s": Q * K / dtb, "plain_amplitudes_per_s": plain_amps,
+           "speedup_vs_plain": (Q * K / dt) / plain_amps,
+           "effective_tflops": 8.0 * costs["con_serial"] * Q * K / dt / 1e12,
+           "max_rel_err_vs_statevector": max_err, "results_checked": Q,
+           "roofline": roof, "con_serial": costs["con_serial"],
+           "largest_intermediate": costs["largest_intermediate"], "planning_s": w.planning_s,
+           "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},
+           "cost_point": (w.name, int(costs["con_serial"]), roofline_seconds(net, plan), 1.0 / plain_amps)}
+    log(f"brickwork: {rec['amplitudes_per_s']:.3e} amplitudes/s ({rec['ms_per_step']:.3f} ms per step), "
+        f"with upload {rec['amplitudes_per_s_with_upload']:.3e}, plain {plain_amps:.0f}/s, "
+        f"max err {max_err:.1e} over {Q}; k_tree_wave {roof['avg_launch_us']:.1f} us, frac {roof['frac']:.2f}")
+    return rec
 
-    serve = serve_bf16 = None
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--queries", type=int, default=8, help="30-qubit amplitudes per step")
+    ap.add_argument("--prec", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--form", choices=["4m", "3m"], default="3m")
+    ap.add_argument("--arena-gib", type=int, default=48)
+    ap.add_argument("--bw-queries", type=int, default=4096)
+    ap.add_argument("--bw-steps", type=int, default=20)
+    ap.add_argument("--plain-queries", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 512 MiB device-to-device copy (known traffic) so "
+                         "that hardware byte counters can be scaled against it")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="measured window of the serving leg (0 skips it)")
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--no-brickwork", action="store_true", help="skip the 20-qubit brickwork leg")
+    ap.add_argument("--no-largest", action="store_true",
+                    help="skip the 30-qubit GEMM-phase leg (every precision and form)")
+    ap.add_argument("--no-mix", action="store_true", help="skip the uneven 64-circuit batch leg")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}, WORLD_SIZE={world}): this "
+              "build measures one MI355X; a run on several GPUs would place the partitions on "
+              "different devices and exchange partition results on the reduction path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    # the serving pool is planned first, in forked processes, before anything
+    # touches the GPU
+    pool = plan_s = None
     if args.serve_seconds > 0:
-        serve = serve_bench(lib, ctx, args.serve_seconds, args.serve_rate, flags)
-        serve_bf16 = serve_bench(lib, ctx, args.serve_seconds, args.serve_rate,
-                                 lib.TN_PREC_BF16X3 | (lib.TN_FORM_3M if args.form == "3m" else 0))
+        pool, plan_s = serve_pool(processes=min(16, os.cpu_count() or 1))
+        log(f"serving pool planned in {plan_s:.1f} s")
 
-    largest = None
-    if not args.no_largest:
-        largest = gemm_phase_leg(lib)
+    import torch
+    from paper_2507_20667_amd import lib
 
-    mix = None
-    if not args.no_mix:
-        mix = batch_mix_leg(lib)
-
+    if args.copy_calibration:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    w, head = headline_random30(lib, torch, args)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(net, plan, circ, args.cpu_seconds)
-
+        cpu = cpu_baseline_random30(w, 10.0)
+        log(f"oracle: {cpu['value']:.4f} amplitudes/s on {cpu['cores']} threads "
+            f"({cpu['gmac_per_s']:.2f} GMAC/s), one thread {cpu['single_thread']['value']:.5f}/s")
+    bw = None if args.no_brickwork else brickwork_leg(lib, torch, args)
+    largest = None if args.no_largest else gemm_phase_leg(lib)
+    mix = None if args.no_mix else batch_mix_leg(lib)
+    serve = serve_bf16 = None
+    if args.serve_seconds > 0:
+        torch.cuda.empty_cache()
+        free, total = torch.cuda.mem_get_info()
+        arena = int(min(free - (4 << 30), 256 << 30)) // 256 * 256
+        sctx = lib.Context(arena)
+        desc = ("128 random-family circuits (n ~ U{12..32}, depth ~ U{8..24}, n/4 CX pairs per layer), "
+                "amplitude + 2 <Z_i Z_j> networks each (light-cone pruned), 4 partitions each, largest "
+                "intermediate <= 2^32, con_serial <= 2^36; Poisson arrivals, circuit ~ Zipf(1.1), 50/50 "
+                f"amplitude/<ZZ>; arena {arena / 2**30:.0f} GiB (free memory - 4 GiB)")
+        serve = serve_bench(lib, sctx, pool, 0, args.serve_rate, args.serve_warmup, args.serve_seconds)
+        serve_bf16 = serve_bench(lib, sctx, pool, lib.TN_PREC_BF16X3 | lib.TN_FORM_3M, args.serve_rate,
+                                 args.serve_warmup, args.serve_seconds, seed=1)
+        for rec, name in ((serve, "fp32"), (serve_bf16, "bf16x3_3m")):
+            rec.update(pool=desc, planning_s=plan_s, precision=name)
+            log(f"serve {name}: offered {rec['offered_per_s']:.0f}/s, achieved {rec['achieved_per_s']:.0f}/s, "
+                f"p50 {rec['p50_ms']:.2f} ms, p99 {rec['p99_ms']:.2f} ms, alone-vs-mix "
+                f"{rec['alone_vs_mix_max_err']:.1e}")
+        sctx.close()
+    # the paper's cost model against MI355X time over every measured plan
+    pts = [head.pop("cost_point")]
+    if bw:
+        pts.append(bw.pop("cost_point"))
+    if mix:
+        pts.extend(mix.pop("cost_points"))
+    cost_fit = cost_model_fit(pts) if len(pts) > 2 else None
     out = {
         "metric": METRIC,
-        "value": amps,
+        "value": head["amplitudes_per_s"],
         "unit": "amplitudes/s",
         "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": dt / K * 1e3,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.prec,
+        "dtype": "f32" if args.prec == "fp32" else "bf16x3",
         "data": "synthetic",
-        "config": {"workload": "brickwork 20 qubits depth 14 seed 0, single-amplitude networks "
-                               f"(247 tensors), 4 SA partitions, {Q} bitstrings per step",
-                   "form": args.form, "queries_per_step": Q,
-                   "con_serial": con_serial, "con_dist": costs["con_dist"],
-                   "largest_intermediate": costs["largest_intermediate"]},
-        "effective_tflops": eff_tflops,
-        "executed_tflops": exec_tflops,
-        "batch_api_amplitudes_per_s": batch_api_amps,
-        "plain_amplitudes_per_s": plain_amps,
-        "speedup_vs_plain": amps / plain_amps,
-        "max_rel_err": max_err,
-        "planning_s": plan_s,
-        "roofline": roof,
+        "config": {"workload": head["workload"] + f", {args.queries} bitstrings per step",
+                   "precision": args.prec, "form": args.form, "queries_per_step": args.queries,
+                   "con_serial": head["con_serial"], "con_dist": head["con_dist"],
+                   "largest_intermediate": head["largest_intermediate"]},
+        "effective_tflops": head["effective_tflops"],
+        "executed_tflops": head["executed_tflops"],
+        "plain_fp32_amplitudes_per_s": head["plain_fp32_amplitudes_per_s"],
+        "speedup_vs_plain_fp32": head["speedup_vs_plain_fp32"],
+        "max_rel_err": head["max_rel_err_vs_statevector"],
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "serve": serve,
-        "serve_bf16x3": serve_bf16,
+        "permute": head["permute"],
+        "headline_detail": {k: v for k, v in head.items() if k not in ("roofline", "permute")},
+        "brickwork20": bw,
         "largest_config_gemm_phase": largest,
         "uneven_batch": mix,
-        "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},
+        "serve": serve,
+        "serve_bf16x3": serve_bf16,
+        "cost_model_vs_time": cost_fit,
     }
-    ctx.close()
     print(json.dumps(out))
 
 

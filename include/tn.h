@@ -137,6 +137,8 @@ typedef struct {
   uint64_t live_peak_bytes, largest_intermediate_elems;
   int32_t num_internal_nodes, num_gemm_nodes, num_tiny_nodes;
   int32_t num_stream_nodes, num_permutations;
+  uint64_t fingerprint;  /* hash of the network, partition, tree and flags: the
+                            key of the plan's entry in the tuning table */
 } tn_plan_costs;
 
 /* A leaf override: tensor `tensor` takes `data` (same size) for one query. */

@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtn.so")
 ARCH = os.environ.get("TN_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "tree.hip", "gemm_bf16.hip", "gemm_f32.hip", "plan.cpp", "exec.cpp", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "tree.hip", "gemm_bf16.hip", "gemm_f32.hip", "plan.cpp", "exec.cpp", "api.cpp",
+           "serve.cpp", "tune.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           f"--offload-arch={ARCH}",
@@ -51,7 +52,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread", "-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

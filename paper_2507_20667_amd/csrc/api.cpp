@@ -1,4 +1,6 @@
 // C entry points of libtn (declared in include/tn.h).
+#include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -43,6 +45,13 @@ tn_status tn_ctx_create(void *arena_dev_ptr, size_t arena_bytes, void *hip_strea
   }
   c->arena.init((uint8_t *)arena_dev_ptr, arena_bytes);
   c->stream = (hipStream_t)hip_stream;
+  // budget of the shared-part cache: TN_CACHE_BYTES, else an eighth of the
+  // arena up to 8 GiB (0 turns the cache off)
+  {
+    const char *cb = getenv("TN_CACHE_BYTES");
+    c->rcache_budget = cb ? (size_t)strtoull(cb, nullptr, 10)
+                          : std::min<size_t>(arena_bytes / 8, (size_t)8 << 30);
+  }
   // this device's static scratch (tn_contract_strided_noalloc); without it
   // that call reports an error, every other call works as before
   void *sp = nullptr;
@@ -189,6 +198,7 @@ tn_status tn_plan_costs_get(const tn_plan *p, tn_plan_costs *out) {
   out->num_tiny_nodes = p->num_tiny;
   out->num_stream_nodes = p->num_stream;
   out->num_permutations = p->num_perm;
+  out->fingerprint = p->fingerprint;
   return TN_OK;
 }
 
@@ -208,9 +218,11 @@ tn_status tn_plan_free(tn_plan *p) {
     hipStreamSynchronize(ctx->stream);
     ctx->arena.release(p->dev_leaf, p->dev_leaf_bytes, true);
     ctx->arena.release(p->dev_desc, p->dev_desc_bytes, true);
-    for (auto &kv : p->layouts)
+    for (auto &kv : p->layouts) {
       if (kv.second->tree_dev >= 0)
         ctx->arena.release(kv.second->tree_dev, kv.second->tree_dev_bytes, true);
+      rcache_drop(ctx, *kv.second);
+    }
     if (p->graph) release_graph(ctx, *p->graph);
     ctx->live_plans--;
   }

@@ -84,6 +84,77 @@ static tn_status ensure_pinned(ExecRes &r, size_t bytes, hipStream_t st) {
   return TN_OK;
 }
 
+// ------------------------------------------------------ shared-part cache
+// A layout's shared part (the vertices no override reaches, computed once per
+// call for all its queries) depends only on the plan's own leaves, so it is
+// the same on every call (order independence of the contraction, Section
+// 2.3): it is kept in the arena after a first call fills it, and later calls
+// skip those vertices.  Entries are evicted least recently used first when
+// the cached bytes would pass the context's budget, never while a call uses
+// them; a plan's entries go with the plan.
+enum { RC_NONE = 0, RC_READ = 1, RC_FILL = 2 };
+
+static bool rcache_evict_one(tn_ctx *ctx, const ExecLayout *keep) {
+  ExecLayout *victim = nullptr;
+  for (ExecLayout *e : ctx->rcache)
+    if (e != keep && e->rc_pins == 0 && e->rc_state != 1 && (!victim || e->rc_used < victim->rc_used))
+      victim = e;
+  if (!victim) return false;
+  ctx->arena.release(victim->rc_off, victim->rc_bytes, true);
+  ctx->rcache_bytes -= victim->rc_bytes;
+  victim->rc_off = -1;
+  victim->rc_bytes = 0;
+  victim->rc_state = 0;
+  ctx->rcache.erase(std::find(ctx->rcache.begin(), ctx->rcache.end(), victim));
+  return true;
+}
+
+// RC_READ: the cache holds the shared part; RC_FILL: this call computes it
+// into the cache; RC_NONE: it computes it in its own workspace.
+static int rcache_acquire(tn_ctx *ctx, ExecLayout &L, size_t bytes, bool may_fill) {
+  std::lock_guard<std::mutex> g(ctx->rcache_mu);
+  if (L.rc_state == 2) {
+    L.rc_pins++;
+    L.rc_used = ++ctx->rcache_clock;
+    return RC_READ;
+  }
+  if (L.rc_state == 1 || !may_fill || bytes > ctx->rcache_budget) return RC_NONE;
+  if (L.rc_off < 0) {
+    while (ctx->rcache_bytes + bytes > ctx->rcache_budget && rcache_evict_one(ctx, &L)) {
+    }
+    if (ctx->rcache_bytes + bytes > ctx->rcache_budget) return RC_NONE;
+    int64_t off = ctx->arena.alloc(bytes, true);
+    while (off < 0 && rcache_evict_one(ctx, &L)) off = ctx->arena.alloc(bytes, true);
+    if (off < 0) return RC_NONE;
+    L.rc_off = off;
+    L.rc_bytes = bytes;
+    ctx->rcache_bytes += bytes;
+    ctx->rcache.push_back(&L);
+  }
+  L.rc_state = 1;
+  L.rc_pins++;
+  L.rc_used = ++ctx->rcache_clock;
+  return RC_FILL;
+}
+
+static void rcache_release(tn_ctx *ctx, ExecLayout &L, int mode, bool ok) {
+  if (mode == RC_NONE) return;
+  std::lock_guard<std::mutex> g(ctx->rcache_mu);
+  if (mode == RC_FILL) L.rc_state = ok ? 2 : 0;
+  L.rc_pins--;
+}
+
+void rcache_drop(tn_ctx *ctx, ExecLayout &L) {
+  std::lock_guard<std::mutex> g(ctx->rcache_mu);
+  if (L.rc_off < 0) return;
+  ctx->arena.release(L.rc_off, L.rc_bytes, true);
+  ctx->rcache_bytes -= L.rc_bytes;
+  ctx->rcache.erase(std::find(ctx->rcache.begin(), ctx->rcache.end(), &L));
+  L.rc_off = -1;
+  L.rc_bytes = 0;
+  L.rc_state = 0;
+}
+
 // Device bytes of one execution chunk of Q queries (carved in run_group).
 size_t group_workspace_bytes(const tn_plan *p, const ExecLayout &L, int Q) {
   const int nn = 2 * p->nv - 1;
@@ -393,6 +464,26 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     uint8_t *shared_base = base + r_shared, *perq_base = base + r_perq;
     Slot *slots = (Slot *)(base + r_slots);
     Slot *slots_sh = slots, *slots_q = slots + nn;
+    // the shared part from the context's cache (read, or filled by this
+    // call); not with graphs, nor when the root itself is shared (the whole
+    // result is then one shared computation), and never filled by a call
+    // that must not allocate
+    int rcm = RC_NONE;
+    if (share && !gmode && !L.shared[p->root] && ctx->rcache_budget > 0) {
+      bool any = L.n_tree_shared > 0;
+      for (size_t k = 0; k < p->order.size() && !any; ++k) {
+        const int id = p->nodes[p->order[k]].id;
+        any = L.shared[id] && !(trees && p->in_tree[id]);
+      }
+      if (any) {
+        ExecLayout &Lm = const_cast<ExecLayout &>(L);
+        rcm = rcache_acquire(ctx, Lm, rnd(L.shared_bytes) + rnd(slot_bytes), !rs.ext_ws);
+        if (rcm != RC_NONE) {
+          shared_base = ctx->arena.base() + L.rc_off;
+          slots_sh = (Slot *)(shared_base + rnd(L.shared_bytes));
+        }
+      }
+    }
     uint8_t *ovr_base = base + r_ovr;
     Result *res = (Result *)(base + r_res);
     float2 *fin = (float2 *)(base + r_final);
@@ -607,8 +698,14 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       } else {
       // scale records start at zero; not needed when the subtree kernel runs
       // every vertex (it keeps its scales in LDS and writes its results' records)
-      if (!(trees && L.all_in_tree))
-        TN_HIP(launch_init_slots(st, slots, (int64_t)nn * (Q + 1)), "slot init");
+      if (!(trees && L.all_in_tree)) {
+        if (rcm == RC_NONE) {
+          TN_HIP(launch_init_slots(st, slots, (int64_t)nn * (Q + 1)), "slot init");
+        } else {
+          TN_HIP(launch_init_slots(st, slots_q, (int64_t)nn * Q), "slot init");
+          if (rcm == RC_FILL) TN_HIP(launch_init_slots(st, slots_sh, (int64_t)nn), "slot init");
+        }
+      }
       const double t_staged = dbg ? ms_since(t_enter) : 0.0;
       if (dbg)
         fprintf(stderr, "[tn] run_group host: layout %.3f, carve %.3f, alloc %.3f, staged %.3f ms\n",
@@ -645,7 +742,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         tl.res = res_out;
         tl.dres = direct ? so->dout + (int64_t)q0 * so->dout_stride : nullptr;
         tl.dres_stride = so ? so->dout_stride : 0;
-        if (L.n_tree_shared) {
+        if (L.n_tree_shared && rcm != RC_READ) {
           tl.nq = 1;
           tl.qw = 1;
           TN_HIP(prof.timed(st, TN_KCLASS_TREE, tree_bytes_sh, tree_flops_sh,
@@ -698,6 +795,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           TN_HIP(join_parts(), "partition join");
         }
         const bool sh = L.shared[n.id] != 0;
+        if (sh && rcm == RC_READ) continue;  // in the cache
         const int nb = sh ? 1 : Q;
         const double wflops = 8.0 * (double)n.weight * nb;
         const double c1b = 8.0 * (double)(n.c1 < nv ? p->leaf[n.c1].size()
@@ -777,6 +875,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           g.pb = n.N * n.K;
           g.ksplit = n.ksplit;
           g.ktile = n.ktile ? 1 : 0;
+          g.tile = n.tile;
           g.kchunk = n.kchunk;
           if (n.ksplit > 1) {
             g.part = (float2 *)(pbase + L.partial[j]);
@@ -908,6 +1007,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       prof.pend.clear();
       prof.used = 0;
     }
+    rcache_release(ctx, const_cast<ExecLayout &>(L), rcm, rc == TN_OK);
     if (own_ws) ctx->arena.release(ws, total);
   }
   return rc;

@@ -39,10 +39,10 @@ typedef float v16f_c __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void_f;
 
-constexpr int FT = 128;               // tile rows and columns
 constexpr int FBK = 16;               // k per stage
-constexpr int FPLANE = FT * FBK;      // floats per plane tile (8 KB)
-constexpr int FSTAGE = 4 * FPLANE;    // A re, A im, B re, B im (32 KB)
+
+// s_waitcnt immediate: vmcnt(v) expcnt(7) lgkmcnt(0)
+__host__ __device__ constexpr int f_wait_imm(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4); }
 
 // (b3 ^ b1, b2) of the row index: rows r..r+15 cover every (r % 4, chunk)
 // pair and rows r..r+7 every (r % 2, chunk) pair once
@@ -50,12 +50,20 @@ __device__ __forceinline__ int fswz(int r) {
   return ((((r >> 3) ^ (r >> 1)) & 1) << 1) | ((r >> 2) & 1);
 }
 
-template <int FORM>
+// WMW = waves along M (the four waves form a WMW x 4/WMW grid, 64 x 64
+// outputs each): 2 gives a 128 x 128 tile, 1 a 64 x 256 tile (for M <= 64),
+// 4 a 256 x 64 tile (for N <= 64).
+template <int FORM, int WMW>
 __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
   constexpr int NACC = FORM == kForm3M ? 3 : 2;
+  constexpr int WNW = 4 / WMW;
+  constexpr int BM = 64 * WMW, BN = 64 * WNW;          // tile rows of A and of B
+  constexpr int APL = BM * FBK, BPL = BN * FBK;        // floats per plane tile
+  constexpr int FSTAGE = 2 * (APL + BPL);              // A re, A im, B re, B im
+  constexpr int JA = BM / 64, JB = BN / 64;            // load instructions per wave and plane
   __shared__ __align__(16) float ring0[FSTAGE], ring1[FSTAGE], ring2[FSTAGE], ring3[FSTAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WNW, wn = wave % WNW;
   const int q = blockIdx.y;
   const float *A = (const float *)g.A + q * g.abs;
   const float *B = (const float *)g.B + q * g.bbs;
@@ -68,7 +76,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
   const int ks = (int)(blockIdx.x / ntiles);
   int64_t t = blockIdx.x - (int64_t)ks * ntiles;
   if (ntiles % 8 == 0 && ntiles >= 64) t = (t % 8) * (ntiles / 8) + t / 8;
-  const int64_t m0 = (t % g.tiles_m) * FT, n0 = (t / g.tiles_m) * FT;
+  const int64_t m0 = (t % g.tiles_m) * BM, n0 = (t / g.tiles_m) * BN;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
   const int ea = tn_scale_exp(sa->maxbits), eb = tn_scale_exp(sb->maxbits);
@@ -84,39 +92,47 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[a][b][c][v] = 0.0f;
 
-  // this lane's loads: instruction j covers rows 32 * wave + 16 * j + lane / 4
-  // of a plane tile; position lane % 4 of the row holds logical chunk
-  // (lane % 4) ^ fswz(row) (rows past M or N clamped to the last one)
+  // this lane's loads: instruction j covers rows (R / 4) * wave + 16 * j +
+  // lane / 4 of an R-row plane tile; position lane % 4 of the row holds
+  // logical chunk (lane % 4) ^ fswz(row) (rows past M or N clamped to the
+  // last one)
   const uint8_t *abase = (const uint8_t *)(A + m0 * FBK);
   const uint8_t *bbase = (const uint8_t *)(B + n0 * FBK);
-  uint32_t aoff[2], boff[2];
+  uint32_t aoff[JA], boff[JB];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int r = 32 * wave + 16 * j + (lane >> 2);
+  for (int j = 0; j < JA; ++j) {
+    const int r = (BM / 4) * wave + 16 * j + (lane >> 2);
     const int c = (lane & 3) ^ fswz(r);
     const int64_t ra_ = m0 + r < g.M ? r : g.M - 1 - m0;
-    const int64_t rb_ = n0 + r < g.N ? r : g.N - 1 - n0;
     aoff[j] = (uint32_t)((ra_ * FBK + c * 4) * 4);
+  }
+#pragma unroll
+  for (int j = 0; j < JB; ++j) {
+    const int r = (BN / 4) * wave + 16 * j + (lane >> 2);
+    const int c = (lane & 3) ^ fswz(r);
+    const int64_t rb_ = n0 + r < g.N ? r : g.N - 1 - n0;
     boff[j] = (uint32_t)((rb_ * FBK + c * 4) * 4);
   }
   const int64_t nk = (kend - kbeg) / FBK;
 #define TN_FRING(S) ((S) == 0 ? ring0 : (S) == 1 ? ring1 : (S) == 2 ? ring2 : ring3)
   auto issue = [&](auto slot, int64_t stg) {
     constexpr int S = decltype(slot)::value;
-    float *rb = TN_FRING(S) + wave * (FPLANE / 4);
+    float *rb = TN_FRING(S);
     const int64_t kb = kbeg / FBK + (stg < nk ? stg : nk - 1);
     const uint8_t *ak = abase + kb * g.M * FBK * 4, *bk = bbase + kb * g.N * FBK * 4;
 #pragma unroll
-    for (int pl = 0; pl < 2; ++pl)
+    for (int pl = 0; pl < 2; ++pl) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < JA; ++j)
         __builtin_amdgcn_global_load_lds((const void *)(ak + pl * g.pa * 4 + aoff[j]),
-                                         (lds_void_f *)(rb + pl * FPLANE + j * (FPLANE / 8)), 16, 0,
-                                         0);
-        __builtin_amdgcn_global_load_lds((const void *)(bk + pl * g.pb * 4 + boff[j]),
-                                         (lds_void_f *)(rb + (2 + pl) * FPLANE + j * (FPLANE / 8)),
+                                         (lds_void_f *)(rb + pl * APL + ((BM / 4) * wave + 16 * j) * FBK),
                                          16, 0, 0);
-      }
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(bk + pl * g.pb * 4 + boff[j]),
+            (lds_void_f *)(rb + 2 * APL + pl * BPL + ((BN / 4) * wave + 16 * j) * FBK), 16, 0, 0);
+    }
   };
   // fragments: lane half h reads k 8h .. 8h+7 of its row (logical chunks 2h
   // and 2h + 1) from each plane
@@ -129,7 +145,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl) {
-        const float *row = rb + pl * FPLANE + (wm * 64 + mb * 32 + fr) * FBK;
+        const float *row = rb + pl * APL + (wm * 64 + mb * 32 + fr) * FBK;
         a[mb][pl][0] = *(const v4f *)(row + fp0);
         a[mb][pl][1] = *(const v4f *)(row + fp1);
       }
@@ -137,7 +153,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl) {
-        const float *row = rb + (2 + pl) * FPLANE + (wn * 64 + nb * 32 + fr) * FBK;
+        const float *row = rb + 2 * APL + pl * BPL + (wn * 64 + nb * 32 + fr) * FBK;
         b[nb][pl][0] = *(const v4f *)(row + fp0);
         b[nb][pl][1] = *(const v4f *)(row + fp1);
       }
@@ -212,7 +228,8 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
   // stage kt's (3M)
   auto stage = [&](auto slot, int64_t kt, bool first) {
     constexpr int S = decltype(slot)::value;
-    __builtin_amdgcn_s_waitcnt((1 << 14) | (7 << 4));  // vmcnt(16) expcnt(7) lgkmcnt(0)
+    // this wave's loads of the two stages after this one may stay in flight
+    __builtin_amdgcn_s_waitcnt(f_wait_imm(2 * 2 * (JA + JB)));
     __builtin_amdgcn_s_barrier();
     issue(std::integral_constant<int, (S + 3) % 4>(), kt + 3);
     if constexpr (FORM == kForm3M) {
@@ -294,13 +311,18 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
   }
 }
 
+// Tile shape of variant v: 0 = 128 x 128, 1 = 64 x 256, 2 = 256 x 64.
+int gemm_planes_tile_m(int v) { return v == 1 ? 64 : v == 2 ? 256 : 128; }
+int gemm_planes_tile_n(int v) { return v == 1 ? 256 : v == 2 ? 64 : 128; }
+
 hipError_t launch_gemm_f32_planes(hipStream_t st, const GemmArgs &g0, int form, int nbatch) {
   GemmArgs g = g0;
   if (g.opA != 0 || g.opB != 1 || g.planes != 2 || !g.ktile || g.K % FBK != 0 ||
-      (form != kForm4M && form != kForm3M))
+      (form != kForm4M && form != kForm3M) || g.tile < 0 || g.tile > 2)
     return hipErrorInvalidValue;
-  g.tiles_m = (int)((g.M + FT - 1) / FT);
-  g.tiles_n = (int)((g.N + FT - 1) / FT);
+  const int tm = gemm_planes_tile_m(g.tile), tn = gemm_planes_tile_n(g.tile);
+  g.tiles_m = (int)((g.M + tm - 1) / tm);
+  g.tiles_n = (int)((g.N + tn - 1) / tn);
   if (g.ksplit < 1) g.ksplit = 1;
   if (g.ksplit == 1) g.kchunk = g.K;
   if (g.kchunk < 1 || g.kchunk % FBK != 0 || (int64_t)g.ksplit * g.kchunk < g.K ||
@@ -309,10 +331,17 @@ hipError_t launch_gemm_f32_planes(hipStream_t st, const GemmArgs &g0, int form, 
   const int64_t blocks = (int64_t)g.tiles_m * g.tiles_n * g.ksplit;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks, nbatch);
-  if (form == kForm4M)
-    hipLaunchKernelGGL(k_cgemm_f32_planes<kForm4M>, grid, dim3(256), 0, st, g);
-  else
-    hipLaunchKernelGGL(k_cgemm_f32_planes<kForm3M>, grid, dim3(256), 0, st, g);
+#define TN_F32P(F, W) hipLaunchKernelGGL((k_cgemm_f32_planes<F, W>), grid, dim3(256), 0, st, g)
+  if (form == kForm4M) {
+    if (g.tile == 0) TN_F32P(kForm4M, 2);
+    else if (g.tile == 1) TN_F32P(kForm4M, 1);
+    else TN_F32P(kForm4M, 4);
+  } else {
+    if (g.tile == 0) TN_F32P(kForm3M, 2);
+    else if (g.tile == 1) TN_F32P(kForm3M, 1);
+    else TN_F32P(kForm3M, 4);
+  }
+#undef TN_F32P
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.ksplit == 1) return e;
   return launch_splitk_reduce(st, g, nbatch);

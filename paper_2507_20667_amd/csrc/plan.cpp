@@ -327,9 +327,38 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   out.insert(out.end(), FB.begin(), FB.end());
   n.out = make_layout(out, A, B);
   n.variant = (n.M >= 128 && n.N >= 128) ? 0 : 1;
+  // FP32 planes: a 64-row or 64-column tile when that side is that small
+  // (a 128 x 128 tile would run half empty), unless the tuning table says
+  // otherwise
+  n.tile = 0;
+  if (n.planes == 2) n.tile = n.M <= 64 && n.N > 64 ? 1 : n.N <= 64 && n.M > 64 ? 2 : 0;
   {
-    const int tile = n.planes > 0 ? 128 : gemm_variant_tile_m(n.variant);
-    n.ksplit = gemm_ksplit(n.M, n.N, n.K, tile, tile, &n.kchunk);
+    const int tm = n.planes == 2 ? gemm_planes_tile_m(n.tile)
+                                 : n.planes > 0 ? 128 : gemm_variant_tile_m(n.variant);
+    const int tn = n.planes == 2 ? gemm_planes_tile_n(n.tile)
+                                 : n.planes > 0 ? 128 : gemm_variant_tile_n(n.variant);
+    n.ksplit = gemm_ksplit(n.M, n.N, n.K, tm, tn, &n.kchunk);
+  }
+  // the tuning table's choice for this shape, or TN_GEMM_FORCE="tile,ksplit"
+  // (tuning runs): a tile shape for the FP32 planes, k chunks of a multiple
+  // of 32 entries
+  {
+    int tile = -1, ks = 0;
+    if (const char *e = getenv("TN_GEMM_FORCE")) {
+      if (sscanf(e, "%d,%d", &tile, &ks) != 2) tile = -1, ks = 0;
+    } else if (n.planes > 0 && p->tuned) {
+      if (const GemmRule *r = tune_gemm(n.planes > 2, (p->flags & TN_FORM_3M) != 0, n.M, n.N, n.K)) {
+        tile = r->tile;
+        ks = r->ksplit;
+      }
+    }
+    if (n.planes == 2 && tile >= 0 && tile <= 2) n.tile = tile;
+    if (n.planes > 0 && ks >= 1) {
+      int64_t kc = (n.K + ks - 1) / ks;
+      kc = (kc + 31) / 32 * 32;
+      n.kchunk = kc;
+      n.ksplit = (int)((n.K + kc - 1) / kc);
+    }
   }
   n.ktile = n.planes > 0 && n.K % 16 == 0 &&
             (n.ksplit == 1 || n.kchunk % 16 == 0);
@@ -553,6 +582,40 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
     parent[a] = parent[b] = v;
   }
   p->root = nn - 1;
+  // fingerprint (FNV-1a, 64 bits) of what a plan's launch choices depend
+  // on: ranks, labels and dimensions, partition, tree, precision and form,
+  // output legs; the key of the plan's tuning-table entry
+  {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t x) {
+      for (int b = 0; b < 8; ++b) {
+        h ^= (uint64_t)((x >> (8 * b)) & 0xff);
+        h *= 1099511628211ull;
+      }
+    };
+    mix(nv);
+    for (int v = 0; v < nv; ++v) {
+      mix(p->leaf[v].rank());
+      for (int i = 0; i < p->leaf[v].rank(); ++i) {
+        mix(p->leaf[v].lab[i]);
+        mix(p->leaf[v].dim[i]);
+      }
+      mix(p->partition_of[v]);
+    }
+    for (int32_t x : p->tree) mix(x);
+    mix(p->flags & (TN_PREC_BF16X3 | TN_FORM_3M));
+    for (int i = 0; i < d->num_output_legs; ++i) mix(d->output_legs ? d->output_legs[i] : 0);
+    p->fingerprint = h;
+  }
+  // subtree kernel choices: built-in defaults, the tuning table's entry for
+  // this plan, then the TN_TREE_* overrides (tuning runs)
+  // (TN_TUNE_OFF, read at every load, sets the table aside: a comparison of
+  // tuned and untuned plans in one process)
+  p->tuned = !getenv("TN_TUNE_OFF");
+  if (const TreeKnobs *k = p->tuned ? tune_tree(p->fingerprint) : nullptr) p->knobs = *k;
+  if (const char *e = getenv("TN_TREE_QW")) p->knobs.qw = atoi(e);
+  if (const char *e = getenv("TN_TREE_SPILL")) p->knobs.spill = std::max(1, atoi(e));
+  if (const char *e = getenv("TN_TREE_PACK_NC")) p->knobs.pack_nc = std::max(1, atoi(e));
   // acceptance: partition of all leaves under each vertex
   std::vector<int> pk(nn), nleaf(nn);
   for (int v = 0; v < nv; ++v) {
@@ -716,9 +779,9 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
   if (getenv("TN_DEBUG")) {
     for (const Node &n : p->nodes)
       if (n.kind == NK_GEMM)
-        fprintf(stderr, "[tn] gemm vertex %d: M %lld N %lld K %lld op %d%d perm %d%d variant %d ksplit %d\n",
+        fprintf(stderr, "[tn] gemm vertex %d: M %lld N %lld K %lld op %d%d perm %d%d variant %d tile %d ksplit %d\n",
                 n.id, (long long)n.M, (long long)n.N, (long long)n.K, n.opA, n.opB,
-                (int)n.pa.needed, (int)n.pb.needed, n.variant, n.ksplit);
+                (int)n.pa.needed, (int)n.pb.needed, n.variant, n.tile, n.ksplit);
     fprintf(stderr, "[tn] plan: %d vertices, %d gemm, %d stream, %d in subtrees (%zu roots)\n",
             nv - 1, p->num_gemm, p->num_stream,
             (int)std::count(p->in_tree.begin(), p->in_tree.end(), (char)1), p->tree_roots.size());
@@ -1341,8 +1404,8 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
         L.tree_qw = qw;
         break;
       }
-  if (const char *e = getenv("TN_TREE_QW")) {  // tuning override
-    const int qw = atoi(e);
+  if (p->knobs.qw > 0) {  // the plan's tuned (or overridden) choice
+    const int qw = p->knobs.qw;
     if (qw >= 1 && qw <= 16 && tree_lds_bytes(qw, max_scale_q, max_sh_q, max_pq_q, L.tree_wave) <= lim)
       L.tree_qw = qw;
   }
@@ -1365,9 +1428,9 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   // 4 steps.
   std::vector<TreeLaneRec> lanes;
   {
-    int mode = 2, most = 64;
+    int mode = 2;
+    const int most = p->knobs.pack_nc;
     if (const char *e = getenv("TN_TREE_PACK")) mode = atoi(e);
-    if (const char *e = getenv("TN_TREE_PACK_NC")) most = std::max(1, atoi(e));  // tuning
     const bool one_q = (L.tree_wave && L.tree_qw <= 4) || L.tree_qw == 1;
     std::vector<TreeStep> out;
     out.reserve(steps.size());
@@ -1646,10 +1709,7 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
     // of the workspace (their whole lifetime), which keeps each query's LDS
     // small enough for more queries per CU
     L.spill.clear();
-    static const int64_t spill_at = [] {  // tuning: TN_TREE_SPILL entries
-      const char *e = getenv("TN_TREE_SPILL");
-      return e && atoll(e) > 0 ? (int64_t)atoll(e) : (int64_t)kTreeSpillElems;
-    }();
+    const int64_t spill_at = p->knobs.spill;  // the plan's choice (tuning table, TN_TREE_SPILL)
     for (int r : p->tree_roots) {
       if (L.shared[r]) continue;
       std::vector<int> stack{p->nodes[r - nv].c1, p->nodes[r - nv].c2};

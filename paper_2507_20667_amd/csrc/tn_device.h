@@ -95,7 +95,10 @@ struct GemmArgs {
   int64_t partbs, kchunk;
   // ktile = 1: the planes are k-tiled (row r, k at ((k / 16) * rows + r) * 16
   // + k % 16, rows = M for A and N for B), K a multiple of 16
-  int32_t ktile, pad2;
+  int32_t ktile;
+  // tile shape of the FP32 plane kernel: 0 = 128 x 128, 1 = 64 x 256,
+  // 2 = 256 x 64 (M x N)
+  int32_t tile;
 };
 
 // Output order of a permutation into split planes: ktile.on = 1 writes the
@@ -307,6 +310,8 @@ hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int prec, int form, in
                        int nbatch);
 hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g, int form, int nbatch);
 hipError_t launch_gemm_f32_planes(hipStream_t st, const GemmArgs &g, int form, int nbatch);
+int gemm_planes_tile_m(int v);
+int gemm_planes_tile_n(int v);
 hipError_t launch_splitk_reduce(hipStream_t st, const GemmArgs &g, int nbatch);
 // k chunks of a GEMM with tiles_m x tiles_n output tiles (1: no split)
 int gemm_ksplit(int64_t M, int64_t N, int64_t K, int tile_m, int tile_n, int64_t *kchunk);

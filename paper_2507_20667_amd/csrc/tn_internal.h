@@ -85,6 +85,7 @@ struct Node {
   int64_t kchunk = 0;
   int64_t M = 0, N = 0, K = 0, lda = 0, ldb = 0, ldc = 0;
   int variant = 0;
+  int tile = 0;      // FP32 plane kernel tile shape (GemmArgs::tile)
   // NK_DOT
   size_t ddesc_off = 0;
   int64_t nelem = 0;
@@ -127,9 +128,46 @@ struct ExecLayout {
   bool all_in_tree = false;                // every vertex runs in the subtree kernel
   int64_t tree_dev = -1;                   // arena offset of the uploaded blob
   size_t tree_dev_bytes = 0;
+  // device cache of the shared part: the results of the vertices no
+  // override reaches (and their scale records), kept across calls of this
+  // layout; every field below is guarded by the context's rcache_mu
+  int64_t rc_off = -1;     // arena offset (persistent allocation)
+  size_t rc_bytes = 0;
+  int rc_state = 0;        // 0 empty, 1 being filled by one call, 2 valid
+  int rc_pins = 0;         // calls reading or filling it (not evictable)
+  uint64_t rc_used = 0;    // last use (LRU clock)
 };
 
 struct tn_plan_impl;
+
+// Launch choices of the subtree kernel for one plan: queries per workgroup
+// (0: chosen from the LDS budget), per-query intermediates of at least
+// `spill` entries in device memory, packed gate steps of at most `pack_nc`
+// entries.
+struct TreeKnobs {
+  int qw = 0;
+  int spill = kTreeSpillElems;
+  int pack_nc = 64;
+};
+// Tuning table (tune.cpp)
+struct GemmRule {
+  bool bf16 = false, m3 = false;
+  int lm = 0, ln = 0, lk = 0;  // ceil log2 of M, N, K
+  int tile = 0, ksplit = 0;    // ksplit 0: the heuristic's
+};
+struct TreeRule {
+  uint64_t fingerprint = 0;
+  TreeKnobs knobs;
+};
+struct TuneTable {
+  bool loaded = false;
+  std::string path;
+  std::vector<GemmRule> gemm;
+  std::vector<TreeRule> tree;
+};
+const TuneTable &tune_table();
+const GemmRule *tune_gemm(bool bf16, bool m3, int64_t M, int64_t N, int64_t K);
+const TreeKnobs *tune_tree(uint64_t fingerprint);
 
 struct ServeState;  // serve.cpp
 
@@ -222,6 +260,12 @@ struct tn_ctx {
   hipEvent_t part_ev0 = nullptr;
   // this device's static scratch (tn_contract_strided_noalloc), or NULL
   uint8_t *scratch = nullptr;
+  // layouts whose shared part is cached in the arena, least recently used
+  // evicted first when the cached bytes would exceed the budget
+  std::mutex rcache_mu;
+  std::vector<tn::ExecLayout *> rcache;
+  size_t rcache_bytes = 0, rcache_budget = 0;
+  uint64_t rcache_clock = 0;
 };
 
 namespace tn {
@@ -242,6 +286,9 @@ struct GraphEntry {
 struct tn_plan {
   tn_ctx *ctx = nullptr;
   uint32_t flags = 0;
+  uint64_t fingerprint = 0;      // of the network, partition, tree and flags
+  tn::TreeKnobs knobs;           // subtree kernel launch choices
+  bool tuned = true;             // the tuning table applies
   int nv = 0;
   int K = 0;
   std::vector<tn::Layout> leaf;
@@ -327,6 +374,9 @@ size_t group_workspace_bytes(const tn_plan *p, const ExecLayout &L, int Q);
 size_t result_elems(const tn_plan *p);
 // drops a captured graph with its workspace and pinned buffer (stream idle)
 void release_graph(tn_ctx *ctx, GraphEntry &g);
+
+// cache of shared parts (exec.cpp): drop a layout's entry (its plan is freed)
+void rcache_drop(tn_ctx *ctx, ExecLayout &L);
 
 // serve.cpp
 void serve_shutdown(tn_ctx *ctx);

@@ -64,7 +64,7 @@ class tn_plan_costs(ctypes.Structure):
                 ("largest_intermediate_elems", ctypes.c_uint64),
                 ("num_internal_nodes", ctypes.c_int32), ("num_gemm_nodes", ctypes.c_int32),
                 ("num_tiny_nodes", ctypes.c_int32), ("num_stream_nodes", ctypes.c_int32),
-                ("num_permutations", ctypes.c_int32)]
+                ("num_permutations", ctypes.c_int32), ("fingerprint", ctypes.c_uint64)]
 
 
 class tn_leaf(ctypes.Structure):
@@ -175,7 +175,7 @@ def tn_plan_costs_get(plan) -> dict:
                 largest_intermediate=int(c.largest_intermediate_elems),
                 num_internal_nodes=c.num_internal_nodes, num_gemm_nodes=c.num_gemm_nodes,
                 num_tiny_nodes=c.num_tiny_nodes, num_stream_nodes=c.num_stream_nodes,
-                num_permutations=c.num_permutations)
+                num_permutations=c.num_permutations, fingerprint=f"{c.fingerprint:016x}")
 
 
 def tn_plan_free(plan):

@@ -185,7 +185,13 @@ def test_permutation_is_bit_exact(ctx, shape, perm):
                                          (1024, 512, 1024, lib.TN_FORM_3M)]
                          # 1, 3, 5, 7 and 11 stages of 16 k: every tail of the four-slot ring
                          + [(130, k, 200, f) for k in (16, 48, 80, 112, 176)
-                            for f in (lib.TN_FORM_4M, lib.TN_FORM_3M)])
+                            for f in (lib.TN_FORM_4M, lib.TN_FORM_3M)]
+                         # 64 x 256 tiles (M <= 64) and 256 x 64 tiles (N <= 64), ragged
+                         # and split into k chunks
+                         + [(64, 512, 1000, f) for f in (lib.TN_FORM_4M, lib.TN_FORM_3M)]
+                         + [(40, 48, 300, lib.TN_FORM_4M), (1000, 64, 48, lib.TN_FORM_3M),
+                            (300, 176, 50, lib.TN_FORM_4M), (64, 4096, 600, lib.TN_FORM_3M),
+                            (600, 4096, 33, lib.TN_FORM_4M)])
 def test_gemm_vertex_against_fp64(ctx, M, K, N, form):
     """Two tensors A(m, k) and B(k, n) with an open output: one GEMM vertex.
     Error bound |dC| <= gamma * |A||B| with gamma = 4 * K * 2^-24 (FP32 inputs
@@ -292,4 +298,26 @@ def test_gemm_heavy_circuit_bf16x3(ctx, form):
         worst = max(worst, e)
         assert e < 1e-3, (x, got, ref)
     print("bf16x3 circuit max err", worst)
+    ctx.free_plan(p)
+
+
+@pytest.mark.parametrize("force", ["0,1", "1,1", "2,1", "0,4", "1,8", "2,2", "1,3"])
+@pytest.mark.parametrize("form", [lib.TN_FORM_4M, lib.TN_FORM_3M])
+def test_gemm_forced_tiles_and_chunks(ctx, monkeypatch, force, form):
+    """Every FP32 plane tile shape and k-chunk count the tuner may choose
+    (TN_GEMM_FORCE at plan load) on ragged shapes: within the FP32 bound of
+    the FP64 product."""
+    M, K, N = 150, 1024, 230
+    rng = np.random.default_rng(sum(map(ord, force)) + form)
+    A = rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
+    monkeypatch.setenv("TN_GEMM_FORCE", force)
+    p = ctx.plan_load([[1, 2], [2, 3]], {1: M, 2: K, 3: N}, [A, B], [0, 1], 2, [(0, 1)], [1, 3], form)
+    monkeypatch.delenv("TN_GEMM_FORCE")
+    got, _ = lib.tn_contract(p, result_shape=(M, N))
+    A32 = A.astype(np.complex64).astype(np.complex128)
+    B32 = B.astype(np.complex64).astype(np.complex128)
+    ref = A32 @ B32
+    bound = (np.abs(A32) @ np.abs(B32)) * (4 * K * 2.0 ** -24) * (2 if form == lib.TN_FORM_3M else 1)
+    assert np.all(np.abs(got - ref) <= bound + 1e-30)
     ctx.free_plan(p)
