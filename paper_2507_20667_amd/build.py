@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libtn.so")
 ARCH = os.environ.get("TN_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kernels.hip", "tree.hip", "gemm_bf16.hip", "gemm_f32.hip", "plan.cpp", "exec.cpp", "api.cpp",
-           "serve.cpp", "tune.cpp"]
+           "serve.cpp", "tune.cpp", "slice.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           f"--offload-arch={ARCH}",

@@ -207,10 +207,15 @@ tn_status tn_plan_free(tn_plan *p) {
     set_error("tn_plan_free: NULL plan");
     return TN_E_INVALID_ARG;
   }
-  if (p->ctx && serve_pending_on(p->ctx, p) > 0) {
-    set_error("tn_plan_free: %d serve request(s) on this plan are still pending",
-              serve_pending_on(p->ctx, p));
+  if (p->ctx && (serve_pending_on(p->ctx, p) > 0 ||
+                 (p->auto_sliced && serve_pending_on(p->ctx, p->auto_sliced) > 0))) {
+    set_error("tn_plan_free: serve requests on this plan are still pending");
     return TN_E_INVALID_ARG;
+  }
+  if (p->auto_sliced) {
+    tn_status st = tn_plan_free(p->auto_sliced);
+    if (st != TN_OK) return st;
+    p->auto_sliced = nullptr;
   }
   if (p->ctx) {
     tn_ctx *ctx = p->ctx;
@@ -241,6 +246,16 @@ tn_status tn_contract(tn_plan *p, int32_t num_overrides, const tn_leaf *override
     set_error("tn_contract: bad overrides or flags");
     return TN_E_INVALID_ARG;
   }
+  if (p->nslices > 0) {
+    if (!out) {
+      set_error("tn_contract: out is NULL");
+      return TN_E_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> g(p->ctx->exec_mu);
+    ExecRes r = ctx_res(p->ctx);
+    return run_sliced(p->ctx, p, num_overrides, overrides, out, out_dtype, log2_scale,
+                      flags & TN_FLAG_KEEP_SCALE, r);
+  }
   QueryIO q;
   q.ovr = overrides;
   q.novr = num_overrides;
@@ -263,6 +278,10 @@ tn_status tn_contract_strided(tn_plan *p, int32_t num_queries, int32_t num_overr
       (num_queries > 0 && !out) || (flags & ~(TN_FLAG_KEEP_SCALE | TN_FLAG_GRAPH)) ||
       (out_dtype != TN_C64 && out_dtype != TN_C128)) {
     set_error("tn_contract_strided: bad arguments");
+    return TN_E_INVALID_ARG;
+  }
+  if (p->nslices > 0) {
+    set_error("tn_contract_strided: a sliced plan runs through tn_contract or serving");
     return TN_E_INVALID_ARG;
   }
   if (out_stride < (int64_t)result_elems(p)) {
@@ -306,6 +325,18 @@ tn_status tn_contract_strided(tn_plan *p, int32_t num_queries, int32_t num_overr
   return run_group(p->ctx, p, qs, out_dtype, flags, true, r, &so);
 }
 
+tn_status tn_plan_slice(tn_plan *plan, int32_t num_labels, const int64_t *labels,
+                        int64_t max_intermediate, tn_plan **out) {
+  if (!plan || !out || num_labels < 0 || (num_labels > 0 && !labels) ||
+      (num_labels == 0 && max_intermediate < 1)) {
+    set_error("tn_plan_slice: bad arguments (a plan, labels or max_intermediate >= 1, out)");
+    return TN_E_INVALID_ARG;
+  }
+  *out = nullptr;
+  std::vector<int64_t> l(labels, labels + num_labels);
+  return make_sliced_plan(plan->ctx, plan, l, max_intermediate, out);
+}
+
 tn_status tn_contract_strided_noalloc(tn_plan *p, int32_t num_queries, int32_t num_overrides,
                                       const tn_leaf *overrides, const int64_t *strides, void *out,
                                       int64_t out_stride, uint32_t flags) {
@@ -319,9 +350,9 @@ tn_status tn_contract_strided_noalloc(tn_plan *p, int32_t num_queries, int32_t n
               "out_stride >= 1, flags = 0)");
     return TN_E_INVALID_ARG;
   }
-  if (!p->closed || p->nv < 2) {
+  if (!p->closed || p->nv < 2 || p->nslices > 0) {
     set_error("tn_contract_strided_noalloc: only closed networks of two or more tensors (one "
-              "amplitude per query)");
+              "amplitude per query), not sliced");
     return TN_E_INVALID_ARG;
   }
   for (int32_t i = 0; i < num_overrides; ++i)
@@ -389,6 +420,11 @@ tn_status tn_contract_batch(tn_ctx *ctx, int32_t num_queries, const tn_query *qu
   std::vector<std::vector<int>> members;
   for (int i = 0; i < num_queries; ++i) {
     tn_plan *p = queries[i].plan;
+    if (p && p->nslices > 0) {
+      set_error("tn_contract_batch: query %d is on a sliced plan (use tn_contract or serving)", i);
+      if (per_query) per_query[i] = TN_E_INVALID_ARG;
+      return TN_E_INVALID_ARG;
+    }
     if (!p || p->ctx != ctx || queries[i].num_overrides < 0 ||
         (queries[i].num_overrides > 0 && !queries[i].overrides)) {
       set_error("tn_contract_batch: query %d has no plan of this context or bad overrides", i);

@@ -155,6 +155,29 @@ void rcache_drop(tn_ctx *ctx, ExecLayout &L) {
   L.rc_state = 0;
 }
 
+// First use of a layout: its subtree programs go to the arena (persistent,
+// kept with the plan).  The caller holds the plan's cache_mu.
+tn_status upload_tree_programs(tn_ctx *ctx, const ExecLayout &L, hipStream_t st) {
+  if (L.n_tree_shared + L.n_tree_perq == 0 || L.tree_dev >= 0) return TN_OK;
+  ExecLayout &Lm = const_cast<ExecLayout &>(L);
+  Lm.tree_dev_bytes = std::max<size_t>(L.tree_blob.size(), 256);
+  Lm.tree_dev = ctx->arena.alloc(Lm.tree_dev_bytes, true);
+  if (Lm.tree_dev < 0) {
+    set_error("arena cannot hold the subtree programs (%zu bytes)", Lm.tree_dev_bytes);
+    return TN_E_NOMEM;
+  }
+  hipError_t e = hipMemcpyAsync(ctx->arena.base() + Lm.tree_dev, L.tree_blob.data(), L.tree_blob.size(),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    ctx->arena.release(Lm.tree_dev, Lm.tree_dev_bytes, true);
+    Lm.tree_dev = -1;
+    set_error("subtree program upload: %s", hipGetErrorString(e));
+    return TN_E_DEVICE;
+  }
+  return TN_OK;
+}
+
 // Device bytes of one execution chunk of Q queries (carved in run_group).
 size_t group_workspace_bytes(const tn_plan *p, const ExecLayout &L, int Q) {
   const int nn = 2 * p->nv - 1;
@@ -210,7 +233,7 @@ static void write_out(void *out, tn_dtype dt, size_t i, double re, double im) {
   } while (0)
 
 tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_dtype out_dtype,
-                    uint32_t flags, bool share, ExecRes &rs, const StridedOvr *so) {
+                    uint32_t flags, bool share, ExecRes &rs, const StridedOvr *so, SliceSum *sum) {
   const int nv = p->nv, nn = 2 * nv - 1;
   if (qs.empty()) return TN_OK;
   if (out_dtype != TN_C64 && out_dtype != TN_C128) {
@@ -282,24 +305,9 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
   const size_t ovr_bytes = (size_t)L.ovr_bytes;
   const bool trees = L.n_tree_shared + L.n_tree_perq > 0;
   std::unique_lock<std::mutex> upload_lock(p->cache_mu);
-  if (trees && L.tree_dev < 0) {
-    // first use of this layout: upload its subtree programs
-    ExecLayout &Lm = const_cast<ExecLayout &>(L);
-    Lm.tree_dev_bytes = std::max<size_t>(L.tree_blob.size(), 256);
-    Lm.tree_dev = ctx->arena.alloc(Lm.tree_dev_bytes, true);
-    if (Lm.tree_dev < 0) {
-      set_error("arena cannot hold the subtree programs (%zu bytes)", Lm.tree_dev_bytes);
-      return TN_E_NOMEM;
-    }
-    hipError_t e = hipMemcpyAsync(ctx->arena.base() + Lm.tree_dev, L.tree_blob.data(),
-                                  L.tree_blob.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-      ctx->arena.release(Lm.tree_dev, Lm.tree_dev_bytes, true);
-      Lm.tree_dev = -1;
-      set_error("subtree program upload: %s", hipGetErrorString(e));
-      return TN_E_DEVICE;
-    }
+  {
+    const tn_status us = upload_tree_programs(ctx, L, st);
+    if (us != TN_OK) return us;
   }
   // algorithmic traffic and work of the subtree kernel (for the profiler),
   // once per layout
@@ -355,11 +363,24 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
     }
     chunk = qs.size();
   } else if (rs.ws >= 0) {
-    if (group_workspace_bytes(p, L, (int)qs.size()) > rs.ws_bytes) {
-      set_error("reserved workspace too small for %zu queries", qs.size());
-      return TN_E_NOMEM;
-    }
     chunk = qs.size();
+    if (group_workspace_bytes(p, L, (int)chunk) > rs.ws_bytes) {
+      // the slices of a sliced request run in chunks of the reserved
+      // workspace: the most queries whose workspace fits it
+      size_t lo = 0, hi = sum ? qs.size() : 0;
+      while (lo < hi) {
+        const size_t mid = (lo + hi + 1) / 2;
+        if (group_workspace_bytes(p, L, (int)mid) <= rs.ws_bytes)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      if (lo == 0) {
+        set_error("reserved workspace too small for %zu queries", qs.size());
+        return TN_E_NOMEM;
+      }
+      chunk = lo;
+    }
   } else {
     size_t avail = ctx->arena.largest_free();
     if (avail < shared_fixed + per_query + 4096) {
@@ -659,7 +680,8 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       if (gmode) {
         h = (uint8_t *)p->graph->pinned;
       } else if (!devout) {
-        rc = ensure_pinned(rs, rb_bytes, st);
+        // a slice sum needs room for one FP64 result and its scale
+        rc = ensure_pinned(rs, sum ? std::max(rb_bytes, relems * 16 + 64) : rb_bytes, st);
         if (rc) goto done;
         h = (uint8_t *)*rs.pinned;
       }
@@ -669,7 +691,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       // a closed root's records go straight to the pinned staging buffer
       // (host memory the device writes to; visible after the synchronize
       // below), which saves the copy back
-      Result *res_out = dot_root && !devout ? hr : res;
+      Result *res_out = dot_root && !devout && !sum ? hr : res;
       // results straight into the caller's pinned array: complex128 values
       // scaled to 1, a closed root computed by the subtree kernel, no graph
       const bool direct = so && so->dout && out_dtype == TN_C128 && !(flags & TN_FLAG_KEEP_SCALE) &&
@@ -884,7 +906,7 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           const int prec = (p->flags & TN_PREC_BF16X3) ? kPrecBF16x3 : kPrecFP32;
           const int form = (p->flags & TN_FORM_3M) ? kForm3M : kForm4M;
           const auto tg = std::chrono::steady_clock::now();
-          TN_HIP(prof.timed(xs, TN_KCLASS_GEMM, nodeb, wflops,
+          TN_HIP(prof.timed(xs, n.ktile ? TN_KCLASS_GEMM : TN_KCLASS_GEMM_SMALL, nodeb, wflops,
                             [&] { return launch_gemm(xs, g, prec, form, n.variant, nb); }),
                  "complex GEMM");
           if (dbg_gemm) {
@@ -921,8 +943,24 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
         TN_HIP(launch_results_to_c128(st, res, root_shared ? 0 : 1, Q,
                                       so->dout + (int64_t)q0 * so->dout_stride, so->dout_stride),
                "result conversion");
+      // slices: their sum, on the device, into the staging buffer
+      if (sum) {
+        const int nq = root_shared ? 1 : Q;
+        if (dot_root) {
+          TN_HIP(launch_slice_sum_records(st, res, root_shared ? 0 : 1, nq, (Result *)h), "slice sum");
+        } else {
+          Operand S = R;
+          if (p->fperm.needed) {
+            S.p = fin;
+            S.bs = root_shared ? 0 : (int64_t)(final_bytes / 8);
+          }
+          TN_HIP(launch_slice_sum_tensors(st, S, nq, (int64_t)relems, (double2 *)h,
+                                          (double *)(h + relems * 16)),
+                 "slice sum");
+        }
+      }
       // read back
-      if (!dot_root && !devout) {
+      if (!dot_root && !devout && !sum) {
         const int rq = root_shared ? 1 : Q;
         if (p->fperm.needed) {
           // the permuted results lie final_bytes apart (256-byte rounded)
@@ -959,7 +997,16 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
       // written by the kernel: only the scales (1) remain, if asked for
       for (int qi = 0; qi < Q && direct && so->log2s; ++qi)
         if (qs[q0 + qi].log2s) *qs[q0 + qi].log2s = 0.0;
-      for (int qi = 0; qi < Q && !direct && !devout; ++qi) {
+      if (sum) {
+        if (dot_root) {
+          const Result &r = *(const Result *)h;
+          const double v[2] = {r.re, r.im};
+          sum->add(v, 1, r.log2s);
+        } else {
+          sum->add((const double *)h, relems, *(const double *)(h + relems * 16));
+        }
+      }
+      for (int qi = 0; qi < Q && !direct && !devout && !sum; ++qi) {
         const QueryIO &q = qs[q0 + qi];
         const bool keep = (flags & TN_FLAG_KEEP_SCALE) != 0;
         if (dot_root) {

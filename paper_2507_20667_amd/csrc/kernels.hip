@@ -777,4 +777,77 @@ hipError_t launch_results_to_c128(hipStream_t st, const Result *res, int64_t rbs
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------- slice sums
+// Slicing: the full contraction is the sum of its slices' (Section 2.2, a sum
+// over every bound index in any grouping).  The slice results carry scales
+// of their own; the sum aligns them to the largest and adds in FP64, in
+// slice order (deterministic).
+
+// Closed roots: nq records (query q's at res[q * rbs]) into one record.
+__global__ void k_slice_sum_records(const Result *res, int64_t rbs, int nq, Result *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double emax = -1e300;
+  bool any = false;
+  for (int q = 0; q < nq; ++q) {
+    const Result r = res[q * rbs];
+    if (r.re != 0.0 || r.im != 0.0) {
+      emax = any ? fmax(emax, r.log2s) : r.log2s;
+      any = true;
+    }
+  }
+  double vr = 0.0, vi = 0.0;
+  if (any)
+    for (int q = 0; q < nq; ++q) {
+      const Result r = res[q * rbs];
+      const int sh = (int)(r.log2s - emax);
+      vr += ldexp(r.re, sh);
+      vi += ldexp(r.im, sh);
+    }
+  double log2s = any ? emax : 0.0;
+  const double m = fmax(fabs(vr), fabs(vi));
+  if (m > 0.0 && isfinite(m)) {
+    int e;
+    frexp(m, &e);
+    vr = ldexp(vr, -e);
+    vi = ldexp(vi, -e);
+    log2s += (double)e;
+  }
+  out->re = vr;
+  out->im = vi;
+  out->log2s = log2s;
+  out->pad = 0.0;
+}
+
+// Open results: nq tensors of n complex64 entries (query q's values at
+// R.p + q * R.bs with scale record R.slot + q * R.sbs) into out[i] =
+// sum_q v_q[i] 2^(l_q - lmax), with lmax (the largest l_q) in *out_log2.
+__global__ __launch_bounds__(256) void k_slice_sum_tensors(Operand R, int nq, int64_t n, double2 *out,
+                                                           double *out_log2) {
+  double lmax = R.slot[0].log2s;
+  for (int q = 1; q < nq; ++q) lmax = fmax(lmax, R.slot[q * R.sbs].log2s);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out_log2 = lmax;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double vr = 0.0, vi = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      const float2 v = R.p[q * R.bs + i];
+      const int sh = (int)(R.slot[q * R.sbs].log2s - lmax);
+      vr += ldexp((double)v.x, sh);
+      vi += ldexp((double)v.y, sh);
+    }
+    out[i] = make_double2(vr, vi);
+  }
+}
+
+hipError_t launch_slice_sum_records(hipStream_t st, const Result *res, int64_t rbs, int nq, Result *out) {
+  hipLaunchKernelGGL(k_slice_sum_records, dim3(1), dim3(64), 0, st, res, rbs, nq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_sum_tensors(hipStream_t st, Operand R, int nq, int64_t n, double2 *out,
+                                    double *out_log2) {
+  hipLaunchKernelGGL(k_slice_sum_tensors, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, R, nq, n, out,
+                     out_log2);
+  return hipGetLastError();
+}
+
 }  // namespace tn

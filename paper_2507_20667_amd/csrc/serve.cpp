@@ -40,14 +40,36 @@ class DeviceBackend : public sched::Backend {
 
   size_t footprint(const std::vector<sched::Req *> &batch, size_t n) override {
     tn_plan *p = static_cast<ServeReq *>(batch[0])->p;
+    // a sliced plan runs one request at a time, its slices as one group
+    if (p->nslices > 0 && n > 1) return SIZE_MAX / 4;
+    return request_bytes(p, batch, n, capacity());
+  }
+  // Workspace to reserve for n requests of plan p.  A sliced request reserves
+  // room for a chunk of its slices (all of them if that takes at most half of
+  // `cap`, else halves of them down to one) and runs its slices chunk by chunk.
+  static size_t request_bytes(tn_plan *p, const std::vector<sched::Req *> &batch, size_t n,
+                              size_t cap) {
+    std::shared_ptr<ExecLayout> L = layout_of(p, batch, n);
+    int64_t nq = p->nslices > 0 ? p->nslices * (int64_t)n : (int64_t)n;
+    size_t b = Arena::round(group_workspace_bytes(p, *L, (int)nq));
+    while (p->nslices > 0 && nq > 1 && b > cap / 2) {
+      nq = (nq + 1) / 2;
+      b = Arena::round(group_workspace_bytes(p, *L, (int)nq));
+    }
+    return b;
+  }
+  // The execution layout of n requests of plan p (their overridden tensors,
+  // and those a sliced plan overrides per slice).
+  static std::shared_ptr<ExecLayout> layout_of(tn_plan *p, const std::vector<sched::Req *> &batch,
+                                               size_t n) {
     std::vector<char> is(p->nv, 0);
     for (size_t i = 0; i < n; ++i)
       for (const tn_leaf &l : static_cast<ServeReq *>(batch[i])->leaves) is[l.tensor] = 1;
+    for (int t : p->slice_touched) is[t] = 1;
     std::vector<int> ovr;
     for (int t = 0; t < p->nv; ++t)
       if (is[t]) ovr.push_back(t);
-    std::shared_ptr<ExecLayout> L = cached_layout(p, ovr, true);
-    return Arena::round(group_workspace_bytes(p, *L, (int)n));
+    return cached_layout(p, ovr, true);
   }
   int64_t reserve(size_t bytes) override { return ctx_->arena.alloc(bytes); }
   void release(int64_t off, size_t bytes) override { ctx_->arena.release(off, bytes); }
@@ -93,6 +115,16 @@ class DeviceBackend : public sched::Backend {
     res.pinned_bytes = &w->pinned_bytes;
     res.ws = ws;
     res.ws_bytes = bytes;
+    if (p->nslices > 0) {  // one request: its slices summed
+      ServeReq *r = static_cast<ServeReq *>(batch[0]);
+      const tn_status rc = run_sliced(ctx_, p, (int32_t)r->leaves.size(), r->leaves.data(),
+                                      outs[0].data(), TN_C128, &l2[0], TN_FLAG_KEEP_SCALE, res);
+      if (rc != TN_OK) return rc;
+      r->result.swap(outs[0]);
+      r->log2s = l2[0];
+      st[0] = TN_OK;
+      return TN_OK;
+    }
     const tn_status rc = run_group(ctx_, p, qs, TN_C128, TN_FLAG_KEEP_SCALE, true, res);
     if (rc != TN_OK) return rc;
     for (size_t i = 0; i < batch.size(); ++i) {
@@ -192,6 +224,47 @@ tn_status tn_serve_submit(tn_ctx *ctx, const tn_query *query, uint64_t *ticket) 
     r->leaves.push_back(c);
   }
   ServeState *S = serve_state(ctx);
+  // a request whose workspace can never fit the arena runs on a sliced copy
+  // of its plan (made once, kept with the plan): slices small enough to fit.
+  // The room is measured with the sliced plan's own persistent data (leaves,
+  // subtree programs) already in the arena.
+  {
+    std::vector<sched::Req *> one{r};
+    if (p->nslices == 0 &&
+        DeviceBackend::request_bytes(p, one, 1, ctx->arena.work_capacity()) > ctx->arena.work_capacity()) {
+      std::lock_guard<std::mutex> g(p->slice_mu);
+      for (int64_t target = p->largest / 2; !p->auto_sliced && target >= 1; target /= 2) {
+        tn_plan *sl = nullptr;
+        if (make_sliced_plan(ctx, p, {}, target, &sl) != TN_OK) break;
+        r->p = sl;
+        {
+          std::shared_ptr<ExecLayout> L = DeviceBackend::layout_of(sl, one, 1);
+          std::lock_guard<std::mutex> gl(sl->cache_mu);
+          (void)upload_tree_programs(ctx, *L, ctx->stream);
+        }
+        const size_t cap = ctx->arena.work_capacity();
+        if (DeviceBackend::request_bytes(sl, one, 1, cap) <= cap) {
+          p->auto_sliced = sl;
+        } else {
+          tn_plan_free(sl);
+          if (target < 2) break;
+        }
+        r->p = p;
+      }
+      if (p->auto_sliced) {
+        r->p = p->auto_sliced;
+        r->plan = p->auto_sliced;
+      }
+    }
+  }
+  // the request's subtree programs go to the arena now (persistent), before
+  // an admission reserves the room they would need at run time
+  {
+    std::vector<sched::Req *> one{r};
+    std::shared_ptr<ExecLayout> L = DeviceBackend::layout_of(r->p, one, 1);
+    std::lock_guard<std::mutex> g(r->p->cache_mu);
+    (void)upload_tree_programs(ctx, *L, ctx->stream);  // a failure shows when the request runs
+  }
   if (S->sched.submit(r, ticket) != sched::kOk) {
     delete r;
     set_error("tn_serve_submit: queue full");

@@ -332,6 +332,12 @@ size_t tree_lds_limit();
 constexpr size_t kScratchBytes = (size_t)64 << 20;
 constexpr int kScratchMaxDevices = 64;
 hipError_t scratch_address(int device, void **ptr);
+// slice sums (FP64, scales aligned to the largest): nq closed-root records
+// into one record, or nq result tensors of n entries into FP64 values and one
+// log2 scale
+hipError_t launch_slice_sum_records(hipStream_t st, const Result *res, int64_t rbs, int nq, Result *out);
+hipError_t launch_slice_sum_tensors(hipStream_t st, Operand R, int nq, int64_t n, double2 *out,
+                                    double *out_log2);
 // closed-root records of nq queries (query q's at res[q * rbs]) to
 // complex128 values at out[q * stride]
 hipError_t launch_results_to_c128(hipStream_t st, const Result *res, int64_t rbs, int nq,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cmath>
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
@@ -318,6 +319,21 @@ struct tn_plan {
   std::mutex cache_mu;
   std::map<std::vector<int>, std::shared_ptr<tn::ExecLayout>> layouts;  // by override set
   std::unique_ptr<tn::GraphEntry> graph;  // TN_FLAG_GRAPH: the captured launch sequence
+  // slicing (tn_plan_slice): the fixed legs (their dimensions in the sliced
+  // network are 1) and, per slice, the sub-tensors of the tensors that carry
+  // one; slice s fixes label k to digit k of s in the radix of their original
+  // dimensions (the last label fastest)
+  int64_t nslices = 0;
+  std::vector<int64_t> slice_labels, slice_radix;
+  std::vector<int> slice_touched;        // tensor ids
+  std::vector<int64_t> slice_sub_off;    // per touched tensor: offset in one slice's block
+  int64_t slice_block = 0;               // float2 entries per slice
+  std::vector<float2> slice_data;        // nslices * slice_block
+  std::vector<tn::Layout> slice_full;    // per touched tensor: its layout before slicing
+  // serving: a sliced copy made when a request on this plan cannot fit the
+  // arena (freed with the plan)
+  std::mutex slice_mu;
+  tn_plan *auto_sliced = nullptr;
 };
 
 namespace tn {
@@ -368,9 +384,38 @@ struct ExecRes {
   uint8_t *ext_ws = nullptr;
   size_t ext_ws_bytes = 0;
 };
+// The queries of one group are the slices of a sliced plan: run_group adds
+// their results on the device (FP64, scales aligned) instead of returning
+// them one by one, and adds each chunk's sum here on the host.
+struct SliceSum {
+  std::vector<double> acc;  // interleaved complex128 mantissas
+  double log2s = 0.0;
+  bool any = false;
+  void add(const double *v, size_t n, double l) {
+    if (!any) {
+      acc.assign(v, v + 2 * n);
+      log2s = l;
+      any = true;
+      return;
+    }
+    const double e = l > log2s ? l : log2s;
+    const int sa = (int)(log2s - e), sb = (int)(l - e);
+    for (size_t i = 0; i < 2 * n; ++i) acc[i] = std::ldexp(acc[i], sa) + std::ldexp(v[i], sb);
+    log2s = e;
+  }
+};
 tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_dtype out_dtype,
-                    uint32_t flags, bool share, ExecRes &rs, const StridedOvr *so = nullptr);
+                    uint32_t flags, bool share, ExecRes &rs, const StridedOvr *so = nullptr,
+                    SliceSum *sum = nullptr);
+// slice.cpp: a sliced copy of a plan (labels given, or chosen so that no
+// intermediate exceeds max_intermediate entries), and the contraction of a
+// sliced plan (every slice one query, summed)
+tn_status make_sliced_plan(tn_ctx *ctx, const tn_plan *p, std::vector<int64_t> labels,
+                           int64_t max_intermediate, tn_plan **out);
+tn_status run_sliced(tn_ctx *ctx, tn_plan *p, int32_t novr, const tn_leaf *ovr, void *out,
+                     tn_dtype out_dtype, double *log2_scale, uint32_t flags, ExecRes &rs);
 size_t group_workspace_bytes(const tn_plan *p, const ExecLayout &L, int Q);
+tn_status upload_tree_programs(tn_ctx *ctx, const ExecLayout &L, hipStream_t st);
 size_t result_elems(const tn_plan *p);
 // drops a captured graph with its workspace and pinned buffer (stream idle)
 void release_graph(tn_ctx *ctx, GraphEntry &g);

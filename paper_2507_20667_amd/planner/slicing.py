@@ -7,7 +7,7 @@ and the partition stay as they are.  Here a sliced leg keeps its label with
 dimension 1, and slice number s overrides every tensor that carries a sliced
 leg with its sub-tensor at that leg's value: all slices share one plan (the
 network with the sliced dimensions) and run as one batch of queries through
-the library; the slice results are added in FP64.
+the library; the slice results are added in FP64 on the device (tn_plan_slice).
 """
 from __future__ import annotations
 
@@ -95,20 +95,17 @@ def sliced_problem(leaf_legs, dims, tensors, sliced):
 
 def contract_sliced(lib, ctx, leaf_legs, dims, tensors, partition_of, num_partitions, tree,
                     sliced, output_legs=None, flags=0, result_shape=(), extra_overrides=None):
-    """Contract the network with the legs in `sliced` fixed slice by slice (one
-    batch through the library) and add the slice results in FP64.  Returns
-    the result (complex128, `result_shape`)."""
-    d, base, ovrs = sliced_problem(leaf_legs, dims, tensors, sliced)
-    p = ctx.plan_load(leaf_legs, d, base, partition_of, num_partitions, tree, output_legs, flags)
+    """Contract the network with the legs in `sliced` fixed slice by slice: the
+    library's sliced plan (tn_plan_slice) runs every slice as one query of one
+    batch and adds the slice results on the device in FP64.  Returns the
+    result (complex128, `result_shape`)."""
+    p = ctx.plan_load(leaf_legs, dims, tensors, partition_of, num_partitions, tree, output_legs, flags)
     try:
-        extra = extra_overrides or {}
-        queries = [(p, {**extra, **o}) for o in ovrs]
-        outs, l2, st = lib.tn_contract_batch(ctx.handle, queries, [tuple(result_shape)] * len(queries))
-        if not np.all(st == 0):
-            raise RuntimeError(f"slice contraction failed: {st}")
-        total = np.zeros(tuple(result_shape), dtype=np.complex128)
-        for o in outs:
-            total += np.asarray(o, dtype=np.complex128)
-        return total
+        s = ctx.slice_plan(p, list(sliced))
+        try:
+            out, _ = lib.tn_contract(s, extra_overrides or {}, result_shape=tuple(result_shape))
+            return np.asarray(out, dtype=np.complex128)
+        finally:
+            ctx.free_plan(s)
     finally:
         ctx.free_plan(p)

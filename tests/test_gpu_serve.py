@@ -171,3 +171,40 @@ def test_serve_request_too_big_fails_alone():
         for t in ts:
             st, out, _ = _wait(c, t)
             assert st == lib.TN_OK
+
+
+def test_serve_queue_bound(monkeypatch):
+    """TN_SERVE_QUEUE bounds the requests waiting for admission: with one
+    worker busy on a long request (a closed 8192^3 complex GEMM network), the
+    bound's worth of requests is accepted and the next submit returns
+    TN_E_AGAIN; every accepted request completes, and once the queue has
+    drained submits are accepted again."""
+    monkeypatch.setenv("TN_SERVE_WORKERS", "1")
+    monkeypatch.setenv("TN_SERVE_QUEUE", "4")
+    L = 8192
+    with lib.Context(8 << 30) as c:
+        ones = np.full((L, L), 1.0 / L, dtype=np.complex64)
+        big = c.plan_load([[1, 2], [2, 3], [1, 3]], {1: L, 2: L, 3: L}, [ones, ones, ones], [0, 0, 1], 2,
+                          [(0, 1), (3, 2)], None, 0, lib.TN_C64)
+        small = random_circuit(10, 6, 2)
+        snet = amplitude_network(small, 0)
+        spl = _plan(snet, 2)
+        sp = c.load_network(snet, spl.partition_of, 2, spl.tree)
+        lib.tn_contract(big)                      # plan warm (first-call set-up outside the window)
+        tb = lib.tn_serve_submit(c.handle, big, {})
+        time.sleep(0.005)                         # the worker takes it
+        accepted = []
+        with pytest.raises(lib.TnError) as e:
+            for x in random_bitstrings(10, 16, 4):
+                accepted.append((x, lib.tn_serve_submit(c.handle, sp, amplitude_overrides(snet, small, x))))
+        assert e.value.status == lib.TN_E_AGAIN
+        assert len(accepted) == 4
+        st, out, _ = _wait(c, tb)
+        assert st == lib.TN_OK and abs(_c(out) - 1.0) < 1e-4     # sum over i, j of (1/L)^3 * L
+        for x, t in accepted:
+            st, out, _ = _wait(c, t)
+            assert st == lib.TN_OK
+            alone, _ = lib.tn_contract(sp, amplitude_overrides(snet, small, x))
+            assert abs(_c(out) - _c(alone)) <= TOL * max(abs(_c(alone)), 2.0 ** -5)
+        t = lib.tn_serve_submit(c.handle, sp, {})
+        assert _wait(c, t)[0] == lib.TN_OK

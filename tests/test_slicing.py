@@ -46,3 +46,32 @@ def test_sum_of_slices_is_the_contraction():
     # and one slice alone is not the whole (the slicing is real)
     one = list(base)
     assert abs(complex(oracle.contract_tree(net.legs, d, one, plan.tree)) - ref) > 1e-6 * abs(ref)
+
+
+def test_library_slice_choice_matches_planner():
+    """tn_plan_slice on a host-only plan chooses legs by the same greedy rule
+    as choose_slices: the sliced plan's largest intermediate and con_serial
+    are those of the network with choose_slices' legs at dimension 1; with
+    the legs given explicitly the same sliced network results."""
+    from paper_2507_20667_amd import lib
+    from paper_2507_20667_amd.planner import cost
+    for seed, div in ((3, 4), (4, 8), (6, 16)):
+        circ, net, plan = _setup(seed=seed)
+        top = largest_intermediate(net.legs, net.dims, plan.tree)
+        target = max(top // div, 2)
+        sl = choose_slices(net.legs, net.dims, plan.tree, target, max_legs=30)
+        d = dict(net.dims)
+        for l in sl:
+            d[l] = 1
+        p = lib.tn_plan_load(None, net.legs, net.dims, net.tensors, plan.partition_of, 2, plan.tree)
+        for s in (lib.tn_plan_slice(p, (), target), lib.tn_plan_slice(p, sl)):
+            c = lib.tn_plan_costs_get(s)
+            assert c["largest_intermediate"] == largest_after(net.legs, net.dims, plan.tree, sl) <= target
+            assert c["con_serial"] == cost.con_serial(net.legs, d, plan.tree)
+            lib.tn_plan_free(s)
+        # a leg that is not bound is refused
+        open_like = max(max(l) for l in net.legs) + 1
+        import pytest
+        with pytest.raises(lib.TnError):
+            lib.tn_plan_slice(p, [open_like])
+        lib.tn_plan_free(p)
