@@ -191,6 +191,29 @@ tn_status tn_plan_costs_get(const tn_plan *plan, tn_plan_costs *out);
 tn_status tn_plan_free(tn_plan *plan);
 
 /*
+ * Slicing on top of partitioning (the paper slices on top of its partitions,
+ * Section 5.3.2).  A contraction sums over every bound index (Section 2.2),
+ * so fixing some bound legs value by value and adding the results of the
+ * fixed networks (the slices) gives the same result with smaller
+ * intermediates.  tn_plan_slice makes a new plan of the same network,
+ * partitioning and tree in which the bound legs `labels` (num_labels > 0)
+ * have dimension 1, or, with num_labels == 0, legs chosen greedily (the leg
+ * whose fixing shrinks the current largest intermediate most) until no
+ * intermediate holds more than max_intermediate entries.  tn_contract and
+ * serving on the sliced plan run every slice as one query of one batch and
+ * add the slice results on the device in FP64 (their scales aligned to the
+ * largest): the result is the original network's.  Overrides of tensors
+ * that carry a sliced leg must be host data of the original (unsliced)
+ * shape.  tn_plan_costs_get reports one slice's costs.  The batched calls
+ * refuse a sliced plan (TN_E_INVALID_ARG).  The sliced plan is freed with
+ * tn_plan_free; the original stays valid.
+ * Errors: TN_E_INVALID_ARG (a label that is not a bound leg, no leg to fix,
+ * more than 2^24 slices, an already sliced plan), those of tn_plan_load.
+ */
+tn_status tn_plan_slice(tn_plan *plan, int32_t num_labels, const int64_t *labels,
+                        int64_t max_intermediate, tn_plan **out);
+
+/*
  * Contract the plan's network once (the plain path: one launch sequence per
  * tree vertex, nothing cached).  Leaves listed in `overrides` are replaced
  * for this call only.  Synchronous: returns when `out` (host memory, the
@@ -334,7 +357,11 @@ enum {
                              per launch (the shared subtrees, single queries) */
   TN_KCLASS_TREE_BATCH = 5, /* the same for a batch of queries, every wave
                                taking its own queries through the subtree */
-  TN_KCLASS_COUNT = 6
+  TN_KCLASS_GEMM_SMALL = 6, /* complex GEMM on the register-tiled kernels
+                               (operands not stored as k-tiled planes); the
+                               GEMM class above is the k-tiled matrix-core
+                               kernels with their split-k reduction */
+  TN_KCLASS_COUNT = 7
 };
 typedef struct {
   uint64_t launches;

@@ -33,8 +33,8 @@ STATUS_NAMES = {0: "TN_OK", 1: "TN_PENDING", -1: "TN_E_INVALID_ARG", -2: "TN_E_I
 
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_last_error", "tn_plan_load",
             "tn_plan_costs_get", "tn_plan_free", "tn_contract", "tn_contract_batch", "tn_contract_strided",
-            "tn_contract_strided_noalloc", "tn_serve_submit", "tn_serve_poll", "tn_profile_enable",
-            "tn_profile_read"]
+            "tn_contract_strided_noalloc", "tn_plan_slice", "tn_serve_submit", "tn_serve_poll",
+            "tn_profile_enable", "tn_profile_read"]
 
 
 class TnError(RuntimeError):
@@ -96,6 +96,7 @@ def load():
             "tn_contract_batch": [P, I32, P, P, ctypes.c_int, P, P, U32],
             "tn_contract_strided": [P, I32, I32, P, P, P, ctypes.c_int64, ctypes.c_int, P, U32],
             "tn_contract_strided_noalloc": [P, I32, I32, P, P, P, ctypes.c_int64, U32],
+            "tn_plan_slice": [P, I32, P, ctypes.c_int64, P],
             "tn_serve_submit": [P, P, P],
             "tn_serve_poll": [P, ctypes.c_uint64, P, ctypes.c_int, P, P],
         }
@@ -180,6 +181,16 @@ def tn_plan_costs_get(plan) -> dict:
 
 def tn_plan_free(plan):
     _check(load().tn_plan_free(ctypes.c_void_p(plan)))
+
+
+def tn_plan_slice(plan, labels=(), max_intermediate=0):
+    """A sliced copy of a loaded plan: the given bound legs fixed, or legs
+    chosen until no intermediate exceeds max_intermediate entries."""
+    lab = np.array(list(labels) or [0], dtype=np.int64)
+    out = ctypes.c_void_p()
+    _check(load().tn_plan_slice(ctypes.c_void_p(plan), len(labels), _p(lab), int(max_intermediate),
+                                ctypes.byref(out)))
+    return out.value
 
 
 # -------------------------------------------------------------- contraction
@@ -338,6 +349,11 @@ class Context:
         self.plans.append(p)
         return p
 
+    def slice_plan(self, p, labels=(), max_intermediate=0):
+        s = tn_plan_slice(p, labels, max_intermediate)
+        self.plans.append(s)
+        return s
+
     def free_plan(self, p):
         tn_plan_free(p)
         self.plans.remove(p)
@@ -349,6 +365,7 @@ class Context:
         if self.handle:
             tn_ctx_destroy(self.handle)
             self.handle = None
+        self.arena = None
 
     def __enter__(self):
         return self
@@ -359,7 +376,7 @@ class Context:
 
 # ------------------------------------------------------------------ timing
 
-KCLASS_NAMES = ["stream", "permute", "gemm", "dot", "tree", "tree_batch"]
+KCLASS_NAMES = ["stream", "permute", "gemm", "dot", "tree", "tree_batch", "gemm_small"]
 
 
 class tn_kernel_stats(ctypes.Structure):
