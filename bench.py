@@ -289,9 +289,13 @@ def gemm_phase_leg(lib, reps=3):
                                SAConfig(iterations=8, seed=0))
     plan_s = time.perf_counter() - t0
     ctx = lib.Context(48 << 30)  # the concurrent layout holds every partition's peak at once
+    # what the matrix cores sustain on this device with no memory traffic
+    probe = {"fp32": lib.tn_probe_mfma(ctx.handle, lib.TN_PREC_FP32),
+             "bf16x3": lib.tn_probe_mfma(ctx.handle, lib.TN_PREC_BF16X3)}
     out = {"workload": f"random circuit {c['n']} qubits depth {c['depth']} seed {c['seed']}, "
                        f"{c['cx_per_layer']} CX pairs per layer (p_nn {c['p_nn']}), single-amplitude "
-                       "networks, 8 SA partitions", "planning_s": plan_s}
+                       "networks, 8 SA partitions", "planning_s": plan_s,
+           "mfma_probe_tflops": probe}
     # bf16 MFMA operations per effective complex flop: 4M = 12 products of
     # 2 flops per 8 effective flops, 3M = 9 products
     for name, flags, peak, mul in [("fp32_4m", 0, MFMA_PEAK_TFLOPS["fp32"], 1.0),
@@ -333,9 +337,12 @@ def gemm_phase_leg(lib, reps=3):
         st = lib.tn_profile_read(ctx.handle, reset=True)
         g = st["gemm"]
         eff = g["algo_flops"] / g["seconds"] / 1e12
+        ach = probe["fp32" if name.startswith("fp32") else "bf16x3"]
         out[name] = {"gemm_effective_tflops": eff, "mfma_peak_tflops": peak,
-                     "mfma_util": eff * mul / peak, "gemm_ms_per_amplitude": g["seconds"] / reps * 1e3,
+                     "mfma_util": eff * mul / peak, "mfma_frac_of_achievable": eff * mul / ach,
+                     "gemm_ms_per_amplitude": g["seconds"] / reps * 1e3,
                      "gemm_launches_per_amplitude": g["launches"] // reps,
+                     "gemm_small_ms_per_amplitude": st["gemm_small"]["seconds"] / reps * 1e3,
                      "plain_ms_per_amplitude": amp_ms,
                      "plain_concurrent_ms_per_amplitude": camp_ms,
                      "con_serial_over_con_par": float(costs["con_serial"]) / float(costs["con_par"]),
@@ -708,15 +715,18 @@ def headline_random30(lib, torch, args):
     nl = max(g["launches"], 1)
     kname = GEMM_KERNEL[(prec, form)]
     traffic = traffic_record(kname)
+    ach = lib.tn_probe_mfma(ctx.handle, lib.TN_PREC_FP32 if prec == "fp32" else lib.TN_PREC_BF16X3)
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": traffic, "kernel": kname,
+            "achievable_tflops": ach, "frac_of_achievable": achieved / ach,
             "launches": g["launches"], "avg_launch_us": g["seconds"] / nl * 1e6,
             "algo_flops_per_launch": g["algo_flops"] / nl * mul,
             "algo_bytes_per_launch": g["algo_bytes"] / nl,
             "effective_tflops": eff,
             "note": "achieved = MFMA flops of the form (8 M N K for 4M, 6 M N K for 3M, times 3 or 2.25 "
                     "bf16 products for BF16x3) per launch / event-timed average launch, the split-k "
-                    "reduction of the one split vertex included"}
+                    "reduction of the one split vertex included; achievable_tflops = the rate the matrix "
+                    "cores sustain on this device with no memory traffic (tn_probe_mfma)"}
     perm = stats["permute"]
     perm_gbs = perm["algo_bytes"] / perm["seconds"] / 1e9 if perm["seconds"] else None
     kern_s = sum(v["seconds"] for v in stats.values())

@@ -373,6 +373,20 @@ typedef struct {
 tn_status tn_profile_enable(tn_ctx *ctx, int enable);
 tn_status tn_profile_read(tn_ctx *ctx, tn_kernel_stats *out, int reset);
 
+/*
+ * Measurement support, not an operation of the method: the rate the matrix
+ * cores sustain on this device with no memory traffic (four independent
+ * accumulation chains per wave, four waves per SIMD, one timed launch of
+ * about 40 ms on the context's stream, long enough for the clock to settle
+ * where a long GEMM runs).  precision: TN_PREC_FP32
+ * (v_mfma_f32_32x32x2_f32) or TN_PREC_BF16X3 (v_mfma_f32_32x32x16_bf16);
+ * *tflops receives the achieved TFLOP/s, the ceiling against which a GEMM
+ * kernel's rate can be read beside the nominal peak.  Borrows 1 MiB of the
+ * arena for the call.
+ * Errors: TN_E_INVALID_ARG, TN_E_NOMEM (arena full), TN_E_DEVICE.
+ */
+tn_status tn_probe_mfma(tn_ctx *ctx, uint32_t precision, double *tflops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -120,6 +120,52 @@ tn_status tn_profile_read(tn_ctx *ctx, tn_kernel_stats *out, int reset) {
   return TN_OK;
 }
 
+tn_status tn_probe_mfma(tn_ctx *ctx, uint32_t precision, double *tflops) {
+  if (!ctx || !tflops || (precision != TN_PREC_FP32 && precision != TN_PREC_BF16X3)) {
+    set_error("tn_probe_mfma: NULL argument or precision not TN_PREC_FP32 / TN_PREC_BF16X3");
+    return TN_E_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> g(ctx->exec_mu);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+      cus < 1) {
+    set_error("tn_probe_mfma: compute unit count unavailable");
+    return TN_E_DEVICE;
+  }
+  const int blocks = 4 * cus;  // four blocks of four waves per CU: four waves per SIMD
+  const size_t bytes = Arena::round((size_t)blocks * 256 * sizeof(float));
+  const int64_t off = ctx->arena.alloc(bytes);
+  if (off < 0) {
+    set_error("tn_probe_mfma: arena cannot hold %zu bytes", bytes);
+    return TN_E_NOMEM;
+  }
+  float *buf = (float *)(ctx->arena.base() + off);
+  const int prec = precision == TN_PREC_FP32 ? kPrecFP32 : kPrecBF16x3;
+  // about 40 ms: long enough for the clock to settle where a long GEMM runs
+  const int iters = prec == kPrecFP32 ? 100000 : 200000;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double flops = 0.0;
+  float ms = 0.0f;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch_probe_mfma(ctx->stream, prec, buf, blocks, 64, &flops);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+  if (e == hipSuccess) e = launch_probe_mfma(ctx->stream, prec, buf, blocks, iters, &flops);
+  if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipStreamSynchronize(ctx->stream);
+  ctx->arena.release(off, bytes);
+  if (e != hipSuccess || ms <= 0.0f) {
+    set_error("tn_probe_mfma: %s", hipGetErrorString(e));
+    return TN_E_DEVICE;
+  }
+  *tflops = flops / ((double)ms * 1e9);
+  return TN_OK;
+}
+
 tn_status tn_plan_load(tn_ctx *ctx, const tn_plan_desc *desc, uint32_t flags, tn_plan **out) {
   if (!out) {
     set_error("tn_plan_load: out is NULL");

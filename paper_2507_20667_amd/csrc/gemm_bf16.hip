@@ -110,13 +110,9 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
   const Slot *sa = g.sa + q * g.sabs;
   const Slot *sb = g.sb + q * g.sbbs;
   Slot *sc = g.sc + q * g.scbs;
-  // block -> (k chunk, tile); XCD-aware tile order: blocks land on the 8 XCDs
-  // round-robin, so give each XCD a contiguous run of tiles, M-tiles fastest,
-  // and the tiles that share a B panel run together on one XCD's L2
-  const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
-  const int ks = (int)(blockIdx.x / ntiles);
-  int64_t t = blockIdx.x - (int64_t)ks * ntiles;
-  if (ntiles % 8 == 0 && ntiles >= 64) t = (t % 8) * (ntiles / 8) + t / 8;
+  int ks;
+  int64_t t;
+  gemm_block_tile(g, ks, t);  // XCD-aware block -> (k chunk, tile)
   const int64_t m0 = (t % g.tiles_m) * BT, n0 = (t / g.tiles_m) * BT;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
@@ -322,20 +318,26 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(GemmArgs g) {
 // into LDS (global_load_lds_dwordx4: each lane's 16 bytes land at the wave's
 // LDS segment base + 16 * lane), with no staging registers and no LDS
 // stores.  The stages form a ring of NSLOT slots, filled NSLOT - 1 stages
-// ahead: 4M (four planes, 32 KB a stage) keeps four slots, 3M (six planes,
-// 48 KB a stage) three, within the 160 KB of LDS.  A wave waits for its own
-// loads of a stage (vmcnt, the later stages' loads may stay in flight) and
-// the barrier that follows publishes everyone's.  Past the last stage the
-// requests repeat the last stage into the free slot, so the count of loads
-// in flight, and the wait, are the same in every iteration.  The slots are
-// distinct arrays named statically (the loop is unrolled by the least common
-// multiple of NSLOT and the two fragment sets), which lets the compiler see
-// that a read of one slot does not depend on loads into another.
+// ahead.  A bf16 stage is 48 MFMAs of 32 cycles per wave (4M), a sixth of an
+// FP32 stage's matrix work for the same fragment reads, so the barrier and
+// the fragment reads of a stage are not hidden behind its products when one
+// block holds the CU.  4M (four planes, 32 KB a stage) therefore keeps two
+// slots and one fragment set (64 KB of LDS, at most 256 registers), so that
+// two blocks share a CU and one block's barrier and fragment reads overlap
+// the other's products (measured 1.12-1.21 x on the 30-qubit shapes against
+// one block with four slots and two fragment sets).  3M (six planes, 48 KB a
+// stage) keeps three slots, one block per CU.  A wave waits for its own loads
+// of a stage (vmcnt, the later stages' loads may stay in flight) and the
+// barrier that follows publishes everyone's.  Past the last stage the
+// requests repeat the last stage into the free slot, so the count of loads in
+// flight, and the wait, are the same in every iteration.  The slots are
+// distinct arrays named statically (the loop is unrolled by NSLOT), which
+// lets the compiler see that a read of one slot does not depend on loads
+// into another.
 //
 // LDS layout of a slot: [A planes][B planes], each 128 rows x 32 bytes; row
 // r's 16-byte chunk c sits at position c ^ dswz(r), so the 16 rows read
-// together fall on distinct banks.  While the fragments of stage kt are read,
-// the products of stage kt - 1 that did not run before the barrier run.
+// together fall on distinct banks.
 constexpr int DBK = 16;               // k per stage
 constexpr int DPLANE = BT * DBK;      // bf16 per plane tile (4 KB)
 typedef __attribute__((address_space(3))) void lds_void;
@@ -346,18 +348,15 @@ __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 __host__ __device__ constexpr int dma_wait_imm(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4); }
 
 template <int FORM>
-__global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
+__global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_dma(GemmArgs g) {
   constexpr int NP = FORM == kForm3M ? 6 : 4;        // planes per operand
-  constexpr int NSLOT = FORM == kForm3M ? 3 : 4;     // ring slots
+  constexpr int NSLOT = FORM == kForm3M ? 3 : 2;     // ring slots
   constexpr int NACC = FORM == kForm3M ? 3 : 2;
   constexpr int NPROD = FORM == kForm3M ? 9 : 12;
-  constexpr int SPLIT = FORM == kForm3M ? 3 : 4;     // products of a stage before the next barrier
-  constexpr int UNROLL = NSLOT == 4 ? 4 : 6;         // lcm(NSLOT, 2)
   constexpr int STAGE = 2 * NP * DPLANE;
   // loads of a wave per stage: one 1 KB instruction per plane of A and of B
   constexpr int LOADS = 2 * NP;
-  __shared__ __align__(16) uint16_t ring0[STAGE], ring1[STAGE], ring2[STAGE];
-  __shared__ __align__(16) uint16_t ring3[NSLOT == 4 ? STAGE : 8];
+  __shared__ __align__(16) uint16_t ring0[STAGE], ring1[STAGE], ring2[NSLOT == 3 ? STAGE : 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int q = blockIdx.y;
@@ -366,10 +365,9 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
   const Slot *sa = g.sa + q * g.sabs;
   const Slot *sb = g.sb + q * g.sbbs;
   Slot *sc = g.sc + q * g.scbs;
-  const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
-  const int ks = (int)(blockIdx.x / ntiles);
-  int64_t t = blockIdx.x - (int64_t)ks * ntiles;
-  if (ntiles % 8 == 0 && ntiles >= 64) t = (t % 8) * (ntiles / 8) + t / 8;
+  int ks;
+  int64_t t;
+  gemm_block_tile(g, ks, t);  // XCD-aware block -> (k chunk, tile)
   const int64_t m0 = (t % g.tiles_m) * BT, n0 = (t / g.tiles_m) * BT;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
@@ -401,7 +399,7 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
     boff = (uint32_t)((rb_ * DBK + c * 8) * 2);
   }
   const int64_t nk = (kend - kbeg) / DBK;
-#define TN_RING(S) ((S) == 0 ? ring0 : (S) == 1 ? ring1 : (S) == 2 ? ring2 : ring3)
+#define TN_RING(S) ((S) == 0 ? ring0 : (S) == 1 ? ring1 : ring2)
   auto issue = [&](auto slot, int64_t stg) {
     constexpr int S = decltype(slot)::value;
     uint16_t *rb = TN_RING(S) + wave * (DPLANE / 4);
@@ -436,10 +434,9 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
     }
   };
 #undef TN_RING
-  auto mma = [&](const v4u (&a)[2][NP], const v4u (&b)[2][NP], int p0, int p1) {
+  auto mma = [&](const v4u (&a)[2][NP], const v4u (&b)[2][NP]) {
 #pragma unroll
     for (int pi = 0; pi < NPROD; ++pi) {
-      if (pi < p0 || pi >= p1) continue;
       const int c = FORM == kForm3M ? prod_3m_g(pi, 0) : prod_4m(pi, 0);
       const int ap = FORM == kForm3M ? prod_3m_g(pi, 1) : prod_4m(pi, 1);
       const int bp = FORM == kForm3M ? prod_3m_g(pi, 2) : prod_4m(pi, 2);
@@ -454,80 +451,31 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3_dma(GemmArgs g) {
       }
     }
   };
-  // 4M: two fragment sets (stage kt's are read while stage kt - 1's last
-  // products run); 3M: one set (its six planes and third accumulator set
-  // leave no room for a second), read pair by pair ahead of the products
-  constexpr int NFS = FORM == kForm3M ? 1 : 2;
-  v4u fa0[2][NP], fb0[2][NP], fa1[NFS][2][NP], fb1[NFS][2][NP];
-  // one stage (ring slot S, fragment set F = kt % 2): wait for it (the loads
-  // of the NSLOT - 2 stages after it may stay in flight; every fragment read
-  // done), barrier, request stage kt + NSLOT - 1 into the slot freed by stage
-  // kt - 1, read stage kt's fragments, then the remaining products of stage
-  // kt - 1 and the first SPLIT of stage kt's
-  auto run_stage = [&](auto slot, auto fset, int64_t kt, bool first) {
+  v4u fa[2][NP], fb[2][NP];
+  // one stage (ring slot S): wait for it (the loads of the NSLOT - 2 stages
+  // after it may stay in flight), barrier (every wave has read the fragments
+  // of stage kt - 1), request stage kt + NSLOT - 1 into the slot stage kt - 1
+  // used, read stage kt's fragments pair by pair and run its products
+  auto run_stage = [&](auto slot, int64_t kt) {
     constexpr int S = decltype(slot)::value;
-    constexpr int F = decltype(fset)::value;
     __builtin_amdgcn_s_waitcnt(dma_wait_imm((NSLOT - 2) * LOADS));
     __builtin_amdgcn_s_barrier();
     issue(std::integral_constant<int, (S + NSLOT - 1) % NSLOT>(), kt + NSLOT - 1);
-    if constexpr (NFS == 1) {
-      fread(slot, fa0, fb0);
-      mma(fa0, fb0, 0, NPROD);
-    } else {
-      if (F == 0)
-        fread(slot, fa0, fb0);
-      else
-        fread(slot, fa1[0], fb1[0]);
-      __builtin_amdgcn_sched_barrier(0);
-      if (!first) {
-        if (F == 0)
-          mma(fa1[0], fb1[0], SPLIT, NPROD);
-        else
-          mma(fa0, fb0, SPLIT, NPROD);
-      }
-      if (F == 0)
-        mma(fa0, fb0, 0, SPLIT);
-      else
-        mma(fa1[0], fb1[0], 0, SPLIT);
-    }
+    fread(slot, fa, fb);
+    mma(fa, fb);
     __builtin_amdgcn_sched_barrier(0);
-  };
-  // stage j of an unrolled block that starts at kt = 1 (mod UNROLL): slot
-  // (1 + j) % NSLOT, fragment set (1 + j) % 2
-  auto nth = [&](auto j, int64_t kt) {
-    constexpr int J = decltype(j)::value;
-    run_stage(std::integral_constant<int, (1 + J) % NSLOT>(), std::integral_constant<int, (1 + J) % 2>(),
-              kt, false);
   };
   __builtin_amdgcn_s_waitcnt(0);  // nothing else in flight when the ring starts
   issue(std::integral_constant<int, 0>(), 0);
-  issue(std::integral_constant<int, 1>(), 1);
-  if constexpr (NSLOT == 4) issue(std::integral_constant<int, 2>(), 2);
-  run_stage(std::integral_constant<int, 0>(), std::integral_constant<int, 0>(), 0, true);
-  int64_t kt = 1;
-  for (; kt + UNROLL <= nk; kt += UNROLL) {
-    nth(std::integral_constant<int, 0>(), kt);
-    nth(std::integral_constant<int, 1>(), kt + 1);
-    nth(std::integral_constant<int, 2>(), kt + 2);
-    nth(std::integral_constant<int, 3>(), kt + 3);
-    if constexpr (UNROLL == 6) {
-      nth(std::integral_constant<int, 4>(), kt + 4);
-      nth(std::integral_constant<int, 5>(), kt + 5);
-    }
+  if constexpr (NSLOT == 3) issue(std::integral_constant<int, 1>(), 1);
+  int64_t kt = 0;
+  for (; kt + NSLOT <= nk; kt += NSLOT) {
+    run_stage(std::integral_constant<int, 0>(), kt);
+    run_stage(std::integral_constant<int, 1>(), kt + 1);
+    if constexpr (NSLOT == 3) run_stage(std::integral_constant<int, 2>(), kt + 2);
   }
-  if (kt < nk) nth(std::integral_constant<int, 0>(), kt);
-  if (kt + 1 < nk) nth(std::integral_constant<int, 1>(), kt + 1);
-  if (kt + 2 < nk) nth(std::integral_constant<int, 2>(), kt + 2);
-  if constexpr (UNROLL == 6) {
-    if (kt + 3 < nk) nth(std::integral_constant<int, 3>(), kt + 3);
-    if (kt + 4 < nk) nth(std::integral_constant<int, 4>(), kt + 4);
-  }
-  if constexpr (NFS == 2) {
-    if ((nk - 1) & 1)
-      mma(fa1[0], fb1[0], SPLIT, NPROD);
-    else
-      mma(fa0, fb0, SPLIT, NPROD);
-  }
+  if (kt < nk) run_stage(std::integral_constant<int, 0>(), kt);
+  if (NSLOT == 3 && kt + 1 < nk) run_stage(std::integral_constant<int, 1>(), kt + 1);
   __builtin_amdgcn_s_waitcnt(0);  // no load may still write LDS when the block ends
 
   const bool partial = g.ksplit > 1;

@@ -70,12 +70,9 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
   const Slot *sa = g.sa + q * g.sabs;
   const Slot *sb = g.sb + q * g.sbbs;
   Slot *sc = g.sc + q * g.scbs;
-  // block -> (k chunk, tile); XCD-aware order: each XCD takes a contiguous
-  // run of tiles, M-tiles fastest, so tiles sharing a B panel share an L2
-  const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
-  const int ks = (int)(blockIdx.x / ntiles);
-  int64_t t = blockIdx.x - (int64_t)ks * ntiles;
-  if (ntiles % 8 == 0 && ntiles >= 64) t = (t % 8) * (ntiles / 8) + t / 8;
+  int ks;
+  int64_t t;
+  gemm_block_tile(g, ks, t);  // XCD-aware block -> (k chunk, tile)
   const int64_t m0 = (t % g.tiles_m) * BM, n0 = (t / g.tiles_m) * BN;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;

@@ -428,14 +428,9 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
   const Slot *sa = g.sa + q * g.sabs;
   const Slot *sb = g.sb + q * g.sbbs;
   Slot *sc = g.sc + q * g.scbs;
-  // block -> (k chunk ks, tile)
-  const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
-  const int ks = (int)(blockIdx.x / ntiles);
-  int64_t tile = blockIdx.x - (int64_t)ks * ntiles;
-  // XCD-aware order: blocks land on the 8 XCDs round-robin; each XCD takes a
-  // contiguous run of tiles, M-tiles fastest, so that the tiles sharing a B
-  // panel run together on one XCD's L2
-  if (ntiles % 8 == 0 && ntiles >= 64) tile = (tile % 8) * (ntiles / 8) + tile / 8;
+  int ks;
+  int64_t tile;
+  gemm_block_tile(g, ks, tile);  // XCD-aware block -> (k chunk, tile)
   const int64_t m0 = (tile % g.tiles_m) * BM, n0 = (tile / g.tiles_m) * BN;
   const int64_t kbeg = (int64_t)ks * g.kchunk;
   const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
@@ -847,6 +842,61 @@ hipError_t launch_slice_sum_tensors(hipStream_t st, Operand R, int nq, int64_t n
                                     double *out_log2) {
   hipLaunchKernelGGL(k_slice_sum_tensors, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, R, nq, n, out,
                      out_log2);
+  return hipGetLastError();
+}
+
+}  // namespace tn
+
+namespace tn {
+
+// Matrix-core rate probe: every wave runs four independent accumulation
+// chains of one MFMA instruction with no memory traffic in the loop (one
+// store per lane at the end keeps the chains live), four waves per SIMD.
+// The rate it reaches is what the matrix cores sustain at the clock the
+// device holds under that load, the ceiling a GEMM kernel can approach.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_probe_mfma(float *out, int iters, float seed) {
+  v16f acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[c][v] = 0.0f;
+  const float x = seed + (float)threadIdx.x * 1e-7f;
+  if (PREC == kPrecFP32) {
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, seed, acc[c], 0, 0, 0);
+    }
+  } else {
+    typedef __bf16 v8b __attribute__((ext_vector_type(8)));
+    v8b a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      a[j] = (__bf16)(x + (float)j);
+      b[j] = (__bf16)(seed - (float)j);
+    }
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[c], 0, 0, 0);
+    }
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) s += acc[c][v];
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// `out` holds blocks * 256 floats; flops per launch returned in *flops.
+hipError_t launch_probe_mfma(hipStream_t st, int prec, float *out, int blocks, int iters, double *flops) {
+  if (blocks < 1 || iters < 1) return hipErrorInvalidValue;
+  const double per = prec == kPrecFP32 ? 2.0 * 32 * 32 * 2 : 2.0 * 32 * 32 * 16;
+  *flops = per * 4.0 * iters * (double)blocks * 4.0;
+  if (prec == kPrecFP32)
+    hipLaunchKernelGGL(k_probe_mfma<kPrecFP32>, dim3(blocks), dim3(256), 0, st, out, iters, 1.0f);
+  else
+    hipLaunchKernelGGL(k_probe_mfma<kPrecBF16x3>, dim3(blocks), dim3(256), 0, st, out, iters, 1.0f);
   return hipGetLastError();
 }
 

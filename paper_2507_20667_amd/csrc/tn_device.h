@@ -101,6 +101,25 @@ struct GemmArgs {
   int32_t tile;
 };
 
+// Block -> (k chunk ks, output tile t) of a GEMM launch.  Blocks go to the
+// eight XCDs round robin (block b on XCD b % 8), each XCD with its own L2.
+// Without k chunks each XCD takes a contiguous run of tiles, M-tiles
+// fastest, so the tiles that share a B panel share an L2.  With k chunks the
+// chunk is the fastest index: the blocks of one chunk sit on 8 / gcd(8,
+// chunks) XCDs (one when the chunk count is a multiple of eight), so each
+// chunk's panels are fetched into that many L2s instead of all eight.
+__device__ __forceinline__ void gemm_block_tile(const GemmArgs &g, int &ks, int64_t &t) {
+  const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
+  if (g.ksplit > 1) {
+    ks = (int)(blockIdx.x % (unsigned)g.ksplit);
+    t = (int64_t)(blockIdx.x / (unsigned)g.ksplit);
+  } else {
+    ks = 0;
+    t = blockIdx.x;
+    if (ntiles % 8 == 0 && ntiles >= 64) t = (t % 8) * (ntiles / 8) + t / 8;
+  }
+}
+
 // Output order of a permutation into split planes: ktile.on = 1 writes the
 // row-major [rows][kdim] index o = r * kdim + k at ((k / 16) * rows + r) * 16
 // + k % 16, so that 16 consecutive k of consecutive rows are contiguous (one
@@ -340,6 +359,7 @@ hipError_t launch_slice_sum_tensors(hipStream_t st, Operand R, int nq, int64_t n
                                     double *out_log2);
 // closed-root records of nq queries (query q's at res[q * rbs]) to
 // complex128 values at out[q * stride]
+hipError_t launch_probe_mfma(hipStream_t st, int prec, float *out, int blocks, int iters, double *flops);
 hipError_t launch_results_to_c128(hipStream_t st, const Result *res, int64_t rbs, int nq,
                                   double2 *out, int64_t stride);
 

@@ -34,7 +34,7 @@ STATUS_NAMES = {0: "TN_OK", 1: "TN_PENDING", -1: "TN_E_INVALID_ARG", -2: "TN_E_I
 EXPORTED = ["tn_ctx_create", "tn_ctx_destroy", "tn_last_error", "tn_plan_load",
             "tn_plan_costs_get", "tn_plan_free", "tn_contract", "tn_contract_batch", "tn_contract_strided",
             "tn_contract_strided_noalloc", "tn_plan_slice", "tn_serve_submit", "tn_serve_poll",
-            "tn_profile_enable", "tn_profile_read"]
+            "tn_profile_enable", "tn_profile_read", "tn_probe_mfma"]
 
 
 class TnError(RuntimeError):
@@ -97,6 +97,7 @@ def load():
             "tn_contract_strided": [P, I32, I32, P, P, P, ctypes.c_int64, ctypes.c_int, P, U32],
             "tn_contract_strided_noalloc": [P, I32, I32, P, P, P, ctypes.c_int64, U32],
             "tn_plan_slice": [P, I32, P, ctypes.c_int64, P],
+            "tn_probe_mfma": [P, U32, P],
             "tn_serve_submit": [P, P, P],
             "tn_serve_poll": [P, ctypes.c_uint64, P, ctypes.c_int, P, P],
         }
@@ -382,6 +383,14 @@ KCLASS_NAMES = ["stream", "permute", "gemm", "dot", "tree", "tree_batch", "gemm_
 class tn_kernel_stats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
                 ("algo_bytes", ctypes.c_double), ("algo_flops", ctypes.c_double)]
+
+
+def tn_probe_mfma(ctx, precision) -> float:
+    """TFLOP/s the matrix cores sustain with no memory traffic
+    (TN_PREC_FP32: the FP32 MFMA; TN_PREC_BF16X3: the bf16 MFMA)."""
+    t = ctypes.c_double(0.0)
+    _check(load().tn_probe_mfma(ctypes.c_void_p(ctx), int(precision), ctypes.byref(t)))
+    return t.value
 
 
 def tn_profile_enable(ctx, enable=True):
