@@ -1575,6 +1575,101 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       if (!L.tree_wave) L.lds_perq += rec_q;
     }
   }
+  // The batch kernel's form of each per-query program: a run of whole-vertex
+  // kind 4 steps in which each step's X operand is the step before's result
+  // (a gate chain: one consumer per vertex, so no other step reads the
+  // results inside the run) becomes one kind 5 step whose running tensor
+  // stays in registers.  Its records: 64 per link (lanes past a link's
+  // entries are copies of its first record), w[6] = ns | nc << 8; after the
+  // first link the X terms name the lanes of the link before that hold them
+  // (lane * 4, the ds_bpermute address).  The level kernel, which runs the
+  // same programs for single queries and the shared subtrees, keeps the
+  // steps as they are.  TN_TREE_CHAIN=0 turns chains off.
+  {
+    const bool chain_on = !getenv("TN_TREE_CHAIN") || atoi(getenv("TN_TREE_CHAIN")) != 0;
+    for (size_t hi = 0; hi < hdrs.size(); ++hi) {
+      TreeHdr &h = hdrs[hi];
+      h.wstep0 = h.step0;
+      h.wnsteps = h.nsteps;
+      if (!chain_on || (int)hi < L.n_tree_shared || !L.tree_wave) continue;
+      auto whole = [&](const TreeStep &st) { return st.kind == 4 && st.nss == 1 && st.nc >= 1 && st.nc <= 64; };
+      // entry byte offset -> lane of a whole step's records
+      auto lane_of = [&](const TreeStep &st) {
+        std::map<uint32_t, int> m;
+        for (int l = 0; l < st.nc; ++l) m[lanes[st.tab + l].w[2] & 0xffffu] = l;
+        return m;
+      };
+      auto x_fields = [](const TreeLaneRec &r, int ns, uint32_t *xo) {
+        xo[0] = r.w[0] & 0xffffu;
+        xo[1] = r.w[0] >> 16;
+        xo[2] = r.w[4] & 0xffffu;
+        xo[3] = r.w[4] >> 16;
+        return ns;
+      };
+      // B takes A's result as its X operand, every X term an entry A writes
+      auto links = [&](const TreeStep &A, const TreeStep &B) {
+        if (!whole(A) || !whole(B)) return false;
+        const TreeLaneRec &ra = lanes[A.tab], &rb = lanes[B.tab];
+        if ((rb.w[3] & 0x8000u) || (rb.w[3] & 0x7fffu) != ((ra.w[2] >> 16) & 0x7fffu)) return false;
+        const std::map<uint32_t, int> m = lane_of(A);
+        for (int l = 0; l < B.nc; ++l) {
+          uint32_t xo[4];
+          const int ns = x_fields(lanes[B.tab + l], B.ns, xo);
+          for (int v = 0; v < ns; ++v)
+            if (!m.count(xo[v])) return false;
+        }
+        return true;
+      };
+      std::vector<TreeStep> prog;
+      std::vector<TreeLaneRec> crec;
+      bool any = false;
+      const int kend = h.step0 + h.nsteps;
+      for (int k = h.step0; k < kend;) {
+        int k2 = k;
+        while (k2 + 1 < kend && links(steps[k2], steps[k2 + 1])) ++k2;
+        if (k2 == k) {
+          prog.push_back(steps[k++]);
+          continue;
+        }
+        TreeStep ps;
+        memset(&ps, 0, sizeof(ps));
+        ps.kind = 5;
+        ps.nc = k2 - k + 1;  // links
+        ps.ns = 4;
+        ps.tab = (int32_t)(lanes.size() + crec.size());
+        for (int j = k; j <= k2; ++j) {
+          const TreeStep &st = steps[j];
+          std::map<uint32_t, int> m;
+          if (j > k) m = lane_of(steps[j - 1]);
+          for (int l = 0; l < 64; ++l) {
+            TreeLaneRec r = lanes[st.tab + (l < st.nc ? l : 0)];
+            if (j > k) {
+              uint32_t xo[4];
+              x_fields(r, st.ns, xo);
+              uint32_t a[4] = {0, 0, 0, 0};
+              for (int v = 0; v < st.ns; ++v) a[v] = 4u * (uint32_t)m.at(xo[v]);
+              r.w[0] = a[0] | a[1] << 16;
+              r.w[4] = a[2] | a[3] << 16;
+            }
+            r.w[6] = (uint32_t)st.ns | (uint32_t)st.nc << 8;
+            r.w[7] = 0;
+            crec.push_back(r);
+          }
+        }
+        prog.push_back(ps);
+        any = true;
+        k = k2 + 1;
+      }
+      if (!any) continue;
+      h.wstep0 = (int32_t)steps.size();
+      h.wnsteps = (int32_t)prog.size();
+      steps.insert(steps.end(), prog.begin(), prog.end());
+      lanes.insert(lanes.end(), crec.begin(), crec.end());
+      if (getenv("TN_DEBUG"))
+        fprintf(stderr, "[tn]   subtree root %d: batch program of %d steps (kind 5 chains: %d links)\n",
+                h.root_slot, h.wnsteps, (int)(crec.size() / 64));
+    }
+  }
   if (getenv("TN_DEBUG"))
     for (const TreeHdr &h : hdrs) {
       int gate = 0, packed = 0, nsteps = 0;
@@ -1601,7 +1696,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   // form): power-of-two maps carry their masks (extent - 1) and the kind 2
   // offsets are in bytes, which saves the kernels that arithmetic per step
   for (TreeStep &st : steps) {
-    if (st.kind == 4) continue;
+    if (st.kind == 4 || st.kind == 5) continue;
     if (st.pow2) {
       // the kernels run every segment of a power-of-two map: the unused ones
       // must be all zero (mask, shift and strides)

@@ -202,7 +202,8 @@ struct TreeStep {
   int32_t tab;            // kind 4: the first lane's record in the lane table
 };
 
-// A kind 4 lane's record (32 bytes).  Each address is a 16-bit byte offset in
+// A kind 4 lane's record (32 bytes); kind 5 links use the same layout (see
+// tree_chain in tree.hip).  Each address is a 16-bit byte offset in
 // its operand's LDS region.  w[0]: xa_0 | xa_1 << 16, w[1]: ya_0 | ya_1 << 16,
 // w[2]: c (query region) | csl << 16 | (the step's first entry) << 31,
 // w[3]: asl | (X in the shared region) << 15 | bsl << 16 | (Y in the shared
@@ -246,6 +247,7 @@ struct TreeHdr {
   int32_t sg0, nsg;                  // gather list of the shared intermediates
   int32_t rec0, nrec;                // kind 4 lane records [rec0, rec0 + nrec)
   int32_t rec_lds;                   // the level kernel copies them into LDS
+  int32_t wstep0, wnsteps;           // the batch kernel's program (kind 5 chains)
   int32_t pad;
 };
 

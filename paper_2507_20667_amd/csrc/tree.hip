@@ -650,6 +650,125 @@ __device__ __forceinline__ void tree_lane_whole(uint4 r0, uint4 r1, bool act, in
   if (lane == 0) scl[(wz >> 16) & 0x7fffu] = make_int2(zax + zbx + e, (int)mx);
 }
 
+// Kind 5 (the batch kernel's program only): a chain of whole-vertex gate
+// steps in which every step after the first takes the previous one's result
+// as its X operand.  The running tensor stays in registers (lane l holds the
+// entry its record names); a link reads its X terms from the lanes that hold
+// them (ds_bpermute, the source lanes prepared on the host), its Y terms (the
+// gate's entries) from LDS, and its X scale record from the link before (in
+// scalar registers).  Only the last link writes its result and scale record
+// to LDS: no other step reads the others (each vertex has one consumer).
+// Term order, scaling and the wave-wide max are those of the kind 4 steps it
+// replaces, so the results are the same bit for bit.  Link j's records are
+// the 64 at rec + 64 j: w[0], w[4] the X terms (link 0: byte offsets in the
+// X region; later links: source lane * 4), w[1], w[5] the Y byte offsets,
+// w[2], w[3] as in kind 4, w[6] = ns | nc << 8 (lanes past nc are padding
+// with valid offsets, inactive in the result).
+template <int NS, bool FIRST, bool LAST>
+__device__ __forceinline__ void chain_link(uint4 a0, uint4 a1, int lane, float2 *pq, const float2 *shr,
+                                           int2 *scl, float &vre, float &vim, int &zx, int &zy) {
+  const uint32_t w3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)a0.w);
+  const uint32_t wz = (uint32_t)__builtin_amdgcn_readfirstlane((int)a0.z);
+  const int nc = (__builtin_amdgcn_readfirstlane((int)a1.z) >> 8) & 0xff;
+  const bool act = lane < nc;
+  const int2 zb = scl[(w3 >> 16) & 0x7fffu];
+  int2 za = make_int2(0, 0);
+  if (FIRST) za = scl[w3 & 0x7fffu];
+  const char *yb = (const char *)((w3 >> 31) ? shr : pq);
+  auto at = [](const char *base, uint32_t off) -> float2 { return *(const float2 *)(base + off); };
+  float2 x[NS], y[NS];
+  y[0] = at(yb, a0.y & 0xffffu);
+  if (NS >= 2) y[1] = at(yb, a0.y >> 16);
+  if (NS == 4) {
+    y[2] = at(yb, a1.y & 0xffffu);
+    y[3] = at(yb, a1.y >> 16);
+  }
+  if (FIRST) {
+    const char *xb = (const char *)((w3 & 0x8000u) ? shr : pq);
+    x[0] = at(xb, a0.x & 0xffffu);
+    if (NS >= 2) x[1] = at(xb, a0.x >> 16);
+    if (NS == 4) {
+      x[2] = at(xb, a1.x & 0xffffu);
+      x[3] = at(xb, a1.x >> 16);
+    }
+  } else {
+    const int ir = __float_as_int(vre), ii = __float_as_int(vim);
+    auto from = [&](uint32_t addr) {
+      return make_float2(__int_as_float(__builtin_amdgcn_ds_bpermute((int)addr, ir)),
+                         __int_as_float(__builtin_amdgcn_ds_bpermute((int)addr, ii)));
+    };
+    x[0] = from(a0.x & 0xffffu);
+    if (NS >= 2) x[1] = from(a0.x >> 16);
+    if (NS == 4) {
+      x[2] = from(a1.x & 0xffffu);
+      x[3] = from(a1.x >> 16);
+    }
+  }
+  if (FIRST) {
+    zx = __builtin_amdgcn_readfirstlane(za.x);
+    zy = __builtin_amdgcn_readfirstlane(za.y);
+  }
+  const int zbx = __builtin_amdgcn_readfirstlane(zb.x), zby = __builtin_amdgcn_readfirstlane(zb.y);
+  const int e = tn_scale_exp((uint32_t)zy) + tn_scale_exp((uint32_t)zby);
+  const float f = ldexpf(1.0f, -e);
+  float re = 0.f, im = 0.f;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    re = fmaf(x[s].x, y[s].x, re);
+    re = fmaf(-x[s].y, y[s].y, re);
+    im = fmaf(x[s].x, y[s].y, im);
+    im = fmaf(x[s].y, y[s].x, im);
+  }
+  re *= f;
+  im *= f;
+  const float m = act ? fmaxf(fabsf(re), fabsf(im)) : 0.f;
+  const unsigned mx = wave_max_u32(__float_as_uint(m));
+  zx = zx + zbx + e;
+  zy = (int)mx;
+  if (LAST) {
+    if (act) *(float2 *)((char *)pq + (a0.z & 0xffffu)) = make_float2(re, im);
+    if (lane == 0) scl[(wz >> 16) & 0x7fffu] = make_int2(zx, zy);
+  }
+  vre = re;
+  vim = im;
+}
+
+template <bool FIRST, bool LAST>
+__device__ __forceinline__ void chain_link_ns(int ns, uint4 a0, uint4 a1, int lane, float2 *pq,
+                                              const float2 *shr, int2 *scl, float &vre, float &vim, int &zx,
+                                              int &zy) {
+  if (ns == 1)
+    chain_link<1, FIRST, LAST>(a0, a1, lane, pq, shr, scl, vre, vim, zx, zy);
+  else if (ns == 2)
+    chain_link<2, FIRST, LAST>(a0, a1, lane, pq, shr, scl, vre, vim, zx, zy);
+  else
+    chain_link<4, FIRST, LAST>(a0, a1, lane, pq, shr, scl, vre, vim, zx, zy);
+}
+
+// A whole kind 5 step: `nlinks` links, link 0's record prefetched in r0, r1;
+// each later link's record is loaded while the link before runs.
+__device__ __forceinline__ void tree_chain(const TreeLaneRec *rec, int nlinks, uint4 r0, uint4 r1, int lane,
+                                           float2 *pq, const float2 *shr, int2 *scl) {
+  float vre = 0.f, vim = 0.f;
+  int zx = 0, zy = 0;
+  uint4 n0 = r0, n1 = r1;
+  for (int j = 0; j < nlinks; ++j) {
+    const uint4 a0 = n0, a1 = n1;
+    if (j + 1 < nlinks) {
+      const uint4 *nx = (const uint4 *)(rec + (j + 1) * 64 + lane);
+      n0 = nx[0];
+      n1 = nx[1];
+    }
+    const int ns = __builtin_amdgcn_readfirstlane((int)a1.z) & 0xff;
+    if (j == 0)
+      chain_link_ns<true, false>(ns, a0, a1, lane, pq, shr, scl, vre, vim, zx, zy);
+    else if (j + 1 < nlinks)
+      chain_link_ns<false, false>(ns, a0, a1, lane, pq, shr, scl, vre, vim, zx, zy);
+    else
+      chain_link_ns<false, true>(ns, a0, a1, lane, pq, shr, scl, vre, vim, zx, zy);
+  }
+}
+
 template <int NS>
 __device__ __forceinline__ void tree_lane_step(const TreeLaneRec *rec, int lane, int nl, float2 *pq,
                                                const float2 *shr, int2 *scl) {
@@ -974,8 +1093,8 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
   {
     const TreeHdr h = *hp;
     nscale = h.nscale;
-    nsteps = h.nsteps;
-    step0 = h.step0;
+    nsteps = h.wnsteps;  // this kernel's form of the program (with kind 5 chains)
+    step0 = h.wstep0;
     final_dot = h.final_dot;
     // LDS: [scales: qw * nscale int2][shared region][qw per-query regions]
     scl = (int2 *)tree_lds;
@@ -1003,7 +1122,11 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
   uint4 n0 = make_uint4(0u, 0u, 0u, 0u), n1 = n0;
   auto fetch = [&](int k) {
     const CStep S = prog + k;
-    if (S->kind == 4 && lane < S->nc) {
+    if (S->kind == 5) {  // link 0 of a chain (64 records a link)
+      const uint4 *r = (const uint4 *)(t.lanes + S->tab + lane);
+      n0 = r[0];
+      n1 = r[1];
+    } else if (S->kind == 4 && lane < S->nc) {
       const uint4 *r = (const uint4 *)(t.lanes + S->tab + lane);
       n0 = r[0];
       if (S->ns == 4) n1 = r[1];
@@ -1014,7 +1137,9 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
     const CStep S = prog + k;
     const uint4 c0 = n0, c1 = n1;
     if (k + 1 < nloop) fetch(k + 1);
-    if (S->kind == 4) {
+    if (S->kind == 5) {
+      tree_chain(t.lanes + S->tab, S->nc, c0, c1, lane, wpq, shr, wscl);
+    } else if (S->kind == 4) {
       if (S->nss) {  // one whole step: the whole wave, one scale store
         const bool act = lane < S->nc;
         if (S->ns == 1)

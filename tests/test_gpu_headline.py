@@ -152,3 +152,27 @@ def test_headline_shape_batch_descriptors(ctx):
     assert _err(outs, ref, n).max() < TOL
     assert np.max(np.abs(outs - got)) <= 1e-6 * 2.0 ** (-n / 2)
     ctx.free_plan(p)
+
+
+def test_gate_chains_bit_identical(ctx, monkeypatch):
+    """The batch kernel runs the brickwork's 31-gate chain as one kind 5 step
+    (the running tensor in registers, X terms exchanged between lanes); with
+    TN_TREE_CHAIN=0 it runs the same gates as separate kind 4 steps through
+    LDS.  Both give the same 4096 results bit for bit, and the state vector's
+    within the FP32 bound."""
+    import torch
+    w = brickwork20()
+    circ, net, plan, n = w.circ, w.net, w.plan, w.circ.n
+    xs = random_bitstrings(n, Q, 1002)
+    dev = _device_basis(torch, n, xs)
+    p = ctx.load_network(net, plan.partition_of, w.num_partitions, plan.tree)
+    chained, _ = _strided_pinned(torch, p, net, n, dev)
+    ctx.free_plan(p)
+    monkeypatch.setenv("TN_TREE_CHAIN", "0")
+    p = ctx.load_network(net, plan.partition_of, w.num_partitions, plan.tree)
+    plain, _ = _strided_pinned(torch, p, net, n, dev)
+    ctx.free_plan(p)
+    assert np.array_equal(chained, plain)
+    psi = oracle.statevector(circ)
+    ref = psi[np.array(xs, dtype=np.int64)]
+    assert _err(chained, ref, n).max() < TOL
