@@ -4,14 +4,15 @@
 // two float planes (re, im), divided by 2^e of the operand's scale record and
 // k-tiled: row r, k sits at ((k / 16) * rows + r) * 16 + k % 16, so that one
 // 16-deep stage of a 128-row tile is a contiguous 8 KB block of each plane.
-// Stages stream straight from global memory into a four-slot LDS ring
-// (global_load_lds_dwordx4, three stages ahead, no staging registers); the
-// wait for a stage is a vmcnt on the wave's own loads followed by a barrier.
-// Past the last stage the requests repeat the last stage into the free slot,
-// so the number of loads in flight, and the wait, never change.  The slots are
-// distinct arrays named statically (the loop is unrolled by four), which lets
-// the compiler see that a read of one slot does not wait on loads into
-// another.
+// Stages stream straight from global memory into a ring of LDS slots
+// (global_load_lds_dwordx4, no staging registers): two slots, one stage
+// ahead, when two blocks share a CU (see TWO below), else four slots, three
+// stages ahead.  The wait for a stage is a vmcnt on the wave's own loads
+// followed by a barrier.  Past the last stage the requests repeat the last
+// stage into the free slot, so the number of loads in flight, and the wait,
+// never change.  The slots are distinct arrays named statically (the loop is
+// unrolled by the slot count), which lets the compiler see that a read of one
+// slot does not wait on loads into another.
 //
 // Block = 4 waves in a 2 x 2 grid over a 128 x 128 output tile, each wave
 // 64 x 64 outputs as 2 x 2 MFMA tiles.  For that instruction lane l supplies
@@ -20,15 +21,12 @@
 // gives lane half h the k value 8h + s (A and B alike, so the sum over k is
 // unchanged): a lane's eight k of a row are two 16-byte LDS reads.  Rows are
 // 64 bytes; row r's chunk c sits at position c ^ swz(r), so the rows one LDS
-// access touches fall on distinct banks.  A stage is 128 MFMAs per wave (4M),
-// so the fragments of stage kt are read while stage kt-1 multiplies.
+// access touches fall on distinct banks.  A stage is 128 MFMAs per wave (4M).
 // FORM = 4M: Re = ArBr - AiBi, Im = ArBi + AiBr (four products per complex
 // one).  FORM = 3M (Gauss): T1 = ArBr, T2 = AiBi, T3 = (Ar + Ai)(Br + Bi),
 // Re = T1 - T2, Im = T3 - T1 - T2; the sums are formed in registers from the
 // fragments (one add per value), so the planes and the LDS traffic are the
-// same as 4M's and the MFMA work is three quarters of it.  The third
-// accumulator set lives beside the two fragment sets (the kernel runs one
-// wave per SIMD, with the accumulation registers).
+// same as 4M's and the MFMA work is three quarters of it.
 #include <type_traits>
 
 #include "tn_device.h"
@@ -53,15 +51,28 @@ __device__ __forceinline__ int fswz(int r) {
 // WMW = waves along M (the four waves form a WMW x 4/WMW grid, 64 x 64
 // outputs each): 2 gives a 128 x 128 tile, 1 a 64 x 256 tile (for M <= 64),
 // 4 a 256 x 64 tile (for N <= 64).
+//
+// TWO: two blocks share a CU.  The ring then has two slots (64 KB of LDS for
+// the 128 x 128 tile) and a wave reads a stage's fragments in two halves of
+// eight k (32 fragment registers), so that a block fits in 256 registers;
+// one block's barrier and fragment reads overlap the other's products
+// (1.04-1.14 x on the 30-qubit shapes against one block with four slots).
+// The 3M form of the 64 x 256 and 256 x 64 tiles would not fit and keeps one
+// block per CU with the four-slot ring.
 template <int FORM, int WMW>
-__global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
+__device__ __forceinline__ constexpr bool planes_two() { return FORM == kForm4M || WMW == 2; }
+
+template <int FORM, int WMW>
+__global__ __launch_bounds__(256, (FORM == kForm4M || WMW == 2) ? 2 : 1) void k_cgemm_f32_planes(GemmArgs g) {
+  constexpr bool TWO = planes_two<FORM, WMW>();
+  constexpr int NSLOT = TWO ? 2 : 4;
   constexpr int NACC = FORM == kForm3M ? 3 : 2;
   constexpr int WNW = 4 / WMW;
   constexpr int BM = 64 * WMW, BN = 64 * WNW;          // tile rows of A and of B
   constexpr int APL = BM * FBK, BPL = BN * FBK;        // floats per plane tile
   constexpr int FSTAGE = 2 * (APL + BPL);              // A re, A im, B re, B im
   constexpr int JA = BM / 64, JB = BN / 64;            // load instructions per wave and plane
-  __shared__ __align__(16) float ring0[FSTAGE], ring1[FSTAGE], ring2[FSTAGE], ring3[FSTAGE];
+  __shared__ __align__(16) float ring0[FSTAGE], ring1[FSTAGE], ring2[TWO ? 4 : FSTAGE], ring3[TWO ? 4 : FSTAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WNW, wn = wave % WNW;
   const int q = blockIdx.y;
@@ -135,37 +146,33 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
   // and 2h + 1) from each plane
   const int fr = lane & 31, fh = lane >> 5;
   const int fp0 = ((2 * fh) ^ fswz(fr)) * 4, fp1 = ((2 * fh + 1) ^ fswz(fr)) * 4;
-  auto fread = [&](auto slot, v4f (&a)[2][2][2], v4f (&b)[2][2][2]) {
+  auto fread = [&](auto slot, int h, v4f (&a)[2][2], v4f (&b)[2][2]) {
     constexpr int S = decltype(slot)::value;
     const float *rb = TN_FRING(S);
+    const int fp = h ? fp1 : fp0;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int pl = 0; pl < 2; ++pl) {
-        const float *row = rb + pl * APL + (wm * 64 + mb * 32 + fr) * FBK;
-        a[mb][pl][0] = *(const v4f *)(row + fp0);
-        a[mb][pl][1] = *(const v4f *)(row + fp1);
-      }
+      for (int pl = 0; pl < 2; ++pl)
+        a[mb][pl] = *(const v4f *)(rb + pl * APL + (wm * 64 + mb * 32 + fr) * FBK + fp);
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int pl = 0; pl < 2; ++pl) {
-        const float *row = rb + 2 * APL + pl * BPL + (wn * 64 + nb * 32 + fr) * FBK;
-        b[nb][pl][0] = *(const v4f *)(row + fp0);
-        b[nb][pl][1] = *(const v4f *)(row + fp1);
-      }
+      for (int pl = 0; pl < 2; ++pl)
+        b[nb][pl] = *(const v4f *)(rb + 2 * APL + pl * BPL + (wn * 64 + nb * 32 + fr) * FBK + fp);
   };
 #undef TN_FRING
-  auto mma = [&](const v4f (&a)[2][2][2], const v4f (&b)[2][2][2]) {
+  // the four k of one fragment half (k 8h + 4c + s of lane half c), in order
+  auto mma = [&](const v4f (&a)[2][2], const v4f (&b)[2][2]) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < 4; ++s) {
       float ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
-        ar[x] = a[x][0][s >> 2][s & 3];
-        ai[x] = a[x][1][s >> 2][s & 3];
-        br[x] = b[x][0][s >> 2][s & 3];
-        bi[x] = b[x][1][s >> 2][s & 3];
+        ar[x] = a[x][0][s];
+        ai[x] = a[x][1][s];
+        br[x] = b[x][0][s];
+        bi[x] = b[x][1][s];
       }
       if (FORM == kForm4M) {
 #pragma unroll
@@ -213,37 +220,27 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
       }
     }
   };
-  // 4M: two fragment sets (stage kt's are read while stage kt - 1's
-  // multiply); 3M: one set, whose third accumulator set takes the registers
-  // of the second (a stage is 96 MFMAs of 64 cycles per wave, so the LDS
-  // latency it exposes is small)
-  constexpr int NFS = FORM == kForm3M ? 1 : 2;
-  v4f fa0[2][2][2], fb0[2][2][2], fa1[NFS][2][2][2], fb1[NFS][2][2][2];
-  // one stage: wait for it (two stages of loads may stay in flight, every
-  // fragment read done), barrier, request stage kt + 3 into the slot stage
-  // kt - 1 used, read stage kt's fragments, multiply stage kt - 1's (4M) or
-  // stage kt's (3M)
-  auto stage = [&](auto slot, int64_t kt, bool first) {
+  // one stage: wait for it (the loads of the NSLOT - 2 stages after it may
+  // stay in flight), barrier, request stage kt + NSLOT - 1 into the slot
+  // stage kt - 1 used, then the stage's products.  TWO: the two halves of the
+  // stage's k one after the other (read, multiply); otherwise both halves'
+  // fragments first (one set of 64 registers), then the products.
+  v4f fa[2][2], fb[2][2], ga[2][2], gb[2][2];
+  auto stage = [&](auto slot, int64_t kt) {
     constexpr int S = decltype(slot)::value;
-    // this wave's loads of the two stages after this one may stay in flight
-    __builtin_amdgcn_s_waitcnt(f_wait_imm(2 * 2 * (JA + JB)));
+    __builtin_amdgcn_s_waitcnt(f_wait_imm((NSLOT - 2) * 2 * (JA + JB)));
     __builtin_amdgcn_s_barrier();
-    issue(std::integral_constant<int, (S + 3) % 4>(), kt + 3);
-    if constexpr (FORM == kForm3M) {
-      fread(slot, fa0, fb0);
-      mma(fa0, fb0);
+    issue(std::integral_constant<int, (S + NSLOT - 1) % NSLOT>(), kt + NSLOT - 1);
+    if constexpr (TWO) {
+      fread(slot, 0, fa, fb);
+      mma(fa, fb);
+      fread(slot, 1, fa, fb);
+      mma(fa, fb);
     } else {
-      if (S % 2 == 0)
-        fread(slot, fa0, fb0);
-      else
-        fread(slot, fa1[0], fb1[0]);
-      __builtin_amdgcn_sched_barrier(0);
-      if (!first) {
-        if (S % 2 == 0)
-          mma(fa1[0], fb1[0]);
-        else
-          mma(fa0, fb0);
-      }
+      fread(slot, 0, fa, fb);
+      fread(slot, 1, ga, gb);
+      mma(fa, fb);
+      mma(ga, gb);
     }
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -253,25 +250,22 @@ __global__ __launch_bounds__(256) void k_cgemm_f32_planes(GemmArgs g) {
   const std::integral_constant<int, 3> s3;
   __builtin_amdgcn_s_waitcnt(0);  // nothing else in flight when the ring starts
   issue(s0, 0);
-  issue(s1, 1);
-  issue(s2, 2);
-  stage(s0, 0, true);
-  int64_t kt = 1;
-  for (; kt + 4 <= nk; kt += 4) {
-    stage(s1, kt, false);
-    stage(s2, kt + 1, false);
-    stage(s3, kt + 2, false);
-    stage(s0, kt + 3, false);
+  if constexpr (NSLOT == 4) {
+    issue(s1, 1);
+    issue(s2, 2);
   }
-  if (kt < nk) stage(s1, kt, false);
-  if (kt + 1 < nk) stage(s2, kt + 1, false);
-  if (kt + 2 < nk) stage(s3, kt + 2, false);
-  if constexpr (FORM == kForm4M) {
-    if ((nk - 1) & 1)
-      mma(fa1[0], fb1[0]);
-    else
-      mma(fa0, fb0);
+  int64_t kt = 0;
+  for (; kt + NSLOT <= nk; kt += NSLOT) {
+    stage(s0, kt);
+    stage(s1, kt + 1);
+    if constexpr (NSLOT == 4) {
+      stage(s2, kt + 2);
+      stage(s3, kt + 3);
+    }
   }
+  if (kt < nk) stage(s0, kt);
+  if (NSLOT == 4 && kt + 1 < nk) stage(s1, kt + 1);
+  if (NSLOT == 4 && kt + 2 < nk) stage(s2, kt + 2);
   __builtin_amdgcn_s_waitcnt(0);  // no load may still write LDS when the block ends
 
   const bool partial = g.ksplit > 1;
