@@ -289,13 +289,17 @@ def gemm_phase_leg(lib, reps=3):
                                SAConfig(iterations=8, seed=0))
     plan_s = time.perf_counter() - t0
     ctx = lib.Context(48 << 30)  # the concurrent layout holds every partition's peak at once
-    # what the matrix cores sustain on this device with no memory traffic
+    # what the matrix cores sustain on this device with no memory traffic, on
+    # operands that change from product to product (the GEMM's ceiling) and
+    # on constant ones (the top clock)
     probe = {"fp32": lib.tn_probe_mfma(ctx.handle, lib.TN_PREC_FP32),
              "bf16x3": lib.tn_probe_mfma(ctx.handle, lib.TN_PREC_BF16X3)}
+    probe_const = {"fp32": lib.tn_probe_mfma(ctx.handle, lib.TN_PREC_FP32 | lib.TN_PROBE_CONST_OPERANDS),
+                   "bf16x3": lib.tn_probe_mfma(ctx.handle, lib.TN_PREC_BF16X3 | lib.TN_PROBE_CONST_OPERANDS)}
     out = {"workload": f"random circuit {c['n']} qubits depth {c['depth']} seed {c['seed']}, "
                        f"{c['cx_per_layer']} CX pairs per layer (p_nn {c['p_nn']}), single-amplitude "
                        "networks, 8 SA partitions", "planning_s": plan_s,
-           "mfma_probe_tflops": probe}
+           "mfma_probe_tflops": probe, "mfma_probe_const_operands_tflops": probe_const}
     # bf16 MFMA operations per effective complex flop: 4M = 12 products of
     # 2 flops per 8 effective flops, 3M = 9 products
     for name, flags, peak, mul in [("fp32_4m", 0, MFMA_PEAK_TFLOPS["fp32"], 1.0),
@@ -726,7 +730,8 @@ def headline_random30(lib, torch, args):
             "note": "achieved = MFMA flops of the form (8 M N K for 4M, 6 M N K for 3M, times 3 or 2.25 "
                     "bf16 products for BF16x3) per launch / event-timed average launch, the split-k "
                     "reduction of the one split vertex included; achievable_tflops = the rate the matrix "
-                    "cores sustain on this device with no memory traffic (tn_probe_mfma)"}
+                    "cores sustain on this device with no memory traffic on operands that change from "
+                    "product to product (tn_probe_mfma)"}
     perm = stats["permute"]
     perm_gbs = perm["algo_bytes"] / perm["seconds"] / 1e9 if perm["seconds"] else None
     kern_s = sum(v["seconds"] for v in stats.values())

@@ -379,12 +379,18 @@ tn_status tn_profile_read(tn_ctx *ctx, tn_kernel_stats *out, int reset);
  * accumulation chains per wave, four waves per SIMD, one timed launch of
  * about 40 ms on the context's stream, long enough for the clock to settle
  * where a long GEMM runs).  precision: TN_PREC_FP32
- * (v_mfma_f32_32x32x2_f32) or TN_PREC_BF16X3 (v_mfma_f32_32x32x16_bf16);
- * *tflops receives the achieved TFLOP/s, the ceiling against which a GEMM
- * kernel's rate can be read beside the nominal peak.  Borrows 1 MiB of the
- * arena for the call.
+ * (v_mfma_f32_32x32x2_f32) or TN_PREC_BF16X3 (v_mfma_f32_32x32x16_bf16),
+ * optionally or-ed with TN_PROBE_CONST_OPERANDS.  By default each product
+ * takes operands of pseudo-random values that change from one product to
+ * the next, as a GEMM on real data does: the matrix cores then draw more
+ * power and the device may lower its clock, so this rate, not the nominal
+ * peak, is the ceiling a GEMM kernel can approach.  With
+ * TN_PROBE_CONST_OPERANDS every product repeats the same operands (little
+ * switching, the top clock).  *tflops receives the achieved TFLOP/s.
+ * Borrows 1 MiB of the arena for the call.
  * Errors: TN_E_INVALID_ARG, TN_E_NOMEM (arena full), TN_E_DEVICE.
  */
+#define TN_PROBE_CONST_OPERANDS (1u << 8)
 tn_status tn_probe_mfma(tn_ctx *ctx, uint32_t precision, double *tflops);
 
 #ifdef __cplusplus

@@ -121,10 +121,12 @@ tn_status tn_profile_read(tn_ctx *ctx, tn_kernel_stats *out, int reset) {
 }
 
 tn_status tn_probe_mfma(tn_ctx *ctx, uint32_t precision, double *tflops) {
-  if (!ctx || !tflops || (precision != TN_PREC_FP32 && precision != TN_PREC_BF16X3)) {
+  const uint32_t p = precision & ~(uint32_t)TN_PROBE_CONST_OPERANDS;
+  if (!ctx || !tflops || (p != TN_PREC_FP32 && p != TN_PREC_BF16X3)) {
     set_error("tn_probe_mfma: NULL argument or precision not TN_PREC_FP32 / TN_PREC_BF16X3");
     return TN_E_INVALID_ARG;
   }
+  const bool random = (precision & TN_PROBE_CONST_OPERANDS) == 0;
   std::lock_guard<std::mutex> g(ctx->exec_mu);
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
@@ -140,7 +142,7 @@ tn_status tn_probe_mfma(tn_ctx *ctx, uint32_t precision, double *tflops) {
     return TN_E_NOMEM;
   }
   float *buf = (float *)(ctx->arena.base() + off);
-  const int prec = precision == TN_PREC_FP32 ? kPrecFP32 : kPrecBF16x3;
+  const int prec = p == TN_PREC_FP32 ? kPrecFP32 : kPrecBF16x3;
   // about 40 ms: long enough for the clock to settle where a long GEMM runs
   const int iters = prec == kPrecFP32 ? 100000 : 200000;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -148,9 +150,9 @@ tn_status tn_probe_mfma(tn_ctx *ctx, uint32_t precision, double *tflops) {
   float ms = 0.0f;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e == hipSuccess) e = launch_probe_mfma(ctx->stream, prec, buf, blocks, 64, &flops);  // warm-up
+  if (e == hipSuccess) e = launch_probe_mfma(ctx->stream, prec, random, buf, blocks, 64, &flops);  // warm-up
   if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
-  if (e == hipSuccess) e = launch_probe_mfma(ctx->stream, prec, buf, blocks, iters, &flops);
+  if (e == hipSuccess) e = launch_probe_mfma(ctx->stream, prec, random, buf, blocks, iters, &flops);
   if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);

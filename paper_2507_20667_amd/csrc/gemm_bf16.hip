@@ -512,11 +512,240 @@ __global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_d
   }
 }
 
+// ------------------------------------------------ two wave groups (4M form)
+// One block of eight waves owns a 256 x 128 output tile (WIDE_A: 256 rows of
+// A) or 128 x 256 (256 rows of B), as two groups of four waves, each group a
+// 128 x 128 half laid out like the four-wave kernel above.  Waves w and w + 4
+// share a SIMD, and the two groups take turns: while one group's waves run
+// the 48 products of a stage, the other group's waves read the next
+// fragments, and a barrier between the halves keeps them in opposite phases,
+// so the matrix pipe of each SIMD has one wave feeding it at every moment
+// (with one group per block, or two independent blocks per CU, the fragment
+// reads and the barrier of a stage left the pipe idle a third of the time).
+// A stage of both operands is 48 KB (4 planes x 384 rows x 16 k); the ring
+// has three slots, filled two stages ahead, which spans four half-stages of
+// products for the load latency.
+//
+// Iteration j, slot j % 3: wait for this wave's loads of stage j (stage
+// j + 1's may stay in flight; the wait also drains this wave's LDS reads);
+// barrier (stage j is in LDS, every wave is done with stage j - 1's slot);
+// request stage j + 2 into that slot; group 0 reads stage j while group 1
+// multiplies stage j - 1; barrier; group 0 multiplies stage j while group 1
+// reads stage j.  After the last iteration group 1 multiplies the last stage.
+// Each wave issues the same number of loads per stage: every plane of the
+// 256-row operand at rows 32 w .. 32 w + 31, and half the planes of the
+// 128-row operand at rows 32 (w % 4) ...
+constexpr int PPW = 256;  // rows of the wide operand's tile
+
+int gemm_bf16_tile_m(int tile) { return tile == 2 ? PPW : BT; }
+int gemm_bf16_tile_n(int tile) { return tile == 1 ? PPW : BT; }
+
+template <bool WIDE_A>
+__global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_pp(GemmArgs g) {
+  constexpr int NP = 4, NACC = 2, NPROD = 12;
+  constexpr int RA = WIDE_A ? PPW : BT, RB = WIDE_A ? BT : PPW;
+  constexpr int DPA = RA * DBK, DPB = RB * DBK;  // bf16 per plane tile
+  constexpr int STAGE = NP * (DPA + DPB);
+  constexpr int LW = NP + NP / 2;                // loads of a wave per stage
+  __shared__ __align__(16) uint16_t ring0[STAGE], ring1[STAGE], ring2[STAGE];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int grp = wave >> 2, wm = (wave >> 1) & 1, wn = wave & 1;
+  const int q = blockIdx.y;
+  const uint16_t *A = (const uint16_t *)g.A + q * g.abs;
+  const uint16_t *B = (const uint16_t *)g.B + q * g.bbs;
+  const Slot *sa = g.sa + q * g.sabs;
+  const Slot *sb = g.sb + q * g.sbbs;
+  Slot *sc = g.sc + q * g.scbs;
+  int ks;
+  int64_t t;
+  gemm_block_tile(g, ks, t);  // XCD-aware block -> (k chunk, tile)
+  const int64_t m0 = (t % g.tiles_m) * RA, n0 = (t / g.tiles_m) * RB;
+  const int64_t kbeg = (int64_t)ks * g.kchunk;
+  const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
+  const int ea = tn_scale_exp(sa->maxbits), eb = tn_scale_exp(sb->maxbits);
+  if (blockIdx.x == 0 && tid == 0) sc->log2s = sa->log2s + sb->log2s + (double)(ea + eb);
+
+  v16f_b acc[2][2][NACC];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < NACC; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[a][b][c][v] = 0.0f;
+
+  // this wave's loads: rows ra0 / rb0 .. + 31 of the planes from pa0 / pb0
+  // on (all of the wide operand's, half of the other's); this lane's row is
+  // lane / 2 of those, logical chunk (lane % 2) ^ dswz(row), rows past M or
+  // N clamped to the last one
+  const int ra0 = WIDE_A ? 32 * wave : 32 * (wave & 3), rb0 = WIDE_A ? 32 * (wave & 3) : 32 * wave;
+  const int pa0 = WIDE_A ? 0 : (wave >> 2) * (NP / 2), pb0 = WIDE_A ? (wave >> 2) * (NP / 2) : 0;
+  constexpr int NLA = WIDE_A ? NP : NP / 2, NLB = WIDE_A ? NP / 2 : NP;
+  const uint8_t *abase = (const uint8_t *)(A + m0 * DBK);
+  const uint8_t *bbase = (const uint8_t *)(B + n0 * DBK);
+  uint32_t aoff, boff;  // per lane, below 16 KB; the rest of an address is uniform
+  {
+    const int ra = ra0 + (lane >> 1), rb = rb0 + (lane >> 1);
+    const int64_t ra_ = m0 + ra < g.M ? ra : g.M - 1 - m0;
+    const int64_t rb_ = n0 + rb < g.N ? rb : g.N - 1 - n0;
+    aoff = (uint32_t)((ra_ * DBK + ((lane & 1) ^ dswz(ra)) * 8) * 2);
+    boff = (uint32_t)((rb_ * DBK + ((lane & 1) ^ dswz(rb)) * 8) * 2);
+  }
+  const int64_t nk = (kend - kbeg) / DBK;
+#define TN_RING(S) ((S) == 0 ? ring0 : (S) == 1 ? ring1 : ring2)
+  auto issue = [&](auto slot, int64_t stg) {
+    constexpr int S = decltype(slot)::value;
+    uint16_t *rs = TN_RING(S);
+    const int64_t kb = kbeg / DBK + (stg < nk ? stg : nk - 1);
+    const uint8_t *ak = abase + kb * g.M * DBK * 2, *bk = bbase + kb * g.N * DBK * 2;
+#pragma unroll
+    for (int i = 0; i < NLA; ++i)
+      __builtin_amdgcn_global_load_lds((const void *)(ak + (pa0 + i) * g.pa * 2 + aoff),
+                                       (lds_void *)(rs + (pa0 + i) * DPA + ra0 * DBK), 16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NLB; ++i)
+      __builtin_amdgcn_global_load_lds((const void *)(bk + (pb0 + i) * g.pb * 2 + boff),
+                                       (lds_void *)(rs + NP * DPA + (pb0 + i) * DPB + rb0 * DBK), 16, 0, 0);
+  };
+  // fragment rows of this wave's 64 x 64 part of its group's half
+  const int fr = lane & 31, fpos = ((lane >> 5) ^ dswz(fr)) * 8;
+  const int arow = (WIDE_A ? grp * BT : 0) + wm * 64 + fr;
+  const int brow = (WIDE_A ? 0 : grp * BT) + wn * 64 + fr;
+  auto fread = [&](auto slot, v4u (&a)[2][NP], v4u (&b)[2][NP]) {
+    constexpr int S = decltype(slot)::value;
+    const uint16_t *rs = TN_RING(S);
+#pragma unroll
+    for (int pp = 0; pp < NP; pp += 2) {
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int pl = pp; pl < pp + 2; ++pl)
+          a[mb][pl] = *(const v4u *)(rs + pl * DPA + (arow + mb * 32) * DBK + fpos);
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int pl = pp; pl < pp + 2; ++pl)
+          b[nb][pl] = *(const v4u *)(rs + NP * DPA + pl * DPB + (brow + nb * 32) * DBK + fpos);
+    }
+  };
+#undef TN_RING
+  auto mma = [&](const v4u (&a)[2][NP], const v4u (&b)[2][NP]) {
+#pragma unroll
+    for (int pi = 0; pi < NPROD; ++pi) {
+      const int c = prod_4m(pi, 0), ap = prod_4m(pi, 1), bp = prod_4m(pi, 2), ng = prod_4m(pi, 3);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const v8bf av = as_bf(ng ? neg4(a[mb][ap]) : a[mb][ap]);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb][c] =
+              __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf(b[nb][bp]), acc[mb][nb][c], 0, 0, 0);
+      }
+    }
+  };
+  v4u fa[2][NP], fb[2][NP];
+  // wait for stage j, barrier, request stage j + 2 into the slot of j - 1
+  auto head = [&](auto slot, int64_t j) {
+    constexpr int S = decltype(slot)::value;
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(dma_wait_imm(LW));
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    issue(std::integral_constant<int, (S + 2) % 3>(), j + 2);
+  };
+  auto half = [&]() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  __builtin_amdgcn_s_waitcnt(0);  // nothing else in flight when the ring starts
+  if (nk > 0) {
+    issue(S0(), 0);
+    issue(S1(), 1);
+  }
+  // each group runs its own loop (no branch inside, so the accumulators stay
+  // in place); both pass the same barriers in the same order, two an
+  // iteration
+  if (grp == 0) {
+    auto it = [&](auto slot, int64_t j) {
+      head(slot, j);
+      fread(slot, fa, fb);
+      half();
+      mma(fa, fb);
+    };
+    int64_t j = 0;
+    for (; j + 3 <= nk; j += 3) {
+      it(S0(), j);
+      it(S1(), j + 1);
+      it(S2(), j + 2);
+    }
+    if (j < nk) it(S0(), j);
+    if (j + 1 < nk) it(S1(), j + 1);
+  } else if (nk > 0) {
+    // the loop turned so that a body reads its fragments and uses them
+    // (nothing carried across the back edge): barrier, read stage j, wait and
+    // barrier of stage j + 1 (with its request; none after the last stage),
+    // products of stage j
+    auto it = [&](auto slot, int64_t j) {
+      constexpr int S = decltype(slot)::value;
+      half();
+      fread(slot, fa, fb);
+      if (j + 1 < nk) head(std::integral_constant<int, (S + 1) % 3>(), j + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(fa, fb);
+    };
+    head(S0(), 0);
+    int64_t j = 0;
+    for (; j + 3 <= nk; j += 3) {
+      it(S0(), j);
+      it(S1(), j + 1);
+      it(S2(), j + 2);
+    }
+    if (j < nk) it(S0(), j);
+    if (j + 1 < nk) it(S1(), j + 1);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // no load may still write LDS when the block ends
+
+  const bool partial = g.ksplit > 1;
+  float2 *C = partial ? g.part + q * g.partbs + (int64_t)ks * g.M * g.N : g.C + q * g.cbs;
+  const int64_t ldc = partial ? g.N : g.ldc;
+  const int rbase = (WIDE_A ? grp * BT : 0) + wm * 64, cbase = (WIDE_A ? 0 : grp * BT) + wn * 64;
+  float mx = 0.0f;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = rbase + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int col = cbase + nb * 32 + (lane & 31);
+        const int64_t cm = m0 + row, cn = n0 + col;
+        const float re = acc[mb][nb][0][v], im = acc[mb][nb][1][v];
+        if (cm < g.M && cn < g.N) {
+          C[cm * ldc + cn] = make_float2(re, im);
+          mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+        }
+      }
+  if (!partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) atomicMax(&sc->maxbits, __float_as_uint(mx));
+  }
+}
+
 hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g0, int form, int nbatch) {
   GemmArgs g = g0;
   if (g.opA != 0 || g.opB != 1 || g.planes != (form == kForm3M ? 6 : 4)) return hipErrorInvalidValue;
-  g.tiles_m = (int)((g.M + BT - 1) / BT);
-  g.tiles_n = (int)((g.N + BT - 1) / BT);
+  if (g.tile < 0 || g.tile > 2) return hipErrorInvalidValue;
+  // the two-group kernel: 4M from k-tiled planes with a wide tile
+  const bool pp = g.ktile && form == kForm4M && g.tile != 0;
+  g.tiles_m = (int)((g.M + (pp ? gemm_bf16_tile_m(g.tile) : BT) - 1) / (pp ? gemm_bf16_tile_m(g.tile) : BT));
+  g.tiles_n = (int)((g.N + (pp ? gemm_bf16_tile_n(g.tile) : BT) - 1) / (pp ? gemm_bf16_tile_n(g.tile) : BT));
   if (g.ksplit < 1) g.ksplit = 1;
   if (g.ksplit == 1) g.kchunk = g.K;
   if (g.kchunk < 1 || (int64_t)g.ksplit * g.kchunk < g.K || (g.ksplit > 1 && !g.part))
@@ -527,7 +756,11 @@ hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g0, int form, int 
   const bool exact = g.K % BKS == 0 && g.kchunk % BKS == 0;
   if (g.ktile) {
     if (g.K % DBK != 0 || g.kchunk % DBK != 0) return hipErrorInvalidValue;
-    if (form == kForm4M)
+    if (pp && g.tile == 2)
+      hipLaunchKernelGGL(k_cgemm_bf16x3_pp<true>, grid, dim3(512), 0, st, g);
+    else if (pp)
+      hipLaunchKernelGGL(k_cgemm_bf16x3_pp<false>, grid, dim3(512), 0, st, g);
+    else if (form == kForm4M)
       hipLaunchKernelGGL(k_cgemm_bf16x3_dma<kForm4M>, grid, dim3(256), 0, st, g);
     else
       hipLaunchKernelGGL(k_cgemm_bf16x3_dma<kForm3M>, grid, dim3(256), 0, st, g);

@@ -869,32 +869,62 @@ namespace tn {
 // Matrix-core rate probe: every wave runs four independent accumulation
 // chains of one MFMA instruction with no memory traffic in the loop (one
 // store per lane at the end keeps the chains live), four waves per SIMD.
-// The rate it reaches is what the matrix cores sustain at the clock the
-// device holds under that load, the ceiling a GEMM kernel can approach.
-template <int PREC>
+// RANDOM: each lane holds four A and four B operands of pseudo-random values
+// in [-1, 1) (a hash of lane, block and index) and consecutive products
+// take different pairs of them.  A matrix unit fed the same operands over
+// and over switches few bits and draws little power, so the device holds
+// its top clock; on data that changes from product to product, as in a GEMM,
+// it may not.  The random rate is the ceiling a GEMM kernel on real data can
+// approach; the constant one shows the clock's share of the gap.
+template <int PREC, bool RANDOM>
 __global__ __launch_bounds__(256) void k_probe_mfma(float *out, int iters, float seed) {
   v16f acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[c][v] = 0.0f;
-  const float x = seed + (float)threadIdx.x * 1e-7f;
+  auto rnd = [&](uint32_t k) {
+    uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 0x9E3779B1u + k * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    // constant operands: per-lane values, fixed for the whole run
+    return RANDOM ? ((float)(h >> 8) * (2.0f / 16777216.0f) - 1.0f) * seed
+                  : seed + (float)((threadIdx.x + k) & 7) * 0.125f;
+  };
+  // loop of iters / 4 rounds of 16 products (iters a multiple of 4)
   if (PREC == kPrecFP32) {
-    for (int i = 0; i < iters; ++i) {
+    float a[4], b[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, seed, acc[c], 0, 0, 0);
+    for (int j = 0; j < 4; ++j) {
+      a[j] = rnd(j);
+      b[j] = rnd(4 + j);
+    }
+    for (int i = 0; i < iters; i += 4) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[(c + r) & 3], b[c], acc[c], 0, 0, 0);
     }
   } else {
     typedef __bf16 v8b __attribute__((ext_vector_type(8)));
-    v8b a, b;
+    v8b a[4], b[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      a[j] = (__bf16)(x + (float)j);
-      b[j] = (__bf16)(seed - (float)j);
-    }
-    for (int i = 0; i < iters; ++i) {
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[c], 0, 0, 0);
+      for (int e = 0; e < 8; ++e) {
+        a[j][e] = (__bf16)rnd(8 * j + e);
+        b[j][e] = (__bf16)rnd(32 + 8 * j + e);
+      }
+    for (int i = 0; i < iters; i += 4) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[(c + r) & 3], b[c], acc[c], 0, 0, 0);
     }
   }
   float s = 0.0f;
@@ -906,14 +936,20 @@ __global__ __launch_bounds__(256) void k_probe_mfma(float *out, int iters, float
 }
 
 // `out` holds blocks * 256 floats; flops per launch returned in *flops.
-hipError_t launch_probe_mfma(hipStream_t st, int prec, float *out, int blocks, int iters, double *flops) {
-  if (blocks < 1 || iters < 1) return hipErrorInvalidValue;
+hipError_t launch_probe_mfma(hipStream_t st, int prec, bool random, float *out, int blocks, int iters,
+                             double *flops) {
+  if (blocks < 1 || iters < 4 || iters % 4 != 0) return hipErrorInvalidValue;
   const double per = prec == kPrecFP32 ? 2.0 * 32 * 32 * 2 : 2.0 * 32 * 32 * 16;
   *flops = per * 4.0 * iters * (double)blocks * 4.0;
-  if (prec == kPrecFP32)
-    hipLaunchKernelGGL(k_probe_mfma<kPrecFP32>, dim3(blocks), dim3(256), 0, st, out, iters, 1.0f);
-  else
-    hipLaunchKernelGGL(k_probe_mfma<kPrecBF16x3>, dim3(blocks), dim3(256), 0, st, out, iters, 1.0f);
+#define TN_PROBE(P, R) hipLaunchKernelGGL((k_probe_mfma<P, R>), dim3(blocks), dim3(256), 0, st, out, iters, 1.0f)
+  if (prec == kPrecFP32) {
+    if (random) TN_PROBE(kPrecFP32, true);
+    else TN_PROBE(kPrecFP32, false);
+  } else {
+    if (random) TN_PROBE(kPrecBF16x3, true);
+    else TN_PROBE(kPrecBF16x3, false);
+  }
+#undef TN_PROBE
   return hipGetLastError();
 }
 

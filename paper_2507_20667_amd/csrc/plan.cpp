@@ -330,18 +330,23 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   // FP32 planes: a 64-row or 64-column tile when that side is that small
   // (a 128 x 128 tile would run half empty), unless the tuning table says
   // otherwise
+  // BF16x3 4M: the two wave-group kernel's 256 x 128 (or 128 x 256) tile when
+  // both sides fill it
   n.tile = 0;
   if (n.planes == 2) n.tile = n.M <= 64 && n.N > 64 ? 1 : n.N <= 64 && n.M > 64 ? 2 : 0;
-  {
-    const int tm = n.planes == 2 ? gemm_planes_tile_m(n.tile)
-                                 : n.planes > 0 ? 128 : gemm_variant_tile_m(n.variant);
-    const int tn = n.planes == 2 ? gemm_planes_tile_n(n.tile)
-                                 : n.planes > 0 ? 128 : gemm_variant_tile_n(n.variant);
-    n.ksplit = gemm_ksplit(n.M, n.N, n.K, tm, tn, &n.kchunk);
-  }
+  if (n.planes == 4) n.tile = n.M >= 256 && n.N >= 128 ? 2 : n.N >= 256 && n.M >= 128 ? 1 : 0;
+  auto tile_m = [&](int tile) {
+    return n.planes == 2 ? gemm_planes_tile_m(tile)
+                         : n.planes > 0 ? gemm_bf16_tile_m(tile) : gemm_variant_tile_m(n.variant);
+  };
+  auto tile_n = [&](int tile) {
+    return n.planes == 2 ? gemm_planes_tile_n(tile)
+                         : n.planes > 0 ? gemm_bf16_tile_n(tile) : gemm_variant_tile_n(n.variant);
+  };
+  n.ksplit = gemm_ksplit(n.M, n.N, n.K, tile_m(n.tile), tile_n(n.tile), &n.kchunk);
   // the tuning table's choice for this shape, or TN_GEMM_FORCE="tile,ksplit"
-  // (tuning runs): a tile shape for the FP32 planes, k chunks of a multiple
-  // of 32 entries
+  // (tuning runs): a tile shape for the FP32 planes or BF16x3 4M, k chunks
+  // of a multiple of 32 entries
   {
     int tile = -1, ks = 0;
     if (const char *e = getenv("TN_GEMM_FORCE")) {
@@ -352,7 +357,10 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
         ks = r->ksplit;
       }
     }
-    if (n.planes == 2 && tile >= 0 && tile <= 2) n.tile = tile;
+    if ((n.planes == 2 || n.planes == 4) && tile >= 0 && tile <= 2 && tile != n.tile) {
+      n.tile = tile;
+      if (ks < 1) n.ksplit = gemm_ksplit(n.M, n.N, n.K, tile_m(n.tile), tile_n(n.tile), &n.kchunk);
+    }
     if (n.planes > 0 && ks >= 1) {
       int64_t kc = (n.K + ks - 1) / ks;
       kc = (kc + 31) / 32 * 32;

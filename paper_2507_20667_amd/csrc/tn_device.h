@@ -96,8 +96,9 @@ struct GemmArgs {
   // ktile = 1: the planes are k-tiled (row r, k at ((k / 16) * rows + r) * 16
   // + k % 16, rows = M for A and N for B), K a multiple of 16
   int32_t ktile;
-  // tile shape of the FP32 plane kernel: 0 = 128 x 128, 1 = 64 x 256,
-  // 2 = 256 x 64 (M x N)
+  // tile shape (M x N) of the FP32 plane kernel: 0 = 128 x 128, 1 = 64 x
+  // 256, 2 = 256 x 64; of the BF16x3 4M kernels on k-tiled planes: 0 = 128 x
+  // 128, 1 = 128 x 256, 2 = 256 x 128 (the two wave-group kernel)
   int32_t tile;
 };
 
@@ -333,6 +334,10 @@ hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g, int form, int n
 hipError_t launch_gemm_f32_planes(hipStream_t st, const GemmArgs &g, int form, int nbatch);
 int gemm_planes_tile_m(int v);
 int gemm_planes_tile_n(int v);
+// tile rows / columns of the BF16x3 kernels: 0 = 128 x 128, 1 = 128 x 256,
+// 2 = 256 x 128 (the last two 4M from k-tiled planes only)
+int gemm_bf16_tile_m(int v);
+int gemm_bf16_tile_n(int v);
 hipError_t launch_splitk_reduce(hipStream_t st, const GemmArgs &g, int nbatch);
 // k chunks of a GEMM with tiles_m x tiles_n output tiles (1: no split)
 int gemm_ksplit(int64_t M, int64_t N, int64_t K, int tile_m, int tile_n, int64_t *kchunk);
@@ -359,9 +364,12 @@ hipError_t scratch_address(int device, void **ptr);
 hipError_t launch_slice_sum_records(hipStream_t st, const Result *res, int64_t rbs, int nq, Result *out);
 hipError_t launch_slice_sum_tensors(hipStream_t st, Operand R, int nq, int64_t n, double2 *out,
                                     double *out_log2);
+// matrix-core rate probe (random or constant operands): `out` holds blocks *
+// 256 floats, iters a multiple of 4; the launch's flops in *flops
+hipError_t launch_probe_mfma(hipStream_t st, int prec, bool random, float *out, int blocks, int iters,
+                             double *flops);
 // closed-root records of nq queries (query q's at res[q * rbs]) to
 // complex128 values at out[q * stride]
-hipError_t launch_probe_mfma(hipStream_t st, int prec, float *out, int blocks, int iters, double *flops);
 hipError_t launch_results_to_c128(hipStream_t st, const Result *res, int64_t rbs, int nq,
                                   double2 *out, int64_t stride);
 

@@ -26,6 +26,7 @@ TN_FORM_4M, TN_FORM_3M = 0, 1 << 4
 TN_FLAG_KEEP_SCALE = 1 << 8
 TN_FLAG_GRAPH = 1 << 9
 TN_FLAG_CONCURRENT = 1 << 10
+TN_PROBE_CONST_OPERANDS = 1 << 8   # tn_probe_mfma only
 
 STATUS_NAMES = {0: "TN_OK", 1: "TN_PENDING", -1: "TN_E_INVALID_ARG", -2: "TN_E_INVALID_PLAN",
                 -3: "TN_E_NOMEM", -4: "TN_E_DEVICE", -5: "TN_E_AGAIN", -6: "TN_E_CANCELLED",
@@ -387,7 +388,9 @@ class tn_kernel_stats(ctypes.Structure):
 
 def tn_probe_mfma(ctx, precision) -> float:
     """TFLOP/s the matrix cores sustain with no memory traffic
-    (TN_PREC_FP32: the FP32 MFMA; TN_PREC_BF16X3: the bf16 MFMA)."""
+    (TN_PREC_FP32: the FP32 MFMA; TN_PREC_BF16X3: the bf16 MFMA), on operands
+    that change from product to product, or, with TN_PROBE_CONST_OPERANDS
+    or-ed in, on constant ones."""
     t = ctypes.c_double(0.0)
     _check(load().tn_probe_mfma(ctypes.c_void_p(ctx), int(precision), ctypes.byref(t)))
     return t.value

@@ -6,11 +6,12 @@
 GEMM vertices (the G of TTGT, Section 5.1): every GEMM shape of the 30-qubit
 plan in FP32 and split BF16 (4M and 3M) and of the uneven batch's plans, in
 buckets of ceil(log2) of M, N and K.  Candidates: the FP32 plane kernel's
-tile shape (128 x 128; 64 x 256 when M <= 128; 256 x 64 when N <= 128) and the
-number of k chunks (1 to 32, each chunk at least 256 deep).  Each candidate
-runs a network of that one GEMM vertex (A[m, k] B[k, n], closed by C[m, n])
-with TN_GEMM_FORCE, and the event-timed GEMM launches are compared (median of
-three after a warm-up).
+tile shape (128 x 128; 64 x 256 when M <= 128; 256 x 64 when N <= 128), the
+BF16x3 4M tile (128 x 128; 128 x 256 or 256 x 128 on the two wave-group
+kernel) and the number of k chunks (1 to 32, each chunk at least 256 deep).  Each candidate
+runs a network of that one GEMM vertex (A[m, k] B[k, n], closed by C[m, n],
+seeded random entries) with TN_GEMM_FORCE, and the event-timed GEMM launches
+are compared (median of three after a warm-up).
 
 Subtree kernel (the batched path of the small vertices): for the 20-qubit
 brickwork plan, queries per workgroup, the size from which a per-query
@@ -78,13 +79,35 @@ def gemm_shapes(lib, net, plan, k, flags):
     return out
 
 
+_OPERANDS = {}
+
+
+def _operands(M, N, K):
+    """Seeded random tensors of one GEMM shape (entries uniform in the unit
+    square around 0), made once per shape.  Random, not constant: the clock
+    the device holds under a matrix-core load depends on how many operand
+    bits switch, so constant data would time a faster device than real
+    data meets."""
+    key = (M, N, K)
+    if key not in _OPERANDS:
+        _OPERANDS.clear()
+        rng = np.random.default_rng(M * 1000003 + N * 1009 + K)
+
+        def r(*sh):
+            x = np.empty(sh, dtype=np.complex64)
+            x.real = rng.random(sh, dtype=np.float32) - 0.5
+            x.imag = rng.random(sh, dtype=np.float32) - 0.5
+            return x
+        _OPERANDS[key] = [r(M, K), r(K, N), r(M, N)]
+    return _OPERANDS[key]
+
+
 def time_gemm(lib, ctx, M, N, K, flags, force, reps=3):
     """Event-timed GEMM launches (ms) of the network A[m,k] B[k,n] C[m,n]
     with TN_GEMM_FORCE = force (None: the heuristic)."""
     legs = [[1, 2], [2, 3], [1, 3]]
     dims = {1: M, 2: K, 3: N}
-    ts = [np.full((M, K), 0.5 + 0.25j, np.complex64), np.full((K, N), 0.25 - 0.5j, np.complex64),
-          np.full((M, N), 1.0, np.complex64)]
+    ts = _operands(M, N, K)
     if force is not None:
         os.environ["TN_GEMM_FORCE"] = f"{force[0]},{force[1]}"
     try:
@@ -106,8 +129,11 @@ def time_gemm(lib, ctx, M, N, K, flags, force, reps=3):
         ctx.free_plan(p)
 
 
-def gemm_candidates(M, N, K, bf16):
-    tiles = [0] if bf16 else [0] + ([1] if M <= 128 else []) + ([2] if N <= 128 else [])
+def gemm_candidates(M, N, K, bf16, form3m):
+    if bf16:
+        tiles = [0] if form3m else [0, 1, 2]
+    else:
+        tiles = [0] + ([1] if M <= 128 else []) + ([2] if N <= 128 else [])
     ks = [s for s in (1, 2, 4, 8, 16, 32) if s == 1 or K // s >= 256]
     return [(t, s) for t in tiles for s in ks]
 
@@ -138,7 +164,7 @@ def tune_gemm(lib, quick=False):
             prec, form = key[0], key[1]
             base = time_gemm(lib, ctx, M, N, K, flags, None)
             best, best_t = None, base
-            for cand in gemm_candidates(M, N, K, prec == "bf16x3"):
+            for cand in gemm_candidates(M, N, K, prec == "bf16x3", form == "3m"):
                 t = time_gemm(lib, ctx, M, N, K, flags, cand)
                 if t < best_t * 0.98:
                     best, best_t = cand, t

@@ -46,6 +46,7 @@ def ctx():
 
 
 @pytest.mark.parametrize("flags,tol", [(lib.TN_PREC_FP32, 1e-4), (lib.TN_FORM_3M, 1e-4),
+                                       (lib.TN_PREC_BF16X3, 1e-3),
                                        (lib.TN_PREC_BF16X3 | lib.TN_FORM_3M, 1e-3)])
 def test_2pow32_entry_intermediate(ctx, network, flags, tol):
     ts, ref = network
