@@ -1593,13 +1593,22 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
   // (lane * 4, the ds_bpermute address).  The level kernel, which runs the
   // same programs for single queries and the shared subtrees, keeps the
   // steps as they are.  TN_TREE_CHAIN=0 turns chains off.
+  //
+  // The same pass fuses a kind 3 pair into one kind 6 step (the pair's two
+  // descriptors, the first marked kind 6): P writes an intermediate T to the
+  // query's device workspace and Q, the next step, contracts T with an
+  // operand B that has no free legs, so each entry of T enters exactly one of
+  // Q's products (checked here by enumerating them), and no other step reads
+  // T or its scale record.  The batch kernel then keeps T in registers
+  // (tree_pair).  TN_TREE_PAIR=0 turns pairs off.
   {
     const bool chain_on = !getenv("TN_TREE_CHAIN") || atoi(getenv("TN_TREE_CHAIN")) != 0;
+    const bool pair_on = !getenv("TN_TREE_PAIR") || atoi(getenv("TN_TREE_PAIR")) != 0;
     for (size_t hi = 0; hi < hdrs.size(); ++hi) {
       TreeHdr &h = hdrs[hi];
       h.wstep0 = h.step0;
       h.wnsteps = h.nsteps;
-      if (!chain_on || (int)hi < L.n_tree_shared || !L.tree_wave) continue;
+      if ((!chain_on && !pair_on) || (int)hi < L.n_tree_shared || !L.tree_wave) continue;
       auto whole = [&](const TreeStep &st) { return st.kind == 4 && st.nss == 1 && st.nc >= 1 && st.nc <= 64; };
       // entry byte offset -> lane of a whole step's records
       auto lane_of = [&](const TreeStep &st) {
@@ -1631,12 +1640,119 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       std::vector<TreeStep> prog;
       std::vector<TreeLaneRec> crec;
       bool any = false;
+      int npairs = 0;
       const int kend = h.step0 + h.nsteps;
-      for (int k = h.step0; k < kend;) {
-        int k2 = k;
-        while (k2 + 1 < kend && links(steps[k2], steps[k2 + 1])) ++k2;
-        if (k2 == k) {
-          prog.push_back(steps[k++]);
+      // a map (extents, as the host keeps them): index -> offset
+      auto decode = [](const int32_t *ext, const int32_t *st, int nseg, int idx) {
+        int o = 0;
+        for (int i = 0; i < nseg; ++i) {
+          o += (idx % ext[i]) * st[i];
+          idx /= ext[i];
+        }
+        return o;
+      };
+      // the consumer of P's intermediate, if P and it form a pair that can run
+      // at P's place: every step between them is a kind 4 step that neither
+      // reads nor writes Q's result entries, writes no entry of Q's B, and
+      // touches none of Q's scale records (from its lane records); -1 if not
+      auto pair_partner = [&](int k) {
+        const TreeStep &P = steps[k];
+        if (P.kind != 3 || P.glob != 4 || !P.pow2 || P.csl < 0 || P.ns > 64) return -1;
+        auto reads_t = [&](const TreeStep &o) {
+          return (o.kind == 3 && (((o.glob & 1) && o.a == P.c) || ((o.glob & 2) && o.b == P.c))) ||
+                 (o.kind != 4 && (o.asl == P.csl || o.bsl == P.csl));
+        };
+        int q = -1;
+        for (int j = k + 1; j < kend; ++j)
+          if (reads_t(steps[j])) {
+            if (q >= 0) return -1;  // a second reader
+            q = j;
+          }
+        if (q < 0) return -1;
+        const TreeStep &Q = steps[q];
+        if (Q.kind != 3 || Q.glob != 1 || !Q.pow2 || Q.a != P.c || Q.asl != P.csl || Q.ns > 4 ||
+            Q.nc > 256 || Q.nc * Q.ns != P.nc || !(Q.c & kPerQuery))
+          return -1;
+        for (int i = 0; i < Q.ncs; ++i)
+          if (Q.cext[i] > 1 && Q.cb[i] != 0) return -1;  // B has a free leg
+        std::vector<char> hit((size_t)P.nc, 0);
+        for (int co = 0; co < Q.nc; ++co) {
+          const int ao = decode(Q.cext, Q.ca, Q.ncs, co);
+          for (int sh = 0; sh < Q.ns; ++sh) {
+            const int so = decode(Q.sext, Q.sa, Q.nss, sh);
+            const int t = ao + so;
+            // the kernel splits P's map of t over the bits of ao and of so
+            if ((ao & so) != 0 || t < 0 || t >= P.nc || hit[(size_t)t]++) return -1;
+          }
+        }
+        // Q's result entries and B's entries (in the query region or shared)
+        const int qc0 = Q.c & ~kPerQuery, qc1 = qc0 + Q.nc;
+        const bool b_q = (Q.b & kPerQuery) != 0;
+        std::vector<int> bent;
+        for (int sh = 0; sh < Q.ns; ++sh) bent.push_back((Q.b & ~kPerQuery) + decode(Q.sext, Q.sb, Q.nss, sh));
+        for (int j = k + 1; j < q; ++j) {
+          const TreeStep &m = steps[j];
+          if (m.kind != 4) return -1;
+          for (int l = 0; l < m.nc; ++l) {
+            const TreeLaneRec &r = lanes[m.tab + l];
+            const int csl = (int)((r.w[2] >> 16) & 0x7fffu), asl = (int)(r.w[3] & 0x7fffu),
+                      bsl = (int)((r.w[3] >> 16) & 0x7fffu);
+            if (csl == Q.bsl || csl == Q.csl || asl == Q.csl || bsl == Q.csl) return -1;
+            const int ce = (int)(r.w[2] & 0xffffu) / 8;  // result entry (query region)
+            if (ce >= qc0 && ce < qc1) return -1;
+            if (b_q)
+              for (int e : bent)
+                if (e == ce) return -1;
+            const uint32_t xo[4] = {r.w[0] & 0xffffu, r.w[0] >> 16, r.w[4] & 0xffffu, r.w[4] >> 16};
+            const uint32_t yo[4] = {r.w[1] & 0xffffu, r.w[1] >> 16, r.w[5] & 0xffffu, r.w[5] >> 16};
+            for (int v = 0; v < m.ns; ++v) {
+              const int xe = (int)xo[v] / 8, ye = (int)yo[v] / 8;
+              if (!(r.w[3] & 0x8000u) && xe >= qc0 && xe < qc1) return -1;
+              if (!(r.w[3] & 0x80000000u) && ye >= qc0 && ye < qc1) return -1;
+            }
+          }
+        }
+        return q;
+      };
+      // this kernel's step order: the consumer of each pair moved up to its
+      // producer, the steps between them after it
+      std::vector<int> ord;
+      std::vector<char> head;
+      {
+        std::vector<char> moved((size_t)(kend - h.step0), 0);
+        for (int k = h.step0; k < kend; ++k) {
+          if (moved[(size_t)(k - h.step0)]) continue;
+          const int q = pair_on ? pair_partner(k) : -1;
+          ord.push_back(k);
+          head.push_back(q >= 0);
+          if (q >= 0) {
+            ord.push_back(q);
+            head.push_back(0);
+            moved[(size_t)(q - h.step0)] = 1;
+            ++npairs;
+          }
+        }
+      }
+      for (size_t x = 0; x < ord.size();) {
+        const int k = ord[x];
+        if (head[x]) {
+          TreeStep ps = steps[k];
+          ps.kind = 6;
+          prog.push_back(ps);
+          prog.push_back(steps[ord[x + 1]]);
+          any = true;
+          x += 2;
+          continue;
+        }
+        // a run of chained steps: consecutive in this order, none in a pair
+        size_t x2 = x;
+        while (chain_on && x2 + 1 < ord.size() && !head[x2 + 1] && ord[x2 + 1] == ord[x2] + 1 &&
+               links(steps[ord[x2]], steps[ord[x2 + 1]]))
+          ++x2;
+        const int k2 = ord[x2];
+        if (x2 == x) {
+          prog.push_back(steps[k]);
+          ++x;
           continue;
         }
         TreeStep ps;
@@ -1666,7 +1782,7 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
         }
         prog.push_back(ps);
         any = true;
-        k = k2 + 1;
+        x = x2 + 1;
       }
       if (!any) continue;
       h.wstep0 = (int32_t)steps.size();
@@ -1674,8 +1790,8 @@ static void build_tree_programs(const tn_plan *p, ExecLayout &L, const std::vect
       steps.insert(steps.end(), prog.begin(), prog.end());
       lanes.insert(lanes.end(), crec.begin(), crec.end());
       if (getenv("TN_DEBUG"))
-        fprintf(stderr, "[tn]   subtree root %d: batch program of %d steps (kind 5 chains: %d links)\n",
-                h.root_slot, h.wnsteps, (int)(crec.size() / 64));
+        fprintf(stderr, "[tn]   subtree root %d: batch program of %d steps (kind 5 chains: %d links; "
+                "kind 6 pairs: %d)\n", h.root_slot, h.wnsteps, (int)(crec.size() / 64), npairs);
     }
   }
   if (getenv("TN_DEBUG"))

@@ -779,6 +779,170 @@ __device__ __forceinline__ void tree_lane_step(const TreeLaneRec *rec, int lane,
 
 // DEV: the program may hold kind 3 steps (per-query subtrees; a shared
 // subtree never does, and its launch leaves that code out)
+// A kind 3 step (operands in the query's device workspace), whatever its
+// kind field says (a kind 6 pair runs as two of these when a wave holds more
+// than one query).
+template <class SP>
+__device__ __forceinline__ void tree_kind3(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
+                                           const float2 *shr, int2 *scl, int nscale, float2 *gq,
+                                           int64_t gstride) {
+  if (nqw == 1 && Sp->pow2) {
+    switch (Sp->glob) {  // 1 .. 7 (checked on the host)
+      case 1: tree_dev_one<1>(Sp, lane, nthr, pq, shr, scl, gq); break;
+      case 2: tree_dev_one<2>(Sp, lane, nthr, pq, shr, scl, gq); break;
+      case 3: tree_dev_one<3>(Sp, lane, nthr, pq, shr, scl, gq); break;
+      case 4: tree_dev_one<4>(Sp, lane, nthr, pq, shr, scl, gq); break;
+      case 5: tree_dev_one<5>(Sp, lane, nthr, pq, shr, scl, gq); break;
+      case 6: tree_dev_one<6>(Sp, lane, nthr, pq, shr, scl, gq); break;
+      default: tree_dev_one<7>(Sp, lane, nthr, pq, shr, scl, gq); break;
+    }
+  } else if (Sp->pow2) {
+    tree_dev_impl<true>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
+  } else {
+    tree_dev_impl<false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
+  }
+  // a later step of this wave reads what this one stored to device memory
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+// Kind 6 (batch kernel, one query per wave): a kind 3 pair in one step.  P
+// writes an intermediate T to the query's device workspace and Q contracts T
+// with an operand B that has no free legs, so each entry of T enters exactly
+// one of Q's products (checked on the host, which also moved Q up to P).
+// Each lane computes the entries of T its own results need (result co = lane
+// + 64 j takes T at ao(co) + oa(s) for its ns terms s), keeps them in
+// registers, takes the wave-wide max |re|/|im| for T's scale record, and
+// finishes Q: T never goes through device memory.  T's entries, its scale
+// and Q's results come from the same operations in the same order as when
+// the two steps run apart, so the results are bit-identical.  Q: nc <= 256,
+// ns <= 4; P: ns <= 64; both power-of-two maps.
+__device__ __forceinline__ void tree_pair(CStep P, CStep Q, int lane, float2 *pq, const float2 *shr,
+                                          int2 *scl) {
+  int32_t pcext[kTreeSeg], pca[kTreeSeg], pcb[kTreeSeg], pclg[kTreeSeg];
+  int32_t psext[kTreeSeg], psa[kTreeSeg], psb[kTreeSeg], pslg[kTreeSeg];
+  int32_t qcext[kTreeSeg], qca[kTreeSeg], qcb[kTreeSeg], qclg[kTreeSeg];
+  int32_t qsext[kTreeSeg], qsa[kTreeSeg], qsb[kTreeSeg], qslg[kTreeSeg];
+#pragma unroll
+  for (int i = 0; i < kTreeSeg; ++i) {
+    pcext[i] = P->cext[i];
+    pca[i] = P->ca[i];
+    pcb[i] = P->cb[i];
+    pclg[i] = P->clg[i];
+    psext[i] = P->sext[i];
+    psa[i] = P->sa[i];
+    psb[i] = P->sb[i];
+    pslg[i] = P->slg[i];
+    qcext[i] = Q->cext[i];
+    qca[i] = Q->ca[i];
+    qcb[i] = Q->cb[i];
+    qclg[i] = Q->clg[i];
+    qsext[i] = Q->sext[i];
+    qsa[i] = Q->sa[i];
+    qsb[i] = Q->sb[i];
+    qslg[i] = Q->slg[i];
+  }
+  const int hl = threadIdx.x & 63;
+  const int pns = P->ns, pnss = P->nss, pncs = P->ncs;
+  const int qns = Q->ns, qnss = Q->nss, qncs = Q->ncs, qnc = Q->nc;
+  // shared-index offsets, lane l holding those of term l (as in the kinds 0
+  // and 3 forms): P's of X and Y, Q's of T and B
+  int psoa = 0, psob = 0, qsoa = 0, qsob = 0;
+  if (hl < pns) seg2r<true>(psext, psa, psb, pslg, pnss, hl, psoa, psob);
+  if (hl < qns) seg2r<true>(qsext, qsa, qsb, qslg, qnss, hl, qsoa, qsob);
+  // T's entry ao(co) + oa(s) has the bits of ao(co) and of oa(s) apart (a
+  // bijection of power-of-two maps), and P's map of T's index is linear over
+  // disjoint bits: P's offsets of the entry are those of ao(co) plus those of
+  // oa(s), the latter held by lane s
+  int pxs = 0, pys = 0;
+  if (hl < qns) seg2r<true>(pcext, pca, pcb, pclg, pncs, qsoa, pxs, pys);
+  const int pa = P->a, pb = P->b, qb = Q->b;
+  const float2 *X0 = (pa & kPerQuery) ? pq + (pa & ~kPerQuery) : shr + pa;
+  const float2 *Y0 = (pb & kPerQuery) ? pq + (pb & ~kPerQuery) : shr + pb;
+  const float2 *B0 = (qb & kPerQuery) ? pq + (qb & ~kPerQuery) : shr + qb;
+  float2 *C = pq + (Q->c & ~kPerQuery);
+  const ItemScale zp = uniform_scale(scl, P->asl, P->bsl);
+  const int ep = zp.e();
+  const float fp = ldexpf(1.0f, -ep);
+  // T's entries of this lane's results
+  float2 tv[4][4];
+  int bo[4];
+  float mt = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int co = lane + 64 * j;
+    bo[j] = 0;
+#pragma unroll
+    for (int sh = 0; sh < 4; ++sh) tv[j][sh] = make_float2(0.f, 0.f);
+    if (co < qnc) {
+      int ao, b_, xb, yb;
+      seg2r<true>(qcext, qca, qcb, qclg, qncs, co, ao, b_);
+      seg2r<true>(pcext, pca, pcb, pclg, pncs, ao, xb, yb);
+      bo[j] = b_;
+#pragma unroll
+      for (int sh = 0; sh < 4; ++sh)
+        if (sh < qns) {
+          const int xo = xb + __builtin_amdgcn_readlane(pxs, sh), yo = yb + __builtin_amdgcn_readlane(pys, sh);
+          const float2 r =
+              dot_terms<true>(X0 + xo, Y0 + yo, pns, true, psoa, psob, psext, psa, psb, pslg, pnss);
+          tv[j][sh] = make_float2(r.x * fp, r.y * fp);
+          mt = fmaxf(mt, fmaxf(fabsf(tv[j][sh].x), fabsf(tv[j][sh].y)));
+        }
+    }
+  }
+  // T's scale record as P leaves it (max bits: non-negative floats order as
+  // their bit patterns), and Q's operand scales
+  const unsigned tbits = wave_max_u32(__float_as_uint(mt));
+  const int tlog = zp.za.x + zp.zb.x + ep;
+  int2 zb = Q->bsl >= 0 ? scl[Q->bsl] : make_int2(0, 0);
+  zb.x = __builtin_amdgcn_readfirstlane(zb.x);
+  zb.y = __builtin_amdgcn_readfirstlane(zb.y);
+  const int eq = tn_scale_exp(tbits) + tn_scale_exp((uint32_t)zb.y);
+  const float fq = ldexpf(1.0f, -eq);
+  float mx = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int co = lane + 64 * j;
+    if (co < qnc) {
+      // the order of dot_terms: four terms at a time, the even ones into
+      // (re0, im0) and the odd ones into (re1, im1), then the rest into
+      // (re0, im0)
+      float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+      if (qns == 4) {
+        float2 y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = B0[bo[j] + __builtin_amdgcn_readlane(qsob, u)];
+#pragma unroll
+        for (int u = 0; u < 4; u += 2) {
+          const float2 x0 = tv[j][u], x1 = tv[j][u + 1];
+          re0 = fmaf(x0.x, y[u].x, re0);
+          re0 = fmaf(-x0.y, y[u].y, re0);
+          im0 = fmaf(x0.x, y[u].y, im0);
+          im0 = fmaf(x0.y, y[u].x, im0);
+          re1 = fmaf(x1.x, y[u + 1].x, re1);
+          re1 = fmaf(-x1.y, y[u + 1].y, re1);
+          im1 = fmaf(x1.x, y[u + 1].y, im1);
+          im1 = fmaf(x1.y, y[u + 1].x, im1);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (u < qns) {
+            const float2 x = tv[j][u], y = B0[bo[j] + __builtin_amdgcn_readlane(qsob, u)];
+            re0 = fmaf(x.x, y.x, re0);
+            re0 = fmaf(-x.y, y.y, re0);
+            im0 = fmaf(x.x, y.y, im0);
+            im0 = fmaf(x.y, y.x, im0);
+          }
+      }
+      const float rr = (re0 + re1) * fq, ii = (im0 + im1) * fq;
+      C[co] = make_float2(rr, ii);
+      mx = fmaxf(mx, fmaxf(fabsf(rr), fabsf(ii)));
+    }
+  }
+  if (lane == 0) scl[Q->csl].x = tlog + zb.x + eq;
+  atomicMax((unsigned int *)&scl[Q->csl].y, __float_as_uint(mx));
+}
+
 template <bool DEV, class SP>
 __device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, float2 *pq, int perq,
                                           const float2 *shr, int2 *scl, int nscale, float2 *gq,
@@ -796,23 +960,7 @@ __device__ __forceinline__ void tree_step(SP Sp, int lane, int nthr, int nqw, fl
     return;
   }
   if (DEV && Sp->kind == 3) {
-    if (nqw == 1 && Sp->pow2) {
-      switch (Sp->glob) {  // 1 .. 7 (checked on the host)
-        case 1: tree_dev_one<1>(Sp, lane, nthr, pq, shr, scl, gq); break;
-        case 2: tree_dev_one<2>(Sp, lane, nthr, pq, shr, scl, gq); break;
-        case 3: tree_dev_one<3>(Sp, lane, nthr, pq, shr, scl, gq); break;
-        case 4: tree_dev_one<4>(Sp, lane, nthr, pq, shr, scl, gq); break;
-        case 5: tree_dev_one<5>(Sp, lane, nthr, pq, shr, scl, gq); break;
-        case 6: tree_dev_one<6>(Sp, lane, nthr, pq, shr, scl, gq); break;
-        default: tree_dev_one<7>(Sp, lane, nthr, pq, shr, scl, gq); break;
-      }
-    } else if (Sp->pow2) {
-      tree_dev_impl<true>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
-    } else {
-      tree_dev_impl<false>(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
-    }
-    // a later step of this wave reads what this one stored to device memory
-    __builtin_amdgcn_s_waitcnt(0);
+    tree_kind3(Sp, lane, nthr, nqw, pq, perq, shr, scl, nscale, gq, gstride);
     return;
   }
   if (nqw == 1)
@@ -1139,6 +1287,16 @@ __global__ __launch_bounds__(256) void k_tree_wave(TreeLaunch t) {
     if (k + 1 < nloop) fetch(k + 1);
     if (S->kind == 5) {
       tree_chain(t.lanes + S->tab, S->nc, c0, c1, lane, wpq, shr, wscl);
+    } else if (S->kind == 6) {
+      // a kind 3 pair: this step and the next
+      if (wn == 1) {
+        tree_pair(S, S + 1, lane, wpq, shr, wscl);
+      } else {
+        tree_kind3(S, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride);
+        tree_kind3(S + 1, lane, 64, wn, wpq, perq, shr, wscl, nscale, wgq, gstride);
+      }
+      ++k;
+      if (k + 1 < nloop) fetch(k + 1);
     } else if (S->kind == 4) {
       if (S->nss) {  // one whole step: the whole wave, one scale store
         const bool act = lane < S->nc;

@@ -176,3 +176,32 @@ def test_gate_chains_bit_identical(ctx, monkeypatch):
     psi = oracle.statevector(circ)
     ref = psi[np.array(xs, dtype=np.int64)]
     assert _err(chained, ref, n).max() < TOL
+
+
+@pytest.mark.parametrize("qw", [None, "8"])
+def test_kind3_pair_bit_identical(ctx, monkeypatch, qw):
+    """The batch kernel fuses the brickwork's kind 3 pair (a 1024-entry
+    intermediate written to the query's device workspace and read back by the
+    step that contracts it with a two-leg operand) into one kind 6 step that
+    keeps the intermediate in registers; with TN_TREE_PAIR=0 the two steps run
+    apart.  Both give the same 4096 results bit for bit, and the state
+    vector's within the FP32 bound.  With eight queries per workgroup (two per
+    wave) the kind 6 step runs as its two kind 3 steps."""
+    import torch
+    if qw:
+        monkeypatch.setenv("TN_TREE_QW", qw)
+    w = brickwork20()
+    circ, net, plan, n = w.circ, w.net, w.plan, w.circ.n
+    xs = random_bitstrings(n, Q, 1003)
+    dev = _device_basis(torch, n, xs)
+    p = ctx.load_network(net, plan.partition_of, w.num_partitions, plan.tree)
+    paired, _ = _strided_pinned(torch, p, net, n, dev)
+    ctx.free_plan(p)
+    monkeypatch.setenv("TN_TREE_PAIR", "0")
+    p = ctx.load_network(net, plan.partition_of, w.num_partitions, plan.tree)
+    plain, _ = _strided_pinned(torch, p, net, n, dev)
+    ctx.free_plan(p)
+    assert np.array_equal(paired, plain)
+    psi = oracle.statevector(circ)
+    ref = psi[np.array(xs, dtype=np.int64)]
+    assert _err(paired, ref, n).max() < TOL
