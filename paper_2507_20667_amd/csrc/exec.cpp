@@ -898,6 +898,23 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           g.ksplit = n.ksplit;
           g.ktile = n.ktile ? 1 : 0;
           g.tile = n.tile;
+          // an operand whose planes a GEMM child wrote (unscaled, in floats)
+          if (n.fuse_a) {
+            g.abs = A.bs * 2;
+            g.raw_a = 1;
+          }
+          if (n.fuse_b) {
+            g.bbs = B.bs * 2;
+            g.raw_b = 1;
+          }
+          // this GEMM's result written as its parent's operand planes
+          if (n.fo) {
+            g.fo_on = 1;
+            g.fo_nbits = n.fo_nbits;
+            g.fo_mbits = n.fo_mbits;
+            g.fo_plane = n.fo_plane;
+            memcpy(g.fo_d, n.fo_d, sizeof(g.fo_d));
+          }
           g.kchunk = n.kchunk;
           if (n.ksplit > 1) {
             g.part = (float2 *)(pbase + L.partial[j]);

@@ -271,6 +271,32 @@ __global__ __launch_bounds__(256, (FORM == kForm4M || WMW == 2) ? 2 : 1) void k_
   const bool partial = g.ksplit > 1;
   float2 *C = partial ? g.part + q * g.partbs + (int64_t)ks * g.M * g.N : g.C + q * g.cbs;
   const int64_t ldc = partial ? g.N : g.ldc;
+  // an operand read as it is (raw) scales the result instead: exact
+  const float post = (g.raw_a | g.raw_b) ? ldexpf(1.0f, -(g.raw_a ? ea : 0) - (g.raw_b ? eb : 0)) : 1.0f;
+  // the consumer's planes: d(m N + n) = dm(m) + dn(n), bit by bit; the
+  // tile-local parts of m and n occupy bits apart from m0's and n0's, so
+  // each part is the sum of the tile's (uniform) and the row's or column's
+  const bool fo = g.fo_on != 0;
+  auto fo_map = [&](int64_t idx, int base, int nbits) {
+    int64_t d = 0;
+    for (int b = 0; b < nbits; ++b)
+      if ((idx >> b) & 1) d += (int64_t)1 << g.fo_d[base + b];
+    return d;
+  };
+  // the row of accumulator entry v of 32-row block mb is wm 64 + mb 32 +
+  // (v / 4) 8 + (lane / 32) 4 + v % 4: the lane's part (wm, lane / 32, the
+  // tile's m0 and the column) goes into dl[nb], the entry's (bits 0, 1, 3, 4
+  // and 5 of the row, the same for every lane) into drow[mb][v]
+  float *P = (float *)(g.C + q * g.cbs);
+  int64_t dl[2] = {0, 0};
+  int64_t rbit[6] = {0, 0, 0, 0, 0, 0};
+  if (fo) {
+    const int64_t dt = fo_map(n0, 0, g.fo_nbits) + fo_map(m0 + wm * 64 + (lane >> 5) * 4, g.fo_nbits, g.fo_mbits);
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) dl[nb] = dt + fo_map(wn * 64 + nb * 32 + (lane & 31), 0, g.fo_nbits);
+#pragma unroll
+    for (int b = 0; b < 6; ++b) rbit[b] = b < g.fo_mbits ? (int64_t)1 << g.fo_d[g.fo_nbits + b] : 0;
+  }
   float mx = 0.0f;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -290,8 +316,18 @@ __global__ __launch_bounds__(256, (FORM == kForm4M || WMW == 2) ? 2 : 1) void k_
           re = t1 - t2;
           im = t3 - t1 - t2;
         }
+        re *= post;
+        im *= post;
         if (cm < g.M && cn < g.N) {
-          C[cm * ldc + cn] = make_float2(re, im);
+          if (fo) {
+            const int64_t drow = ((v & 1) ? rbit[0] : 0) + ((v & 2) ? rbit[1] : 0) + ((v & 4) ? rbit[3] : 0) +
+                                 ((v & 8) ? rbit[4] : 0) + (mb ? rbit[5] : 0);
+            const int64_t d = dl[nb] + drow;
+            P[d] = re;
+            P[d + g.fo_plane] = im;
+          } else {
+            C[cm * ldc + cn] = make_float2(re, im);
+          }
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
       }

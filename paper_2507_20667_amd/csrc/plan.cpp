@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <set>
 #include <unordered_map>
 
@@ -240,7 +242,51 @@ static Layout make_layout(const std::vector<int64_t> &labs, const Layout &a, con
   return L;
 }
 
-static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layout &B) {
+// FP32 plane GEMMs fused with a GEMM child (see Node::fuse_a, fo): the
+// child's result index m N + n (its layout, row-major) maps to the k-tiled
+// plane index of this GEMM's operand bit by bit when every dimension is a
+// power of two.  Bits of a leg keep their order; the operand's row-major
+// index o = r kdim + k becomes ((k / 16) rows + r) 16 + k % 16.  Fusion needs
+// the four lowest bits to map to themselves, so that 16 consecutive results
+// of a tile row land in 64 consecutive bytes of each plane.
+static bool fuse_bits(const Layout &X, const Layout &D, int64_t rows, int64_t kdim, uint8_t *d, int &nbits) {
+  auto lg = [](int64_t v) {
+    int b = 0;
+    while (((int64_t)1 << b) < v) ++b;
+    return ((int64_t)1 << b) == v ? b : -1;
+  };
+  const int rb = lg(rows), kb = lg(kdim);
+  if (rb < 0 || kb < 4 || X.rank() != D.rank()) return false;
+  std::map<int64_t, int> spos, opos;
+  int acc = 0;
+  for (int i = X.rank() - 1; i >= 0; --i) {
+    const int b = lg(X.dim[i]);
+    if (b < 0) return false;
+    spos[X.lab[i]] = acc;
+    acc += b;
+  }
+  nbits = acc;
+  if (acc > 48 || acc != rb + kb) return false;
+  int oacc = 0;
+  for (int i = D.rank() - 1; i >= 0; --i) {
+    opos[D.lab[i]] = oacc;
+    oacc += lg(D.dim[i]);
+  }
+  for (int i = 0; i < X.rank(); ++i) {
+    const int64_t l = X.lab[i];
+    if (!opos.count(l)) return false;
+    for (int c = 0; c < lg(X.dim[i]); ++c) {
+      const int ob = opos[l] + c;
+      d[spos[l] + c] = (uint8_t)(ob < 4 ? ob : ob < kb ? ob + rb : ob - kb + 4);
+    }
+  }
+  for (int b = 0; b < 4; ++b)
+    if (d[b] != b) return false;
+  return true;
+}
+
+static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layout &B,
+                               const std::set<int64_t> &pcon) {
   n.kind = NK_GEMM;
   n.ga = n.c1;
   n.gb = n.c2;
@@ -264,9 +310,27 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
     n.planes = (p->flags & TN_FORM_3M) ? 6 : 4;
   else if (k_all % 16 == 0)
     n.planes = 2;
+  // a GEMM child whose result this GEMM may read as planes it writes itself
+  // (FP32 planes both; the child not split in k): the larger one
+  const int nv = (int)p->leaf.size();
+  const bool fuse_on = !getenv("TN_GEMM_FUSE") || atoi(getenv("TN_GEMM_FUSE")) != 0;
+  auto fusable = [&](int c) {
+    if (c < nv || n.planes != 2) return false;
+    const Node &u = p->nodes[c - nv];
+    return u.kind == NK_GEMM && u.planes == 2 && u.ktile && u.ksplit == 1 && !u.fo;
+  };
+  int fx = 0;  // 1: A, 2: B
+  if (fusable(n.c1)) fx = 1;
+  if (fusable(n.c2) && (fx == 0 || B.size() > A.size())) fx = 2;
   if (n.planes > 0) {
-    sorder = !permA || permB ? sA : sB;
+    // k in the order of the fused operand, so that its child can write it
+    sorder = fx == 2 ? sB : fx == 1 ? sA : (!permA || permB ? sA : sB);
     permA = permB = true;
+    // the legs the parent contracts last among B's free legs: they are the
+    // lowest bits of this GEMM's result, which the parent may read as its
+    // k-tiled operand written by this GEMM
+    if (!pcon.empty())
+      std::stable_partition(FB.begin(), FB.end(), [&](int64_t l) { return pcon.count(l) == 0; });
   } else if (!permA && !permB) {
     if (sA != sB) {
       if (A.size() <= B.size()) {
@@ -370,6 +434,42 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   }
   n.ktile = n.planes > 0 && n.K % 16 == 0 &&
             (n.ksplit == 1 || n.kchunk % 16 == 0);
+  // fusion with the chosen child: its epilogue writes this GEMM's operand
+  // planes (unscaled; this GEMM scales its result instead)
+  if (fx && fuse_on && n.ktile) {
+    const bool fa = fx == 1;
+    const Layout &X = fa ? A : B;
+    Node &u = p->nodes[(fa ? n.c1 : n.c2) - nv];
+    uint8_t d[48];
+    int nbits = 0;
+    const Layout &D = fa ? n.pa.dst : n.pb.dst;
+    // (both vertices too large for a subtree batch, which writes complex64)
+    if (X.size() > kTreeMaxElems && fuse_bits(X, D, fa ? n.M : n.N, n.K, d, nbits) && u.N >= 16 &&
+        u.M * u.N == X.size()) {
+      u.fo = true;
+      memcpy(u.fo_d, d, sizeof(d));
+      int nb = 0, mb = 0;
+      while (((int64_t)1 << nb) < u.N) ++nb;
+      while (((int64_t)1 << mb) < u.M) ++mb;
+      u.fo_nbits = nb;
+      u.fo_mbits = mb;
+      u.fo_plane = X.size();
+      // the operand as the planes kernel reads it: [rows][K], k-tiled
+      if (fa) {
+        n.fuse_a = true;
+        n.pa.needed = false;
+        n.opA = 0;
+        n.lda = n.K;
+        permA = false;
+      } else {
+        n.fuse_b = true;
+        n.pb.needed = false;
+        n.opB = 1;
+        n.ldb = n.K;
+        permB = false;
+      }
+    }
+  }
   p->num_perm += (int)permA + (int)permB;
   return TN_OK;
 }
@@ -432,6 +532,17 @@ static bool node_in_bounds(const tn_plan *p, const Node &n, const std::vector<La
     const int64_t ea = n.opA == 0 ? (n.M - 1) * n.lda + n.K - 1 : (n.K - 1) * n.lda + n.M - 1;
     const int64_t eb = n.opB == 0 ? (n.K - 1) * n.ldb + n.N - 1 : (n.N - 1) * n.ldb + n.K - 1;
     const int64_t ec = (n.M - 1) * n.ldc + n.N - 1;
+    // a result written as planes: every index bit to a distinct bit below
+    // log2 of the result's size
+    if (n.fo) {
+      const int nb = n.fo_nbits + n.fo_mbits;
+      if (nb > 48 || ((int64_t)1 << nb) != n.out.size() || n.fo_plane != n.out.size()) return false;
+      int64_t seen = 0;
+      for (int b = 0; b < nb; ++b) {
+        if (n.fo_d[b] >= nb || ((seen >> n.fo_d[b]) & 1)) return false;
+        seen |= (int64_t)1 << n.fo_d[b];
+      }
+    }
     return n.M * n.K == sa && n.K * n.N == sb && ea < sa && eb < sb && ec < n.out.size();
   }
   const DotDesc &d = *(const DotDesc *)(blob + n.ddesc_off);
@@ -659,6 +770,18 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
   p->nodes.resize(nv - 1);
   u128 con_serial = 0, mem = 0;
   int64_t largest = 0;
+  // every tensor's leg set (a vertex's: the symmetric difference of its
+  // children's), known before the vertices are scheduled, so that a GEMM can
+  // order its result's legs by what its parent contracts
+  std::vector<std::vector<int64_t>> legset(nn);
+  for (int v = 0; v < nv; ++v) {
+    legset[v] = lay[v].lab;
+    std::sort(legset[v].begin(), legset[v].end());
+  }
+  for (int j = 0; j < nv - 1; ++j) {
+    const std::vector<int64_t> &a = legset[p->tree[2 * j]], &b = legset[p->tree[2 * j + 1]];
+    std::set_symmetric_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(legset[nv + j]));
+  }
   for (int j = 0; j < nv - 1; ++j) {
     Node &n = p->nodes[j];
     n.id = nv + j;
@@ -706,7 +829,15 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
       st = a_big ? schedule_stream(p, n, A, B, n.c1, n.c2) : schedule_stream(p, n, B, A, n.c2, n.c1);
       p->num_stream++;
     } else {
-      st = schedule_gemm(p, n, A, B);
+      // the legs of this vertex its parent contracts
+      std::set<int64_t> pcon;
+      const int pv = parent[n.id];
+      if (pv >= 0) {
+        const int sib = p->tree[2 * (pv - nv)] == n.id ? p->tree[2 * (pv - nv) + 1] : p->tree[2 * (pv - nv)];
+        std::set_intersection(legset[n.id].begin(), legset[n.id].end(), legset[sib].begin(), legset[sib].end(),
+                              std::inserter(pcon, pcon.begin()));
+      }
+      st = schedule_gemm(p, n, A, B, pcon);
       p->num_gemm++;
     }
     if (st) return st;
@@ -787,9 +918,10 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
   if (getenv("TN_DEBUG")) {
     for (const Node &n : p->nodes)
       if (n.kind == NK_GEMM)
-        fprintf(stderr, "[tn] gemm vertex %d: M %lld N %lld K %lld op %d%d perm %d%d variant %d tile %d ksplit %d\n",
+        fprintf(stderr, "[tn] gemm vertex %d: M %lld N %lld K %lld op %d%d perm %d%d variant %d tile %d ksplit %d planes %d fused %d%d writes %d\n",
                 n.id, (long long)n.M, (long long)n.N, (long long)n.K, n.opA, n.opB,
-                (int)n.pa.needed, (int)n.pb.needed, n.variant, n.tile, n.ksplit);
+                (int)n.pa.needed, (int)n.pb.needed, n.variant, n.tile, n.ksplit, n.planes,
+                (int)n.fuse_a, (int)n.fuse_b, (int)n.fo);
     fprintf(stderr, "[tn] plan: %d vertices, %d gemm, %d stream, %d in subtrees (%zu roots)\n",
             nv - 1, p->num_gemm, p->num_stream,
             (int)std::count(p->in_tree.begin(), p->in_tree.end(), (char)1), p->tree_roots.size());

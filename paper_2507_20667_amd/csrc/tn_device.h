@@ -100,6 +100,18 @@ struct GemmArgs {
   // 256, 2 = 256 x 64; of the BF16x3 4M kernels on k-tiled planes: 0 = 128 x
   // 128, 1 = 128 x 256, 2 = 256 x 128 (the two wave-group kernel)
   int32_t tile;
+  // FP32 plane kernel only.  raw_a / raw_b: that operand's planes hold its
+  // values as they are, not divided by 2^e of its scale record (a producer
+  // GEMM wrote them, see fo_on): the result is multiplied by 2^-e instead,
+  // which is exact, so it is the same as from divided planes.  fo_on: write
+  // the result not to C as complex64 but as the consumer's k-tiled operand
+  // planes (re at C + d, im at C + d + fo_plane, in floats), d of the result
+  // index m N + n given bit by bit: bit b of it goes to bit fo_d[b] of d
+  // (fo_nbits = log2 N bits of n, then those of m)
+  int32_t raw_a, raw_b;
+  int32_t fo_on, fo_nbits, fo_mbits;
+  int64_t fo_plane;
+  uint8_t fo_d[48];
 };
 
 // Block -> (k chunk ks, output tile t) of a GEMM launch.  Blocks go to the

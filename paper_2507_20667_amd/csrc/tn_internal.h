@@ -87,6 +87,15 @@ struct Node {
   int64_t M = 0, N = 0, K = 0, lda = 0, ldb = 0, ldc = 0;
   int variant = 0;
   int tile = 0;      // FP32 plane kernel tile shape (GemmArgs::tile)
+  // FP32 plane GEMMs fused with their GEMM children: fuse_a / fuse_b: that
+  // operand's planes are written by the child's epilogue (no permutation;
+  // read raw); fo: this GEMM writes its result as its parent's operand
+  // planes (GemmArgs::fo_*)
+  bool fuse_a = false, fuse_b = false;
+  bool fo = false;
+  int fo_nbits = 0, fo_mbits = 0;
+  int64_t fo_plane = 0;
+  uint8_t fo_d[48] = {0};
   // NK_DOT
   size_t ddesc_off = 0;
   int64_t nelem = 0;

@@ -55,3 +55,24 @@ def test_config3_amplitudes(setup, flags, tol):
           f"max err {worst:.2e}, largest intermediate {costs['largest_intermediate']}, "
           f"con_serial {costs['con_serial']}")
     ctx.free_plan(p)
+
+
+@pytest.mark.parametrize("flags", [lib.TN_PREC_FP32, lib.TN_PREC_FP32 | lib.TN_FORM_3M])
+def test_fused_gemm_epilogue_bit_identical(setup, flags, monkeypatch):
+    """The FP32 plane GEMMs that write their parent's operand planes in their
+    epilogue (the parent then reads them as they are and scales its result by
+    the power of two instead) give the same bits as the permuted operands."""
+    gold, circ, net, plan, ctx = setup
+    perms, amps = {}, {}
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("TN_GEMM_FUSE", fuse)
+        p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 8, plan.tree, None, flags)
+        perms[fuse] = lib.tn_plan_costs_get(p)["num_permutations"]
+        amps[fuse] = np.array([np.asarray(lib.tn_contract(p, amplitude_overrides(net, circ, x))[0]).reshape(-1)[0]
+                               for x in gold["bitstrings"]], dtype=np.complex128)
+        ctx.free_plan(p)
+    assert perms["1"] < perms["0"], perms
+    assert np.array_equal(amps["1"].view(np.uint64), amps["0"].view(np.uint64)), (amps["0"], amps["1"])
+    for i, x in enumerate(gold["bitstrings"]):
+        ref = complex(*gold["amplitudes"][str(x)])
+        assert abs(amps["1"][i] - ref) / max(abs(ref), 2.0 ** -15) < 1e-5

@@ -153,3 +153,26 @@ def test_single_tensor_and_scalar_plans_load():
     p = lib.tn_plan_load(None, [[], []], {}, [np.array(2.0), np.array(3.0)], [0, 1], 2, [(0, 1)])
     assert lib.tn_plan_costs_get(p)["con_serial"] == 1
     lib.tn_plan_free(p)
+
+
+def test_gemm_epilogue_fusion_in_plan(monkeypatch):
+    """On the 30-qubit random circuit (FP32, both forms) the three largest
+    plane GEMMs read their B operand as planes their GEMM child writes in its
+    epilogue: three permutations fewer; TN_GEMM_FUSE=0 keeps them, and the
+    BF16x3 plans (split planes, no fusion) are the same either way."""
+    from paper_2507_20667_amd.planner.workloads import random30
+    w = random30()
+
+    def perms(flags):
+        p = lib.tn_plan_load(None, w.net.legs, w.net.dims, w.net.tensors, w.plan.partition_of, 8, w.plan.tree,
+                             None, flags)
+        try:
+            return lib.tn_plan_costs_get(p)["num_permutations"]
+        finally:
+            lib.tn_plan_free(p)
+
+    flags = [lib.TN_PREC_FP32, lib.TN_PREC_FP32 | lib.TN_FORM_3M, lib.TN_PREC_BF16X3]
+    fused = [perms(f) for f in flags]
+    monkeypatch.setenv("TN_GEMM_FUSE", "0")
+    plain = [perms(f) for f in flags]
+    assert [a - b for a, b in zip(plain, fused)] == [3, 3, 0], (plain, fused)
