@@ -898,13 +898,14 @@ tn_status run_group(tn_ctx *ctx, tn_plan *p, const std::vector<QueryIO> &qs, tn_
           g.ksplit = n.ksplit;
           g.ktile = n.ktile ? 1 : 0;
           g.tile = n.tile;
-          // an operand whose planes a GEMM child wrote (unscaled, in floats)
+          // an operand whose planes a GEMM child wrote (unscaled): its batch
+          // stride in plane entries, two floats or four bf16 to a complex64
           if (n.fuse_a) {
-            g.abs = A.bs * 2;
+            g.abs = A.bs * (n.planes == 2 ? 2 : 4);
             g.raw_a = 1;
           }
           if (n.fuse_b) {
-            g.bbs = B.bs * 2;
+            g.bbs = B.bs * (n.planes == 2 ? 2 : 4);
             g.raw_b = 1;
           }
           // this GEMM's result written as its parent's operand planes

@@ -344,6 +344,18 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 
+// One result entry as its parent's four k-tiled bf16 operand planes (re hi,
+// re lo, im hi, im lo; the split of the operand permutation), entry d of each.
+__device__ __forceinline__ void store_planes4(uint16_t *P, int64_t plane, int64_t d, float re, float im) {
+  uint16_t h, l;
+  tn_split_bf16(re, h, l);
+  P[d] = h;
+  P[d + plane] = l;
+  tn_split_bf16(im, h, l);
+  P[d + 2 * plane] = h;
+  P[d + 3 * plane] = l;
+}
+
 // s_waitcnt immediate: vmcnt(v) expcnt(7) lgkmcnt(0)
 __host__ __device__ constexpr int dma_wait_imm(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4); }
 
@@ -481,6 +493,13 @@ __global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_d
   const bool partial = g.ksplit > 1;
   float2 *C = partial ? g.part + q * g.partbs + (int64_t)ks * g.M * g.N : g.C + q * g.cbs;
   const int64_t ldc = partial ? g.N : g.ldc;
+  // an operand read as it is (raw) scales the result instead: exact; the 4M
+  // form may write the result as its parent's four operand planes
+  const float post = (g.raw_a | g.raw_b) ? ldexpf(1.0f, -(g.raw_a ? ea : 0) - (g.raw_b ? eb : 0)) : 1.0f;
+  const bool fo = FORM == kForm4M && g.fo_on != 0;
+  uint16_t *P = (uint16_t *)(g.C + q * g.cbs);
+  PlaneOut po;
+  if (fo) po.init(g, m0 + wm * 64 + (lane >> 5) * 4, n0 + wn * 64 + (lane & 31));
   float mx = 0.0f;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -500,8 +519,13 @@ __global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_d
           re = t1 - t2;
           im = t3 - t1 - t2;
         }
+        re *= post;
+        im *= post;
         if (cm < g.M && cn < g.N) {
-          C[cm * ldc + cn] = make_float2(re, im);
+          if (fo)
+            store_planes4(P, g.fo_plane, po.at(mb, nb, v), re, im);
+          else
+            C[cm * ldc + cn] = make_float2(re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
       }
@@ -715,6 +739,13 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_pp(GemmArgs g) {
   float2 *C = partial ? g.part + q * g.partbs + (int64_t)ks * g.M * g.N : g.C + q * g.cbs;
   const int64_t ldc = partial ? g.N : g.ldc;
   const int rbase = (WIDE_A ? grp * BT : 0) + wm * 64, cbase = (WIDE_A ? 0 : grp * BT) + wn * 64;
+  // raw operands and the result as its parent's planes, as in the one-group
+  // kernel
+  const float post = (g.raw_a | g.raw_b) ? ldexpf(1.0f, -(g.raw_a ? ea : 0) - (g.raw_b ? eb : 0)) : 1.0f;
+  const bool fo = g.fo_on != 0;
+  uint16_t *P = (uint16_t *)(g.C + q * g.cbs);
+  PlaneOut po;
+  if (fo) po.init(g, m0 + rbase + (lane >> 5) * 4, n0 + cbase + (lane & 31));
   float mx = 0.0f;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -725,9 +756,12 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_pp(GemmArgs g) {
         const int row = rbase + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
         const int col = cbase + nb * 32 + (lane & 31);
         const int64_t cm = m0 + row, cn = n0 + col;
-        const float re = acc[mb][nb][0][v], im = acc[mb][nb][1][v];
+        const float re = acc[mb][nb][0][v] * post, im = acc[mb][nb][1][v] * post;
         if (cm < g.M && cn < g.N) {
-          C[cm * ldc + cn] = make_float2(re, im);
+          if (fo)
+            store_planes4(P, g.fo_plane, po.at(mb, nb, v), re, im);
+          else
+            C[cm * ldc + cn] = make_float2(re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
       }
@@ -742,6 +776,8 @@ hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g0, int form, int 
   GemmArgs g = g0;
   if (g.opA != 0 || g.opB != 1 || g.planes != (form == kForm3M ? 6 : 4)) return hipErrorInvalidValue;
   if (g.tile < 0 || g.tile > 2) return hipErrorInvalidValue;
+  if ((g.raw_a || g.raw_b || g.fo_on) && !g.ktile) return hipErrorInvalidValue;
+  if (g.fo_on && (form != kForm4M || g.ksplit > 1)) return hipErrorInvalidValue;
   // the two-group kernel: 4M from k-tiled planes with a wide tile
   const bool pp = g.ktile && form == kForm4M && g.tile != 0;
   g.tiles_m = (int)((g.M + (pp ? gemm_bf16_tile_m(g.tile) : BT) - 1) / (pp ? gemm_bf16_tile_m(g.tile) : BT));

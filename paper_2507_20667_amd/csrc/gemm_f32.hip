@@ -273,30 +273,11 @@ __global__ __launch_bounds__(256, (FORM == kForm4M || WMW == 2) ? 2 : 1) void k_
   const int64_t ldc = partial ? g.N : g.ldc;
   // an operand read as it is (raw) scales the result instead: exact
   const float post = (g.raw_a | g.raw_b) ? ldexpf(1.0f, -(g.raw_a ? ea : 0) - (g.raw_b ? eb : 0)) : 1.0f;
-  // the consumer's planes: d(m N + n) = dm(m) + dn(n), bit by bit; the
-  // tile-local parts of m and n occupy bits apart from m0's and n0's, so
-  // each part is the sum of the tile's (uniform) and the row's or column's
+  // or the result as its parent's operand planes
   const bool fo = g.fo_on != 0;
-  auto fo_map = [&](int64_t idx, int base, int nbits) {
-    int64_t d = 0;
-    for (int b = 0; b < nbits; ++b)
-      if ((idx >> b) & 1) d += (int64_t)1 << g.fo_d[base + b];
-    return d;
-  };
-  // the row of accumulator entry v of 32-row block mb is wm 64 + mb 32 +
-  // (v / 4) 8 + (lane / 32) 4 + v % 4: the lane's part (wm, lane / 32, the
-  // tile's m0 and the column) goes into dl[nb], the entry's (bits 0, 1, 3, 4
-  // and 5 of the row, the same for every lane) into drow[mb][v]
   float *P = (float *)(g.C + q * g.cbs);
-  int64_t dl[2] = {0, 0};
-  int64_t rbit[6] = {0, 0, 0, 0, 0, 0};
-  if (fo) {
-    const int64_t dt = fo_map(n0, 0, g.fo_nbits) + fo_map(m0 + wm * 64 + (lane >> 5) * 4, g.fo_nbits, g.fo_mbits);
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) dl[nb] = dt + fo_map(wn * 64 + nb * 32 + (lane & 31), 0, g.fo_nbits);
-#pragma unroll
-    for (int b = 0; b < 6; ++b) rbit[b] = b < g.fo_mbits ? (int64_t)1 << g.fo_d[g.fo_nbits + b] : 0;
-  }
+  PlaneOut po;
+  if (fo) po.init(g, m0 + wm * 64 + (lane >> 5) * 4, n0 + wn * 64 + (lane & 31));
   float mx = 0.0f;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -320,9 +301,7 @@ __global__ __launch_bounds__(256, (FORM == kForm4M || WMW == 2) ? 2 : 1) void k_
         im *= post;
         if (cm < g.M && cn < g.N) {
           if (fo) {
-            const int64_t drow = ((v & 1) ? rbit[0] : 0) + ((v & 2) ? rbit[1] : 0) + ((v & 4) ? rbit[3] : 0) +
-                                 ((v & 8) ? rbit[4] : 0) + (mb ? rbit[5] : 0);
-            const int64_t d = dl[nb] + drow;
+            const int64_t d = po.at(mb, nb, v);
             P[d] = re;
             P[d + g.fo_plane] = im;
           } else {
@@ -345,7 +324,7 @@ int gemm_planes_tile_n(int v) { return v == 1 ? 256 : v == 2 ? 64 : 128; }
 hipError_t launch_gemm_f32_planes(hipStream_t st, const GemmArgs &g0, int form, int nbatch) {
   GemmArgs g = g0;
   if (g.opA != 0 || g.opB != 1 || g.planes != 2 || !g.ktile || g.K % FBK != 0 ||
-      (form != kForm4M && form != kForm3M) || g.tile < 0 || g.tile > 2)
+      (form != kForm4M && form != kForm3M) || g.tile < 0 || g.tile > 2 || (g.fo_on && g.ksplit > 1))
     return hipErrorInvalidValue;
   const int tm = gemm_planes_tile_m(g.tile), tn = gemm_planes_tile_n(g.tile);
   g.tiles_m = (int)((g.M + tm - 1) / tm);

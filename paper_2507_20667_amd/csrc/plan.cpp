@@ -311,13 +311,15 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   else if (k_all % 16 == 0)
     n.planes = 2;
   // a GEMM child whose result this GEMM may read as planes it writes itself
-  // (FP32 planes both; the child not split in k): the larger one
+  // (both FP32 planes, or both BF16x3 4M; the child on k-tiled planes, not
+  // split in k): the larger one
   const int nv = (int)p->leaf.size();
   const bool fuse_on = !getenv("TN_GEMM_FUSE") || atoi(getenv("TN_GEMM_FUSE")) != 0;
+  const bool fuse_kind = n.planes == 2 || n.planes == 4;
   auto fusable = [&](int c) {
-    if (c < nv || n.planes != 2) return false;
+    if (c < nv || !fuse_kind) return false;
     const Node &u = p->nodes[c - nv];
-    return u.kind == NK_GEMM && u.planes == 2 && u.ktile && u.ksplit == 1 && !u.fo;
+    return u.kind == NK_GEMM && u.planes == n.planes && u.ktile && u.ksplit == 1 && !u.fo;
   };
   int fx = 0;  // 1: A, 2: B
   if (fusable(n.c1)) fx = 1;
@@ -329,7 +331,7 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
     // the legs the parent contracts last among B's free legs: they are the
     // lowest bits of this GEMM's result, which the parent may read as its
     // k-tiled operand written by this GEMM
-    if (!pcon.empty())
+    if (fuse_kind && !pcon.empty())
       std::stable_partition(FB.begin(), FB.end(), [&](int64_t l) { return pcon.count(l) == 0; });
   } else if (!permA && !permB) {
     if (sA != sB) {

@@ -100,18 +100,50 @@ struct GemmArgs {
   // 256, 2 = 256 x 64; of the BF16x3 4M kernels on k-tiled planes: 0 = 128 x
   // 128, 1 = 128 x 256, 2 = 256 x 128 (the two wave-group kernel)
   int32_t tile;
-  // FP32 plane kernel only.  raw_a / raw_b: that operand's planes hold its
-  // values as they are, not divided by 2^e of its scale record (a producer
-  // GEMM wrote them, see fo_on): the result is multiplied by 2^-e instead,
-  // which is exact, so it is the same as from divided planes.  fo_on: write
-  // the result not to C as complex64 but as the consumer's k-tiled operand
-  // planes (re at C + d, im at C + d + fo_plane, in floats), d of the result
-  // index m N + n given bit by bit: bit b of it goes to bit fo_d[b] of d
-  // (fo_nbits = log2 N bits of n, then those of m)
+  // Kernels on k-tiled planes only (FP32, and BF16x3 4M).  raw_a / raw_b:
+  // that operand's planes hold its values as they are, not divided by 2^e of
+  // its scale record (a producer GEMM wrote them, see fo_on): the result is
+  // multiplied by 2^-e instead, which is exact (and so is the bf16 split of
+  // a value times a power of two), so it is the same as from divided planes.
+  // fo_on: write the result not to C as complex64 but as the consumer's
+  // k-tiled operand planes, d of the result index m N + n given bit by bit
+  // (bit b of it goes to bit fo_d[b] of d; fo_nbits = log2 N bits of n, then
+  // those of m), plane p at C + p fo_plane + d: two float planes (re, im)
+  // from the FP32 kernel, four bf16 planes (re hi, re lo, im hi, im lo) from
+  // the BF16x3 4M kernels
   int32_t raw_a, raw_b;
   int32_t fo_on, fo_nbits, fo_mbits;
   int64_t fo_plane;
   uint8_t fo_d[48];
+};
+
+// Plane index of the result entries a lane holds (GemmArgs::fo_on).  In the
+// 32 x 32 accumulator tiles entry v of 32-row block mb and 32-column block nb
+// is row mlane + mb 32 + (v / 4) 8 + v % 4 and column ncol + nb 32, with
+// mlane = m0 + (the wave's row base) + (lane / 32) 4 and ncol = n0 + (the
+// wave's column base) + lane % 32.  The map is linear over disjoint bits: the
+// lane's part is mapped once, the entry's (row bits 0, 1, 3, 4, 5, the same
+// for every lane) is a sum of per-bit terms.
+struct PlaneOut {
+  int64_t dl[2];
+  int64_t rbit[6];
+  __device__ __forceinline__ static int64_t map(const GemmArgs &g, int64_t idx, int base, int nbits) {
+    int64_t d = 0;
+    for (int b = 0; b < nbits; ++b)
+      if ((idx >> b) & 1) d += (int64_t)1 << g.fo_d[base + b];
+    return d;
+  }
+  __device__ __forceinline__ void init(const GemmArgs &g, int64_t mlane, int64_t ncol) {
+    const int64_t dm = map(g, mlane, g.fo_nbits, g.fo_mbits);
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) dl[nb] = dm + map(g, ncol + nb * 32, 0, g.fo_nbits);
+#pragma unroll
+    for (int b = 0; b < 6; ++b) rbit[b] = b < g.fo_mbits ? (int64_t)1 << g.fo_d[g.fo_nbits + b] : 0;
+  }
+  __device__ __forceinline__ int64_t at(int mb, int nb, int v) const {
+    return dl[nb] + ((v & 1) ? rbit[0] : 0) + ((v & 2) ? rbit[1] : 0) + ((v & 4) ? rbit[3] : 0) +
+           ((v & 8) ? rbit[4] : 0) + (mb ? rbit[5] : 0);
+  }
 };
 
 // Block -> (k chunk ks, output tile t) of a GEMM launch.  Blocks go to the
