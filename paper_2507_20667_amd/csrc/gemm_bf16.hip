@@ -345,15 +345,15 @@ typedef __attribute__((address_space(3))) void lds_void;
 __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 
 // One result entry as its parent's four k-tiled bf16 operand planes (re hi,
-// re lo, im hi, im lo; the split of the operand permutation), entry d of each.
-__device__ __forceinline__ void store_planes4(uint16_t *P, int64_t plane, int64_t d, float re, float im) {
-  uint16_t h, l;
-  tn_split_bf16(re, h, l);
-  P[d] = h;
-  P[d + plane] = l;
-  tn_split_bf16(im, h, l);
-  P[d + 2 * plane] = h;
-  P[d + 3 * plane] = l;
+// re lo, im hi, im lo at P[0..3] + d bytes; the split of the operand
+// permutation).
+__device__ __forceinline__ void store_planes4(uint8_t *const (&P)[4], uint32_t d, float re, float im) {
+  uint32_t h, l;
+  tn_split_bf16x2(re, im, h, l);
+  *(uint16_t *)(P[0] + d) = (uint16_t)h;
+  *(uint16_t *)(P[1] + d) = (uint16_t)l;
+  *(uint16_t *)(P[2] + d) = (uint16_t)(h >> 16);
+  *(uint16_t *)(P[3] + d) = (uint16_t)(l >> 16);
 }
 
 // s_waitcnt immediate: vmcnt(v) expcnt(7) lgkmcnt(0)
@@ -497,8 +497,9 @@ __global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_d
   // form may write the result as its parent's four operand planes
   const float post = (g.raw_a | g.raw_b) ? ldexpf(1.0f, -(g.raw_a ? ea : 0) - (g.raw_b ? eb : 0)) : 1.0f;
   const bool fo = FORM == kForm4M && g.fo_on != 0;
-  uint16_t *P = (uint16_t *)(g.C + q * g.cbs);
-  PlaneOut po;
+  uint8_t *const P0 = (uint8_t *)(g.C + q * g.cbs);
+  uint8_t *const P[4] = {P0, P0 + g.fo_plane * 2, P0 + g.fo_plane * 4, P0 + g.fo_plane * 6};
+  PlaneOut<2> po;
   if (fo) po.init(g, m0 + wm * 64 + (lane >> 5) * 4, n0 + wn * 64 + (lane & 31));
   float mx = 0.0f;
 #pragma unroll
@@ -523,7 +524,7 @@ __global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_d
         im *= post;
         if (cm < g.M && cn < g.N) {
           if (fo)
-            store_planes4(P, g.fo_plane, po.at(mb, nb, v), re, im);
+            store_planes4(P, po.at(mb, nb, v), re, im);
           else
             C[cm * ldc + cn] = make_float2(re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
@@ -743,8 +744,9 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_pp(GemmArgs g) {
   // kernel
   const float post = (g.raw_a | g.raw_b) ? ldexpf(1.0f, -(g.raw_a ? ea : 0) - (g.raw_b ? eb : 0)) : 1.0f;
   const bool fo = g.fo_on != 0;
-  uint16_t *P = (uint16_t *)(g.C + q * g.cbs);
-  PlaneOut po;
+  uint8_t *const P0 = (uint8_t *)(g.C + q * g.cbs);
+  uint8_t *const P[4] = {P0, P0 + g.fo_plane * 2, P0 + g.fo_plane * 4, P0 + g.fo_plane * 6};
+  PlaneOut<2> po;
   if (fo) po.init(g, m0 + rbase + (lane >> 5) * 4, n0 + cbase + (lane & 31));
   float mx = 0.0f;
 #pragma unroll
@@ -759,7 +761,7 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_pp(GemmArgs g) {
         const float re = acc[mb][nb][0][v] * post, im = acc[mb][nb][1][v] * post;
         if (cm < g.M && cn < g.N) {
           if (fo)
-            store_planes4(P, g.fo_plane, po.at(mb, nb, v), re, im);
+            store_planes4(P, po.at(mb, nb, v), re, im);
           else
             C[cm * ldc + cn] = make_float2(re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));

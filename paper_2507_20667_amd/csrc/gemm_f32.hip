@@ -275,8 +275,8 @@ __global__ __launch_bounds__(256, (FORM == kForm4M || WMW == 2) ? 2 : 1) void k_
   const float post = (g.raw_a | g.raw_b) ? ldexpf(1.0f, -(g.raw_a ? ea : 0) - (g.raw_b ? eb : 0)) : 1.0f;
   // or the result as its parent's operand planes
   const bool fo = g.fo_on != 0;
-  float *P = (float *)(g.C + q * g.cbs);
-  PlaneOut po;
+  uint8_t *P = (uint8_t *)(g.C + q * g.cbs), *P1 = P + g.fo_plane * 4;
+  PlaneOut<4> po;
   if (fo) po.init(g, m0 + wm * 64 + (lane >> 5) * 4, n0 + wn * 64 + (lane & 31));
   float mx = 0.0f;
 #pragma unroll
@@ -301,9 +301,9 @@ __global__ __launch_bounds__(256, (FORM == kForm4M || WMW == 2) ? 2 : 1) void k_
         im *= post;
         if (cm < g.M && cn < g.N) {
           if (fo) {
-            const int64_t d = po.at(mb, nb, v);
-            P[d] = re;
-            P[d + g.fo_plane] = im;
+            const uint32_t d = po.at(mb, nb, v);
+            *(float *)(P + d) = re;
+            *(float *)(P1 + d) = im;
           } else {
             C[cm * ldc + cn] = make_float2(re, im);
           }

@@ -285,8 +285,61 @@ static bool fuse_bits(const Layout &X, const Layout &D, int64_t rows, int64_t kd
   return true;
 }
 
+// A GEMM whose result its parent may read as k-tiled planes written by this
+// GEMM orders B's free legs [others..., contracted by the parent...] (the
+// latter are the result's lowest bits, the parent's k).  The plane index of
+// an entry has k % 16 in bits 0-3 and the parent operand's row in the bits
+// above; when the result bits just above the lowest four are that row's
+// lowest bits, a tile's 32 consecutive columns (a wave's store) land in 32
+// consecutive plane entries instead of two runs of 16.  So move up to two
+// bits' worth of free legs between the lowest four bits and the rest of the
+// parent-contracted block: legs the parent keeps as its own lowest result
+// bits (those the grandparent contracts, which the parent orders last), or
+// any kept leg when the grandparent contracts none of them.  FB[0, npc) are
+// the legs the parent keeps, FB[npc, end) those it contracts.
+static void interleave_rows(std::vector<int64_t> &FB, int npc, const Layout &B, const Layout &A,
+                            const std::set<int64_t> &pcon, const std::set<int64_t> &pcon2) {
+  auto bits = [&](int64_t l) {
+    const int64_t d = B.dim[B.find(l)];
+    int b = 0;
+    while (((int64_t)1 << b) < d) ++b;
+    return ((int64_t)1 << b) == d ? b : -1;
+  };
+  // the parent-contracted legs that make the lowest four bits
+  int low = (int)FB.size(), acc = 0;
+  while (low > npc && acc < 4) {
+    const int b = bits(FB[low - 1]);
+    if (b < 0) return;
+    acc += b;
+    --low;
+  }
+  if (acc != 4 || low == npc) return;
+  // does the grandparent contract any leg the parent keeps from this result?
+  bool kept2 = false;
+  for (int64_t l : A.lab)
+    if (pcon.count(l) == 0 && pcon2.count(l)) kept2 = true;
+  for (int i = 0; i < npc; ++i)
+    if (pcon2.count(FB[i])) kept2 = true;
+  std::vector<int64_t> rows;
+  int rb = 0;
+  for (int i = npc - 1; i >= 0 && rb < 2; --i) {
+    const int b = bits(FB[i]);
+    if (b < 1 || rb + b > 2 || (kept2 && !pcon2.count(FB[i]))) continue;
+    rows.insert(rows.begin(), FB[i]);
+    rb += b;
+  }
+  if (rows.empty()) return;
+  std::vector<int64_t> out;
+  for (int i = 0; i < npc; ++i)
+    if (std::find(rows.begin(), rows.end(), FB[i]) == rows.end()) out.push_back(FB[i]);
+  out.insert(out.end(), FB.begin() + npc, FB.begin() + low);
+  out.insert(out.end(), rows.begin(), rows.end());
+  out.insert(out.end(), FB.begin() + low, FB.end());
+  FB = out;
+}
+
 static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layout &B,
-                               const std::set<int64_t> &pcon) {
+                               const std::set<int64_t> &pcon, const std::set<int64_t> &pcon2) {
   n.kind = NK_GEMM;
   n.ga = n.c1;
   n.gb = n.c2;
@@ -331,8 +384,10 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
     // the legs the parent contracts last among B's free legs: they are the
     // lowest bits of this GEMM's result, which the parent may read as its
     // k-tiled operand written by this GEMM
-    if (fuse_kind && !pcon.empty())
-      std::stable_partition(FB.begin(), FB.end(), [&](int64_t l) { return pcon.count(l) == 0; });
+    if (fuse_kind && !pcon.empty()) {
+      const auto mid = std::stable_partition(FB.begin(), FB.end(), [&](int64_t l) { return pcon.count(l) == 0; });
+      interleave_rows(FB, (int)(mid - FB.begin()), B, A, pcon, pcon2);
+    }
   } else if (!permA && !permB) {
     if (sA != sB) {
       if (A.size() <= B.size()) {
@@ -445,9 +500,10 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
     uint8_t d[48];
     int nbits = 0;
     const Layout &D = fa ? n.pa.dst : n.pb.dst;
-    // (both vertices too large for a subtree batch, which writes complex64)
-    if (X.size() > kTreeMaxElems && fuse_bits(X, D, fa ? n.M : n.N, n.K, d, nbits) && u.N >= 16 &&
-        u.M * u.N == X.size()) {
+    // (both vertices too large for a subtree batch, which writes complex64;
+    // the planes, 8 bytes an entry, within 4 GiB)
+    if (X.size() > kTreeMaxElems && X.size() <= ((int64_t)1 << 29) &&
+        fuse_bits(X, D, fa ? n.M : n.N, n.K, d, nbits) && u.N >= 16 && u.M * u.N == X.size()) {
       u.fo = true;
       memcpy(u.fo_d, d, sizeof(d));
       int nb = 0, mb = 0;
@@ -538,7 +594,7 @@ static bool node_in_bounds(const tn_plan *p, const Node &n, const std::vector<La
     // log2 of the result's size
     if (n.fo) {
       const int nb = n.fo_nbits + n.fo_mbits;
-      if (nb > 48 || ((int64_t)1 << nb) != n.out.size() || n.fo_plane != n.out.size()) return false;
+      if (nb > 29 || ((int64_t)1 << nb) != n.out.size() || n.fo_plane != n.out.size()) return false;
       int64_t seen = 0;
       for (int b = 0; b < nb; ++b) {
         if (n.fo_d[b] >= nb || ((seen >> n.fo_d[b]) & 1)) return false;
@@ -831,15 +887,19 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
       st = a_big ? schedule_stream(p, n, A, B, n.c1, n.c2) : schedule_stream(p, n, B, A, n.c2, n.c1);
       p->num_stream++;
     } else {
-      // the legs of this vertex its parent contracts
-      std::set<int64_t> pcon;
-      const int pv = parent[n.id];
-      if (pv >= 0) {
-        const int sib = p->tree[2 * (pv - nv)] == n.id ? p->tree[2 * (pv - nv) + 1] : p->tree[2 * (pv - nv)];
-        std::set_intersection(legset[n.id].begin(), legset[n.id].end(), legset[sib].begin(), legset[sib].end(),
-                              std::inserter(pcon, pcon.begin()));
-      }
-      st = schedule_gemm(p, n, A, B, pcon);
+      // the legs of this vertex its parent contracts, and the legs of the
+      // parent's result that the grandparent contracts
+      auto contracted = [&](int v, std::set<int64_t> &out) {
+        const int pv = parent[v];
+        if (pv < 0) return false;
+        const int sib = p->tree[2 * (pv - nv)] == v ? p->tree[2 * (pv - nv) + 1] : p->tree[2 * (pv - nv)];
+        std::set_intersection(legset[v].begin(), legset[v].end(), legset[sib].begin(), legset[sib].end(),
+                              std::inserter(out, out.begin()));
+        return true;
+      };
+      std::set<int64_t> pcon, pcon2;
+      if (contracted(n.id, pcon)) contracted(parent[n.id], pcon2);
+      st = schedule_gemm(p, n, A, B, pcon, pcon2);
       p->num_gemm++;
     }
     if (st) return st;
@@ -919,11 +979,16 @@ tn_status build_plan(tn_plan *p, const tn_plan_desc *d) {
   p->plain = make_exec_layout(p, {}, false, false);
   if (getenv("TN_DEBUG")) {
     for (const Node &n : p->nodes)
-      if (n.kind == NK_GEMM)
-        fprintf(stderr, "[tn] gemm vertex %d: M %lld N %lld K %lld op %d%d perm %d%d variant %d tile %d ksplit %d planes %d fused %d%d writes %d\n",
+      if (n.kind == NK_GEMM) {
+        // (writes: the run of result bits that map to themselves, 2^run
+        // consecutive entries of a plane)
+        int run = 0;
+        while (n.fo && run < n.fo_nbits && n.fo_d[run] == run) ++run;
+        fprintf(stderr, "[tn] gemm vertex %d: M %lld N %lld K %lld op %d%d perm %d%d variant %d tile %d ksplit %d planes %d fused %d%d writes %d (run %d)\n",
                 n.id, (long long)n.M, (long long)n.N, (long long)n.K, n.opA, n.opB,
                 (int)n.pa.needed, (int)n.pb.needed, n.variant, n.tile, n.ksplit, n.planes,
-                (int)n.fuse_a, (int)n.fuse_b, (int)n.fo);
+                (int)n.fuse_a, (int)n.fuse_b, (int)n.fo, run);
+      }
     fprintf(stderr, "[tn] plan: %d vertices, %d gemm, %d stream, %d in subtrees (%zu roots)\n",
             nv - 1, p->num_gemm, p->num_stream,
             (int)std::count(p->in_tree.begin(), p->in_tree.end(), (char)1), p->tree_roots.size());

@@ -110,23 +110,26 @@ struct GemmArgs {
   // (bit b of it goes to bit fo_d[b] of d; fo_nbits = log2 N bits of n, then
   // those of m), plane p at C + p fo_plane + d: two float planes (re, im)
   // from the FP32 kernel, four bf16 planes (re hi, re lo, im hi, im lo) from
-  // the BF16x3 4M kernels
+  // the BF16x3 4M kernels; 8 fo_plane bytes at most 2^32
   int32_t raw_a, raw_b;
   int32_t fo_on, fo_nbits, fo_mbits;
   int64_t fo_plane;
   uint8_t fo_d[48];
 };
 
-// Plane index of the result entries a lane holds (GemmArgs::fo_on).  In the
-// 32 x 32 accumulator tiles entry v of 32-row block mb and 32-column block nb
-// is row mlane + mb 32 + (v / 4) 8 + v % 4 and column ncol + nb 32, with
-// mlane = m0 + (the wave's row base) + (lane / 32) 4 and ncol = n0 + (the
-// wave's column base) + lane % 32.  The map is linear over disjoint bits: the
-// lane's part is mapped once, the entry's (row bits 0, 1, 3, 4, 5, the same
-// for every lane) is a sum of per-bit terms.
+// Plane offsets of the result entries a lane holds (GemmArgs::fo_on), in
+// bytes from the first plane's base (ES bytes an entry; the planner keeps
+// every plane within 4 GiB of it, so offsets are 32-bit).  In the 32 x 32
+// accumulator tiles entry v of 32-row block mb and 32-column block nb is row
+// mlane + mb 32 + (v / 4) 8 + v % 4 and column ncol + nb 32, with mlane = m0 +
+// (the wave's row base) + (lane / 32) 4 and ncol = n0 + (the wave's column
+// base) + lane % 32.  The map is linear over disjoint bits: the lane's part is
+// mapped once, the entry's (row bits 0, 1, 3, 4, 5, the same for every lane)
+// is a sum of per-bit terms.
+template <int ES>
 struct PlaneOut {
-  int64_t dl[2];
-  int64_t rbit[6];
+  uint32_t dl[2];
+  uint32_t rbit[6];
   __device__ __forceinline__ static int64_t map(const GemmArgs &g, int64_t idx, int base, int nbits) {
     int64_t d = 0;
     for (int b = 0; b < nbits; ++b)
@@ -136,13 +139,13 @@ struct PlaneOut {
   __device__ __forceinline__ void init(const GemmArgs &g, int64_t mlane, int64_t ncol) {
     const int64_t dm = map(g, mlane, g.fo_nbits, g.fo_mbits);
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) dl[nb] = dm + map(g, ncol + nb * 32, 0, g.fo_nbits);
+    for (int nb = 0; nb < 2; ++nb) dl[nb] = (uint32_t)((dm + map(g, ncol + nb * 32, 0, g.fo_nbits)) * ES);
 #pragma unroll
-    for (int b = 0; b < 6; ++b) rbit[b] = b < g.fo_mbits ? (int64_t)1 << g.fo_d[g.fo_nbits + b] : 0;
+    for (int b = 0; b < 6; ++b) rbit[b] = b < g.fo_mbits ? (uint32_t)(((int64_t)1 << g.fo_d[g.fo_nbits + b]) * ES) : 0u;
   }
-  __device__ __forceinline__ int64_t at(int mb, int nb, int v) const {
-    return dl[nb] + ((v & 1) ? rbit[0] : 0) + ((v & 2) ? rbit[1] : 0) + ((v & 4) ? rbit[3] : 0) +
-           ((v & 8) ? rbit[4] : 0) + (mb ? rbit[5] : 0);
+  __device__ __forceinline__ uint32_t at(int mb, int nb, int v) const {
+    return dl[nb] + (((v & 1) ? rbit[0] : 0u) + ((v & 2) ? rbit[1] : 0u) + ((v & 4) ? rbit[3] : 0u) +
+                     ((v & 8) ? rbit[4] : 0u) + (mb ? rbit[5] : 0u));
   }
 };
 
@@ -347,15 +350,23 @@ __device__ __forceinline__ int tn_scale_exp(uint32_t bits) {
 }
 
 // Split x = h + l with h = bf16(x) and l = bf16(x - h), both rounded to nearest
-// even (finite inputs): the two terms carry 16 significant bits of x.
-__device__ __forceinline__ uint32_t tn_bf16_rne(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
+// even (finite inputs; the hardware conversion): the two terms carry 16
+// significant bits of x.
+typedef __bf16 tn_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float tn_f32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void tn_split_bf16(float x, uint16_t &h, uint16_t &l) {
-  const uint32_t hb = tn_bf16_rne(x);
-  h = (uint16_t)hb;
-  l = (uint16_t)tn_bf16_rne(x - __uint_as_float(hb << 16));
+  const __bf16 hb = (__bf16)x;
+  h = __builtin_bit_cast(uint16_t, hb);
+  l = __builtin_bit_cast(uint16_t, (__bf16)(x - (float)hb));
+}
+// The same for two values at once (one packed conversion for the high and
+// one for the low terms): h and l hold the terms of a in bits 0-15 and of b
+// in bits 16-31.
+__device__ __forceinline__ void tn_split_bf16x2(float a, float b, uint32_t &h, uint32_t &l) {
+  const tn_f32x2 v = {a, b};
+  h = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, tn_bf16x2));
+  const tn_f32x2 r = {a - __uint_as_float(h << 16), b - __uint_as_float(h & 0xffff0000u)};
+  l = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, tn_bf16x2));
 }
 
 enum GemmForm { kForm4M = 0, kForm3M = 1 };
