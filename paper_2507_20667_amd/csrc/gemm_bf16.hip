@@ -502,34 +502,52 @@ __global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_d
   PlaneOut<2> po;
   if (fo) po.init(g, m0 + wm * 64 + (lane >> 5) * 4, n0 + wn * 64 + (lane & 31));
   float mx = 0.0f;
+  auto value = [&](int mb, int nb, int v, float &re, float &im) {
+    if (FORM == kForm4M) {
+      re = acc[mb][nb][0][v];
+      im = acc[mb][nb][1][v];
+    } else {
+      const float t1 = acc[mb][nb][0][v], t2 = acc[mb][nb][1][v], t3 = acc[mb][nb][NACC - 1][v];
+      re = t1 - t2;
+      im = t3 - t1 - t2;
+    }
+    re *= post;
+    im *= post;
+  };
+  if (fo && m0 + BT <= g.M && n0 + BT <= g.N) {
+    // a whole tile of planes: no entry to test
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+      for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int row = wm * 64 + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        const int col = wn * 64 + nb * 32 + (lane & 31);
-        const int64_t cm = m0 + row, cn = n0 + col;
-        float re, im;
-        if (FORM == kForm4M) {
-          re = acc[mb][nb][0][v];
-          im = acc[mb][nb][1][v];
-        } else {
-          const float t1 = acc[mb][nb][0][v], t2 = acc[mb][nb][1][v], t3 = acc[mb][nb][NACC - 1][v];
-          re = t1 - t2;
-          im = t3 - t1 - t2;
-        }
-        re *= post;
-        im *= post;
-        if (cm < g.M && cn < g.N) {
-          if (fo)
-            store_planes4(P, po.at(mb, nb, v), re, im);
-          else
-            C[cm * ldc + cn] = make_float2(re, im);
+        for (int v = 0; v < 16; ++v) {
+          float re, im;
+          value(mb, nb, v, re, im);
+          store_planes4(P, po.at(mb, nb, v), re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
-      }
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wm * 64 + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+          const int col = wn * 64 + nb * 32 + (lane & 31);
+          const int64_t cm = m0 + row, cn = n0 + col;
+          float re, im;
+          value(mb, nb, v, re, im);
+          if (cm < g.M && cn < g.N) {
+            if (fo)
+              store_planes4(P, po.at(mb, nb, v), re, im);
+            else
+              C[cm * ldc + cn] = make_float2(re, im);
+            mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+          }
+        }
+  }
   if (!partial) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
@@ -749,24 +767,38 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_pp(GemmArgs g) {
   PlaneOut<2> po;
   if (fo) po.init(g, m0 + rbase + (lane >> 5) * 4, n0 + cbase + (lane & 31));
   float mx = 0.0f;
+  if (fo && m0 + RA <= g.M && n0 + RB <= g.N) {
+    // a whole tile of planes: no entry to test
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+      for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int row = rbase + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        const int col = cbase + nb * 32 + (lane & 31);
-        const int64_t cm = m0 + row, cn = n0 + col;
-        const float re = acc[mb][nb][0][v] * post, im = acc[mb][nb][1][v] * post;
-        if (cm < g.M && cn < g.N) {
-          if (fo)
-            store_planes4(P, po.at(mb, nb, v), re, im);
-          else
-            C[cm * ldc + cn] = make_float2(re, im);
+        for (int v = 0; v < 16; ++v) {
+          const float re = acc[mb][nb][0][v] * post, im = acc[mb][nb][1][v] * post;
+          store_planes4(P, po.at(mb, nb, v), re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
-      }
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = rbase + mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+          const int col = cbase + nb * 32 + (lane & 31);
+          const int64_t cm = m0 + row, cn = n0 + col;
+          const float re = acc[mb][nb][0][v] * post, im = acc[mb][nb][1][v] * post;
+          if (cm < g.M && cn < g.N) {
+            if (fo)
+              store_planes4(P, po.at(mb, nb, v), re, im);
+            else
+              C[cm * ldc + cn] = make_float2(re, im);
+            mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+          }
+        }
+  }
   if (!partial) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
