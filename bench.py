@@ -352,6 +352,9 @@ def gemm_phase_leg(lib, reps=3):
                      "con_serial_over_con_par": float(costs["con_serial"]) / float(costs["con_par"]),
                      "batched_ms_per_amplitude": bamp_ms,
                      "permute_ms_per_amplitude": st["permute"]["seconds"] / reps * 1e3,
+                     "permute_launches_per_amplitude": st["permute"]["launches"] // reps,
+                     "permute_hbm_gbs": (st["permute"]["algo_bytes"] / st["permute"]["seconds"] / 1e9
+                                         if st["permute"]["seconds"] else None),
                      "con_serial": costs["con_serial"],
                      "largest_intermediate": costs["largest_intermediate"],
                      "max_rel_err_vs_statevector": worst, "amplitudes_checked": len(gold["bitstrings"])}
@@ -759,7 +762,11 @@ def headline_random30(lib, torch, args):
                        "launches": perm["launches"], "ms_per_step": perm["seconds"] / K * 1e3,
                        "algo_bytes_per_step": perm["algo_bytes"] / K,
                        "note": "algorithmic bytes: 8 read + 8 written per complex entry for float "
-                               "planes, 8 + 2 per bf16 plane"},
+                               "planes, 8 + 2 per bf16 plane; the operands of the three largest GEMMs "
+                               "are written as planes by the GEMM before them (fused epilogues), so the "
+                               "permutations left are of 2^20 to 2^25 entries; the rate on permutations "
+                               "of 2^27-entry operands is largest_config_gemm_phase.bf16x3_3m."
+                               "permute_hbm_gbs (six bf16 planes, not fused)"},
            "kernel_seconds_per_step": kern_s / K,
            "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},
            "con_serial": con_serial, "con_dist": costs["con_dist"],
