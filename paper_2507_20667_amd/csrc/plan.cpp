@@ -506,6 +506,14 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
         fuse_bits(X, D, fa ? n.M : n.N, n.K, d, nbits) && u.N >= 16 && u.M * u.N == X.size()) {
       u.fo = true;
       memcpy(u.fo_d, d, sizeof(d));
+      // a BF16x3 4M producer on the two wave-group kernel where its shape
+      // fills that tile: its 2-byte plane stores cost the one-group kernel a
+      // third of its time on short k (the tuning table times GEMMs that
+      // write complex64)
+      if (u.planes == 4 && u.tile == 0 && u.ksplit == 1) {
+        if (u.M >= 256 && u.N >= 128) u.tile = 2;
+        else if (u.N >= 256 && u.M >= 128) u.tile = 1;
+      }
       int nb = 0, mb = 0;
       while (((int64_t)1 << nb) < u.N) ++nb;
       while (((int64_t)1 << mb) < u.M) ++mb;
