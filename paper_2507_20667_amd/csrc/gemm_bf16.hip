@@ -344,16 +344,23 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 
-// One result entry as its parent's four k-tiled bf16 operand planes (re hi,
-// re lo, im hi, im lo at P[0..3] + d bytes; the split of the operand
-// permutation).
-__device__ __forceinline__ void store_planes4(uint8_t *const (&P)[4], uint32_t d, float re, float im) {
+// One result entry as its parent's k-tiled bf16 operand planes (re hi, re
+// lo, im hi, im lo at P[0..3] + d bytes, and for a 3M parent (re+im) hi and
+// lo at P[4], P[5]; the split of the operand permutation).
+template <int NPL>
+__device__ __forceinline__ void store_planes(uint8_t *const (&P)[6], uint32_t d, float re, float im) {
   uint32_t h, l;
   tn_split_bf16x2(re, im, h, l);
   *(uint16_t *)(P[0] + d) = (uint16_t)h;
   *(uint16_t *)(P[1] + d) = (uint16_t)l;
   *(uint16_t *)(P[2] + d) = (uint16_t)(h >> 16);
   *(uint16_t *)(P[3] + d) = (uint16_t)(l >> 16);
+  if (NPL == 6) {
+    uint16_t sh, sl;
+    tn_split_bf16(re + im, sh, sl);
+    *(uint16_t *)(P[4] + d) = sh;
+    *(uint16_t *)(P[5] + d) = sl;
+  }
 }
 
 // s_waitcnt immediate: vmcnt(v) expcnt(7) lgkmcnt(0)
@@ -493,12 +500,13 @@ __global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_d
   const bool partial = g.ksplit > 1;
   float2 *C = partial ? g.part + q * g.partbs + (int64_t)ks * g.M * g.N : g.C + q * g.cbs;
   const int64_t ldc = partial ? g.N : g.ldc;
-  // an operand read as it is (raw) scales the result instead: exact; the 4M
-  // form may write the result as its parent's four operand planes
+  // an operand read as it is (raw) scales the result instead: exact; the
+  // result may go out as its parent's operand planes (four, six for 3M)
   const float post = (g.raw_a | g.raw_b) ? ldexpf(1.0f, -(g.raw_a ? ea : 0) - (g.raw_b ? eb : 0)) : 1.0f;
-  const bool fo = FORM == kForm4M && g.fo_on != 0;
+  const bool fo = g.fo_on != 0;
   uint8_t *const P0 = (uint8_t *)(g.C + q * g.cbs);
-  uint8_t *const P[4] = {P0, P0 + g.fo_plane * 2, P0 + g.fo_plane * 4, P0 + g.fo_plane * 6};
+  uint8_t *const P[6] = {P0, P0 + g.fo_plane * 2, P0 + g.fo_plane * 4, P0 + g.fo_plane * 6, P0 + g.fo_plane * 8,
+                         P0 + g.fo_plane * 10};
   PlaneOut<2> po;
   if (fo) po.init(g, m0 + wm * 64 + (lane >> 5) * 4, n0 + wn * 64 + (lane & 31));
   float mx = 0.0f;
@@ -524,7 +532,7 @@ __global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_d
         for (int v = 0; v < 16; ++v) {
           float re, im;
           value(mb, nb, v, re, im);
-          store_planes4(P, po.at(mb, nb, v), re, im);
+          store_planes<NP>(P, po.at(mb, nb, v), re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
   } else {
@@ -541,7 +549,7 @@ __global__ __launch_bounds__(256, FORM == kForm3M ? 1 : 2) void k_cgemm_bf16x3_d
           value(mb, nb, v, re, im);
           if (cm < g.M && cn < g.N) {
             if (fo)
-              store_planes4(P, po.at(mb, nb, v), re, im);
+              store_planes<NP>(P, po.at(mb, nb, v), re, im);
             else
               C[cm * ldc + cn] = make_float2(re, im);
             mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
@@ -763,7 +771,7 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_pp(GemmArgs g) {
   const float post = (g.raw_a | g.raw_b) ? ldexpf(1.0f, -(g.raw_a ? ea : 0) - (g.raw_b ? eb : 0)) : 1.0f;
   const bool fo = g.fo_on != 0;
   uint8_t *const P0 = (uint8_t *)(g.C + q * g.cbs);
-  uint8_t *const P[4] = {P0, P0 + g.fo_plane * 2, P0 + g.fo_plane * 4, P0 + g.fo_plane * 6};
+  uint8_t *const P[6] = {P0, P0 + g.fo_plane * 2, P0 + g.fo_plane * 4, P0 + g.fo_plane * 6, P0, P0};
   PlaneOut<2> po;
   if (fo) po.init(g, m0 + rbase + (lane >> 5) * 4, n0 + cbase + (lane & 31));
   float mx = 0.0f;
@@ -776,7 +784,7 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_pp(GemmArgs g) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const float re = acc[mb][nb][0][v] * post, im = acc[mb][nb][1][v] * post;
-          store_planes4(P, po.at(mb, nb, v), re, im);
+          store_planes<4>(P, po.at(mb, nb, v), re, im);
           mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
   } else {
@@ -792,7 +800,7 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_pp(GemmArgs g) {
           const float re = acc[mb][nb][0][v] * post, im = acc[mb][nb][1][v] * post;
           if (cm < g.M && cn < g.N) {
             if (fo)
-              store_planes4(P, po.at(mb, nb, v), re, im);
+              store_planes<4>(P, po.at(mb, nb, v), re, im);
             else
               C[cm * ldc + cn] = make_float2(re, im);
             mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
@@ -811,7 +819,7 @@ hipError_t launch_gemm_bf16x3(hipStream_t st, const GemmArgs &g0, int form, int 
   if (g.opA != 0 || g.opB != 1 || g.planes != (form == kForm3M ? 6 : 4)) return hipErrorInvalidValue;
   if (g.tile < 0 || g.tile > 2) return hipErrorInvalidValue;
   if ((g.raw_a || g.raw_b || g.fo_on) && !g.ktile) return hipErrorInvalidValue;
-  if (g.fo_on && (form != kForm4M || g.ksplit > 1)) return hipErrorInvalidValue;
+  if (g.fo_on && g.ksplit > 1) return hipErrorInvalidValue;
   // the two-group kernel: 4M from k-tiled planes with a wide tile
   const bool pp = g.ktile && form == kForm4M && g.tile != 0;
   g.tiles_m = (int)((g.M + (pp ? gemm_bf16_tile_m(g.tile) : BT) - 1) / (pp ? gemm_bf16_tile_m(g.tile) : BT));

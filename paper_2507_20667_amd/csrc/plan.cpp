@@ -364,11 +364,11 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
   else if (k_all % 16 == 0)
     n.planes = 2;
   // a GEMM child whose result this GEMM may read as planes it writes itself
-  // (both FP32 planes, or both BF16x3 4M; the child on k-tiled planes, not
+  // (both FP32, or both BF16x3 of one form; the child on k-tiled planes, not
   // split in k): the larger one
   const int nv = (int)p->leaf.size();
   const bool fuse_on = !getenv("TN_GEMM_FUSE") || atoi(getenv("TN_GEMM_FUSE")) != 0;
-  const bool fuse_kind = n.planes == 2 || n.planes == 4;
+  const bool fuse_kind = n.planes > 0;
   auto fusable = [&](int c) {
     if (c < nv || !fuse_kind) return false;
     const Node &u = p->nodes[c - nv];
@@ -501,7 +501,8 @@ static tn_status schedule_gemm(tn_plan *p, Node &n, const Layout &A, const Layou
     int nbits = 0;
     const Layout &D = fa ? n.pa.dst : n.pb.dst;
     // (both vertices too large for a subtree batch, which writes complex64;
-    // the planes, 8 bytes an entry, within 4 GiB)
+    // at most 2^29 entries, so that 32-bit byte offsets from each plane's
+    // base reach them)
     if (X.size() > kTreeMaxElems && X.size() <= ((int64_t)1 << 29) &&
         fuse_bits(X, D, fa ? n.M : n.N, n.K, d, nbits) && u.N >= 16 && u.M * u.N == X.size()) {
       u.fo = true;
@@ -618,6 +619,12 @@ static bool node_in_bounds(const tn_plan *p, const Node &n, const std::vector<La
 }
 
 static void select_trees(tn_plan *p, const std::vector<Layout> &lay);
+
+// Bytes of a vertex's result buffer: complex64, or the parent's operand planes
+// its epilogue writes (8 bytes an entry; the six BF16x3 3M planes 12)
+static int64_t out_bytes_of(const Node &n) {
+  return std::max<int64_t>(n.out.size(), 1) * (n.fo && n.planes == 6 ? 12 : 8);
+}
 
 static u128 mul_check(u128 a, u128 b, bool &ovf) {
   if (a != 0 && b > (~(u128)0) / a) ovf = true;
@@ -2129,8 +2136,8 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
   // subtree results are written before any other vertex runs
   if (trees) {
     for (int r : p->tree_roots)
-      L.off[r] = pk[L.shared[r] ? 1 : 0].alloc(std::max<int64_t>(p->nodes[r - nv].out.size(), 1) * 8);
-    for (int u : L.islands) L.off[u] = pk[1].alloc(std::max<int64_t>(p->nodes[u - nv].out.size(), 1) * 8);
+      L.off[r] = pk[L.shared[r] ? 1 : 0].alloc(out_bytes_of(p->nodes[r - nv]));
+    for (int u : L.islands) L.off[u] = pk[1].alloc(out_bytes_of(p->nodes[u - nv]));
     // the large intermediates of per-query subtrees stay in the query's part
     // of the workspace (their whole lifetime), which keeps each query's LDS
     // small enough for more queries per CU
@@ -2150,14 +2157,14 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
       }
     }
     std::sort(L.spill.begin(), L.spill.end());
-    for (int u : L.spill) L.off[u] = pk[0].alloc(p->nodes[u - nv].out.size() * 8);
+    for (int u : L.spill) L.off[u] = pk[0].alloc(out_bytes_of(p->nodes[u - nv]));
   }
   for (int j : p->order) {
     const Node &n = p->nodes[j];
     if (trees && p->in_tree[n.id]) continue;
     Packer &P = packer_of(n);
     if (conc && n.part >= 0) in_part[n.id] = (int8_t)n.part;
-    int64_t out_bytes = std::max<int64_t>(n.out.size(), 1) * 8;
+    int64_t out_bytes = out_bytes_of(n);
     L.off[n.id] = P.alloc(out_bytes);
     std::vector<std::pair<int64_t, int64_t>> tmp;
     if (n.kind == NK_GEMM) {
@@ -2191,7 +2198,7 @@ ExecLayout make_exec_layout(const tn_plan *p, const std::vector<int> &overridden
       if (in_part[c] != in_part[n.id]) continue;
       if (L.shared[c] == L.shared[n.id]) {
         const Node &cn = p->nodes[c - nv];
-        P.release(L.off[c], std::max<int64_t>(cn.out.size(), 1) * 8);
+        P.release(L.off[c], out_bytes_of(cn));
       }
     }
   }

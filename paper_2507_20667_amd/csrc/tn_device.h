@@ -100,7 +100,7 @@ struct GemmArgs {
   // 256, 2 = 256 x 64; of the BF16x3 4M kernels on k-tiled planes: 0 = 128 x
   // 128, 1 = 128 x 256, 2 = 256 x 128 (the two wave-group kernel)
   int32_t tile;
-  // Kernels on k-tiled planes only (FP32, and BF16x3 4M).  raw_a / raw_b:
+  // Kernels on k-tiled planes only (FP32 and BF16x3).  raw_a / raw_b:
   // that operand's planes hold its values as they are, not divided by 2^e of
   // its scale record (a producer GEMM wrote them, see fo_on): the result is
   // multiplied by 2^-e instead, which is exact (and so is the bf16 split of
@@ -110,7 +110,8 @@ struct GemmArgs {
   // (bit b of it goes to bit fo_d[b] of d; fo_nbits = log2 N bits of n, then
   // those of m), plane p at C + p fo_plane + d: two float planes (re, im)
   // from the FP32 kernel, four bf16 planes (re hi, re lo, im hi, im lo) from
-  // the BF16x3 4M kernels; 8 fo_plane bytes at most 2^32
+  // the BF16x3 4M kernels, six (those and (re+im) hi, (re+im) lo) from the
+  // BF16x3 3M kernel; fo_plane at most 2^29
   int32_t raw_a, raw_b;
   int32_t fo_on, fo_nbits, fo_mbits;
   int64_t fo_plane;

@@ -11,9 +11,10 @@ sides, tiles the producer fills only in part (|a| < the tile's rows, or |b1
 b2| < its columns), one-bit and multi-bit contracted legs (the former let the
 planner move row legs into the low result bits), a producer shared by every
 query of a batch (its planes read with batch stride 0) and one computed per
-query.  The CPU test checks the plan decisions; the GPU tests check fused
-against unfused results bit for bit and against the oracle's complex128
-contraction of the same tree.
+query, in FP32 (4M, 3M) and BF16x3 (4M: four planes; 3M: six).  The CPU
+test checks the plan decisions; the GPU tests check fused against unfused
+results bit for bit and against the oracle's complex128 contraction of the
+same tree.
 """
 import math
 import re
@@ -64,7 +65,8 @@ def _load(ctx, name, flags, ts=None):
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
-@pytest.mark.parametrize("flags", [lib.TN_PREC_FP32, lib.TN_PREC_FP32 | lib.TN_FORM_3M, lib.TN_PREC_BF16X3])
+@pytest.mark.parametrize("flags", [lib.TN_PREC_FP32, lib.TN_PREC_FP32 | lib.TN_FORM_3M, lib.TN_PREC_BF16X3,
+                                   lib.TN_PREC_BF16X3 | lib.TN_FORM_3M])
 def test_fusion_in_plan(name, flags, monkeypatch, capfd):
     """The producer writes planes, the root reads the designed operand raw,
     one permutation fewer than with TN_GEMM_FUSE=0."""
@@ -98,7 +100,8 @@ def ctx():
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("name", sorted(CASES))
-@pytest.mark.parametrize("flags", [lib.TN_PREC_FP32, lib.TN_PREC_FP32 | lib.TN_FORM_3M, lib.TN_PREC_BF16X3])
+@pytest.mark.parametrize("flags", [lib.TN_PREC_FP32, lib.TN_PREC_FP32 | lib.TN_FORM_3M, lib.TN_PREC_BF16X3,
+                                   lib.TN_PREC_BF16X3 | lib.TN_FORM_3M])
 def test_fused_single(ctx, name, flags, monkeypatch):
     """One query: fused and unfused bits agree, and both match the oracle."""
     got = {}
@@ -116,7 +119,7 @@ def test_fused_single(ctx, name, flags, monkeypatch):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("name", ["b_side", "a_side", "partial_rows"])
-@pytest.mark.parametrize("flags", [lib.TN_PREC_FP32, lib.TN_PREC_BF16X3])
+@pytest.mark.parametrize("flags", [lib.TN_PREC_FP32, lib.TN_PREC_BF16X3, lib.TN_PREC_BF16X3 | lib.TN_FORM_3M])
 @pytest.mark.parametrize("leaf", [2, 0])
 def test_fused_batch(ctx, name, flags, leaf, monkeypatch):
     """Four queries in one batch, each overriding leaf Z (the producer P is

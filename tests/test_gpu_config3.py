@@ -58,10 +58,11 @@ def test_config3_amplitudes(setup, flags, tol):
 
 
 @pytest.mark.parametrize("flags,tol", [(lib.TN_PREC_FP32, 1e-5), (lib.TN_PREC_FP32 | lib.TN_FORM_3M, 1e-5),
-                                       (lib.TN_PREC_BF16X3 | lib.TN_FORM_4M, 1e-3)])
+                                       (lib.TN_PREC_BF16X3 | lib.TN_FORM_4M, 1e-3),
+                                       (lib.TN_PREC_BF16X3 | lib.TN_FORM_3M, 1e-3)])
 def test_fused_gemm_epilogue_bit_identical(setup, flags, tol, monkeypatch):
-    """The plane GEMMs (FP32; BF16x3 4M, whose producers write the four split
-    bf16 planes) that write their parent's operand planes in their epilogue
+    """The plane GEMMs (FP32; BF16x3, whose producers write the four or six
+    split bf16 planes) that write their parent's operand planes in their epilogue
     (the parent then reads them as they are and scales its result by the
     power of two instead) give the same bits as the permuted operands."""
     gold, circ, net, plan, ctx = setup
