@@ -66,16 +66,32 @@ def test_fused_gemm_epilogue_bit_identical(setup, flags, tol, monkeypatch):
     (the parent then reads them as they are and scales its result by the
     power of two instead) give the same bits as the permuted operands."""
     gold, circ, net, plan, ctx = setup
-    perms, amps = {}, {}
+    perms, amps, batch = {}, {}, {}
     for fuse in ("0", "1"):
         monkeypatch.setenv("TN_GEMM_FUSE", fuse)
         p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 8, plan.tree, None, flags)
         perms[fuse] = lib.tn_plan_costs_get(p)["num_permutations"]
         amps[fuse] = np.array([np.asarray(lib.tn_contract(p, amplitude_overrides(net, circ, x))[0]).reshape(-1)[0]
                                for x in gold["bitstrings"]], dtype=np.complex128)
+        if fuse == "1":
+            # the fused plan with the partitions side by side (one stream
+            # each): the same bits
+            conc = np.array([np.asarray(lib.tn_contract(p, amplitude_overrides(net, circ, x),
+                                                        flags=lib.TN_FLAG_CONCURRENT)[0]).reshape(-1)[0]
+                             for x in gold["bitstrings"]], dtype=np.complex128)
+            assert np.array_equal(conc.view(np.uint64), amps[fuse].view(np.uint64))
+        # all the bitstrings as one batch (its small vertices in the subtree
+        # kernel, the GEMMs batched over the queries)
+        res, _, st = lib.tn_contract_batch(ctx.handle, [(p, amplitude_overrides(net, circ, x))
+                                                        for x in gold["bitstrings"]],
+                                           [()] * len(gold["bitstrings"]))
+        assert all(v == 0 for v in st)
+        batch[fuse] = np.array([complex(np.asarray(r).reshape(-1)[0]) for r in res], dtype=np.complex128)
         ctx.free_plan(p)
     assert perms["1"] < perms["0"], perms
     assert np.array_equal(amps["1"].view(np.uint64), amps["0"].view(np.uint64)), (amps["0"], amps["1"])
+    assert np.array_equal(batch["1"].view(np.uint64), batch["0"].view(np.uint64)), (batch["0"], batch["1"])
     for i, x in enumerate(gold["bitstrings"]):
         ref = complex(*gold["amplitudes"][str(x)])
         assert abs(amps["1"][i] - ref) / max(abs(ref), 2.0 ** -15) < tol
+        assert abs(batch["1"][i] - ref) / max(abs(ref), 2.0 ** -15) < tol
