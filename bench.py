@@ -632,6 +632,15 @@ def headline_random30(lib, torch, args):
     p = ctx.plan_load(net.legs, net.dims, net.tensors, plan.partition_of, 8, plan.tree, None, flags)
     costs = lib.tn_plan_costs_get(p)
     con_serial = costs["con_serial"]
+    # the same plan without fused GEMM epilogues (host-side plan, no device
+    # work): the permutations the fused epilogues take away
+    os.environ["TN_GEMM_FUSE"] = "0"
+    try:
+        pu = lib.tn_plan_load(None, net.legs, net.dims, net.tensors, plan.partition_of, 8, plan.tree, None, flags)
+        perms_unfused = lib.tn_plan_costs_get(pu)["num_permutations"]
+        lib.tn_plan_free(pu)
+    finally:
+        del os.environ["TN_GEMM_FUSE"]
     ids = output_tensor_ids(net)
     Q, K, W = args.queries, args.steps, args.warmup
 
@@ -770,6 +779,8 @@ def headline_random30(lib, torch, args):
            "kernel_classes": {k: v for k, v in stats.items() if v["launches"]},
            "con_serial": con_serial, "con_dist": costs["con_dist"],
            "largest_intermediate": costs["largest_intermediate"], "planning_s": w.planning_s,
+           "permutations_per_amplitude": costs["num_permutations"],
+           "permutations_per_amplitude_without_fused_epilogues": perms_unfused,
            "workload": w.name, "overrides": "host basis vectors copied to the device inside each step",
            "cost_point": cost_point}
     log(f"30-qubit {prec} {form}: {amps:.1f} amplitudes/s ({dt / K * 1e3:.1f} ms per step of {Q}), "
