@@ -104,7 +104,8 @@ struct GemmArgs {
   // that operand's planes hold its values as they are, not divided by 2^e of
   // its scale record (a producer GEMM wrote them, see fo_on): the result is
   // multiplied by 2^-e instead, which is exact (and so is the bf16 split of
-  // a value times a power of two), so it is the same as from divided planes.
+  // a value times a power of two), so it is the same as from divided planes
+  // (values in the normal FP32 range).
   // fo_on: write the result not to C as complex64 but as the consumer's
   // k-tiled operand planes, d of the result index m N + n given bit by bit
   // (bit b of it goes to bit fo_d[b] of d; fo_nbits = log2 N bits of n, then
