@@ -148,3 +148,23 @@ def test_fused_batch(ctx, name, flags, leaf, monkeypatch):
         tq[leaf] = o[leaf]
         ref = oracle.contract_tree(legs, dims, tq, tree, out)
         assert np.max(np.abs(got["1"][q] - ref)) / np.max(np.abs(ref)) < tol
+
+
+@pytest.mark.parametrize("flags", [lib.TN_PREC_FP32, lib.TN_PREC_BF16X3])
+def test_no_fusion_past_2pow29_entries(flags, monkeypatch, capfd):
+    """T1[a, x] T2[b, x] T3[a] T4[b] with |a| = |b| = 2^16, |x| = 16 along
+    ((T1, T2), T3), T4: the first GEMM's result (2^32 entries) is too large for
+    32-bit plane offsets, so its parent permutes it instead of reading planes
+    the first GEMM writes."""
+    a, x = 1 << 16, 16
+    legs = [[1, 3], [2, 3], [1], [2]]
+    dims = {1: a, 2: a, 3: x}
+    ts = [np.ones((a, x), np.complex64), np.ones((a, x), np.complex64), np.ones(a, np.complex64),
+          np.ones(a, np.complex64)]
+    monkeypatch.setenv("TN_DEBUG", "1")
+    p = lib.tn_plan_load(None, legs, dims, ts, [0, 0, 0, 0], 1, [(0, 1), (4, 2), (5, 3)], None, flags,
+                         lib.TN_C64)
+    lib.tn_plan_free(p)
+    err = capfd.readouterr().err
+    assert re.search(r"gemm vertex 4: M 65536 N 65536 K 16 .* fused 00 writes 0", err), err
+    assert re.search(r"gemm vertex 5: .* perm 1. .* fused 00 writes 0", err), err
